@@ -1,0 +1,307 @@
+"""ctypes front end of the FP64 reference implementation in ``gps_oracle.c``.
+
+TEST INFRASTRUCTURE ONLY: imported by ``tests/``, by ``__graft_entry__.smoke()``
+and by the CPU-baseline leg of ``bench.py``.  The product package never imports
+this module, and this module never imports the product package.
+
+All array arguments are NumPy arrays; float32 inputs are passed exactly as the
+GPU kernels receive them, outputs come back as float64.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gps_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# -ffp-contract=off: every binary32 statement of the decision arithmetic rounds once.
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+
+
+def build(force: bool = True) -> str:
+    """Compile gps_oracle.c into liboracle.so with gcc."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.run(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"], check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Cam(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("fx", ctypes.c_float), ("fy", ctypes.c_float),
+                ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("origin", ctypes.c_float * 3), ("voxel", ctypes.c_float),
+                ("trunc", ctypes.c_float), ("max_weight", ctypes.c_float)]
+
+
+class Gauss(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32),
+                ("mean", ctypes.c_void_p), ("log_scale", ctypes.c_void_p),
+                ("quat", ctypes.c_void_p), ("opacity_logit", ctypes.c_void_p),
+                ("rgb", ctypes.c_void_p)]
+
+
+class Cfg(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("eps_cull", ctypes.c_float),
+                ("lambda_depth", ctypes.c_float), ("dilation", ctypes.c_float),
+                ("alpha_min", ctypes.c_float), ("alpha_max", ctypes.c_float),
+                ("T_min", ctypes.c_float), ("z_near", ctypes.c_float)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=True)
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        L.orc_fuse.argtypes = [P, P, P, P, P, P, P, P]
+        L.orc_fuse.restype = None
+        L.orc_raycast.argtypes = [P, P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_int32, P, P, P, P]
+        L.orc_raycast.restype = None
+        L.orc_trilinear.argtypes = [P, P, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.orc_trilinear.restype = ctypes.c_double
+        L.orc_project.argtypes = [P, P, P, P]
+        L.orc_project.restype = None
+        L.orc_render.argtypes = [P, P, P, P, P, ctypes.c_int32, P, P, P, P, P, P, P]
+        L.orc_render.restype = None
+        L.orc_loss.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, ctypes.c_double, P, P, P]
+        L.orc_loss.restype = ctypes.c_double
+        L.orc_render_bwd.argtypes = [P, P, P, P, P, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P]
+        L.orc_render_bwd.restype = None
+        L.orc_adam.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_double, ctypes.c_int32]
+        L.orc_adam.restype = None
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# --------------------------------------------------------------------------- #
+# Plain-data descriptions used by the wrapper (no product types).              #
+# --------------------------------------------------------------------------- #
+@dataclass
+class RenderCfg:
+    """Renderer constants (see the reading of each in gps_oracle.c)."""
+    mode: int = 0
+    eps_cull: float = 0.01
+    lambda_depth: float = 1.0
+    dilation: float = 0.3
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    T_min: float = 1e-4
+    z_near: float = 0.2
+
+    def c(self) -> Cfg:
+        return Cfg(self.mode, self.eps_cull, self.lambda_depth, self.dilation,
+                   self.alpha_min, self.alpha_max, self.T_min, self.z_near)
+
+
+def make_cam(width, height, fx, fy, cx, cy, R, t) -> Cam:
+    c = Cam()
+    c.width, c.height = int(width), int(height)
+    c.fx, c.fy, c.cx, c.cy = float(fx), float(fy), float(cx), float(cy)
+    R = np.asarray(R, dtype=np.float32).reshape(9)
+    t = np.asarray(t, dtype=np.float32).reshape(3)
+    for k in range(9):
+        c.R[k] = float(R[k])
+    for k in range(3):
+        c.t[k] = float(t[k])
+    return c
+
+
+def cam_from(camd) -> Cam:
+    """Accept a Cam, or any object/dict with width, height, fx, fy, cx, cy, R, t."""
+    if isinstance(camd, Cam):
+        return camd
+    g = (lambda k: camd[k]) if isinstance(camd, dict) else (lambda k: getattr(camd, k))
+    return make_cam(g("width"), g("height"), g("fx"), g("fy"), g("cx"), g("cy"), g("R"), g("t"))
+
+
+def make_grid(dims, origin, voxel, trunc, max_weight=100.0) -> Grid:
+    g = Grid()
+    g.nx, g.ny, g.nz = (int(d) for d in dims)
+    for k in range(3):
+        g.origin[k] = float(origin[k])
+    g.voxel, g.trunc, g.max_weight = float(voxel), float(trunc), float(max_weight)
+    return g
+
+
+class _GaussKeep:
+    """Keeps the float32 copies alive for as long as the ctypes struct is used."""
+
+    def __init__(self, mean, log_scale, quat, opacity_logit, rgb):
+        self.arrs = [_f32(mean), _f32(log_scale), _f32(quat), _f32(opacity_logit).reshape(-1), _f32(rgb)]
+        M = self.arrs[3].shape[0]
+        assert self.arrs[0].shape == (3, M) and self.arrs[1].shape == (3, M)
+        assert self.arrs[2].shape == (4, M) and self.arrs[4].shape == (3, M)
+        self.s = Gauss(M, *[_ptr(a) for a in self.arrs])
+        self.M = M
+
+
+def gauss(g) -> _GaussKeep:
+    """g: dict with mean [3,M], log_scale [3,M], quat [4,M], opacity_logit [M], rgb [3,M]."""
+    return _GaussKeep(g["mean"], g["log_scale"], g["quat"], g["opacity_logit"], g["rgb"])
+
+
+# --------------------------------------------------------------------------- #
+# Wrapped entry points                                                         #
+# --------------------------------------------------------------------------- #
+def new_volume(grid: Grid):
+    N = grid.nx * grid.ny * grid.nz
+    return {"tsdf": np.ones(N), "weight": np.zeros(N), "rgb": np.zeros((3, N)), "rgb_weight": np.zeros(N)}
+
+
+def fuse(grid: Grid, vol: dict, cam, depth, rgb):
+    """In-place FP64 fusion of one frame into ``vol`` (dict of float64 arrays)."""
+    cam = cam_from(cam)
+    depth = _f32(depth)
+    rgb = _f32(rgb)
+    assert depth.shape == (cam.height, cam.width) and rgb.shape == (3, cam.height, cam.width)
+    for k in ("tsdf", "weight", "rgb", "rgb_weight"):
+        assert vol[k].dtype == np.float64 and vol[k].flags.c_contiguous
+    lib().orc_fuse(ctypes.byref(grid), _ptr(vol["tsdf"]), _ptr(vol["weight"]), _ptr(vol["rgb"]),
+                   _ptr(vol["rgb_weight"]), ctypes.byref(cam), _ptr(depth), _ptr(rgb))
+    return vol
+
+
+def raycast(grid: Grid, tsdf32, rgb32, cam, z_near=0.2, step=0.0, pix=None):
+    """Returns depth [npix], rgb [3,npix], hit sample index [npix] (-1 = miss)."""
+    cam = cam_from(cam)
+    tsdf32 = _f32(tsdf32).reshape(-1)
+    rgb32 = _f32(rgb32).reshape(3, -1)
+    if pix is None:
+        npix, pixp = cam.width * cam.height, None
+    else:
+        pix = np.ascontiguousarray(pix, dtype=np.int32)
+        npix, pixp = pix.shape[0], pix
+    d = np.zeros(npix)
+    c = np.zeros((3, npix))
+    k = np.zeros(npix, dtype=np.int32)
+    lib().orc_raycast(ctypes.byref(grid), _ptr(tsdf32), _ptr(rgb32), ctypes.byref(cam), z_near, step,
+                      npix, _ptr(pixp), _ptr(d), _ptr(c), _ptr(k))
+    return d, c, k
+
+
+def trilinear(grid: Grid, field32, p):
+    f = _f32(field32).reshape(-1)
+    return lib().orc_trilinear(ctypes.byref(grid), _ptr(f), float(p[0]), float(p[1]), float(p[2]))
+
+
+def project(cfg: RenderCfg, g, cam):
+    """Per-Gaussian projection, a dict of arrays (see orc_project)."""
+    cam = cam_from(cam)
+    G = gauss(g)
+    out = np.zeros((G.M, 16))
+    c = cfg.c()
+    lib().orc_project(ctypes.byref(c), ctypes.byref(G.s), ctypes.byref(cam), _ptr(out))
+    return {"valid": out[:, 0] > 0.5, "m": out[:, 1:3], "cov": out[:, 3:6], "conic": out[:, 6:9],
+            "sigma": out[:, 9], "depth": out[:, 10], "depth32": out[:, 11].astype(np.float32),
+            "box": out[:, 12:16]}
+
+
+def render(cfg: RenderCfg, g, cam, base_rgb, base_depth, pix=None):
+    """Returns dict rgb [3,npix], depth, T, flag, n, W (float64 / int32)."""
+    cam = cam_from(cam)
+    G = gauss(g)
+    base_rgb = _f32(base_rgb).reshape(3, -1)
+    base_depth = _f32(base_depth).reshape(-1)
+    assert base_depth.shape[0] == cam.width * cam.height
+    if pix is None:
+        npix, pixp = cam.width * cam.height, None
+    else:
+        pixp = np.ascontiguousarray(pix, dtype=np.int32)
+        npix = pixp.shape[0]
+    rgb = np.zeros((3, npix))
+    depth = np.zeros(npix)
+    T = np.zeros(npix)
+    flag = np.zeros(npix, dtype=np.int32)
+    n = np.zeros(npix, dtype=np.int32)
+    W = np.zeros(npix)
+    c = cfg.c()
+    lib().orc_render(ctypes.byref(c), ctypes.byref(G.s), ctypes.byref(cam), _ptr(base_rgb), _ptr(base_depth),
+                     npix, _ptr(pixp), _ptr(rgb), _ptr(depth), _ptr(T), _ptr(flag), _ptr(n), _ptr(W))
+    return {"rgb": rgb, "depth": depth, "T": T, "flag": flag, "n": n, "W": W}
+
+
+def loss(cfg: RenderCfg, W: int, H: int, rgb, depth, target_rgb, target_depth, base_depth, scale=1.0,
+         want_grad=True):
+    """Per-view loss; returns (L, g_rgb [3,HW] or None, g_depth [HW] or None, |Omega|)."""
+    rgb = _f64(rgb).reshape(3, -1)
+    depth = _f64(depth).reshape(-1)
+    trgb = _f32(target_rgb).reshape(3, -1)
+    tdep = _f32(target_depth).reshape(-1)
+    bdep = _f32(base_depth).reshape(-1)
+    g_rgb = np.zeros_like(rgb) if want_grad else None
+    g_dep = np.zeros_like(depth) if want_grad else None
+    om = ctypes.c_int64(0)
+    c = cfg.c()
+    L = lib().orc_loss(ctypes.byref(c), W, H, _ptr(rgb), _ptr(depth), _ptr(trgb), _ptr(tdep), _ptr(bdep),
+                       float(scale), _ptr(g_rgb), _ptr(g_dep), ctypes.byref(om))
+    return L, g_rgb, g_dep, om.value
+
+
+def render_bwd(cfg: RenderCfg, g, cam, base_rgb, base_depth, g_pix_rgb, g_pix_depth, pix=None,
+               want_screen=False):
+    """Gradients (float64) for the listed pixels' upstream adjoints."""
+    cam = cam_from(cam)
+    G = gauss(g)
+    M = G.M
+    base_rgb = _f32(base_rgb).reshape(3, -1)
+    base_depth = _f32(base_depth).reshape(-1)
+    if pix is None:
+        npix, pixp = cam.width * cam.height, None
+    else:
+        pixp = np.ascontiguousarray(pix, dtype=np.int32)
+        npix = pixp.shape[0]
+    gpr = _f64(g_pix_rgb).reshape(3, npix)
+    gpd = _f64(g_pix_depth).reshape(npix)
+    out = {"mean": np.zeros((3, M)), "log_scale": np.zeros((3, M)), "quat": np.zeros((4, M)),
+           "opacity_logit": np.zeros(M), "rgb": np.zeros((3, M)), "pose": np.zeros(6)}
+    scr = np.zeros((M, 10)) if want_screen else None
+    c = cfg.c()
+    lib().orc_render_bwd(ctypes.byref(c), ctypes.byref(G.s), ctypes.byref(cam), _ptr(base_rgb),
+                         _ptr(base_depth), npix, _ptr(pixp), _ptr(gpr), _ptr(gpd), _ptr(out["mean"]),
+                         _ptr(out["log_scale"]), _ptr(out["quat"]), _ptr(out["opacity_logit"]),
+                         _ptr(out["rgb"]), _ptr(out["pose"]), _ptr(scr))
+    if want_screen:
+        out["screen"] = scr
+    return out
+
+
+def adam(param, grad, m, v, lr, t, b1=0.9, b2=0.999, eps=1e-15):
+    """In-place FP64 Adam step on float64 arrays."""
+    for a in (param, grad, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    lib().orc_adam(param.size, _ptr(param), _ptr(grad), _ptr(m), _ptr(v), lr, b1, b2, eps, int(t))
+
+
+# Learning rates per attribute, Appendix C (position, SH0 -> rgb, alpha -> opacity
+# logit, scale -> log-scale, rotation -> quaternion).
+PAPER_LR = {"mean": 1.6e-4, "rgb": 2.5e-3, "opacity_logit": 0.05, "log_scale": 5e-3, "quat": 1e-3}
