@@ -1,0 +1,238 @@
+/*
+ * gps.h -- C ABI of the MI355X (gfx950) implementation of the per-frame mapping
+ * path of Gaussian-plus-SDF SLAM (Peng, Zhou, Shao, arXiv 2509.11574):
+ * colourised-TSDF fusion, SDF raycast, the differentiable 3D-Gaussian overlay
+ * composited over the SDF base image, its photometric + depth loss, the
+ * analytic backward pass (Gaussian parameters and 6-DoF camera pose) and Adam.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Pointers are DEVICE pointers unless the comment says "host".  Every array
+ *    is float32, planar (structure of arrays), C order.  Images are [H][W]
+ *    (depth) and [3][H][W] (colour); lattices are indexed
+ *    x + nx*(y + ny*z); Gaussian attributes are [k][M] (one plane per
+ *    component).
+ *  - Cameras map world to camera: p_c = R p_w + t, R row-major, OpenCV axes
+ *    (x right, y down, z forward).  Pixel (col, row) is sampled at (col, row);
+ *    projection is u = fx x/z + cx, v = fy y/z + cy.
+ *  - The caller owns every buffer.  The library allocates no device memory and
+ *    keeps no state between calls other than cached device attributes.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *    enqueues work and returns without synchronising, except gps_device_status
+ *    and gps_read_stats, which synchronise the stream they are given.
+ *  - Argument errors are returned synchronously and nothing is launched.
+ *    Failures discovered on the device (too many tile instances for the
+ *    workspace) set a sticky status word inside the workspace; read it with
+ *    gps_device_status.  Launch failures return GPS_ERR_HIP.
+ *  - A sequence of calls with unchanged arguments launches an identical
+ *    sequence of kernels with identical arguments and never reads device data
+ *    on the host, so it may be captured in a HIP graph and replayed.
+ *  - Every entry point is deterministic: the same inputs give bitwise the same
+ *    outputs (no floating-point atomics anywhere).
+ *  - Calls that share a workspace must not run concurrently.
+ */
+#ifndef GPS_H_
+#define GPS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GPS_ABI_VERSION 1
+#define GPS_MAX_VIEWS 16 /* views per render call */
+
+typedef int32_t gps_status;
+#define GPS_OK 0
+#define GPS_ERR_INVALID_ARG (-1)
+#define GPS_ERR_WORKSPACE_TOO_SMALL (-2)
+#define GPS_ERR_CAPACITY (-3)           /* device: more tile instances than the workspace holds */
+#define GPS_ERR_HIP (-4)                /* a HIP runtime call or launch failed                 */
+#define GPS_ERR_UNSUPPORTED_DEVICE (-5) /* the current device is not gfx950                    */
+#define GPS_ERR_UNSUPPORTED_CONFIG (-6) /* tile / batch / pixels-per-thread not compiled in    */
+
+typedef struct gps_camera {
+    int32_t width, height;
+    float fx, fy, cx, cy;
+    float R[9]; /* world -> camera rotation, row-major */
+    float t[3]; /* world -> camera translation         */
+} gps_camera;
+
+/* Colourised TSDF volume S: every lattice point stores a truncated signed
+ * distance and an RGB colour (Sec. 3.1 "Gaussian-plus-SDF"), here as a dense
+ * lattice.  Point (x,y,z) sits at origin + voxel*(x,y,z). */
+typedef struct gps_volume {
+    int32_t nx, ny, nz;
+    float origin[3];
+    float voxel;      /* lattice spacing (m)                                   */
+    float trunc;      /* truncation distance mu (m)                            */
+    float max_weight; /* fusion weights saturate here                          */
+    float* tsdf;       /* [N] truncated SDF in units of mu, initialise to 1     */
+    float* weight;     /* [N] fusion weight, initialise to 0                    */
+    float* rgb;        /* [3][N] colour, initialise to 0                        */
+    float* rgb_weight; /* [N] colour weight, initialise to 0                    */
+    float* brick_min;  /* optional [ceil(nx/8)*ceil(ny/8)*ceil(nz/8)] scratch
+                          for empty-space skipping in gps_raycast; NULL disables */
+} gps_volume;
+
+/* The Gaussian set G = {p_i, sigma_i, r_i, s_i, SH_i} (Sec. 3.1), with
+ * degree-0 colour stored as linear RGB.  The same struct carries gradients. */
+typedef struct gps_gaussians {
+    int32_t count;        /* M                                              */
+    float* mean;          /* [3][M] centre p_i (world, m)                   */
+    float* log_scale;     /* [3][M] log of the axis scales s_i              */
+    float* quat;          /* [4][M] rotation r_i as (w, x, y, z), any norm  */
+    float* opacity_logit; /* [M]    sigma_i = 1/(1+exp(-logit))             */
+    float* rgb;           /* [3][M] colour c_i                              */
+} gps_gaussians;
+
+/* One view of a render call. */
+typedef struct gps_view {
+    gps_camera cam;
+    const float* base_rgb;     /* [3][H][W] SDF colour C_t  (from gps_raycast)     */
+    const float* base_depth;   /* [H][W]    SDF depth D_t, 0 = ray missed          */
+    const float* target_rgb;   /* [3][H][W] observed colour C_k, NULL = no loss    */
+    const float* target_depth; /* [H][W]    observed depth D_k (0 = invalid)       */
+    float* out_rgb;            /* [3][H][W] rendered C* (written by render_fwd)    */
+    float* out_depth;          /* [H][W]    rendered D* (0 where D_t is invalid)   */
+} gps_view;
+
+/* Renderer constants (each is a reading of the paper where it is silent). */
+typedef struct gps_render_cfg {
+    int32_t tile_w, tile_h;  /* screen tile: 8x8, 16x16 or 16x32                   */
+    int32_t batch;           /* Gaussians staged in LDS per step: 128, 256 or 512  */
+    int32_t pix_per_thread;  /* pixels per lane: 1, 2 or 4                         */
+    int32_t mode;            /* 0 sorted over-compositing (the default); 1 the
+                                sort-free blend of Eq. 1, 2, 4                     */
+    float eps_cull;          /* epsilon of the depth test of Eq. 1-2 (m)           */
+    float lambda_depth;      /* weight of the L1 depth term                        */
+    float dilation;          /* px^2 added to the diagonal of Sigma_2D (0.3)       */
+    float alpha_min;         /* 1/255 (Sec. 3.1, after Eq. 3)                      */
+    float alpha_max;         /* opacity cap of sorted mode (0.99)                  */
+    float T_min;             /* transmittance stop of sorted mode (1e-4, 0 = off)   */
+    float z_near;            /* centres nearer than this are culled (0.2 m)        */
+    int64_t max_instances;   /* capacity for (view, tile, Gaussian) instances;
+                                0 = 32 per view-Gaussian, at least 2^20            */
+} gps_render_cfg;
+
+/* One Adam parameter group. */
+typedef struct gps_adam_group {
+    float* param;
+    const float* grad;
+    float* m; /* first moment, initialise to 0  */
+    float* v; /* second moment, initialise to 0 */
+    int64_t n;
+    float lr;
+} gps_adam_group;
+
+/* Counters of the last render call in a workspace (read with gps_read_stats). */
+typedef struct gps_stats {
+    int32_t status;            /* sticky status word                              */
+    int32_t n_views;
+    int64_t n_instances;       /* tile instances emitted by the last forward      */
+    int64_t capacity;          /* instances the workspace holds                   */
+    int64_t sort_fallback;     /* tiles longer than the LDS sort holds            */
+    int64_t n_tiles;
+    float loss;                /* last forward's loss                             */
+    float view_omega[GPS_MAX_VIEWS]; /* |Omega_v|: pixels in each view's depth term */
+} gps_stats;
+
+int32_t gps_abi_version(void);
+const char* gps_status_string(gps_status s);
+
+/* Fills `cfg` (host) with the defaults: 16x16 tiles, batch 256, 1 pixel per
+ * lane, sorted mode, eps 0.01, lambda 1, dilation 0.3, alpha 1/255..0.99,
+ * T_min 1e-4, z_near 0.2, automatic capacity. */
+void gps_render_cfg_default(gps_render_cfg* cfg);
+
+/* Bytes of workspace a render call with these arguments needs (host call,
+ * nothing launched).  cams: host array of n_views cameras. */
+gps_status gps_workspace_size(const gps_render_cfg* cfg, int32_t n_gaussians, const gps_camera* cams,
+                              int32_t n_views, size_t* out_bytes);
+
+/* Clears the workspace header (sticky status, counters, Adam step counter).
+ * Call once after allocating a workspace, and after a capacity error before
+ * replaying with a larger workspace. */
+gps_status gps_workspace_reset(void* ws, size_t ws_bytes, void* stream);
+
+/* TSDF + colour fusion of one RGB-D frame (Sec. 3.2.1, "SDF fusion", the
+ * projective update of KinectFusion/InfiniTAM).  For every lattice point in
+ * front of the camera whose nearest pixel has depth d > 0: eta = d - z; points
+ * with eta < -mu are left alone; otherwise tsdf <- (w tsdf + min(1, eta/mu))
+ * / (w + 1) and w <- min(w + 1, max_weight); inside |eta| <= mu the colour is
+ * averaged the same way with its own weight.
+ * depth [H][W] (m, 0 = invalid), rgb [3][H][W].  Updates vol in place. */
+gps_status gps_fuse(const gps_volume* vol, const gps_camera* cam, const float* depth, const float* rgb,
+                    void* stream);
+
+/* SDF raycast (Sec. 3.1 first pass; Sec. 3.2.1): each pixel's ray marches with
+ * step `step` (0 = voxel/2) from depth z_near until the trilinear signed
+ * distance turns from positive to non-positive; the crossing is refined by the
+ * secant; D_t is the camera depth of the surface point V and C_t the trilinear
+ * colour of the eight voxels around V.  Misses give D_t = 0, C_t = 0.
+ * cams: host array of n_views (<= GPS_MAX_VIEWS) cameras; out_depth, out_rgb:
+ * host arrays of n_views device pointers ([H][W] and [3][H][W] of each view).
+ * If vol->brick_min is set it is rebuilt from vol->tsdf first and used to skip
+ * samples whose 2x2x2 stencil is known positive (the result is unchanged). */
+gps_status gps_raycast(const gps_volume* vol, const gps_camera* cams, int32_t n_views, float* const* out_depth,
+                       float* const* out_rgb, float z_near, float step, void* stream);
+
+/* Forward render of n_views (<= GPS_MAX_VIEWS) views (views: host array) and,
+ * when every view has target_rgb, the loss
+ *   L = (1/V) sum_v [ mean_{pixels,channels} |C* - C_k| (Eq. 7)
+ *                    + lambda_depth * mean_{Omega_v} |D* - D_k| ],
+ *   Omega_v = { D_k > 0 and D_t > 0 },
+ * written to out_loss (device float, may be NULL).
+ * Per view: EWA projection of every Gaussian (Eq. 3, following 3DGS), binning
+ * into screen tiles with an exact tile-level depth cull, a per-tile depth sort,
+ * and compositing over the SDF base:
+ *   mode 0: front to back, alpha_i = min(alpha_max, sigma_i exp(-q/2)),
+ *           skipping alpha < alpha_min, stopping at the first Gaussian with
+ *           d_i >= D_t + eps (the depth test of Eq. 1-2) or when the
+ *           transmittance would fall below T_min;
+ *           C* = sum alpha_i T_i c_i + T_final C_t, D* likewise with d_i, D_t;
+ *   mode 1: C* = (C_t + sum alpha_i c_i) / (1 + sum alpha_i) (Eq. 1, 2, 4).
+ * The workspace keeps what gps_render_bwd needs; render_bwd must follow on
+ * the same workspace with unchanged inputs. */
+gps_status gps_render_fwd(const gps_render_cfg* cfg, const gps_gaussians* g, const gps_view* views, int32_t n_views,
+                          void* ws, size_t ws_bytes, float* out_loss, void* stream);
+
+/* Backward of gps_render_fwd.  The upstream adjoint is either
+ *   - the fused loss (dL_drgb == NULL): dL/dC*, dL/dD* of the loss above,
+ *     scaled by *loss_scale (device float; NULL = 1), or
+ *   - explicit per-view images (dL_drgb, dL_ddepth: host arrays of n_views
+ *     device pointers to [3][H][W] and [H][W]; dL_ddepth may be NULL).
+ * Per pixel the transmittance and prefix colour are recomputed front to back
+ * (nothing per pixel is stored by the forward); each (tile, Gaussian) instance
+ * gets one partial reduced across its tile's pixels with wavefront DPP
+ * reductions, and each Gaussian sums its instances in a fixed order, so no
+ * floating-point atomics are used.
+ * grads: gradients with respect to every attribute of g (overwritten).
+ * dpose: [n_views][6] gradient with respect to xi = (rho, phi) of the left
+ * perturbation T_cw <- Exp(xi) T_cw at xi = 0 (may be NULL). */
+gps_status gps_render_bwd(const gps_render_cfg* cfg, const gps_gaussians* g, const gps_view* views, int32_t n_views,
+                          const float* const* dL_drgb, const float* const* dL_ddepth, const float* loss_scale,
+                          gps_gaussians* grads, float* dpose, void* ws, size_t ws_bytes, void* stream);
+
+/* Adam over n_groups (<= 8) parameter groups in one launch (groups: host
+ * array), with the per-attribute learning rates of Appendix C supplied by the
+ * caller:  m <- b1 m + (1-b1) g; v <- b2 v + (1-b2) g^2;
+ * p <- p - lr (m/(1-b1^t)) / (sqrt(v/(1-b2^t)) + eps).
+ * The step t is `step` (>= 1) when step_counter is NULL; otherwise
+ * t = *step_counter + 1 is read on the device and the counter is incremented
+ * once the update is done (for graph replay). */
+gps_status gps_adam_step(const gps_adam_group* groups, int32_t n_groups, int32_t step, int32_t* step_counter,
+                         float beta1, float beta2, float eps, void* stream);
+
+/* Reads the sticky status word of a workspace (synchronises `stream`). */
+gps_status gps_device_status(const void* ws, size_t ws_bytes, int32_t* out_status, void* stream);
+
+/* Reads the counters of the last render call (synchronises `stream`). */
+gps_status gps_read_stats(const void* ws, size_t ws_bytes, gps_stats* out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GPS_H_ */

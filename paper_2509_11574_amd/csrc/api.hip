@@ -1,0 +1,365 @@
+// C ABI of libgps (declared in include/gps.h): argument validation, the
+// workspace map, view tables and kernel launches.  No entry point allocates
+// device memory; every argument error is reported before anything is launched.
+#include <atomic>
+#include <cmath>
+#include <cstring>
+
+#include "gps_internal.h"
+
+namespace gps {
+bool tile_config_supported(const gps_render_cfg* cfg);
+
+static inline size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+static bool cam_ok(const gps_camera& c)
+{
+    if (c.width <= 0 || c.height <= 0 || c.width > (1 << 18) || c.height > (1 << 18)) return false;
+    const float vals[4] = {c.fx, c.fy, c.cx, c.cy};
+    for (float v : vals)
+        if (!std::isfinite(v)) return false;
+    if (c.fx == 0.0f || c.fy == 0.0f) return false;
+    for (int k = 0; k < 9; ++k)
+        if (!std::isfinite(c.R[k])) return false;
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(c.t[k])) return false;
+    return true;
+}
+
+static gps_status check_device()
+{
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return GPS_ERR_HIP;
+    if (dev < 0 || dev >= 64) return GPS_ERR_UNSUPPORTED_DEVICE;
+    int st = cache[dev].load(std::memory_order_relaxed);
+    if (st == 0) {
+        hipDeviceProp_t p;
+        if (hipGetDeviceProperties(&p, dev) != hipSuccess) return GPS_ERR_HIP;
+        st = std::strncmp(p.gcnArchName, "gfx950", 6) == 0 ? 1 : -1;
+        cache[dev].store(st, std::memory_order_relaxed);
+    }
+    return st == 1 ? GPS_OK : GPS_ERR_UNSUPPORTED_DEVICE;
+}
+
+static gps_status compute_layout(const gps_render_cfg* cfg, int M, const gps_camera* cams, int V, WsLayout* L)
+{
+    if (!cfg || !cams || !L || M < 0 || V < 1 || V > GPS_MAX_VIEWS) return GPS_ERR_INVALID_ARG;
+    if (cfg->mode != 0 && cfg->mode != 1) return GPS_ERR_INVALID_ARG;
+    if (!tile_config_supported(cfg)) return GPS_ERR_UNSUPPORTED_CONFIG;
+    if (cfg->max_instances < 0) return GPS_ERR_INVALID_ARG;
+    const float consts[7] = {cfg->eps_cull, cfg->lambda_depth, cfg->dilation, cfg->alpha_min,
+                             cfg->alpha_max, cfg->T_min, cfg->z_near};
+    for (float c : consts)
+        if (!std::isfinite(c) || c < 0.0f) return GPS_ERR_INVALID_ARG;
+    if (!(cfg->alpha_min > 0.0f) || !(cfg->alpha_max > cfg->alpha_min) || !(cfg->alpha_max < 1.0f) ||
+        !(cfg->z_near > 0.0f) || !(cfg->dilation > 0.0f))
+        return GPS_ERR_INVALID_ARG;
+    long long n_tiles = 0, npix = 0;
+    for (int v = 0; v < V; ++v) {
+        if (!cam_ok(cams[v])) return GPS_ERR_INVALID_ARG;
+        const long long tx = (cams[v].width + cfg->tile_w - 1) / cfg->tile_w;
+        const long long ty = (cams[v].height + cfg->tile_h - 1) / cfg->tile_h;
+        if (tx > 65534 || ty > 65534) return GPS_ERR_INVALID_ARG;
+        n_tiles += tx * ty;
+        npix += (long long)cams[v].width * cams[v].height;
+    }
+    const long long nvg = (long long)V * M;
+    if (nvg >= (1ll << 31) || n_tiles >= (1ll << 31) || npix >= (1ll << 31)) return GPS_ERR_INVALID_ARG;
+    unsigned long long cap = cfg->max_instances > 0 ? (unsigned long long)cfg->max_instances
+                                                    : (unsigned long long)std::max<long long>(1ll << 20, 32 * nvg);
+    if (cap >= 0xffffffffull) return GPS_ERR_INVALID_ARG;
+    L->n_tiles = (int)n_tiles;
+    L->nvg = (int)nvg;
+    L->nblk_vg = (int)((nvg + kBlk - 1) / kBlk);
+    L->nblk_g = (M + kBlk - 1) / kBlk;
+    L->cap = cap;
+    size_t o = 0;
+    L->hdr = o;
+    o = align_up(o + 1024);
+    L->tilemax = o;
+    o = align_up(o + 4 * (size_t)n_tiles);
+    L->tile_cnt = o;
+    o = align_up(o + 4 * (size_t)n_tiles);
+    L->tile_start = o;
+    o = align_up(o + 4 * (size_t)(n_tiles + 1));
+    L->tile_cursor = o;
+    o = align_up(o + 4 * (size_t)n_tiles);
+    L->tile_loss = o;
+    o = align_up(o + 16 * (size_t)n_tiles);
+    L->pix_aux = o;
+    o = align_up(o + 4 * (size_t)npix);
+    L->rec = o;
+    o = align_up(o + 4 * kRecFloats * (size_t)nvg);
+    L->cnt = o;
+    o = align_up(o + 4 * (size_t)nvg);
+    L->off = o;
+    o = align_up(o + 4 * (size_t)nvg);
+    L->blk_sum = o;
+    o = align_up(o + 4 * (size_t)L->nblk_vg);
+    L->blk_off = o;
+    o = align_up(o + 4 * (size_t)L->nblk_vg);
+    L->keys = o;
+    o = align_up(o + 8 * (size_t)cap);
+    L->inst_vg = o;
+    o = align_up(o + 4 * (size_t)cap);
+    L->partial = o;
+    o = align_up(o + 4 * (size_t)kAdj * cap);
+    L->pose_part = o;
+    o = align_up(o + 4 * 6 * (size_t)V * (size_t)(L->nblk_g > 0 ? L->nblk_g : 1));
+    L->total = o;
+    static_assert(sizeof(WsHeader) <= 1024, "workspace header");
+    return GPS_OK;
+}
+
+static gps_status build_tables(const gps_render_cfg* cfg, const gps_gaussians* g, const gps_view* views, int V,
+                               ViewTable* vt, RParams* rp, WsLayout* L)
+{
+    if (!g || !views) return GPS_ERR_INVALID_ARG;
+    if (g->count < 0) return GPS_ERR_INVALID_ARG;
+    if (g->count > 0 && (!g->mean || !g->log_scale || !g->quat || !g->opacity_logit || !g->rgb))
+        return GPS_ERR_INVALID_ARG;
+    gps_camera cams[GPS_MAX_VIEWS];
+    if (V < 1 || V > GPS_MAX_VIEWS) return GPS_ERR_INVALID_ARG;
+    for (int v = 0; v < V; ++v) cams[v] = views[v].cam;
+    gps_status st = compute_layout(cfg, g->count, cams, V, L);
+    if (st != GPS_OK) return st;
+    std::memset(vt, 0, sizeof(*vt));
+    vt->n = V;
+    int tb = 0, pb = 0;
+    for (int v = 0; v < V; ++v) {
+        const gps_view& s = views[v];
+        if (!s.base_rgb || !s.base_depth || !s.out_rgb || !s.out_depth) return GPS_ERR_INVALID_ARG;
+        DevView& d = vt->v[v];
+        d.cam.fx = s.cam.fx;
+        d.cam.fy = s.cam.fy;
+        d.cam.cx = s.cam.cx;
+        d.cam.cy = s.cam.cy;
+        for (int k = 0; k < 9; ++k) d.cam.R[k] = s.cam.R[k];
+        for (int k = 0; k < 3; ++k) d.cam.t[k] = s.cam.t[k];
+        d.cam.W = s.cam.width;
+        d.cam.H = s.cam.height;
+        d.tiles_x = (s.cam.width + cfg->tile_w - 1) / cfg->tile_w;
+        d.tiles_y = (s.cam.height + cfg->tile_h - 1) / cfg->tile_h;
+        d.tile_base = tb;
+        d.pix_base = pb;
+        tb += d.tiles_x * d.tiles_y;
+        pb += s.cam.width * s.cam.height;
+        d.base_rgb = s.base_rgb;
+        d.base_depth = s.base_depth;
+        d.target_rgb = s.target_rgb;
+        d.target_depth = s.target_depth;
+        d.out_rgb = s.out_rgb;
+        d.out_depth = s.out_depth;
+    }
+    vt->n_tiles = tb;
+    rp->eps = cfg->eps_cull;
+    rp->lambda = cfg->lambda_depth;
+    rp->dil = cfg->dilation;
+    rp->amin = cfg->alpha_min;
+    rp->amax = cfg->alpha_max;
+    rp->Tmin = cfg->T_min;
+    rp->znear = cfg->z_near;
+    rp->mode = cfg->mode;
+    rp->M = g->count;
+    rp->V = V;
+    rp->nvg = L->nvg;
+    rp->tile_w = cfg->tile_w;
+    rp->tile_h = cfg->tile_h;
+    rp->cap = L->cap;
+    return GPS_OK;
+}
+
+__global__ void __launch_bounds__(256) k_ws_reset(char* ws)
+{
+    unsigned int* p = reinterpret_cast<unsigned int*>(ws);
+    p[threadIdx.x] = 0u;  // 256 lanes x 4 bytes = the 1 KiB header
+}
+
+gps_status launch_ws_reset(char* ws, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_ws_reset, dim3(1), dim3(256), 0, s, ws);
+    return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
+}
+
+}  // namespace gps
+
+using namespace gps;
+
+extern "C" {
+
+int32_t gps_abi_version(void) { return GPS_ABI_VERSION; }
+
+const char* gps_status_string(gps_status s)
+{
+    switch (s) {
+    case GPS_OK: return "ok";
+    case GPS_ERR_INVALID_ARG: return "invalid argument";
+    case GPS_ERR_WORKSPACE_TOO_SMALL: return "workspace too small";
+    case GPS_ERR_CAPACITY: return "tile-instance capacity exceeded (device)";
+    case GPS_ERR_HIP: return "HIP runtime error";
+    case GPS_ERR_UNSUPPORTED_DEVICE: return "unsupported device (gfx950 required)";
+    case GPS_ERR_UNSUPPORTED_CONFIG: return "unsupported tile/batch/pixels-per-thread combination";
+    default: return "unknown status";
+    }
+}
+
+void gps_render_cfg_default(gps_render_cfg* c)
+{
+    if (!c) return;
+    c->tile_w = 16;
+    c->tile_h = 16;
+    c->batch = 256;
+    c->pix_per_thread = 1;
+    c->mode = 0;
+    c->eps_cull = 0.01f;
+    c->lambda_depth = 1.0f;
+    c->dilation = 0.3f;
+    c->alpha_min = 1.0f / 255.0f;
+    c->alpha_max = 0.99f;
+    c->T_min = 1e-4f;
+    c->z_near = 0.2f;
+    c->max_instances = 0;
+}
+
+gps_status gps_workspace_size(const gps_render_cfg* cfg, int32_t n_gaussians, const gps_camera* cams,
+                              int32_t n_views, size_t* out_bytes)
+{
+    if (!out_bytes) return GPS_ERR_INVALID_ARG;
+    WsLayout L;
+    gps_status st = compute_layout(cfg, n_gaussians, cams, n_views, &L);
+    if (st != GPS_OK) return st;
+    *out_bytes = L.total;
+    return GPS_OK;
+}
+
+gps_status gps_workspace_reset(void* ws, size_t ws_bytes, void* stream)
+{
+    if (!ws || ws_bytes < 1024 || ((uintptr_t)ws & 255)) return GPS_ERR_INVALID_ARG;
+    gps_status st = check_device();
+    if (st != GPS_OK) return st;
+    return launch_ws_reset(static_cast<char*>(ws), (hipStream_t)stream);
+}
+
+gps_status gps_fuse(const gps_volume* vol, const gps_camera* cam, const float* depth, const float* rgb, void* stream)
+{
+    if (!vol || !cam || !depth || !rgb) return GPS_ERR_INVALID_ARG;
+    if (vol->nx < 2 || vol->ny < 2 || vol->nz < 2) return GPS_ERR_INVALID_ARG;
+    if ((unsigned long long)vol->nx * vol->ny * vol->nz >= (1ull << 32)) return GPS_ERR_INVALID_ARG;
+    if (!vol->tsdf || !vol->weight || !vol->rgb || !vol->rgb_weight) return GPS_ERR_INVALID_ARG;
+    if (!(vol->voxel > 0.0f) || !(vol->trunc > 0.0f) || !(vol->max_weight >= 1.0f)) return GPS_ERR_INVALID_ARG;
+    if (!cam_ok(*cam)) return GPS_ERR_INVALID_ARG;
+    gps_status st = check_device();
+    if (st != GPS_OK) return st;
+    return launch_fuse(vol, cam, depth, rgb, (hipStream_t)stream);
+}
+
+gps_status gps_raycast(const gps_volume* vol, const gps_camera* cams, int32_t n_views, float* const* out_depth,
+                       float* const* out_rgb, float z_near, float step, void* stream)
+{
+    if (!vol || !cams || !out_depth || !out_rgb) return GPS_ERR_INVALID_ARG;
+    if (n_views < 1 || n_views > GPS_MAX_VIEWS) return GPS_ERR_INVALID_ARG;
+    if (vol->nx < 2 || vol->ny < 2 || vol->nz < 2) return GPS_ERR_INVALID_ARG;
+    if ((unsigned long long)vol->nx * vol->ny * vol->nz >= (1ull << 32)) return GPS_ERR_INVALID_ARG;
+    if (!vol->tsdf || !vol->rgb || !(vol->voxel > 0.0f)) return GPS_ERR_INVALID_ARG;
+    if (!(z_near >= 0.0f) || !std::isfinite(z_near) || !(step >= 0.0f) || !std::isfinite(step))
+        return GPS_ERR_INVALID_ARG;
+    if (step != 0.0f && step < 1e-3f * vol->voxel) return GPS_ERR_INVALID_ARG;
+    for (int v = 0; v < n_views; ++v)
+        if (!cam_ok(cams[v]) || !out_depth[v] || !out_rgb[v]) return GPS_ERR_INVALID_ARG;
+    gps_status st = check_device();
+    if (st != GPS_OK) return st;
+    return launch_raycast(vol, cams, n_views, out_depth, out_rgb, z_near, step, (hipStream_t)stream);
+}
+
+gps_status gps_render_fwd(const gps_render_cfg* cfg, const gps_gaussians* g, const gps_view* views, int32_t n_views,
+                          void* ws, size_t ws_bytes, float* out_loss, void* stream)
+{
+    ViewTable vt;
+    RParams rp;
+    WsLayout L;
+    gps_status st = build_tables(cfg, g, views, n_views, &vt, &rp, &L);
+    if (st != GPS_OK) return st;
+    if (!ws || ((uintptr_t)ws & 255)) return GPS_ERR_INVALID_ARG;
+    if (ws_bytes < L.total) return GPS_ERR_WORKSPACE_TOO_SMALL;
+    st = check_device();
+    if (st != GPS_OK) return st;
+    return launch_render_fwd(cfg, rp, g, vt, L, static_cast<char*>(ws), out_loss, (hipStream_t)stream);
+}
+
+gps_status gps_render_bwd(const gps_render_cfg* cfg, const gps_gaussians* g, const gps_view* views, int32_t n_views,
+                          const float* const* dL_drgb, const float* const* dL_ddepth, const float* loss_scale,
+                          gps_gaussians* grads, float* dpose, void* ws, size_t ws_bytes, void* stream)
+{
+    ViewTable vt;
+    RParams rp;
+    WsLayout L;
+    gps_status st = build_tables(cfg, g, views, n_views, &vt, &rp, &L);
+    if (st != GPS_OK) return st;
+    if (!ws || ((uintptr_t)ws & 255)) return GPS_ERR_INVALID_ARG;
+    if (ws_bytes < L.total) return GPS_ERR_WORKSPACE_TOO_SMALL;
+    if (!grads || grads->count != g->count) return GPS_ERR_INVALID_ARG;
+    if (g->count > 0 && (!grads->mean || !grads->log_scale || !grads->quat || !grads->opacity_logit || !grads->rgb))
+        return GPS_ERR_INVALID_ARG;
+    const int explicit_up = dL_drgb != nullptr;
+    for (int v = 0; v < n_views; ++v) {
+        if (explicit_up) {
+            if (!dL_drgb[v]) return GPS_ERR_INVALID_ARG;
+            vt.v[v].g_rgb = dL_drgb[v];
+            vt.v[v].g_depth = dL_ddepth ? dL_ddepth[v] : nullptr;
+        } else if (!views[v].target_rgb) {
+            return GPS_ERR_INVALID_ARG;  // the fused-loss adjoint needs targets
+        }
+    }
+    st = check_device();
+    if (st != GPS_OK) return st;
+    return launch_render_bwd(cfg, rp, g, vt, L, static_cast<char*>(ws), explicit_up, loss_scale, grads, dpose,
+                             (hipStream_t)stream);
+}
+
+gps_status gps_adam_step(const gps_adam_group* groups, int32_t n_groups, int32_t step, int32_t* step_counter,
+                         float beta1, float beta2, float eps, void* stream)
+{
+    if (!groups || n_groups < 1 || n_groups > 8) return GPS_ERR_INVALID_ARG;
+    if (!step_counter && step < 1) return GPS_ERR_INVALID_ARG;
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f))
+        return GPS_ERR_INVALID_ARG;
+    for (int k = 0; k < n_groups; ++k) {
+        const gps_adam_group& gr = groups[k];
+        if (gr.n < 0 || !std::isfinite(gr.lr)) return GPS_ERR_INVALID_ARG;
+        if (gr.n > 0 && (!gr.param || !gr.grad || !gr.m || !gr.v)) return GPS_ERR_INVALID_ARG;
+    }
+    gps_status st = check_device();
+    if (st != GPS_OK) return st;
+    return launch_adam(groups, n_groups, step, step_counter, beta1, beta2, eps, (hipStream_t)stream);
+}
+
+gps_status gps_device_status(const void* ws, size_t ws_bytes, int32_t* out_status, void* stream)
+{
+    if (!ws || ws_bytes < 1024 || !out_status) return GPS_ERR_INVALID_ARG;
+    WsHeader h;
+    if (hipMemcpyAsync(&h, ws, sizeof(h), hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess) return GPS_ERR_HIP;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return GPS_ERR_HIP;
+    *out_status = h.status;
+    return GPS_OK;
+}
+
+gps_status gps_read_stats(const void* ws, size_t ws_bytes, gps_stats* out, void* stream)
+{
+    if (!ws || ws_bytes < 1024 || !out) return GPS_ERR_INVALID_ARG;
+    WsHeader h;
+    if (hipMemcpyAsync(&h, ws, sizeof(h), hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess) return GPS_ERR_HIP;
+    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return GPS_ERR_HIP;
+    std::memset(out, 0, sizeof(*out));
+    out->status = h.status;
+    out->n_views = h.n_views;
+    out->n_instances = (int64_t)h.n_inst;
+    out->sort_fallback = (int64_t)h.n_fallback;
+    out->capacity = (int64_t)h.cap;
+    out->n_tiles = h.n_tiles;
+    out->loss = h.loss;
+    for (int v = 0; v < GPS_MAX_VIEWS; ++v) out->view_omega[v] = h.view_stats[v][2];
+    return GPS_OK;
+}
+
+}  // extern "C"

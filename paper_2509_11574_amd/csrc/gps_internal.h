@@ -1,0 +1,253 @@
+// Internal definitions shared by the HIP translation units of libgps.
+// Device layouts, the workspace map, the binary32 decision arithmetic and
+// wavefront helpers.  Nothing here is part of the public ABI (include/gps.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gps.h"
+
+namespace gps {
+
+constexpr int kBrick = 8;             // empty-space-skipping brick edge (lattice points)
+constexpr float kBrickPositive = 1e-3f;  // a brick whose minimum exceeds this reads positive
+constexpr int kSortCap = 8192;        // longest tile list sorted in LDS (64 KiB of keys)
+constexpr int kRecFloats = 12;        // projected record: 48 bytes
+constexpr int kAdj = 10;              // screen-space adjoints per instance
+constexpr int kBlk = 256;             // threads per block of the per-Gaussian kernels
+
+// ---------------------------------------------------------------------------
+// Camera / view tables passed by value as kernel arguments.
+// ---------------------------------------------------------------------------
+struct DevCam {
+    float fx, fy, cx, cy;
+    float R[9];
+    float t[3];
+    int W, H;
+};
+
+struct DevView {
+    DevCam cam;
+    int tiles_x, tiles_y, tile_base;
+    int pix_base;  // offset of this view's pixels in the per-pixel workspace plane
+    const float* base_rgb;
+    const float* base_depth;
+    const float* target_rgb;
+    const float* target_depth;
+    float* out_rgb;
+    float* out_depth;
+    const float* g_rgb;    // explicit upstream adjoints (backward), or null
+    const float* g_depth;
+};
+
+struct ViewTable {
+    int n;
+    int n_tiles;  // over all views
+    DevView v[GPS_MAX_VIEWS];
+};
+
+// Renderer constants.
+struct RParams {
+    float eps, lambda, dil, amin, amax, Tmin, znear;
+    int mode;
+    int M;          // Gaussians
+    int V;          // views
+    int nvg;        // V * M
+    int tile_w, tile_h;
+    unsigned long long cap;  // instance capacity
+};
+
+// ---------------------------------------------------------------------------
+// Workspace map.  The header occupies the first 1 KiB.
+// ---------------------------------------------------------------------------
+struct WsHeader {
+    int status;                    // sticky gps_status of device-side failures
+    int adam_step;                 // optional Adam step counter
+    unsigned int done_ctr;         // last-block-done ticket
+    unsigned int queue_ctr;        // persistent work-queue ticket
+    unsigned long long n_inst;     // instances emitted by the last forward
+    unsigned long long n_fallback; // tiles sorted by the global-memory fallback
+    unsigned long long cap;        // instance capacity of the last forward
+    float loss;
+    int n_views;
+    int n_tiles;
+    int pad_;
+    float view_stats[GPS_MAX_VIEWS][4];  // per view: colour L1 sum, depth L1 sum, |Omega|, pad
+};
+
+struct WsLayout {
+    size_t total;
+    size_t hdr, tilemax, tile_cnt, tile_start, tile_cursor, tile_loss, pix_aux, rec, cnt, off, blk_sum, blk_off,
+        keys, inst_vg, partial, pose_part;
+    int n_tiles, nvg, nblk_vg, nblk_g;
+    unsigned long long cap;
+};
+
+struct WsPtrs {
+    WsHeader* hdr;
+    float* tilemax;
+    unsigned int* tile_cnt;
+    unsigned int* tile_start;   // n_tiles + 1
+    unsigned int* tile_cursor;
+    float4* tile_loss;          // per tile: colour L1 sum, depth L1 sum, |Omega| count, 0
+    float* pix_aux;             // per pixel: T_final (sorted) or W_G (sort-free)
+    float4* rec;                // 3 float4 per view-Gaussian
+    unsigned int* cnt;
+    unsigned int* off;
+    unsigned int* blk_sum;
+    unsigned int* blk_off;
+    unsigned long long* keys;   // (depth bits << 32) | slot, grouped by tile
+    unsigned int* inst_vg;      // slot -> view * M + Gaussian
+    float* partial;             // [cap][kAdj]
+    float* pose_part;           // [nblk_g][V][6]
+};
+
+inline WsPtrs ws_ptrs(char* ws, const WsLayout& L)
+{
+    WsPtrs p;
+    p.hdr = reinterpret_cast<WsHeader*>(ws + L.hdr);
+    p.tilemax = reinterpret_cast<float*>(ws + L.tilemax);
+    p.tile_cnt = reinterpret_cast<unsigned int*>(ws + L.tile_cnt);
+    p.tile_start = reinterpret_cast<unsigned int*>(ws + L.tile_start);
+    p.tile_cursor = reinterpret_cast<unsigned int*>(ws + L.tile_cursor);
+    p.tile_loss = reinterpret_cast<float4*>(ws + L.tile_loss);
+    p.pix_aux = reinterpret_cast<float*>(ws + L.pix_aux);
+    p.rec = reinterpret_cast<float4*>(ws + L.rec);
+    p.cnt = reinterpret_cast<unsigned int*>(ws + L.cnt);
+    p.off = reinterpret_cast<unsigned int*>(ws + L.off);
+    p.blk_sum = reinterpret_cast<unsigned int*>(ws + L.blk_sum);
+    p.blk_off = reinterpret_cast<unsigned int*>(ws + L.blk_off);
+    p.keys = reinterpret_cast<unsigned long long*>(ws + L.keys);
+    p.inst_vg = reinterpret_cast<unsigned int*>(ws + L.inst_vg);
+    p.partial = reinterpret_cast<float*>(ws + L.partial);
+    p.pose_part = reinterpret_cast<float*>(ws + L.pose_part);
+    return p;
+}
+
+// ---------------------------------------------------------------------------
+// binary32 decision arithmetic.  Each statement is one IEEE operation; the
+// library is compiled with -ffp-contract=on (only a*b+c written as ONE
+// expression may fuse) and these helpers additionally forbid contraction.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float d32_row(const float* R, const float* t, int r, float p0, float p1, float p2)
+{
+#pragma clang fp contract(off)
+    float a = R[3 * r + 0] * p0;
+    float b = R[3 * r + 1] * p1;
+    float s = a + b;
+    float c = R[3 * r + 2] * p2;
+    s = s + c;
+    s = s + t[r];
+    return s;
+}
+
+__device__ __forceinline__ float d32_lattice(float origin, float voxel, int idx)
+{
+#pragma clang fp contract(off)
+    float f = (float)idx;
+    float v = voxel * f;
+    return origin + v;
+}
+
+__device__ __forceinline__ float d32_lerp(float a, float b, float f)
+{
+#pragma clang fp contract(off)
+    float d = b - a;
+    float e = f * d;
+    return a + e;
+}
+
+// ---------------------------------------------------------------------------
+// Opacity of a projected Gaussian at a pixel, Eq. 3:
+//   alpha = sigma * exp(-0.5 * (a dx^2 + 2 b dx dy + c dy^2)).
+// Written with explicit fused operations so that the forward and the backward
+// kernels evaluate bit-identical values (the backward recomputes the
+// transmittance and must stop at the same Gaussian as the forward).
+// ---------------------------------------------------------------------------
+struct AlphaEval {
+    float raw;    // sigma * e
+    float e;      // exp(power)
+    float dx, dy;
+};
+
+__device__ __forceinline__ AlphaEval eval_alpha(float px, float py, float mx, float my, float ca, float cb,
+                                                float cc, float sigma)
+{
+#pragma clang fp contract(off)
+    AlphaEval r;
+    r.dx = px - mx;
+    r.dy = py - my;
+    float q = __builtin_fmaf(ca * r.dx, r.dx, cc * r.dy * r.dy);
+    q = __builtin_fmaf(2.0f * cb * r.dx, r.dy, q);
+    float power = -0.5f * q;
+    r.e = __expf(power);
+    r.raw = sigma * r.e;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// Wavefront (64 lanes) helpers.
+// ---------------------------------------------------------------------------
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf, bool BOUND_ZERO = true>
+__device__ __forceinline__ float dpp_f(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROW_MASK, BANK_MASK, BOUND_ZERO));
+}
+
+// Sum over the 64 lanes; the total is valid in lane 63 only.
+__device__ __forceinline__ float wave_sum_to_lane63(float v)
+{
+    v += dpp_f<0x111>(v);  // row_shr:1
+    v += dpp_f<0x112>(v);  // row_shr:2
+    v += dpp_f<0x114>(v);  // row_shr:4
+    v += dpp_f<0x118>(v);  // row_shr:8   -> lane 15 of each row holds its row sum
+    v += dpp_f<0x142, 0xa, 0xf, false>(v);  // row_bcast:15 into rows 1 and 3
+    v += dpp_f<0x143, 0xc, 0xf, false>(v);  // row_bcast:31 into rows 2 and 3
+    return v;
+}
+
+// Sum over the 64 lanes, result uniform across the wave.
+__device__ __forceinline__ float wave_sum(float v)
+{
+    v = wave_sum_to_lane63(v);
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
+__device__ __forceinline__ float wave_max(float v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ bool wave_any(bool p)
+{
+    return __builtin_amdgcn_ballot_w64(p) != 0ull;
+}
+
+__device__ __forceinline__ int find_view(const ViewTable& vt, int tile)
+{
+    int v = 0;
+#pragma unroll 1
+    for (int k = 1; k < vt.n; ++k)
+        if (tile >= vt.v[k].tile_base) v = k;
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launch entry points (defined in the .hip files).
+// ---------------------------------------------------------------------------
+gps_status launch_fuse(const gps_volume* vol, const gps_camera* cam, const float* depth, const float* rgb,
+                       hipStream_t s);
+gps_status launch_raycast(const gps_volume* vol, const gps_camera* cams, int n_views, float* const* out_depth,
+                          float* const* out_rgb, float z_near, float step, hipStream_t s);
+gps_status launch_render_fwd(const gps_render_cfg* cfg, const RParams& rp, const gps_gaussians* g,
+                             const ViewTable& vt, const WsLayout& L, char* ws, float* out_loss, hipStream_t s);
+gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const gps_gaussians* g,
+                             const ViewTable& vt, const WsLayout& L, char* ws, int explicit_upstream,
+                             const float* loss_scale, gps_gaussians* grads, float* dpose, hipStream_t s);
+gps_status launch_adam(const gps_adam_group* groups, int n_groups, int step, int* step_counter, float b1, float b2,
+                       float eps, hipStream_t s);
+gps_status launch_ws_reset(char* ws, hipStream_t s);
+
+}  // namespace gps

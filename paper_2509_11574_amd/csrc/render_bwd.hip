@@ -1,0 +1,504 @@
+// Backward render (analytic gradient of the forward in render_fwd.hip).
+//
+//   k_composite_bwd<TW,TH,B,PPT>  per tile: recompute the front-to-back
+//       traversal of every pixel (transmittance T_i and prefix colour/depth
+//       P_i), form dL/d{centre, conic, sigma, colour, depth} of each
+//       contributor, reduce them over the tile's pixels (DPP within each
+//       wavefront, LDS across wavefronts, fixed order) and write ONE 10-float
+//       partial per (tile, Gaussian) instance into that instance's slot.
+//   k_gauss_bwd   per Gaussian: sum its instance partials (a contiguous slot
+//       range per view, summed in order), apply the EWA chain rule to the
+//       parameters and form the per-Gaussian pose terms, reduced per block.
+//   k_pose_reduce per view: sum the block pose partials in order.
+// No floating-point atomics: results are bitwise reproducible.
+#include "render_common.h"
+
+namespace gps {
+
+__device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.0f) - (x < 0.0f)); }
+
+template <int TW, int TH, int B, int PPT>
+__global__ void __launch_bounds__(TW * TH / PPT)
+    k_composite_bwd(ViewTable vt, RParams rp, WsPtrs w, int explicit_up, const float* loss_scale)
+{
+    constexpr int NT = TW * TH / PPT;
+    constexpr int NW = NT / 64;
+    constexpr int ROWS = TH / PPT;
+    __shared__ float4 srec[3 * B];
+    __shared__ unsigned int sslot[B];
+    __shared__ float slab[B * NW * kAdj];
+    if (w.hdr->n_inst > rp.cap) return;
+    const int tile = blockIdx.x;
+    const int v = find_view(vt, tile);
+    const DevView& V = vt.v[v];
+    const int lt = tile - V.tile_base;
+    const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
+    const int Wd = V.cam.W, Ht = V.cam.H;
+    const size_t HW = (size_t)Wd * Ht;
+    const int px = tx * TW + (int)(threadIdx.x % TW);
+    const int py0 = ty * TH + (int)(threadIdx.x / TW);
+    const float fpx = (float)px;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+
+    float sc = 1.0f;
+    if (!explicit_up && loss_scale) sc = *loss_scale;
+    const float invV = 1.0f / (float)rp.V;
+    const float om = w.hdr->view_stats[v][2];
+
+    float thr[PPT], T[PPT], G0[PPT], G1[PPT], G2[PPT], GD[PPT], Cs0[PPT], Cs1[PPT], Cs2[PPT], Ds[PPT];
+    float P0[PPT], P1[PPT], P2[PPT], PD[PPT], Wg[PPT];
+    bool done[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int py = py0 + k * ROWS;
+        const bool inb = px < Wd && py < Ht;
+        const size_t p = inb ? (size_t)py * Wd + px : 0;
+        const float dt = inb ? V.base_depth[p] : 0.0f;
+        const bool dvalid = dt > 0.0f;
+        thr[k] = (dvalid ? dt : INFINITY) + rp.eps;
+        T[k] = 1.0f;
+        P0[k] = P1[k] = P2[k] = PD[k] = 0.0f;
+        Cs0[k] = Cs1[k] = Cs2[k] = Ds[k] = 0.0f;
+        G0[k] = G1[k] = G2[k] = GD[k] = 0.0f;
+        Wg[k] = 0.0f;
+        if (inb) {
+            Cs0[k] = V.out_rgb[p];
+            Cs1[k] = V.out_rgb[HW + p];
+            Cs2[k] = V.out_rgb[2 * HW + p];
+            Ds[k] = V.out_depth[p];
+            if (rp.mode == 1) Wg[k] = w.pix_aux[(size_t)V.pix_base + p];
+            if (explicit_up) {
+                G0[k] = V.g_rgb[p];
+                G1[k] = V.g_rgb[HW + p];
+                G2[k] = V.g_rgb[2 * HW + p];
+                GD[k] = (V.g_depth && dvalid) ? V.g_depth[p] : 0.0f;
+            } else {
+                const float cn = sc * invV / (3.0f * (float)HW);
+                G0[k] = cn * sgnf(Cs0[k] - V.target_rgb[p]);
+                G1[k] = cn * sgnf(Cs1[k] - V.target_rgb[HW + p]);
+                G2[k] = cn * sgnf(Cs2[k] - V.target_rgb[2 * HW + p]);
+                if (V.target_depth && dvalid && om > 0.0f) {
+                    const float dobs = V.target_depth[p];
+                    if (dobs > 0.0f) GD[k] = sc * invV * rp.lambda / om * sgnf(Ds[k] - dobs);
+                }
+            }
+        }
+        done[k] = !inb;
+    }
+
+    const unsigned int s = w.tile_start[tile], e = w.tile_start[tile + 1];
+    unsigned int b = s;
+    for (; b < e; b += B) {
+        int alive = 0;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) alive |= !done[k];
+        if (__syncthreads_count(alive) == 0) break;
+        for (int j = threadIdx.x; j < B && b + j < e; j += NT) {
+            const unsigned int slot = (unsigned int)w.keys[b + j];
+            unsigned int vg = slot < rp.cap ? w.inst_vg[slot] : 0u;
+            if (vg >= (unsigned int)rp.nvg) vg = 0u;  // guard: never read outside the records
+            const float4* r = w.rec + 3 * (size_t)vg;
+            srec[3 * j + 0] = r[0];
+            srec[3 * j + 1] = r[1];
+            srec[3 * j + 2] = r[2];
+            sslot[j] = slot;
+        }
+        __syncthreads();
+        const int n = (int)min((unsigned int)B, e - b);
+        for (int j = 0; j < n; ++j) {
+            const float4 r0 = srec[3 * j], r1 = srec[3 * j + 1], r2 = srec[3 * j + 2];
+            const float c0 = r1.w, c1 = r2.x, c2 = r2.y, zi = r1.z;
+            float g[kAdj];
+#pragma unroll
+            for (int q = 0; q < kAdj; ++q) g[q] = 0.0f;
+            bool act = false;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                if (done[k]) continue;
+                if (!(zi < thr[k])) {
+                    done[k] = true;
+                    continue;
+                }
+                const AlphaEval ae = eval_alpha(fpx, (float)(py0 + k * ROWS), r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
+                float a, dal;
+                bool alpha_path;
+                if (rp.mode == 0) {
+                    a = fminf(rp.amax, ae.raw);
+                    if (a < rp.amin) continue;
+                    const float Tn = T[k] * (1.0f - a);
+                    if (Tn < rp.Tmin) {
+                        done[k] = true;
+                        continue;
+                    }
+                    const float wgt = a * T[k];
+                    P0[k] = __builtin_fmaf(wgt, c0, P0[k]);
+                    P1[k] = __builtin_fmaf(wgt, c1, P1[k]);
+                    P2[k] = __builtin_fmaf(wgt, c2, P2[k]);
+                    PD[k] = __builtin_fmaf(wgt, zi, PD[k]);
+                    g[6] += wgt * G0[k];
+                    g[7] += wgt * G1[k];
+                    g[8] += wgt * G2[k];
+                    g[9] += wgt * GD[k];
+                    const float direct = G0[k] * c0 + G1[k] * c1 + G2[k] * c2 + GD[k] * zi;
+                    const float rest = G0[k] * (Cs0[k] - P0[k]) + G1[k] * (Cs1[k] - P1[k]) +
+                                       G2[k] * (Cs2[k] - P2[k]) + GD[k] * (Ds[k] - PD[k]);
+                    dal = T[k] * direct - rest / (1.0f - a);
+                    alpha_path = ae.raw <= rp.amax;
+                    T[k] = Tn;
+                } else {
+                    a = ae.raw;
+                    if (a < rp.amin) continue;
+                    const float inv = 1.0f / (1.0f + Wg[k]);
+                    const float ai = a * inv;
+                    g[6] += ai * G0[k];
+                    g[7] += ai * G1[k];
+                    g[8] += ai * G2[k];
+                    g[9] += ai * GD[k];
+                    dal = inv * (G0[k] * (c0 - Cs0[k]) + G1[k] * (c1 - Cs1[k]) + G2[k] * (c2 - Cs2[k]) +
+                                 GD[k] * (zi - Ds[k]));
+                    alpha_path = true;
+                }
+                act = true;
+                if (alpha_path) {
+                    const float dp = dal * a;  // d alpha / d power = alpha
+                    g[5] += dal * ae.e;        // d alpha / d sigma = exp(power)
+                    g[0] += dp * (r0.z * ae.dx + r0.w * ae.dy);
+                    g[1] += dp * (r0.w * ae.dx + r1.x * ae.dy);
+                    g[2] += -0.5f * dp * ae.dx * ae.dx;
+                    g[3] += -dp * ae.dx * ae.dy;
+                    g[4] += -0.5f * dp * ae.dy * ae.dy;
+                }
+            }
+            float* dst = slab + (j * NW + wid) * kAdj;
+            if (wave_any(act)) {
+#pragma unroll
+                for (int q = 0; q < kAdj; ++q) {
+                    const float t = wave_sum_to_lane63(g[q]);
+                    if (lane == 63) dst[q] = t;
+                }
+            } else if (lane == 0) {
+#pragma unroll
+                for (int q = 0; q < kAdj; ++q) dst[q] = 0.0f;
+            }
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < n; t += NT) {
+            float acc[kAdj];
+#pragma unroll
+            for (int q = 0; q < kAdj; ++q) acc[q] = 0.0f;
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww)
+#pragma unroll
+                for (int q = 0; q < kAdj; ++q) acc[q] += slab[(t * NW + ww) * kAdj + q];
+            if (sslot[t] < rp.cap) {
+                float* out = w.partial + (size_t)sslot[t] * kAdj;
+#pragma unroll
+                for (int q = 0; q < kAdj; ++q) out[q] = acc[q];
+            }
+        }
+    }
+    // Instances after the point where every pixel of the tile had stopped
+    // contribute nothing; their slots still need zeros.
+    for (unsigned int pos = b + threadIdx.x; pos < e; pos += NT) {
+        const unsigned int slot = (unsigned int)w.keys[pos];
+        if (slot >= rp.cap) continue;
+        float* out = w.partial + (size_t)slot * kAdj;
+#pragma unroll
+        for (int q = 0; q < kAdj; ++q) out[q] = 0.0f;
+    }
+}
+
+// ------------------------------------------------------------- gauss bwd
+// EWA chain rule of one Gaussian in one view.  A[10] = dL/d(mx, my, a, b, c,
+// sigma, r, g, b, d) where (a, b, c) is the conic and b multiplies 2 dx dy.
+__global__ void __launch_bounds__(kBlk) k_gauss_bwd(ViewTable vt, RParams rp, GParams gp, GGrads gg, WsPtrs w)
+{
+    const int M = rp.M;
+    const int g = blockIdx.x * kBlk + threadIdx.x;
+    const bool live = g < M;
+    float gmean[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.0f, grgb[3] = {0, 0, 0};
+    __shared__ float pred[kBlk / 64][6];
+
+    float m0 = 0, m1 = 0, m2 = 0, qw = 1, qx = 0, qy = 0, qz = 0, qn = 1, s[3] = {1, 1, 1}, sig = 0.5f;
+    float Rq[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    if (live) {
+        m0 = gp.mean[g];
+        m1 = gp.mean[M + g];
+        m2 = gp.mean[2 * M + g];
+        qw = gp.quat[g];
+        qx = gp.quat[M + g];
+        qy = gp.quat[2 * M + g];
+        qz = gp.quat[3 * M + g];
+        qn = sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+        const float qi = 1.0f / qn;
+        qw *= qi;
+        qx *= qi;
+        qy *= qi;
+        qz *= qi;
+        Rq[0] = 1.f - 2.f * (qy * qy + qz * qz);
+        Rq[1] = 2.f * (qx * qy - qw * qz);
+        Rq[2] = 2.f * (qx * qz + qw * qy);
+        Rq[3] = 2.f * (qx * qy + qw * qz);
+        Rq[4] = 1.f - 2.f * (qx * qx + qz * qz);
+        Rq[5] = 2.f * (qy * qz - qw * qx);
+        Rq[6] = 2.f * (qx * qz - qw * qy);
+        Rq[7] = 2.f * (qy * qz + qw * qx);
+        Rq[8] = 1.f - 2.f * (qx * qx + qy * qy);
+        s[0] = __expf(gp.log_scale[g]);
+        s[1] = __expf(gp.log_scale[M + g]);
+        s[2] = __expf(gp.log_scale[2 * M + g]);
+        sig = 1.0f / (1.0f + __expf(-gp.opacity_logit[g]));
+    }
+    // Mm = Rq diag(s), Sigma_3D = Mm Mm^T
+    float Mm[9], S3[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Mm[3 * r + c] = Rq[3 * r + c] * s[c];
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) S3[3 * r + c] = Mm[3 * r] * Mm[3 * c] + Mm[3 * r + 1] * Mm[3 * c + 1] + Mm[3 * r + 2] * Mm[3 * c + 2];
+
+    for (int v = 0; v < vt.n; ++v) {
+        float pose[6] = {0, 0, 0, 0, 0, 0};
+        const size_t vg = (size_t)v * M + g;
+        unsigned int cnt = live ? w.cnt[vg] : 0u;
+        const unsigned int o = cnt ? w.off[vg] : 0u;
+        if ((unsigned long long)o + cnt > w.hdr->n_inst) cnt = 0u;  // guard: stay inside the emitted slots
+        if (cnt > 0) {
+            const float* part = w.partial + (size_t)o * kAdj;
+            float A[kAdj];
+#pragma unroll
+            for (int q = 0; q < kAdj; ++q) A[q] = 0.0f;
+            for (unsigned int k = 0; k < cnt; ++k)
+#pragma unroll
+                for (int q = 0; q < kAdj; ++q) A[q] += part[(size_t)k * kAdj + q];
+            const DevCam& c = vt.v[v].cam;
+            const float* R = c.R;
+            const float x = R[0] * m0 + R[1] * m1 + R[2] * m2 + c.t[0];
+            const float y = R[3] * m0 + R[4] * m1 + R[5] * m2 + c.t[1];
+            const float z = d32_row(c.R, c.t, 2, m0, m1, m2);
+            const float iz = 1.0f / z, iz2 = iz * iz;
+            const float J00 = c.fx * iz, J02 = -c.fx * x * iz2, J11 = c.fy * iz, J12 = -c.fy * y * iz2;
+            float Wm[6];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                Wm[k] = J00 * R[k] + J02 * R[6 + k];
+                Wm[3 + k] = J11 * R[3 + k] + J12 * R[6 + k];
+            }
+            // conic from Sigma_2D = W S3 W^T + dil
+            float WS[6];
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    WS[3 * r + k] = Wm[3 * r] * S3[k] + Wm[3 * r + 1] * S3[3 + k] + Wm[3 * r + 2] * S3[6 + k];
+            const float SA = WS[0] * Wm[0] + WS[1] * Wm[1] + WS[2] * Wm[2] + rp.dil;
+            const float SB = WS[0] * Wm[3] + WS[1] * Wm[4] + WS[2] * Wm[5];
+            const float SC = WS[3] * Wm[3] + WS[4] * Wm[4] + WS[5] * Wm[5] + rp.dil;
+            const float idet = 1.0f / (SA * SC - SB * SB);
+            const float qa = SC * idet, qb = -SB * idet, qc = SA * idet;
+
+            grgb[0] += A[6];
+            grgb[1] += A[7];
+            grgb[2] += A[8];
+            gop += A[5] * sig * (1.0f - sig);
+            // G2 = -Q Gq Q with Gq = [[A2, A3/2], [A3/2, A4]]
+            const float h = 0.5f * A[3];
+            const float T00 = qa * A[2] + qb * h, T01 = qa * h + qb * A[4];
+            const float T10 = qb * A[2] + qc * h, T11 = qb * h + qc * A[4];
+            const float G00 = -(T00 * qa + T01 * qb), G01 = -(T00 * qb + T01 * qc), G11 = -(T10 * qb + T11 * qc);
+            // G3 = W^T G2 W ; GW = 2 G2 W S3
+            float G2W[6];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                G2W[k] = G00 * Wm[k] + G01 * Wm[3 + k];
+                G2W[3 + k] = G01 * Wm[k] + G11 * Wm[3 + k];
+            }
+            float G3[9];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) G3[3 * r + k] = Wm[r] * G2W[k] + Wm[3 + r] * G2W[3 + k];
+            float GW[6];
+#pragma unroll
+            for (int r = 0; r < 2; ++r)
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    GW[3 * r + k] = 2.0f * (G2W[3 * r] * S3[k] + G2W[3 * r + 1] * S3[3 + k] + G2W[3 * r + 2] * S3[6 + k]);
+            // G_J = GW R^T  (only J00, J02, J11, J12 depend on p_c)
+            const float GJ00 = GW[0] * R[0] + GW[1] * R[1] + GW[2] * R[2];
+            const float GJ02 = GW[0] * R[6] + GW[1] * R[7] + GW[2] * R[8];
+            const float GJ11 = GW[3] * R[3] + GW[4] * R[4] + GW[5] * R[5];
+            const float GJ12 = GW[3] * R[6] + GW[4] * R[7] + GW[5] * R[8];
+            const float iz3 = iz2 * iz;
+            float gpx = GJ02 * (-c.fx * iz2) + A[0] * c.fx * iz;
+            float gpy = GJ12 * (-c.fy * iz2) + A[1] * c.fy * iz;
+            float gpz = GJ00 * (-c.fx * iz2) + GJ02 * (2.0f * c.fx * x * iz3) + GJ11 * (-c.fy * iz2) +
+                        GJ12 * (2.0f * c.fy * y * iz3) - A[0] * c.fx * x * iz2 - A[1] * c.fy * y * iz2 + A[9];
+            gmean[0] += R[0] * gpx + R[3] * gpy + R[6] * gpz;
+            gmean[1] += R[1] * gpx + R[4] * gpy + R[7] * gpz;
+            gmean[2] += R[2] * gpx + R[5] * gpy + R[8] * gpz;
+            // Sigma_3D = Mm Mm^T: G_Mm = 2 G3 Mm
+            float GM[9];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    GM[3 * r + k] = 2.0f * (G3[3 * r] * Mm[k] + G3[3 * r + 1] * Mm[3 + k] + G3[3 * r + 2] * Mm[6 + k]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                gls[k] += (Rq[k] * GM[k] + Rq[3 + k] * GM[3 + k] + Rq[6 + k] * GM[6 + k]) * s[k];
+            float GR[9];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) GR[3 * r + k] = GM[3 * r + k] * s[k];
+            float dq[4];
+            dq[0] = 2.f * (-qz * GR[1] + qy * GR[2] + qz * GR[3] - qx * GR[5] - qy * GR[6] + qx * GR[7]);
+            dq[1] = 2.f * (qy * GR[1] + qz * GR[2] + qy * GR[3] - 2.f * qx * GR[4] - qw * GR[5] + qz * GR[6] +
+                           qw * GR[7] - 2.f * qx * GR[8]);
+            dq[2] = 2.f * (-2.f * qy * GR[0] + qx * GR[1] + qw * GR[2] + qx * GR[3] + qz * GR[5] - qw * GR[6] +
+                           qz * GR[7] - 2.f * qy * GR[8]);
+            dq[3] = 2.f * (-2.f * qz * GR[0] - qw * GR[1] + qx * GR[2] + qw * GR[3] - 2.f * qz * GR[4] +
+                           qy * GR[5] + qx * GR[6] + qy * GR[7]);
+            const float dot = qw * dq[0] + qx * dq[1] + qy * dq[2] + qz * dq[3];
+            const float iqn = 1.0f / qn;
+            gq[0] += (dq[0] - qw * dot) * iqn;
+            gq[1] += (dq[1] - qx * dot) * iqn;
+            gq[2] += (dq[2] - qy * dot) * iqn;
+            gq[3] += (dq[3] - qz * dot) * iqn;
+            // pose: rho gets g_p; phi gets p_c x g_p + 2 vee(Gc Sc - Sc Gc)
+            //   Sc = R S3 R^T, Gc = J^T G2 J (J has zeros at (0,1), (1,0))
+            float RS[9], Sc[9];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) RS[3 * r + k] = R[3 * r] * S3[k] + R[3 * r + 1] * S3[3 + k] + R[3 * r + 2] * S3[6 + k];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) Sc[3 * r + k] = RS[3 * r] * R[3 * k] + RS[3 * r + 1] * R[3 * k + 1] + RS[3 * r + 2] * R[3 * k + 2];
+            const float J[6] = {J00, 0.0f, J02, 0.0f, J11, J12};
+            float Gc[9];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    Gc[3 * r + k] = J[r] * (G00 * J[k] + G01 * J[3 + k]) + J[3 + r] * (G01 * J[k] + G11 * J[3 + k]);
+            float K[9];
+#pragma unroll
+            for (int r = 0; r < 3; ++r)
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+                    K[3 * r + k] = (Gc[3 * r] * Sc[k] + Gc[3 * r + 1] * Sc[3 + k] + Gc[3 * r + 2] * Sc[6 + k]) -
+                                   (Sc[3 * r] * Gc[k] + Sc[3 * r + 1] * Gc[3 + k] + Sc[3 * r + 2] * Gc[6 + k]);
+            pose[0] = gpx;
+            pose[1] = gpy;
+            pose[2] = gpz;
+            pose[3] = y * gpz - z * gpy + 2.0f * K[7];
+            pose[4] = z * gpx - x * gpz + 2.0f * K[2];
+            pose[5] = x * gpy - y * gpx + 2.0f * K[3];
+        }
+        // block partial of the pose gradient of view v (fixed order)
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const float t = wave_sum(pose[q]);
+            if ((threadIdx.x & 63) == 0) pred[threadIdx.x >> 6][q] = t;
+        }
+        __syncthreads();
+        if (threadIdx.x < 6) {
+            float t = 0.0f;
+#pragma unroll
+            for (int ww = 0; ww < kBlk / 64; ++ww) t += pred[ww][threadIdx.x];
+            w.pose_part[((size_t)blockIdx.x * rp.V + v) * 6 + threadIdx.x] = t;
+        }
+        __syncthreads();
+    }
+    if (live) {
+        gg.mean[g] = gmean[0];
+        gg.mean[M + g] = gmean[1];
+        gg.mean[2 * M + g] = gmean[2];
+        gg.log_scale[g] = gls[0];
+        gg.log_scale[M + g] = gls[1];
+        gg.log_scale[2 * M + g] = gls[2];
+        gg.quat[g] = gq[0];
+        gg.quat[M + g] = gq[1];
+        gg.quat[2 * M + g] = gq[2];
+        gg.quat[3 * M + g] = gq[3];
+        gg.opacity_logit[g] = gop;
+        gg.rgb[g] = grgb[0];
+        gg.rgb[M + g] = grgb[1];
+        gg.rgb[2 * M + g] = grgb[2];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_pose_reduce(RParams rp, WsPtrs w, int nblk, float* dpose)
+{
+    const int v = blockIdx.x;
+    for (int q = 0; q < 6; ++q) {
+        float t = 0.0f;
+        for (int b = threadIdx.x; b < nblk; b += 256) t += w.pose_part[((size_t)b * rp.V + v) * 6 + q];
+        t = block_sum<256>(t);
+        if (threadIdx.x == 0) dpose[v * 6 + q] = t;
+    }
+}
+
+// ----------------------------------------------------------------- launch
+template <int TW, int TH, int B, int PPT>
+static void launch_cbwd(const ViewTable& vt, const RParams& rp, const WsPtrs& w, int n_tiles, int explicit_up,
+                        const float* loss_scale, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_composite_bwd<TW, TH, B, PPT>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, vt, rp, w,
+                       explicit_up, loss_scale);
+}
+
+#define GPS_TILE_CONFIGS_B(X) \
+    X(8, 8, 128, 1)           \
+    X(8, 8, 256, 1)           \
+    X(8, 8, 512, 1)           \
+    X(16, 16, 128, 1)         \
+    X(16, 16, 256, 1)         \
+    X(16, 16, 128, 2)         \
+    X(16, 16, 256, 2)         \
+    X(16, 16, 512, 2)         \
+    X(16, 16, 128, 4)         \
+    X(16, 16, 256, 4)         \
+    X(16, 16, 512, 4)         \
+    X(16, 32, 128, 1)         \
+    X(16, 32, 128, 2)         \
+    X(16, 32, 256, 2)         \
+    X(16, 32, 128, 4)         \
+    X(16, 32, 256, 4)         \
+    X(16, 32, 512, 4)
+
+static bool dispatch_cbwd(const gps_render_cfg* cfg, const ViewTable& vt, const RParams& rp, const WsPtrs& w,
+                          int n_tiles, int explicit_up, const float* loss_scale, hipStream_t s)
+{
+#define X(tw, th, b, ppt)                                                                              \
+    if (cfg->tile_w == tw && cfg->tile_h == th && cfg->batch == b && cfg->pix_per_thread == ppt) {   \
+        launch_cbwd<tw, th, b, ppt>(vt, rp, w, n_tiles, explicit_up, loss_scale, s);                 \
+        return true;                                                                                 \
+    }
+    GPS_TILE_CONFIGS_B(X)
+#undef X
+    return false;
+}
+
+gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const gps_gaussians* g,
+                             const ViewTable& vt, const WsLayout& L, char* ws, int explicit_upstream,
+                             const float* loss_scale, gps_gaussians* grads, float* dpose, hipStream_t s)
+{
+    WsPtrs w = ws_ptrs(ws, L);
+    GParams gp{g->mean, g->log_scale, g->quat, g->opacity_logit, g->rgb};
+    GGrads gg{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->rgb};
+    if (!dispatch_cbwd(cfg, vt, rp, w, L.n_tiles, explicit_upstream, loss_scale, s)) return GPS_ERR_UNSUPPORTED_CONFIG;
+    if (L.nblk_g > 0) {
+        hipLaunchKernelGGL(k_gauss_bwd, dim3(L.nblk_g), dim3(kBlk), 0, s, vt, rp, gp, gg, w);
+        if (dpose) hipLaunchKernelGGL(k_pose_reduce, dim3(vt.n), dim3(256), 0, s, rp, w, L.nblk_g, dpose);
+    }
+    return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
+}
+
+}  // namespace gps

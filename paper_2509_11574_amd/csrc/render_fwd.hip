@@ -1,0 +1,581 @@
+// Forward render: EWA projection, tile binning, per-tile depth sort and
+// compositing over the SDF base image, with the loss fused into the
+// compositing epilogue (Sec. 3.1 second pass, Eq. 1-4, Eq. 7).
+//
+// Kernel sequence (one launch each, all grids sized from host-known shapes,
+// so the sequence is graph-capturable):
+//   k_prep       per screen tile: max of the SDF depth (invalid = +inf)
+//   k_project    per (view, Gaussian): projected record, tile rectangle,
+//                instance count after the exact tile depth cull, tile counts
+//   k_scan       one block: offsets of the per-block counts and of the tiles
+//   k_emit       per (view, Gaussian): instance slots and (depth, slot) keys
+//                scattered into their tile's range
+//   k_tile_sort  per tile: bitonic sort of its keys in LDS
+//   k_composite_fwd<TW,TH,B,PPT>  per tile: LDS-staged batches of B records,
+//                front-to-back compositing, loss partial per tile
+//   k_loss_reduce  one block: per-view and total loss
+#include "render_common.h"
+
+namespace gps {
+
+// ------------------------------------------------------------------- prep
+__global__ void __launch_bounds__(256) k_prep(ViewTable vt, RParams rp, WsPtrs w)
+{
+    const int tile = blockIdx.x;
+    if (tile == 0 && threadIdx.x == 0) {
+        w.hdr->n_inst = 0ull;
+        w.hdr->n_fallback = 0ull;
+        w.hdr->queue_ctr = 0u;
+        w.hdr->done_ctr = 0u;
+        w.hdr->n_views = rp.V;
+    }
+    const int v = find_view(vt, tile);
+    const DevView& V = vt.v[v];
+    const int lt = tile - V.tile_base;
+    const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
+    float m = -INFINITY;
+    for (int k = threadIdx.x; k < rp.tile_w * rp.tile_h; k += 256) {
+        int x = tx * rp.tile_w + k % rp.tile_w, y = ty * rp.tile_h + k / rp.tile_w;
+        if (x < V.cam.W && y < V.cam.H) {
+            float d = V.base_depth[(size_t)y * V.cam.W + x];
+            m = fmaxf(m, d > 0.0f ? d : INFINITY);
+        }
+    }
+    m = wave_max(m);
+    __shared__ float red[4];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        w.tilemax[tile] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        w.tile_cnt[tile] = 0u;
+    }
+}
+
+// ---------------------------------------------------------------- project
+// EWA projection of one Gaussian into one view (Eq. 3; 3DGS convention):
+//   p_c = R mu + t, Sigma_3D = R_q diag(s^2) R_q^T, J the pinhole Jacobian,
+//   Sigma_2D = (J R) Sigma_3D (J R)^T + dilation I, conic = Sigma_2D^-1.
+// The support ellipse where sigma exp(-q/2) >= alpha_min has the bounding box
+// m +- sqrt(kappa Sigma_xx), sqrt(kappa Sigma_yy), kappa = 2 ln(sigma/alpha_min);
+// it is padded by one pixel and turned into a tile rectangle.
+struct ProjOut {
+    float4 r0, r1, r2;
+    bool valid;
+};
+
+__device__ __forceinline__ ProjOut project_one(const DevView& V, const RParams& rp, const GParams& gp, int g)
+{
+    ProjOut o;
+    o.valid = false;
+    o.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    o.r1 = make_float4(0.f, 0.f, 0.f, 0.f);
+    o.r2 = make_float4(0.f, 0.f, pack_rect(0, 0), pack_rect(0, 0));
+    const int M = rp.M;
+    const DevCam& c = V.cam;
+    const float m0 = gp.mean[g], m1 = gp.mean[M + g], m2 = gp.mean[2 * M + g];
+    const float z = d32_row(c.R, c.t, 2, m0, m1, m2);  // depth key (binary32 decision)
+    if (!(z >= rp.znear)) return o;
+    const float x = c.R[0] * m0 + c.R[1] * m1 + c.R[2] * m2 + c.t[0];
+    const float y = c.R[3] * m0 + c.R[4] * m1 + c.R[5] * m2 + c.t[1];
+    float qw = gp.quat[g], qx = gp.quat[M + g], qy = gp.quat[2 * M + g], qz = gp.quat[3 * M + g];
+    const float qinv = 1.0f / sqrtf(qw * qw + qx * qx + qy * qy + qz * qz);
+    qw *= qinv;
+    qx *= qinv;
+    qy *= qinv;
+    qz *= qinv;
+    float Rq[9];
+    Rq[0] = 1.f - 2.f * (qy * qy + qz * qz);
+    Rq[1] = 2.f * (qx * qy - qw * qz);
+    Rq[2] = 2.f * (qx * qz + qw * qy);
+    Rq[3] = 2.f * (qx * qy + qw * qz);
+    Rq[4] = 1.f - 2.f * (qx * qx + qz * qz);
+    Rq[5] = 2.f * (qy * qz - qw * qx);
+    Rq[6] = 2.f * (qx * qz - qw * qy);
+    Rq[7] = 2.f * (qy * qz + qw * qx);
+    Rq[8] = 1.f - 2.f * (qx * qx + qy * qy);
+    const float s0 = __expf(gp.log_scale[g]), s1 = __expf(gp.log_scale[M + g]), s2 = __expf(gp.log_scale[2 * M + g]);
+    float Mm[9];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        Mm[3 * r + 0] = Rq[3 * r + 0] * s0;
+        Mm[3 * r + 1] = Rq[3 * r + 1] * s1;
+        Mm[3 * r + 2] = Rq[3 * r + 2] * s2;
+    }
+    // W = J R (2x3)
+    const float iz = 1.0f / z;
+    const float J00 = c.fx * iz, J02 = -c.fx * x * iz * iz, J11 = c.fy * iz, J12 = -c.fy * y * iz * iz;
+    float W0[3], W1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        W0[k] = J00 * c.R[k] + J02 * c.R[6 + k];
+        W1[k] = J11 * c.R[3 + k] + J12 * c.R[6 + k];
+    }
+    // U = W Mm (2x3); Sigma_2D = U U^T
+    float U0[3], U1[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        U0[k] = W0[0] * Mm[k] + W0[1] * Mm[3 + k] + W0[2] * Mm[6 + k];
+        U1[k] = W1[0] * Mm[k] + W1[1] * Mm[3 + k] + W1[2] * Mm[6 + k];
+    }
+    const float A = U0[0] * U0[0] + U0[1] * U0[1] + U0[2] * U0[2] + rp.dil;
+    const float B = U0[0] * U1[0] + U0[1] * U1[1] + U0[2] * U1[2];
+    const float C = U1[0] * U1[0] + U1[1] * U1[1] + U1[2] * U1[2] + rp.dil;
+    const float det = A * C - B * B;
+    if (!(det > 0.0f)) return o;
+    const float idet = 1.0f / det;
+    const float sig = 1.0f / (1.0f + __expf(-gp.opacity_logit[g]));
+    if (!(sig > rp.amin)) return o;
+    const float mx = c.fx * x * iz + c.cx, my = c.fy * y * iz + c.cy;
+    const float kappa = 2.0f * __logf(sig / rp.amin);
+    const float rx = sqrtf(kappa * A), ry = sqrtf(kappa * C);
+    const float xlo = fmaxf(mx - rx - 1.0f, 0.0f), xhi = fminf(mx + rx + 1.0f, (float)(c.W - 1));
+    const float ylo = fmaxf(my - ry - 1.0f, 0.0f), yhi = fminf(my + ry + 1.0f, (float)(c.H - 1));
+    if (!(xlo <= xhi) || !(ylo <= yhi)) return o;
+    const int px0 = (int)ceilf(xlo), px1 = (int)floorf(xhi), py0 = (int)ceilf(ylo), py1 = (int)floorf(yhi);
+    if (px0 > px1 || py0 > py1) return o;
+    const int tx0 = px0 / rp.tile_w, tx1 = px1 / rp.tile_w, ty0 = py0 / rp.tile_h, ty1 = py1 / rp.tile_h;
+    o.r0 = make_float4(mx, my, C * idet, -B * idet);
+    o.r1 = make_float4(A * idet, sig, z, gp.rgb[g]);
+    o.r2 = make_float4(gp.rgb[M + g], gp.rgb[2 * M + g], pack_rect(tx0, tx1 + 1), pack_rect(ty0, ty1 + 1));
+    o.valid = true;
+    return o;
+}
+
+__global__ void __launch_bounds__(kBlk) k_project(ViewTable vt, RParams rp, GParams gp, WsPtrs w)
+{
+    const int vg = blockIdx.x * kBlk + threadIdx.x;
+    unsigned int count = 0;
+    if (vg < rp.nvg) {
+        const int v = vg / rp.M, g = vg - v * rp.M;
+        const DevView& V = vt.v[v];
+        ProjOut p = project_one(V, rp, gp, g);
+        w.rec[3 * (size_t)vg + 0] = p.r0;
+        w.rec[3 * (size_t)vg + 1] = p.r1;
+        w.rec[3 * (size_t)vg + 2] = p.r2;
+        if (p.valid) {
+            int x0, x1, y0, y1;
+            rec_rect(p.r2, &x0, &x1, &y0, &y1);
+            const float z = p.r1.z;
+            for (int ty = y0; ty <= y1; ++ty)
+                for (int tx = x0; tx <= x1; ++tx) {
+                    const int tile = V.tile_base + ty * V.tiles_x + tx;
+                    if (z < w.tilemax[tile] + rp.eps) {  // exact tile-level depth cull
+                        ++count;
+                        atomicAdd(w.tile_cnt + tile, 1u);
+                    }
+                }
+        }
+        w.cnt[vg] = count;
+    }
+    unsigned int tot;
+    block_excl_scan<kBlk>(count, &tot);
+    if (threadIdx.x == 0) w.blk_sum[blockIdx.x] = tot;
+}
+
+// ------------------------------------------------------------------- scan
+// One block of 1024 lanes: exclusive scan of the per-block instance counts and
+// of the per-tile counts; capacity check.
+__device__ unsigned long long scan_array_1024(const unsigned int* in, unsigned int* out, int n, int write_total)
+{
+    __shared__ unsigned int wsum[16];
+    __shared__ unsigned long long carry_s;
+    if (threadIdx.x == 0) carry_s = 0ull;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int base = 0; base < n; base += 4096) {
+        unsigned int v[4], sum = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int i = base + threadIdx.x * 4 + k;
+            v[k] = i < n ? in[i] : 0u;
+            sum += v[k];
+        }
+        unsigned int x = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            unsigned int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wid] = x;
+        __syncthreads();
+        unsigned int before = 0, tot = 0;
+        for (int k = 0; k < 16; ++k) {
+            if (k < wid) before += wsum[k];
+            tot += wsum[k];
+        }
+        unsigned long long carry = carry_s;
+        unsigned int run = (unsigned int)carry + before + x - sum;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            int i = base + threadIdx.x * 4 + k;
+            if (i < n) out[i] = run;
+            run += v[k];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s = carry + tot;
+        __syncthreads();
+    }
+    unsigned long long total = carry_s;
+    if (write_total && threadIdx.x == 0) out[n] = (unsigned int)total;
+    __syncthreads();
+    return total;
+}
+
+__global__ void __launch_bounds__(1024) k_scan(RParams rp, WsPtrs w, int nblk_vg, int n_tiles)
+{
+    unsigned long long total = scan_array_1024(w.blk_sum, w.blk_off, nblk_vg, 0);
+    scan_array_1024(w.tile_cnt, w.tile_start, n_tiles, 1);
+    for (int i = threadIdx.x; i < n_tiles; i += 1024) w.tile_cursor[i] = w.tile_start[i];
+    if (threadIdx.x == 0) {
+        w.hdr->n_inst = total;
+        w.hdr->cap = rp.cap;
+        w.hdr->n_tiles = n_tiles;
+        if (total > rp.cap) atomicCAS(&w.hdr->status, 0, GPS_ERR_CAPACITY);
+    }
+}
+
+// ------------------------------------------------------------------- emit
+__global__ void __launch_bounds__(kBlk) k_emit(ViewTable vt, RParams rp, WsPtrs w)
+{
+    if (w.hdr->n_inst > rp.cap) return;
+    const int vg = blockIdx.x * kBlk + threadIdx.x;
+    const unsigned int c = vg < rp.nvg ? w.cnt[vg] : 0u;
+    unsigned int tot;
+    const unsigned int excl = block_excl_scan<kBlk>(c, &tot);
+    if (vg >= rp.nvg) return;
+    const unsigned int base = w.blk_off[blockIdx.x] + excl;
+    w.off[vg] = base;
+    if (c == 0) return;
+    const int v = vg / rp.M;
+    const DevView& V = vt.v[v];
+    const float4 r1 = w.rec[3 * (size_t)vg + 1];
+    const float4 r2 = w.rec[3 * (size_t)vg + 2];
+    const float z = r1.z;
+    const unsigned long long zkey = (unsigned long long)__float_as_uint(z) << 32;
+    int x0, x1, y0, y1;
+    rec_rect(r2, &x0, &x1, &y0, &y1);
+    unsigned int slot = base;
+    const unsigned int slot_end = base + c;  // the count the projection made
+    for (int ty = y0; ty <= y1; ++ty)
+        for (int tx = x0; tx <= x1; ++tx) {
+            const int tile = V.tile_base + ty * V.tiles_x + tx;
+            if (z < w.tilemax[tile] + rp.eps && slot < slot_end) {
+                w.inst_vg[slot] = (unsigned int)vg;
+                const unsigned int pos = atomicAdd(w.tile_cursor + tile, 1u);
+                if (pos < w.tile_start[tile + 1]) w.keys[pos] = zkey | slot;
+                ++slot;
+            }
+        }
+}
+
+// -------------------------------------------------------------- tile sort
+// Bitonic network in which every compare-exchange puts the smaller key at
+// the lower index (the first step of each merge compares mirrored pairs), so
+// padding with +inf keys never moves into the sorted range.
+__global__ void __launch_bounds__(256) k_tile_sort(RParams rp, WsPtrs w)
+{
+    if (w.hdr->n_inst > rp.cap) return;
+    const int tile = blockIdx.x;
+    const unsigned int s = w.tile_start[tile], e = w.tile_start[tile + 1];
+    const int n = (int)(e - s);
+    if (n <= 1) return;
+    int P = 1;
+    while (P < n) P <<= 1;
+    unsigned long long* key = w.keys + s;
+    if (n <= kSortCap) {
+        __shared__ unsigned long long sh[kSortCap];
+        for (int i = threadIdx.x; i < P; i += 256) sh[i] = i < n ? key[i] : ~0ull;
+        __syncthreads();
+        for (int k = 2; k <= P; k <<= 1) {
+            const int half = k >> 1;
+            for (int c = threadIdx.x; c < P / 2; c += 256) {
+                const int blk = c / half, wi = c - blk * half;
+                const int i = blk * k + wi, j = blk * k + k - 1 - wi;
+                unsigned long long a = sh[i], b = sh[j];
+                if (a > b) {
+                    sh[i] = b;
+                    sh[j] = a;
+                }
+            }
+            __syncthreads();
+            for (int jj = k >> 2; jj > 0; jj >>= 1) {
+                for (int c = threadIdx.x; c < P / 2; c += 256) {
+                    const int i = (c / jj) * 2 * jj + (c % jj), j = i + jj;
+                    unsigned long long a = sh[i], b = sh[j];
+                    if (a > b) {
+                        sh[i] = b;
+                        sh[j] = a;
+                    }
+                }
+                __syncthreads();
+            }
+        }
+        for (int i = threadIdx.x; i < n; i += 256) key[i] = sh[i];
+    } else {
+        // Rare: a tile longer than the LDS holds.  Same network in global
+        // memory; elements at or past n act as +inf and are never touched.
+        if (threadIdx.x == 0) atomicAdd(&w.hdr->n_fallback, 1ull);
+        for (int k = 2; k <= P; k <<= 1) {
+            const int half = k >> 1;
+            for (int c = threadIdx.x; c < P / 2; c += 256) {
+                const int blk = c / half, wi = c - blk * half;
+                const int i = blk * k + wi, j = blk * k + k - 1 - wi;
+                if (j < n) {
+                    unsigned long long a = key[i], b = key[j];
+                    if (a > b) {
+                        key[i] = b;
+                        key[j] = a;
+                    }
+                }
+            }
+            __syncthreads();
+            for (int jj = k >> 2; jj > 0; jj >>= 1) {
+                for (int c = threadIdx.x; c < P / 2; c += 256) {
+                    const int i = (c / jj) * 2 * jj + (c % jj), j = i + jj;
+                    if (j < n) {
+                        unsigned long long a = key[i], b = key[j];
+                        if (a > b) {
+                            key[i] = b;
+                            key[j] = a;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------- composite fwd
+template <int TW, int TH, int B, int PPT>
+__global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(ViewTable vt, RParams rp, WsPtrs w)
+{
+    constexpr int NT = TW * TH / PPT;
+    constexpr int ROWS = TH / PPT;
+    __shared__ float4 srec[3 * B];
+    if (w.hdr->n_inst > rp.cap) return;
+    const int tile = blockIdx.x;
+    const int v = find_view(vt, tile);
+    const DevView& V = vt.v[v];
+    const int lt = tile - V.tile_base;
+    const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
+    const int Wd = V.cam.W, Ht = V.cam.H;
+    const size_t HW = (size_t)Wd * Ht;
+    const int px = tx * TW + (int)(threadIdx.x % TW);
+    const int py0 = ty * TH + (int)(threadIdx.x / TW);
+    const float fpx = (float)px;
+
+    float thr[PPT], T[PPT], ac0[PPT], ac1[PPT], ac2[PPT], ad[PPT];
+    bool done[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int py = py0 + k * ROWS;
+        const bool inb = px < Wd && py < Ht;
+        float dt = inb ? V.base_depth[(size_t)py * Wd + px] : 0.0f;
+        float dcull = dt > 0.0f ? dt : INFINITY;
+        thr[k] = dcull + rp.eps;
+        T[k] = rp.mode == 0 ? 1.0f : 0.0f;
+        ac0[k] = ac1[k] = ac2[k] = ad[k] = 0.0f;
+        done[k] = !inb;
+    }
+    const unsigned int s = w.tile_start[tile], e = w.tile_start[tile + 1];
+    for (unsigned int b = s; b < e; b += B) {
+        int alive = 0;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) alive |= !done[k];
+        if (__syncthreads_count(alive) == 0) break;
+        for (int j = threadIdx.x; j < B && b + j < e; j += NT) {
+            const unsigned int slot = (unsigned int)w.keys[b + j];
+            unsigned int vg = slot < rp.cap ? w.inst_vg[slot] : 0u;
+            if (vg >= (unsigned int)rp.nvg) vg = 0u;  // guard: never read outside the records
+            const float4* r = w.rec + 3 * (size_t)vg;
+            srec[3 * j + 0] = r[0];
+            srec[3 * j + 1] = r[1];
+            srec[3 * j + 2] = r[2];
+        }
+        __syncthreads();
+        const int n = (int)min((unsigned int)B, e - b);
+        for (int j = 0; j < n; ++j) {
+            const float4 r0 = srec[3 * j], r1 = srec[3 * j + 1], r2 = srec[3 * j + 2];
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                if (done[k]) continue;
+                if (!(r1.z < thr[k])) {  // depth test of Eq. 1-2; the list is depth-ordered
+                    done[k] = true;
+                    continue;
+                }
+                const AlphaEval ae = eval_alpha(fpx, (float)(py0 + k * ROWS), r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
+                if (rp.mode == 0) {
+                    const float a = fminf(rp.amax, ae.raw);
+                    if (a < rp.amin) continue;
+                    const float Tn = T[k] * (1.0f - a);
+                    if (Tn < rp.Tmin) {
+                        done[k] = true;
+                        continue;
+                    }
+                    const float wgt = a * T[k];
+                    ac0[k] = __builtin_fmaf(wgt, r1.w, ac0[k]);
+                    ac1[k] = __builtin_fmaf(wgt, r2.x, ac1[k]);
+                    ac2[k] = __builtin_fmaf(wgt, r2.y, ac2[k]);
+                    ad[k] = __builtin_fmaf(wgt, r1.z, ad[k]);
+                    T[k] = Tn;
+                } else {
+                    const float a = ae.raw;
+                    if (a < rp.amin) continue;
+                    T[k] += a;  // W_G
+                    ac0[k] = __builtin_fmaf(a, r1.w, ac0[k]);
+                    ac1[k] = __builtin_fmaf(a, r2.x, ac1[k]);
+                    ac2[k] = __builtin_fmaf(a, r2.y, ac2[k]);
+                    ad[k] = __builtin_fmaf(a, r1.z, ad[k]);
+                }
+            }
+        }
+    }
+
+    // epilogue: outputs and the fused loss partial of this tile
+    float lc = 0.0f, ld = 0.0f, lo = 0.0f;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        const int py = py0 + k * ROWS;
+        if (!(px < Wd && py < Ht)) continue;
+        const size_t p = (size_t)py * Wd + px;
+        const float dt = V.base_depth[p];
+        const bool dvalid = dt > 0.0f;
+        float Cs[3], Ds;
+        const float ct0 = V.base_rgb[p], ct1 = V.base_rgb[HW + p], ct2 = V.base_rgb[2 * HW + p];
+        if (rp.mode == 0) {
+            Cs[0] = __builtin_fmaf(T[k], ct0, ac0[k]);
+            Cs[1] = __builtin_fmaf(T[k], ct1, ac1[k]);
+            Cs[2] = __builtin_fmaf(T[k], ct2, ac2[k]);
+            Ds = dvalid ? __builtin_fmaf(T[k], dt, ad[k]) : 0.0f;
+        } else {
+            const float inv = 1.0f / (1.0f + T[k]);
+            Cs[0] = (ct0 + ac0[k]) * inv;
+            Cs[1] = (ct1 + ac1[k]) * inv;
+            Cs[2] = (ct2 + ac2[k]) * inv;
+            Ds = dvalid ? (dt + ad[k]) * inv : 0.0f;
+        }
+        V.out_rgb[p] = Cs[0];
+        V.out_rgb[HW + p] = Cs[1];
+        V.out_rgb[2 * HW + p] = Cs[2];
+        V.out_depth[p] = Ds;
+        w.pix_aux[(size_t)V.pix_base + p] = T[k];
+        if (V.target_rgb) {
+            lc += fabsf(Cs[0] - V.target_rgb[p]) + fabsf(Cs[1] - V.target_rgb[HW + p]) +
+                  fabsf(Cs[2] - V.target_rgb[2 * HW + p]);
+            if (V.target_depth) {
+                const float dobs = V.target_depth[p];
+                if (dobs > 0.0f && dvalid) {
+                    ld += fabsf(Ds - dobs);
+                    lo += 1.0f;
+                }
+            }
+        }
+    }
+    lc = block_sum<NT>(lc);
+    ld = block_sum<NT>(ld);
+    lo = block_sum<NT>(lo);
+    if (threadIdx.x == 0) w.tile_loss[tile] = make_float4(lc, ld, lo, 0.0f);
+}
+
+// ------------------------------------------------------------ loss reduce
+__global__ void __launch_bounds__(256) k_loss_reduce(ViewTable vt, RParams rp, WsPtrs w, float* out_loss,
+                                                     int has_loss)
+{
+    float L = 0.0f;
+    for (int v = 0; v < vt.n; ++v) {
+        const DevView& V = vt.v[v];
+        const int nt = V.tiles_x * V.tiles_y;
+        float a = 0.0f, b = 0.0f, c = 0.0f;
+        for (int t = threadIdx.x; t < nt; t += 256) {
+            const float4 q = w.tile_loss[V.tile_base + t];
+            a += q.x;
+            b += q.y;
+            c += q.z;
+        }
+        a = block_sum<256>(a);
+        b = block_sum<256>(b);
+        c = block_sum<256>(c);
+        if (threadIdx.x == 0) {
+            w.hdr->view_stats[v][0] = a;
+            w.hdr->view_stats[v][1] = b;
+            w.hdr->view_stats[v][2] = c;
+            w.hdr->view_stats[v][3] = 0.0f;
+            const float npx = 3.0f * (float)V.cam.W * (float)V.cam.H;
+            L += a / npx + (c > 0.0f ? rp.lambda * b / c : 0.0f);
+        }
+    }
+    if (threadIdx.x == 0) {
+        L = L / (float)vt.n;
+        w.hdr->loss = has_loss ? L : 0.0f;
+        if (out_loss && has_loss) *out_loss = L;
+    }
+}
+
+// ----------------------------------------------------------------- launch
+template <int TW, int TH, int B, int PPT>
+static void launch_cfwd(const ViewTable& vt, const RParams& rp, const WsPtrs& w, int n_tiles, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_composite_fwd<TW, TH, B, PPT>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, vt, rp, w);
+}
+
+#define GPS_TILE_CONFIGS(X) \
+    X(8, 8, 128, 1)         \
+    X(8, 8, 256, 1)         \
+    X(8, 8, 512, 1)         \
+    X(16, 16, 128, 1)       \
+    X(16, 16, 256, 1)       \
+    X(16, 16, 128, 2)       \
+    X(16, 16, 256, 2)       \
+    X(16, 16, 512, 2)       \
+    X(16, 16, 128, 4)       \
+    X(16, 16, 256, 4)       \
+    X(16, 16, 512, 4)       \
+    X(16, 32, 128, 1)       \
+    X(16, 32, 128, 2)       \
+    X(16, 32, 256, 2)       \
+    X(16, 32, 128, 4)       \
+    X(16, 32, 256, 4)       \
+    X(16, 32, 512, 4)
+
+static bool dispatch_cfwd(const gps_render_cfg* cfg, const ViewTable& vt, const RParams& rp, const WsPtrs& w,
+                          int n_tiles, hipStream_t s)
+{
+#define X(tw, th, b, ppt)                                                                                  \
+    if (cfg->tile_w == tw && cfg->tile_h == th && cfg->batch == b && cfg->pix_per_thread == ppt) {       \
+        launch_cfwd<tw, th, b, ppt>(vt, rp, w, n_tiles, s);                                             \
+        return true;                                                                                     \
+    }
+    GPS_TILE_CONFIGS(X)
+#undef X
+    return false;
+}
+
+bool tile_config_supported(const gps_render_cfg* cfg)
+{
+#define X(tw, th, b, ppt) \
+    if (cfg->tile_w == tw && cfg->tile_h == th && cfg->batch == b && cfg->pix_per_thread == ppt) return true;
+    GPS_TILE_CONFIGS(X)
+#undef X
+    return false;
+}
+
+gps_status launch_render_fwd(const gps_render_cfg* cfg, const RParams& rp, const gps_gaussians* g,
+                             const ViewTable& vt, const WsLayout& L, char* ws, float* out_loss, hipStream_t s)
+{
+    WsPtrs w = ws_ptrs(ws, L);
+    GParams gp{g->mean, g->log_scale, g->quat, g->opacity_logit, g->rgb};
+    int has_loss = 1;
+    for (int v = 0; v < vt.n; ++v)
+        if (!vt.v[v].target_rgb) has_loss = 0;
+    hipLaunchKernelGGL(k_prep, dim3(L.n_tiles), dim3(256), 0, s, vt, rp, w);
+    if (L.nblk_vg > 0) hipLaunchKernelGGL(k_project, dim3(L.nblk_vg), dim3(kBlk), 0, s, vt, rp, gp, w);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, rp, w, L.nblk_vg, L.n_tiles);
+    if (L.nblk_vg > 0) hipLaunchKernelGGL(k_emit, dim3(L.nblk_vg), dim3(kBlk), 0, s, vt, rp, w);
+    hipLaunchKernelGGL(k_tile_sort, dim3(L.n_tiles), dim3(256), 0, s, rp, w);
+    if (!dispatch_cfwd(cfg, vt, rp, w, L.n_tiles, s)) return GPS_ERR_UNSUPPORTED_CONFIG;
+    hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, s, vt, rp, w, out_loss, has_loss);
+    return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
+}
+
+}  // namespace gps

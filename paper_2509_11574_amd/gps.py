@@ -1,0 +1,488 @@
+"""Thin Python binding of libgps (include/gps.h): ctypes argument marshalling only.
+
+Every step of the mapping path runs in the HIP kernels of libgps.so; this
+module converts torch tensors to device pointers, forwards the current HIP
+stream and raises on any non-OK status.  There is no fallback: importing it
+without the built library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgps.so")
+MAX_VIEWS = 16
+
+OK = 0
+STATUS_NAMES = {0: "ok", -1: "invalid argument", -2: "workspace too small", -3: "capacity exceeded",
+                -4: "HIP error", -5: "unsupported device", -6: "unsupported config"}
+
+
+class GpsError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {STATUS_NAMES.get(status, status)} ({status})")
+        self.status = status
+
+
+class Camera(ctypes.Structure):
+    _fields_ = [("width", ctypes.c_int32), ("height", ctypes.c_int32), ("fx", ctypes.c_float),
+                ("fy", ctypes.c_float), ("cx", ctypes.c_float), ("cy", ctypes.c_float),
+                ("R", ctypes.c_float * 9), ("t", ctypes.c_float * 3)]
+
+
+class VolumeS(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("origin", ctypes.c_float * 3), ("voxel", ctypes.c_float), ("trunc", ctypes.c_float),
+                ("max_weight", ctypes.c_float), ("tsdf", ctypes.c_void_p), ("weight", ctypes.c_void_p),
+                ("rgb", ctypes.c_void_p), ("rgb_weight", ctypes.c_void_p), ("brick_min", ctypes.c_void_p)]
+
+
+class GaussiansS(ctypes.Structure):
+    _fields_ = [("count", ctypes.c_int32), ("mean", ctypes.c_void_p), ("log_scale", ctypes.c_void_p),
+                ("quat", ctypes.c_void_p), ("opacity_logit", ctypes.c_void_p), ("rgb", ctypes.c_void_p)]
+
+
+class ViewS(ctypes.Structure):
+    _fields_ = [("cam", Camera), ("base_rgb", ctypes.c_void_p), ("base_depth", ctypes.c_void_p),
+                ("target_rgb", ctypes.c_void_p), ("target_depth", ctypes.c_void_p),
+                ("out_rgb", ctypes.c_void_p), ("out_depth", ctypes.c_void_p)]
+
+
+class RenderCfgS(ctypes.Structure):
+    _fields_ = [("tile_w", ctypes.c_int32), ("tile_h", ctypes.c_int32), ("batch", ctypes.c_int32),
+                ("pix_per_thread", ctypes.c_int32), ("mode", ctypes.c_int32), ("eps_cull", ctypes.c_float),
+                ("lambda_depth", ctypes.c_float), ("dilation", ctypes.c_float), ("alpha_min", ctypes.c_float),
+                ("alpha_max", ctypes.c_float), ("T_min", ctypes.c_float), ("z_near", ctypes.c_float),
+                ("max_instances", ctypes.c_int64)]
+
+
+class AdamGroupS(ctypes.Structure):
+    _fields_ = [("param", ctypes.c_void_p), ("grad", ctypes.c_void_p), ("m", ctypes.c_void_p),
+                ("v", ctypes.c_void_p), ("n", ctypes.c_int64), ("lr", ctypes.c_float)]
+
+
+class StatsS(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("n_views", ctypes.c_int32), ("n_instances", ctypes.c_int64),
+                ("capacity", ctypes.c_int64), ("sort_fallback", ctypes.c_int64), ("n_tiles", ctypes.c_int64),
+                ("loss", ctypes.c_float), ("view_omega", ctypes.c_float * MAX_VIEWS)]
+
+
+EXPORTS = ["gps_abi_version", "gps_status_string", "gps_render_cfg_default", "gps_workspace_size",
+           "gps_workspace_reset", "gps_fuse", "gps_raycast", "gps_render_fwd", "gps_render_bwd",
+           "gps_adam_step", "gps_device_status", "gps_read_stats"]
+
+_lib = None
+
+
+def lib():
+    """Load libgps.so (built in-tree); raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2509_11574_amd.build` "
+                              "(or __graft_entry__.build()); there is no fallback implementation")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I32, I64, F = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+        L.gps_abi_version.restype = I32
+        L.gps_status_string.argtypes = [I32]
+        L.gps_status_string.restype = ctypes.c_char_p
+        L.gps_render_cfg_default.argtypes = [P]
+        L.gps_render_cfg_default.restype = None
+        L.gps_workspace_size.argtypes = [P, I32, P, I32, ctypes.POINTER(ctypes.c_size_t)]
+        L.gps_workspace_reset.argtypes = [P, ctypes.c_size_t, P]
+        L.gps_fuse.argtypes = [P, P, P, P, P]
+        L.gps_raycast.argtypes = [P, P, I32, P, P, F, F, P]
+        L.gps_render_fwd.argtypes = [P, P, P, I32, P, ctypes.c_size_t, P, P]
+        L.gps_render_bwd.argtypes = [P, P, P, I32, P, P, P, P, P, P, ctypes.c_size_t, P]
+        L.gps_adam_step.argtypes = [P, I32, I32, P, F, F, F, P]
+        L.gps_device_status.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(I32), P]
+        L.gps_read_stats.argtypes = [P, ctypes.c_size_t, P, P]
+        for n in EXPORTS:
+            if n not in ("gps_render_cfg_default", "gps_status_string", "gps_abi_version"):
+                getattr(L, n).restype = I32
+        _lib = L
+    return _lib
+
+
+def _check(st: int, what: str):
+    if st != OK:
+        raise GpsError(st, what)
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t, name="tensor", numel=None):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be on the GPU")
+    if t.dtype not in (torch.float32, torch.int32, torch.uint8):
+        raise TypeError(f"{name} must be float32 (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# --------------------------------------------------------------------------- #
+# Cameras, volumes, Gaussians                                                  #
+# --------------------------------------------------------------------------- #
+def camera(c) -> Camera:
+    """From a dict or object with width, height, fx, fy, cx, cy, R (3x3), t (3)."""
+    if isinstance(c, Camera):
+        return c
+    g = (lambda k: c[k]) if isinstance(c, dict) else (lambda k: getattr(c, k))
+    out = Camera()
+    out.width, out.height = int(g("width")), int(g("height"))
+    out.fx, out.fy, out.cx, out.cy = (float(g(k)) for k in ("fx", "fy", "cx", "cy"))
+    R = np.asarray(g("R"), np.float32).reshape(9)
+    t = np.asarray(g("t"), np.float32).reshape(3)
+    for k in range(9):
+        out.R[k] = float(R[k])
+    for k in range(3):
+        out.t[k] = float(t[k])
+    return out
+
+
+@dataclass
+class Volume:
+    """Dense colourised TSDF lattice on the GPU (planar float32 arrays)."""
+    dims: tuple
+    origin: tuple
+    voxel: float
+    trunc: float
+    max_weight: float = 100.0
+    device: str = "cuda"
+    skip_bricks: bool = True
+    tsdf: torch.Tensor = field(init=False)
+    weight: torch.Tensor = field(init=False)
+    rgb: torch.Tensor = field(init=False)
+    rgb_weight: torch.Tensor = field(init=False)
+    brick_min: torch.Tensor | None = field(init=False)
+
+    def __post_init__(self):
+        nx, ny, nz = (int(d) for d in self.dims)
+        N = nx * ny * nz
+        self.tsdf = torch.ones(N, dtype=torch.float32, device=self.device)
+        self.weight = torch.zeros(N, dtype=torch.float32, device=self.device)
+        self.rgb = torch.zeros(3, N, dtype=torch.float32, device=self.device)
+        self.rgb_weight = torch.zeros(N, dtype=torch.float32, device=self.device)
+        nb = math.ceil(nx / 8) * math.ceil(ny / 8) * math.ceil(nz / 8)
+        self.brick_min = torch.zeros(nb, dtype=torch.float32, device=self.device) if self.skip_bricks else None
+
+    def struct(self) -> VolumeS:
+        s = VolumeS()
+        s.nx, s.ny, s.nz = (int(d) for d in self.dims)
+        for k in range(3):
+            s.origin[k] = float(self.origin[k])
+        s.voxel, s.trunc, s.max_weight = float(self.voxel), float(self.trunc), float(self.max_weight)
+        N = s.nx * s.ny * s.nz
+        s.tsdf = _ptr(self.tsdf, "tsdf", N)
+        s.weight = _ptr(self.weight, "weight", N)
+        s.rgb = _ptr(self.rgb, "rgb", 3 * N)
+        s.rgb_weight = _ptr(self.rgb_weight, "rgb_weight", N)
+        s.brick_min = _ptr(self.brick_min, "brick_min") if self.brick_min is not None else None
+        return s
+
+
+GAUSS_KEYS = ("mean", "log_scale", "quat", "opacity_logit", "rgb")
+GAUSS_ROWS = {"mean": 3, "log_scale": 3, "quat": 4, "opacity_logit": 1, "rgb": 3}
+
+
+def gaussians_struct(g: dict) -> GaussiansS:
+    M = int(g["opacity_logit"].numel())
+    s = GaussiansS()
+    s.count = M
+    for k in GAUSS_KEYS:
+        setattr(s, k, _ptr(g[k], k, GAUSS_ROWS[k] * M))
+    return s
+
+
+def gaussians_to_device(g: dict, device="cuda") -> dict:
+    return {k: torch.as_tensor(np.ascontiguousarray(g[k], np.float32)).to(device) for k in GAUSS_KEYS}
+
+
+def zeros_like_gaussians(g: dict) -> dict:
+    return {k: torch.zeros_like(g[k]) for k in GAUSS_KEYS}
+
+
+@dataclass
+class RenderCfg:
+    tile_w: int = 16
+    tile_h: int = 16
+    batch: int = 256
+    pix_per_thread: int = 1
+    mode: int = 0
+    eps_cull: float = 0.01
+    lambda_depth: float = 1.0
+    dilation: float = 0.3
+    alpha_min: float = 1.0 / 255.0
+    alpha_max: float = 0.99
+    T_min: float = 1e-4
+    z_near: float = 0.2
+    max_instances: int = 0
+
+    def struct(self) -> RenderCfgS:
+        return RenderCfgS(self.tile_w, self.tile_h, self.batch, self.pix_per_thread, self.mode, self.eps_cull,
+                          self.lambda_depth, self.dilation, self.alpha_min, self.alpha_max, self.T_min,
+                          self.z_near, int(self.max_instances))
+
+
+# Tile / batch / pixels-per-lane combinations compiled into libgps.
+TILE_CONFIGS = [(8, 8, 128, 1), (8, 8, 256, 1), (8, 8, 512, 1), (16, 16, 128, 1), (16, 16, 256, 1),
+                (16, 16, 128, 2), (16, 16, 256, 2), (16, 16, 512, 2), (16, 16, 128, 4), (16, 16, 256, 4),
+                (16, 16, 512, 4), (16, 32, 128, 1), (16, 32, 128, 2), (16, 32, 256, 2), (16, 32, 128, 4),
+                (16, 32, 256, 4), (16, 32, 512, 4)]
+
+
+# --------------------------------------------------------------------------- #
+# SDF side                                                                     #
+# --------------------------------------------------------------------------- #
+def fuse(vol: Volume, cam, depth: torch.Tensor, rgb: torch.Tensor, stream=None):
+    c = camera(cam)
+    s = vol.struct()
+    _check(lib().gps_fuse(ctypes.byref(s), ctypes.byref(c), _ptr(depth, "depth", c.width * c.height),
+                          _ptr(rgb, "rgb", 3 * c.width * c.height), _stream(stream)), "gps_fuse")
+
+
+def raycast(vol: Volume, cams, z_near=0.2, step=0.0, out=None, stream=None):
+    """Returns a list of (depth [H,W], rgb [3,H,W]) per camera (allocated unless `out` is given)."""
+    cams = [camera(c) for c in cams]
+    V = len(cams)
+    if out is None:
+        out = [(torch.empty(c.height, c.width, dtype=torch.float32, device=vol.tsdf.device),
+                torch.empty(3, c.height, c.width, dtype=torch.float32, device=vol.tsdf.device)) for c in cams]
+    carr = (Camera * V)(*cams)
+    dptr = (ctypes.c_void_p * V)(*[_ptr(d, "out_depth", c.width * c.height).value for (d, _), c in zip(out, cams)])
+    cptr = (ctypes.c_void_p * V)(*[_ptr(r, "out_rgb", 3 * c.width * c.height).value for (_, r), c in zip(out, cams)])
+    s = vol.struct()
+    _check(lib().gps_raycast(ctypes.byref(s), carr, V, dptr, cptr, float(z_near), float(step), _stream(stream)),
+           "gps_raycast")
+    return out
+
+
+# --------------------------------------------------------------------------- #
+# Render                                                                       #
+# --------------------------------------------------------------------------- #
+@dataclass
+class View:
+    cam: object
+    base_rgb: torch.Tensor
+    base_depth: torch.Tensor
+    target_rgb: torch.Tensor | None = None
+    target_depth: torch.Tensor | None = None
+    out_rgb: torch.Tensor | None = None
+    out_depth: torch.Tensor | None = None
+
+    def __post_init__(self):
+        c = camera(self.cam)
+        dev = self.base_rgb.device
+        if self.out_rgb is None:
+            self.out_rgb = torch.empty(3, c.height, c.width, dtype=torch.float32, device=dev)
+        if self.out_depth is None:
+            self.out_depth = torch.empty(c.height, c.width, dtype=torch.float32, device=dev)
+
+    def struct(self) -> ViewS:
+        c = camera(self.cam)
+        HW = c.width * c.height
+        return ViewS(c, _ptr(self.base_rgb, "base_rgb", 3 * HW), _ptr(self.base_depth, "base_depth", HW),
+                     _ptr(self.target_rgb, "target_rgb", 3 * HW), _ptr(self.target_depth, "target_depth", HW),
+                     _ptr(self.out_rgb, "out_rgb", 3 * HW), _ptr(self.out_depth, "out_depth", HW))
+
+
+def workspace_size(cfg: RenderCfg, n_gaussians: int, cams) -> int:
+    cams = [camera(c) for c in cams]
+    carr = (Camera * len(cams))(*cams)
+    out = ctypes.c_size_t(0)
+    cs = cfg.struct()
+    _check(lib().gps_workspace_size(ctypes.byref(cs), int(n_gaussians), carr, len(cams), ctypes.byref(out)),
+           "gps_workspace_size")
+    return out.value
+
+
+class Workspace:
+    """Caller-owned device workspace for render_fwd / render_bwd (sized for cfg, M and the cameras)."""
+
+    def __init__(self, cfg: RenderCfg, n_gaussians: int, cams, device="cuda", stream=None):
+        self.nbytes = workspace_size(cfg, n_gaussians, cams)
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.reset(stream)
+
+    def ptr(self):
+        return ctypes.c_void_p(self.buf.data_ptr())
+
+    def reset(self, stream=None):
+        _check(lib().gps_workspace_reset(self.ptr(), self.nbytes, _stream(stream)), "gps_workspace_reset")
+
+    def status(self, stream=None) -> int:
+        st = ctypes.c_int32(0)
+        _check(lib().gps_device_status(self.ptr(), self.nbytes, ctypes.byref(st), _stream(stream)),
+               "gps_device_status")
+        return st.value
+
+    def stats(self, stream=None) -> dict:
+        s = StatsS()
+        _check(lib().gps_read_stats(self.ptr(), self.nbytes, ctypes.byref(s), _stream(stream)), "gps_read_stats")
+        return {"status": s.status, "n_views": s.n_views, "n_instances": s.n_instances, "capacity": s.capacity,
+                "sort_fallback": s.sort_fallback, "n_tiles": s.n_tiles, "loss": s.loss,
+                "view_omega": list(s.view_omega)[:max(s.n_views, 0)]}
+
+
+def _views_array(views):
+    V = len(views)
+    if not 1 <= V <= MAX_VIEWS:
+        raise ValueError(f"1..{MAX_VIEWS} views per call")
+    return (ViewS * V)(*[v.struct() for v in views])
+
+
+def render_fwd(cfg: RenderCfg, gauss: dict, views, ws: Workspace, out_loss: torch.Tensor | None = None,
+               stream=None):
+    cs = cfg.struct()
+    gs = gaussians_struct(gauss)
+    va = _views_array(views)
+    _check(lib().gps_render_fwd(ctypes.byref(cs), ctypes.byref(gs), va, len(views), ws.ptr(), ws.nbytes,
+                                _ptr(out_loss, "out_loss", 1) if out_loss is not None else None, _stream(stream)),
+           "gps_render_fwd")
+
+
+def render_bwd(cfg: RenderCfg, gauss: dict, views, ws: Workspace, grads: dict, dpose: torch.Tensor | None = None,
+               dL_drgb=None, dL_ddepth=None, loss_scale: torch.Tensor | None = None, stream=None):
+    cs = cfg.struct()
+    gs = gaussians_struct(gauss)
+    gg = gaussians_struct(grads)
+    va = _views_array(views)
+    V = len(views)
+    rgb_arr = dep_arr = None
+    if dL_drgb is not None:
+        rgb_arr = (ctypes.c_void_p * V)(*[_ptr(t, "dL_drgb").value for t in dL_drgb])
+        if dL_ddepth is not None:
+            dep_arr = (ctypes.c_void_p * V)(*[_ptr(t, "dL_ddepth").value if t is not None else None
+                                             for t in dL_ddepth])
+    _check(lib().gps_render_bwd(ctypes.byref(cs), ctypes.byref(gs), va, V, rgb_arr, dep_arr,
+                                _ptr(loss_scale, "loss_scale", 1) if loss_scale is not None else None,
+                                ctypes.byref(gg), _ptr(dpose, "dpose", 6 * V) if dpose is not None else None,
+                                ws.ptr(), ws.nbytes, _stream(stream)), "gps_render_bwd")
+
+
+# Learning rates per attribute (Appendix C): position, SH0 (applied to rgb),
+# alpha (applied to the opacity logit), scale (log-scale), rotation (quaternion).
+PAPER_LR = {"mean": 1.6e-4, "rgb": 2.5e-3, "opacity_logit": 0.05, "log_scale": 5e-3, "quat": 1e-3}
+
+
+class Adam:
+    """Adam state for a Gaussian set; one fused launch per step (gps_adam_step)."""
+
+    def __init__(self, params: dict, lr: dict | None = None, betas=(0.9, 0.999), eps=1e-15,
+                 device_counter: bool = True):
+        self.params = params
+        self.lr = dict(PAPER_LR if lr is None else lr)
+        self.b1, self.b2 = betas
+        self.eps = eps
+        self.m = {k: torch.zeros_like(params[k]) for k in GAUSS_KEYS}
+        self.v = {k: torch.zeros_like(params[k]) for k in GAUSS_KEYS}
+        self.t = 0
+        self.counter = torch.zeros(1, dtype=torch.int32, device=params["mean"].device) if device_counter else None
+
+    def step(self, grads: dict, stream=None):
+        groups = (AdamGroupS * len(GAUSS_KEYS))()
+        for i, k in enumerate(GAUSS_KEYS):
+            p = self.params[k]
+            groups[i] = AdamGroupS(_ptr(p, k), _ptr(grads[k], "grad " + k, p.numel()), _ptr(self.m[k]),
+                                   _ptr(self.v[k]), p.numel(), float(self.lr[k]))
+        self.t += 1
+        ctr = ctypes.c_void_p(self.counter.data_ptr()) if self.counter is not None else None
+        _check(lib().gps_adam_step(groups, len(GAUSS_KEYS), self.t, ctr, self.b1, self.b2, self.eps,
+                                   _stream(stream)), "gps_adam_step")
+
+
+def adam_step(groups, step, b1=0.9, b2=0.999, eps=1e-15, step_counter=None, stream=None):
+    """groups: list of (param, grad, m, v, lr) tensors."""
+    arr = (AdamGroupS * len(groups))()
+    for i, (p, g, m, v, lr) in enumerate(groups):
+        arr[i] = AdamGroupS(_ptr(p), _ptr(g, "grad", p.numel()), _ptr(m, "m", p.numel()), _ptr(v, "v", p.numel()),
+                            p.numel(), float(lr))
+    ctr = _ptr(step_counter, "step_counter", 1) if step_counter is not None else None
+    _check(lib().gps_adam_step(arr, len(groups), int(step), ctr, float(b1), float(b2), float(eps),
+                               _stream(stream)), "gps_adam_step")
+
+
+# --------------------------------------------------------------------------- #
+# autograd                                                                     #
+# --------------------------------------------------------------------------- #
+class Session:
+    """Everything a differentiable render needs besides the parameters: config, views, workspace."""
+
+    def __init__(self, cfg: RenderCfg, views, n_gaussians: int, device="cuda"):
+        self.cfg = cfg
+        self.views = list(views)
+        self.ws = Workspace(cfg, n_gaussians, [v.cam for v in self.views], device=device)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+
+
+class RenderLoss(torch.autograd.Function):
+    """loss = RenderLoss.apply(mean, log_scale, quat, opacity_logit, rgb, pose_xi, session).
+    pose_xi [V,6] is a placeholder at zero (the poses live in the session's cameras); its gradient is
+    dL/dxi of the left perturbation T <- Exp(xi) T, translation first."""
+
+    @staticmethod
+    def forward(ctx, mean, log_scale, quat, opacity_logit, rgb, pose_xi, session: Session):
+        g = {"mean": mean, "log_scale": log_scale, "quat": quat, "opacity_logit": opacity_logit, "rgb": rgb}
+        render_fwd(session.cfg, g, session.views, session.ws, out_loss=session.loss)
+        ctx.session = session
+        ctx.save_for_backward(mean, log_scale, quat, opacity_logit, rgb)
+        return session.loss.clone().reshape(())
+
+    @staticmethod
+    def backward(ctx, gloss):
+        s = ctx.session
+        mean, log_scale, quat, opacity_logit, rgb = ctx.saved_tensors
+        g = {"mean": mean, "log_scale": log_scale, "quat": quat, "opacity_logit": opacity_logit, "rgb": rgb}
+        grads = zeros_like_gaussians(g)
+        dpose = torch.zeros(len(s.views), 6, dtype=torch.float32, device=mean.device)
+        scale = gloss.detach().to(torch.float32).reshape(1).contiguous()
+        render_bwd(s.cfg, g, s.views, s.ws, grads, dpose, loss_scale=scale)
+        return grads["mean"], grads["log_scale"], grads["quat"], grads["opacity_logit"], grads["rgb"], dpose, None
+
+
+class Render(torch.autograd.Function):
+    """rgb_0, depth_0, rgb_1, depth_1, ... = Render.apply(mean, log_scale, quat, opacity_logit, rgb, pose_xi,
+    session) for arbitrary downstream losses."""
+
+    @staticmethod
+    def forward(ctx, mean, log_scale, quat, opacity_logit, rgb, pose_xi, session: Session):
+        g = {"mean": mean, "log_scale": log_scale, "quat": quat, "opacity_logit": opacity_logit, "rgb": rgb}
+        render_fwd(session.cfg, g, session.views, session.ws)
+        ctx.session = session
+        ctx.save_for_backward(mean, log_scale, quat, opacity_logit, rgb)
+        outs = []
+        for v in session.views:
+            outs += [v.out_rgb.clone(), v.out_depth.clone()]
+        return tuple(outs)
+
+    @staticmethod
+    def backward(ctx, *gouts):
+        s = ctx.session
+        mean, log_scale, quat, opacity_logit, rgb = ctx.saved_tensors
+        g = {"mean": mean, "log_scale": log_scale, "quat": quat, "opacity_logit": opacity_logit, "rgb": rgb}
+        grads = zeros_like_gaussians(g)
+        dpose = torch.zeros(len(s.views), 6, dtype=torch.float32, device=mean.device)
+        drgb, ddep = [], []
+        for i, v in enumerate(s.views):
+            gr, gd = gouts[2 * i], gouts[2 * i + 1]
+            drgb.append((gr if gr is not None else torch.zeros_like(v.out_rgb)).contiguous())
+            ddep.append((gd if gd is not None else torch.zeros_like(v.out_depth)).contiguous())
+        render_bwd(s.cfg, g, s.views, s.ws, grads, dpose, dL_drgb=drgb, dL_ddepth=ddep)
+        return grads["mean"], grads["log_scale"], grads["quat"], grads["opacity_logit"], grads["rgb"], dpose, None

@@ -1,0 +1,42 @@
+"""Helpers shared by the GPU parity tests (input marshalling and comparisons only)."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import torch
+
+DEV = "cuda"
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def t(a):
+    return torch.as_tensor(np.ascontiguousarray(a, np.float32)).to(DEV)
+
+
+def h(x):
+    return x.detach().float().cpu().numpy()
+
+
+def normwise(a, b, mask=None):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    if mask is not None:
+        a, b = a[..., mask], b[..., mask]
+    den = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / den) if den > 0 else float(np.linalg.norm(a - b))
+
+
+def cfg_pair(P, O, mode=0, eps=0.02, tile=(16, 16, 256, 1), **kw):
+    gc = P.RenderCfg(tile_w=tile[0], tile_h=tile[1], batch=tile[2], pix_per_thread=tile[3], mode=mode,
+                     eps_cull=eps, **kw)
+    oc = O.RenderCfg(mode=mode, eps_cull=eps, **kw)
+    return gc, oc
+
+
+def gauss_dev(g):
+    return {k: t(v) for k, v in g.items()}

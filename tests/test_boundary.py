@@ -1,0 +1,132 @@
+"""The C-ABI library loads, exports every entry point include/gps.h declares, and
+rejects bad arguments synchronously, before touching the device (CPU only)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2509_11574_amd as P
+    if not os.path.exists(P.gps.LIB_PATH):
+        from paper_2509_11574_amd import build
+        build.build()
+    P.lib()
+    return P
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "gps.h")).read()
+    return sorted(set(re.findall(r"\b(gps_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_path_calls():
+    names = _declared()
+    for n in ("gps_fuse", "gps_raycast", "gps_render_fwd", "gps_render_bwd", "gps_adam_step"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(P):
+    L = P.lib()
+    for n in _declared():
+        assert hasattr(L, n), n
+    assert set(P.gps.EXPORTS) <= set(_declared())
+
+
+def test_abi_version_and_status_strings(P):
+    L = P.lib()
+    assert L.gps_abi_version() == 1
+    assert L.gps_status_string(0) == b"ok"
+    assert b"capacity" in L.gps_status_string(-3)
+
+
+def test_default_cfg(P):
+    c = P.gps.RenderCfgS()
+    P.lib().gps_render_cfg_default(ctypes.byref(c))
+    assert (c.tile_w, c.tile_h, c.batch, c.pix_per_thread, c.mode) == (16, 16, 256, 1, 0)
+    assert c.alpha_min == pytest.approx(1 / 255) and c.dilation == pytest.approx(0.3)
+
+
+def _cam(W=64, H=48):
+    return {"width": W, "height": H, "fx": 50.0, "fy": 50.0, "cx": W / 2, "cy": H / 2, "R": np.eye(3), "t": np.zeros(3)}
+
+
+def test_workspace_size_grows_with_work(P):
+    cfg = P.RenderCfg()
+    a = P.workspace_size(cfg, 1000, [_cam()])
+    b = P.workspace_size(cfg, 100000, [_cam()])
+    c = P.workspace_size(cfg, 1000, [_cam(), _cam(320, 240)])
+    assert 0 < a < b and a < c
+
+
+@pytest.mark.parametrize("field,value", [("tile_w", 12), ("batch", 100), ("pix_per_thread", 3)])
+def test_unsupported_tile_config(P, field, value):
+    cfg = P.RenderCfg()
+    setattr(cfg, field, value)
+    with pytest.raises(P.GpsError) as e:
+        P.workspace_size(cfg, 1000, [_cam()])
+    assert e.value.status == -6
+
+
+@pytest.mark.parametrize("field,value", [("mode", 2), ("alpha_min", 0.0), ("alpha_max", 1.0), ("z_near", 0.0),
+                                         ("eps_cull", float("nan")), ("max_instances", -5)])
+def test_invalid_cfg(P, field, value):
+    cfg = P.RenderCfg()
+    setattr(cfg, field, value)
+    with pytest.raises(P.GpsError) as e:
+        P.workspace_size(cfg, 1000, [_cam()])
+    assert e.value.status == -1
+
+
+def test_invalid_cameras_and_counts(P):
+    cfg = P.RenderCfg()
+    for bad in (_cam(0, 10), {**_cam(), "fx": 0.0}, {**_cam(), "cx": float("inf")}):
+        with pytest.raises(P.GpsError):
+            P.workspace_size(cfg, 10, [bad])
+    with pytest.raises(P.GpsError):
+        P.workspace_size(cfg, -1, [_cam()])
+    with pytest.raises(ValueError):
+        P.gps._views_array([])
+
+
+def test_null_pointers_rejected_before_launch(P):
+    L = P.lib()
+    cam = P.camera(_cam())
+    vol = P.gps.VolumeS()
+    vol.nx = vol.ny = vol.nz = 8
+    vol.voxel, vol.trunc, vol.max_weight = 0.1, 0.4, 100.0
+    assert L.gps_fuse(ctypes.byref(vol), ctypes.byref(cam), None, None, None) == -1
+    assert L.gps_raycast(ctypes.byref(vol), ctypes.byref(cam), 1, None, None, 0.2, 0.0, None) == -1
+    cfg = P.RenderCfg().struct()
+    g = P.gps.GaussiansS()
+    g.count = 10  # non-zero count with null arrays
+    v = (P.gps.ViewS * 1)()
+    assert L.gps_render_fwd(ctypes.byref(cfg), ctypes.byref(g), v, 1, None, 0, None, None) == -1
+    assert L.gps_render_bwd(ctypes.byref(cfg), ctypes.byref(g), v, 1, None, None, None, None, None, None, 0,
+                            None) == -1
+    grp = (P.gps.AdamGroupS * 1)()
+    grp[0].n = 5
+    assert L.gps_adam_step(grp, 1, 1, None, 0.9, 0.999, 1e-15, None) == -1
+    assert L.gps_adam_step(grp, 0, 1, None, 0.9, 0.999, 1e-15, None) == -1
+    assert L.gps_adam_step(grp, 9, 1, None, 0.9, 0.999, 1e-15, None) == -1
+    st = ctypes.c_int32(0)
+    assert L.gps_device_status(None, 0, ctypes.byref(st), None) == -1
+
+
+def test_oracle_and_product_are_independent():
+    """The product package never imports the reference implementation, and vice versa."""
+    pkg = os.path.join(ROOT, "paper_2509_11574_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert "oracle" not in re.sub(r"#.*|//.*", "", txt).lower() or f == "__init__.py", f
+    for f in os.listdir(os.path.join(ROOT, "oracle")):
+        if f.endswith((".py", ".c", ".h")):
+            txt = open(os.path.join(ROOT, "oracle", f)).read()
+            assert "paper_2509_11574_amd" not in txt and "gps.h" not in txt, f
