@@ -1,0 +1,283 @@
+#!/usr/bin/env python
+"""Per-frame mapping benchmark of the Gaussian-plus-SDF path on one MI355X.
+
+Workload (synthetic, seeded): a 2.56 m procedural room fused into a 256^3 TSDF
+at 1 cm, a smooth camera orbit of 1280x720 RGB-D frames with depth noise
+sigma = 1 mm * z^2, and 100,000 Gaussians seeded near the surfaces seen along
+the orbit.  One step = one frame: fuse the frame, raycast its view (the cached
+SDF base image), then 10 optimisation iterations of render forward (with the
+fused L1 colour + depth loss), backward (Gaussians and pose) and Adam.
+
+Prints one JSON line: iterations/s over the timed frames (value), ms per frame,
+the whole-iteration algorithmic HBM rate, the roofline of the dominant kernel
+(from per-kernel HIP-event times) and the reference implementation timed on
+this host's cores on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd+Adam iters/s @1280x720,100k Gaussians; ms/frame; HBM GB/s"
+ITERS_PER_FRAME = 10
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+
+# Algorithmic operation counts of the compositing kernels:
+# every evaluated (pixel, instance) pair costs 15 flops for the opacity of Eq. 3,
+# every composited pair 11 more in the forward and 66 more in the backward.
+FLOPS_EVAL = 15
+FLOPS_CONTRIB_FWD = 11
+FLOPS_CONTRIB_BWD = 66
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--gaussians", type=int, default=100_000)
+    ap.add_argument("--res", type=str, default="1280x720")
+    ap.add_argument("--volume", type=int, default=256)
+    ap.add_argument("--tile", type=str, default="16x16x256x1", help="tile_w x tile_h x batch x pixels_per_lane")
+    ap.add_argument("--mode", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported in this build "
+              "(the path shards by view across GPUs by design, but no multi-GPU run is made).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2509_11574_amd as P
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = "cuda:0"
+    torch.cuda.set_device(0)
+    W_img, H_img = (int(x) for x in args.res.split("x"))
+    tw, th, tb, ppt = (int(x) for x in args.tile.split("x"))
+    K, Wu, M = args.steps, args.warmup, args.gaussians
+    n_frames = Wu + 2 * K  # warmup, timed pass, profiled pass
+
+    # ---------------------------------------------------------------- inputs
+    t0 = time.time()
+    scene = synth.scene_room(args.volume)
+    cams = synth.orbit_cameras(0, W_img, H_img, frames=list(range(n_frames)))
+    frames = [synth.render_frame(scene, c, noise_sigma_per_m2=1e-3, frame_index=k, device=dev, as_torch=True)
+              for k, c in enumerate(cams)]
+    seed_cams = synth.orbit_cameras(0, W_img, H_img, frames=list(range(0, 100, 10)))
+    seed_depths = [synth.render_frame(scene, c, device=dev, as_torch=True)[0].cpu().numpy() for c in seed_cams]
+    gauss_np = synth.seed_gaussians(scene, seed_cams, seed_depths, M)
+    params = P.gaussians_to_device(gauss_np, dev)
+    torch.cuda.synchronize()
+    log(f"inputs ready in {time.time() - t0:.1f} s: {n_frames} frames {W_img}x{H_img}, {M} Gaussians, "
+        f"{args.volume}^3 volume")
+
+    vol = P.Volume(scene.dims, scene.origin, scene.voxel, scene.trunc, device=dev)
+    cfg = P.RenderCfg(tile_w=tw, tile_h=th, batch=tb, pix_per_thread=ppt, mode=args.mode, eps_cull=scene.voxel)
+    cam0 = cams[0].as_dict()
+    ws = P.Workspace(cfg, M, [cam0], device=dev)
+    base_depth = torch.empty(H_img, W_img, device=dev)
+    base_rgb = torch.empty(3, H_img, W_img, device=dev)
+    out_rgb = torch.empty(3, H_img, W_img, device=dev)
+    out_depth = torch.empty(H_img, W_img, device=dev)
+    loss = torch.zeros(1, device=dev)
+    grads = P.zeros_like_gaussians(params)
+    dpose = torch.zeros(1, 6, device=dev)
+    opt = P.Adam(params)
+
+    def frame_step(k):
+        cam = cams[k].as_dict()
+        depth, rgb = frames[k]
+        P.fuse(vol, cam, depth, rgb)
+        P.raycast(vol, [cam], z_near=cfg.z_near, out=[(base_depth, base_rgb)])
+        view = P.View(cam, base_rgb, base_depth, rgb, depth, out_rgb=out_rgb, out_depth=out_depth)
+        for _ in range(ITERS_PER_FRAME):
+            P.render_fwd(cfg, params, [view], ws, out_loss=loss)
+            P.render_bwd(cfg, params, [view], ws, grads, dpose)
+            opt.step(grads)
+
+    for k in range(Wu):
+        frame_step(k)
+    torch.cuda.synchronize()
+    st0 = ws.stats()
+    if st0["status"] != 0:
+        raise RuntimeError(f"device status {st0['status']} after warm-up: {st0}")
+    first_loss = float(loss.item())
+
+    # ------------------------------------------------------- timed frames
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_start = time.perf_counter()
+    ev0.record()
+    for k in range(Wu, Wu + K):
+        frame_step(k)
+    ev1.record()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_start
+    ms_event = ev0.elapsed_time(ev1)
+    st1 = ws.stats()
+    if st1["status"] != 0:
+        raise RuntimeError(f"device status {st1['status']}: {st1}")
+    ms_per_frame = 1000.0 * t_wall / K
+    iters_per_s = ITERS_PER_FRAME * K / t_wall
+    last_loss = float(loss.item())
+    log(f"timed {K} frames: {ms_per_frame:.3f} ms/frame (events {ms_event / K:.3f}), {iters_per_s:.1f} iters/s, "
+        f"loss {first_loss:.5f} -> {last_loss:.5f}, instances {st1['n_instances']}")
+
+    # --------------------------------------- per-kernel times (HIP events)
+    kernels, pairs = {}, None
+    if not args.no_profile:
+        stp0 = ws.stats()
+        P.gps.profile_start()
+        for k in range(Wu + K, Wu + 2 * K):
+            frame_step(k)
+        torch.cuda.synchronize()
+        P.gps.profile_stop()
+        kernels = P.gps.profile_read()
+        stp1 = ws.stats()
+        n_fwd = kernels.get("composite_fwd", (1, 0))[0]
+        pairs = {"eval_per_launch": (stp1["pairs_eval"] - stp0["pairs_eval"]) / n_fwd,
+                 "contrib_per_launch": (stp1["pairs_contrib"] - stp0["pairs_contrib"]) / n_fwd}
+    roofline = None
+    if kernels:
+        dom = max(kernels, key=lambda n: kernels[n][1])
+        launches, total = kernels[dom]
+        avg_s = total / launches / 1000.0
+        if dom in ("composite_fwd", "composite_bwd"):
+            per = FLOPS_CONTRIB_FWD if dom == "composite_fwd" else FLOPS_CONTRIB_BWD
+            flops = FLOPS_EVAL * pairs["eval_per_launch"] + per * pairs["contrib_per_launch"]
+            ach = flops / avg_s / 1e12
+            roofline = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                        "avg_launch_ms": round(avg_s * 1e3, 4), "flops_per_launch": flops}
+        else:
+            roofline = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": None, "traffic": None, "avg_launch_ms": round(avg_s * 1e3, 4)}
+
+    # ------------------------------ whole-iteration algorithmic HBM bytes
+    I = st1["n_instances"]
+    Pp = W_img * H_img
+    bytes_iter = (56 * M + 48 * M + 8 * M            # project: params in, records + counts out
+                  + 12 * I + 8 * M + 16 * I          # emit (keys, slots), tile sort (read + write)
+                  + 60 * I + 48 * Pp                 # composite fwd: keys/slots/records, base+target+out
+                  + 60 * I + 40 * I + 64 * Pp        # composite bwd: instances, partials out, per-pixel in
+                  + 40 * I + 112 * M + 8 * M         # per-Gaussian reduce: partials, params in, grads out
+                  + 392 * M)                         # Adam: 14 scalars x 28 B
+    iter_ms = None
+    if kernels:
+        it_kernels = ("prep", "project", "scan", "emit", "tile_sort", "composite_fwd", "loss_reduce",
+                      "composite_bwd", "gauss_bwd", "pose_reduce", "adam", "step_incr")
+        iter_ms = sum(kernels[n][1] for n in it_kernels if n in kernels) / (K * ITERS_PER_FRAME)
+    hbm_gbs = bytes_iter / (iter_ms / 1e3) / 1e9 if iter_ms else None
+
+    # ------------------------------- reference implementation on the host
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scene, cams[Wu], frames[Wu], gauss_np, cfg)
+
+    out = {"metric": METRIC, "value": round(iters_per_s, 2), "unit": "iters/s", "n_gpus": 1, "steps": K,
+           "warmup": Wu, "ms_per_step": round(ms_per_frame, 4), "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"plain per-frame mapping: {args.volume}^3 TSDF at {scene.voxel * 100:.3g} cm, "
+                                  f"{W_img}x{H_img} orbit frames, {M} Gaussians, {ITERS_PER_FRAME} iterations/frame",
+                      "tile": args.tile, "mode": "sorted" if args.mode == 0 else "sort-free",
+                      "graph": False},
+           "ms_per_frame": round(ms_per_frame, 4),
+           "ms_per_iteration_kernels": round(iter_ms, 4) if iter_ms else None,
+           "hbm_gbs_iteration": round(hbm_gbs, 1) if hbm_gbs else None,
+           "instances": I, "pairs": pairs,
+           "loss_first_last": [round(first_loss, 6), round(last_loss, 6)],
+           "roofline": roofline,
+           "kernels_ms_per_frame": {n: round(v[1] / K, 4) for n, v in sorted(kernels.items(), key=lambda x: -x[1][1])},
+           "cpu_baseline": cpu}
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(scene, cam, frame, gauss_np, cfg):
+    """The reference implementation, as it stands, on this host: one fusion of the
+    full volume, the raycast of every 8th pixel in each direction and one
+    forward + backward of every 16th, scaled to a whole frame of the same
+    workload (fusion + raycast + 10 iterations); Adam over all parameters."""
+    import numpy as np
+
+    from oracle import oracle as O
+
+    depth = frame[0].cpu().numpy()
+    rgb = frame[1].cpu().numpy()
+    camd = cam.as_dict()
+    H, W = depth.shape
+    Pp = W * H
+    grid = O.make_grid(scene.dims, scene.origin, scene.voxel, scene.trunc, 100.0)
+    vol = O.new_volume(grid)
+    t = time.perf_counter()
+    O.fuse(grid, vol, camd, depth, rgb)
+    t_fuse = time.perf_counter() - t
+    t32, c32 = vol["tsdf"].astype(np.float32), vol["rgb"].astype(np.float32)
+    jj, ii = np.meshgrid(np.arange(0, H, 8), np.arange(0, W, 8), indexing="ij")
+    pix_r = (jj * W + ii).reshape(-1).astype(np.int32)
+    t = time.perf_counter()
+    rd, rc, _ = O.raycast(grid, t32, c32, camd, z_near=cfg.z_near, pix=pix_r)
+    t_ray = (time.perf_counter() - t) * Pp / pix_r.size
+    bd = np.zeros(Pp, np.float32)
+    bc = np.zeros((3, Pp), np.float32)
+    bd[pix_r] = rd
+    bc[:, pix_r] = rc
+    jj, ii = np.meshgrid(np.arange(0, H, 16), np.arange(0, W, 16), indexing="ij")
+    pix_f = (jj * W + ii).reshape(-1).astype(np.int32)
+    ocfg = O.RenderCfg(mode=cfg.mode, eps_cull=cfg.eps_cull)
+    t = time.perf_counter()
+    r = O.render(ocfg, gauss_np, camd, bc, bd, pix=pix_f)
+    t_fwd = time.perf_counter() - t
+    gC = np.sign(r["rgb"] - rgb.reshape(3, -1)[:, pix_f]) / (3.0 * Pp)
+    gD = np.where((depth.reshape(-1)[pix_f] > 0) & (bd[pix_f] > 0), np.sign(r["depth"] - depth.reshape(-1)[pix_f]), 0)
+    gD = gD / max(1, int(((depth.reshape(-1) > 0) & (bd > 0)).sum()))
+    t = time.perf_counter()
+    O.render_bwd(ocfg, gauss_np, camd, bc, bd, gC, gD, pix=pix_f)
+    t_bwd = time.perf_counter() - t
+    t = time.perf_counter()
+    for k, v in gauss_np.items():
+        a = v.astype(np.float64).reshape(-1).copy()
+        O.adam(a, np.ones_like(a), np.zeros_like(a), np.zeros_like(a), O.PAPER_LR[k], 1)
+    t_adam = time.perf_counter() - t
+    scale = Pp / pix_f.size
+    t_iter = (t_fwd + t_bwd) * scale + t_adam
+    t_frame = t_fuse + t_ray + ITERS_PER_FRAME * t_iter
+    return {"value": round(ITERS_PER_FRAME / t_frame, 5), "unit": "iters/s", "cores": 1, "kind": "oracle",
+            "ms_per_frame": round(1e3 * t_frame, 1), "ms_per_iteration": round(1e3 * t_iter, 1),
+            "sample": f"FP64 C reference, 1 thread: full-volume fusion ({t_fuse:.2f} s), raycast of "
+                      f"{pix_r.size} px scaled x{Pp / pix_r.size:.0f}, forward+backward of {pix_f.size} px "
+                      f"({t_fwd + t_bwd:.2f} s) scaled x{scale:.0f}, Adam over all parameters",
+            "cpu": _cpu_model()}
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+if __name__ == "__main__":
+    main()

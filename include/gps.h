@@ -135,6 +135,9 @@ typedef struct gps_stats {
     int64_t capacity;          /* instances the workspace holds                   */
     int64_t sort_fallback;     /* tiles longer than the LDS sort holds            */
     int64_t n_tiles;
+    int64_t pairs_eval;        /* (pixel, instance) opacity evaluations, summed over
+                                  every forward since gps_workspace_reset          */
+    int64_t pairs_contrib;     /* of those, pairs composited into the pixel        */
     float loss;                /* last forward's loss                             */
     float view_omega[GPS_MAX_VIEWS]; /* |Omega_v|: pixels in each view's depth term */
 } gps_stats;
@@ -231,6 +234,23 @@ gps_status gps_device_status(const void* ws, size_t ws_bytes, int32_t* out_statu
 
 /* Reads the counters of the last render call (synchronises `stream`). */
 gps_status gps_read_stats(const void* ws, size_t ws_bytes, gps_stats* out, void* stream);
+
+/* ---- Optional per-kernel timing (not part of the mapping path) ----------
+ * While profiling is on for the calling thread, every kernel the library
+ * launches from that thread is bracketed by two HIP events recorded on its
+ * launch stream.  gps_profile_read synchronises those events and returns, per
+ * kernel name, the number of launches and the summed event time since the last
+ * gps_profile_start.  State is thread-local; events are created on first use
+ * and kept until the thread exits. */
+typedef struct gps_kernel_time {
+    char name[32];
+    int64_t launches;
+    double total_ms;
+} gps_kernel_time;
+
+gps_status gps_profile_start(void);
+gps_status gps_profile_stop(void);
+gps_status gps_profile_read(gps_kernel_time* out, int32_t max_kernels, int32_t* n_out);
 
 #ifdef __cplusplus
 }

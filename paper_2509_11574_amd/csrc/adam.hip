@@ -3,6 +3,7 @@
 // scalar reads param, grad, m, v and writes param, m, v (28 bytes).  Groups
 // whose arrays are 16-byte aligned with n % 4 == 0 are processed as float4.
 #include "gps_internal.h"
+#include "prof.h"
 
 namespace gps {
 
@@ -100,9 +101,9 @@ gps_status launch_adam(const gps_adam_group* groups, int n_groups, int step, int
     if (total > 0) {
         long long blocks = (total + 255) / 256;
         if (blocks > 4096) blocks = 4096;
-        hipLaunchKernelGGL(k_adam, dim3((unsigned)blocks), dim3(256), 0, s, a);
+        GPS_LAUNCH(K_ADAM, s, k_adam, dim3((unsigned)blocks), dim3(256), 0, s, a);
     }
-    if (step_counter) hipLaunchKernelGGL(k_step_incr, dim3(1), dim3(64), 0, s, step_counter);
+    if (step_counter) GPS_LAUNCH(K_STEP_INCR, s, k_step_incr, dim3(1), dim3(64), 0, s, step_counter);
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
 }
 

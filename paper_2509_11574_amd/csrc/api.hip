@@ -6,6 +6,7 @@
 #include <cstring>
 
 #include "gps_internal.h"
+#include "prof.h"
 
 namespace gps {
 bool tile_config_supported(const gps_render_cfg* cfg);
@@ -178,7 +179,7 @@ __global__ void __launch_bounds__(256) k_ws_reset(char* ws)
 
 gps_status launch_ws_reset(char* ws, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_ws_reset, dim3(1), dim3(256), 0, s, ws);
+    GPS_LAUNCH(K_WS_RESET, s, k_ws_reset, dim3(1), dim3(256), 0, s, ws);
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
 }
 
@@ -356,6 +357,8 @@ gps_status gps_read_stats(const void* ws, size_t ws_bytes, gps_stats* out, void*
     out->n_instances = (int64_t)h.n_inst;
     out->sort_fallback = (int64_t)h.n_fallback;
     out->capacity = (int64_t)h.cap;
+    out->pairs_eval = (int64_t)h.pairs_eval;
+    out->pairs_contrib = (int64_t)h.pairs_contrib;
     out->n_tiles = h.n_tiles;
     out->loss = h.loss;
     for (int v = 0; v < GPS_MAX_VIEWS; ++v) out->view_omega[v] = h.view_stats[v][2];

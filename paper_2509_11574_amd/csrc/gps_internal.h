@@ -69,6 +69,8 @@ struct WsHeader {
     unsigned long long n_inst;     // instances emitted by the last forward
     unsigned long long n_fallback; // tiles sorted by the global-memory fallback
     unsigned long long cap;        // instance capacity of the last forward
+    unsigned long long pairs_eval;     // (pixel, instance) opacity evaluations of every forward since reset
+    unsigned long long pairs_contrib;  // of those, pairs composited (alpha >= alpha_min, before a stop)
     float loss;
     int n_views;
     int n_tiles;

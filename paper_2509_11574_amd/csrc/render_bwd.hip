@@ -11,6 +11,7 @@
 //       parameters and form the per-Gaussian pose terms, reduced per block.
 //   k_pose_reduce per view: sum the block pose partials in order.
 // No floating-point atomics: results are bitwise reproducible.
+#include "prof.h"
 #include "render_common.h"
 
 namespace gps {
@@ -450,7 +451,7 @@ template <int TW, int TH, int B, int PPT>
 static void launch_cbwd(const ViewTable& vt, const RParams& rp, const WsPtrs& w, int n_tiles, int explicit_up,
                         const float* loss_scale, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_composite_bwd<TW, TH, B, PPT>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, vt, rp, w,
+    GPS_LAUNCH(K_COMPOSITE_BWD, s, (k_composite_bwd<TW, TH, B, PPT>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, vt, rp, w,
                        explicit_up, loss_scale);
 }
 
@@ -495,8 +496,8 @@ gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const
     GGrads gg{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->rgb};
     if (!dispatch_cbwd(cfg, vt, rp, w, L.n_tiles, explicit_upstream, loss_scale, s)) return GPS_ERR_UNSUPPORTED_CONFIG;
     if (L.nblk_g > 0) {
-        hipLaunchKernelGGL(k_gauss_bwd, dim3(L.nblk_g), dim3(kBlk), 0, s, vt, rp, gp, gg, w);
-        if (dpose) hipLaunchKernelGGL(k_pose_reduce, dim3(vt.n), dim3(256), 0, s, rp, w, L.nblk_g, dpose);
+        GPS_LAUNCH(K_GAUSS_BWD, s, k_gauss_bwd, dim3(L.nblk_g), dim3(kBlk), 0, s, vt, rp, gp, gg, w);
+        if (dpose) GPS_LAUNCH(K_POSE_REDUCE, s, k_pose_reduce, dim3(vt.n), dim3(256), 0, s, rp, w, L.nblk_g, dpose);
     }
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
 }

@@ -14,6 +14,7 @@
 //   k_composite_fwd<TW,TH,B,PPT>  per tile: LDS-staged batches of B records,
 //                front-to-back compositing, loss partial per tile
 //   k_loss_reduce  one block: per-view and total loss
+#include "prof.h"
 #include "render_common.h"
 
 namespace gps {
@@ -367,6 +368,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(ViewTable vt, R
 
     float thr[PPT], T[PPT], ac0[PPT], ac1[PPT], ac2[PPT], ad[PPT];
     bool done[PPT];
+    unsigned int n_eval = 0, n_contrib = 0;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int py = py0 + k * ROWS;
@@ -405,6 +407,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(ViewTable vt, R
                     continue;
                 }
                 const AlphaEval ae = eval_alpha(fpx, (float)(py0 + k * ROWS), r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
+                ++n_eval;
                 if (rp.mode == 0) {
                     const float a = fminf(rp.amax, ae.raw);
                     if (a < rp.amin) continue;
@@ -413,6 +416,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(ViewTable vt, R
                         done[k] = true;
                         continue;
                     }
+                    ++n_contrib;
                     const float wgt = a * T[k];
                     ac0[k] = __builtin_fmaf(wgt, r1.w, ac0[k]);
                     ac1[k] = __builtin_fmaf(wgt, r2.x, ac1[k]);
@@ -422,6 +426,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(ViewTable vt, R
                 } else {
                     const float a = ae.raw;
                     if (a < rp.amin) continue;
+                    ++n_contrib;
                     T[k] += a;  // W_G
                     ac0[k] = __builtin_fmaf(a, r1.w, ac0[k]);
                     ac1[k] = __builtin_fmaf(a, r2.x, ac1[k]);
@@ -475,7 +480,14 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(ViewTable vt, R
     lc = block_sum<NT>(lc);
     ld = block_sum<NT>(ld);
     lo = block_sum<NT>(lo);
-    if (threadIdx.x == 0) w.tile_loss[tile] = make_float4(lc, ld, lo, 0.0f);
+    unsigned int tot_eval, tot_contrib;
+    block_excl_scan<NT>(n_eval, &tot_eval);
+    block_excl_scan<NT>(n_contrib, &tot_contrib);
+    if (threadIdx.x == 0) {
+        w.tile_loss[tile] = make_float4(lc, ld, lo, 0.0f);
+        atomicAdd(&w.hdr->pairs_eval, (unsigned long long)tot_eval);  // integer: order-independent
+        atomicAdd(&w.hdr->pairs_contrib, (unsigned long long)tot_contrib);
+    }
 }
 
 // ------------------------------------------------------------ loss reduce
@@ -516,7 +528,7 @@ __global__ void __launch_bounds__(256) k_loss_reduce(ViewTable vt, RParams rp, W
 template <int TW, int TH, int B, int PPT>
 static void launch_cfwd(const ViewTable& vt, const RParams& rp, const WsPtrs& w, int n_tiles, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_composite_fwd<TW, TH, B, PPT>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, vt, rp, w);
+    GPS_LAUNCH(K_COMPOSITE_FWD, s, (k_composite_fwd<TW, TH, B, PPT>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, vt, rp, w);
 }
 
 #define GPS_TILE_CONFIGS(X) \
@@ -568,13 +580,13 @@ gps_status launch_render_fwd(const gps_render_cfg* cfg, const RParams& rp, const
     int has_loss = 1;
     for (int v = 0; v < vt.n; ++v)
         if (!vt.v[v].target_rgb) has_loss = 0;
-    hipLaunchKernelGGL(k_prep, dim3(L.n_tiles), dim3(256), 0, s, vt, rp, w);
-    if (L.nblk_vg > 0) hipLaunchKernelGGL(k_project, dim3(L.nblk_vg), dim3(kBlk), 0, s, vt, rp, gp, w);
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, rp, w, L.nblk_vg, L.n_tiles);
-    if (L.nblk_vg > 0) hipLaunchKernelGGL(k_emit, dim3(L.nblk_vg), dim3(kBlk), 0, s, vt, rp, w);
-    hipLaunchKernelGGL(k_tile_sort, dim3(L.n_tiles), dim3(256), 0, s, rp, w);
+    GPS_LAUNCH(K_PREP, s, k_prep, dim3(L.n_tiles), dim3(256), 0, s, vt, rp, w);
+    if (L.nblk_vg > 0) GPS_LAUNCH(K_PROJECT, s, k_project, dim3(L.nblk_vg), dim3(kBlk), 0, s, vt, rp, gp, w);
+    GPS_LAUNCH(K_SCAN, s, k_scan, dim3(1), dim3(1024), 0, s, rp, w, L.nblk_vg, L.n_tiles);
+    if (L.nblk_vg > 0) GPS_LAUNCH(K_EMIT, s, k_emit, dim3(L.nblk_vg), dim3(kBlk), 0, s, vt, rp, w);
+    GPS_LAUNCH(K_TILE_SORT, s, k_tile_sort, dim3(L.n_tiles), dim3(256), 0, s, rp, w);
     if (!dispatch_cfwd(cfg, vt, rp, w, L.n_tiles, s)) return GPS_ERR_UNSUPPORTED_CONFIG;
-    hipLaunchKernelGGL(k_loss_reduce, dim3(1), dim3(256), 0, s, vt, rp, w, out_loss, has_loss);
+    GPS_LAUNCH(K_LOSS_REDUCE, s, k_loss_reduce, dim3(1), dim3(256), 0, s, vt, rp, w, out_loss, has_loss);
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
 }
 

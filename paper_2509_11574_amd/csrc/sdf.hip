@@ -15,6 +15,7 @@
 #include <cmath>
 
 #include "gps_internal.h"
+#include "prof.h"
 
 namespace gps {
 
@@ -124,7 +125,7 @@ gps_status launch_fuse(const gps_volume* vol, const gps_camera* cam, const float
     a.col = vol->rgb;
     a.cw = vol->rgb_weight;
     unsigned int blocks = (a.N + 255u) / 256u;
-    hipLaunchKernelGGL(k_fuse, dim3(blocks), dim3(256), 0, s, a);
+    GPS_LAUNCH(K_FUSE, s, k_fuse, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
 }
 
@@ -446,11 +447,11 @@ gps_status launch_raycast(const gps_volume* vol, const gps_camera* cams, int n_v
     }
     if (vol->brick_min) {
         BrickArgs b{vol->nx, vol->ny, vol->nz, a.bx, a.by, a.bz, vol->tsdf, vol->brick_min};
-        hipLaunchKernelGGL(k_brick_min, dim3(a.bx * a.by * a.bz), dim3(256), 0, s, b);
+        GPS_LAUNCH(K_BRICK_MIN, s, k_brick_min, dim3(a.bx * a.by * a.bz), dim3(256), 0, s, b);
         if (hipGetLastError() != hipSuccess) return GPS_ERR_HIP;
     }
     dim3 grid((maxW + 15) / 16, (maxH + 15) / 16, n_views);
-    hipLaunchKernelGGL(k_raycast, grid, dim3(256), 0, s, a);
+    GPS_LAUNCH(K_RAYCAST, s, k_raycast, grid, dim3(256), 0, s, a);
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
 }
 

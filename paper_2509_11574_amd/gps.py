@@ -70,12 +70,18 @@ class AdamGroupS(ctypes.Structure):
 class StatsS(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("n_views", ctypes.c_int32), ("n_instances", ctypes.c_int64),
                 ("capacity", ctypes.c_int64), ("sort_fallback", ctypes.c_int64), ("n_tiles", ctypes.c_int64),
+                ("pairs_eval", ctypes.c_int64), ("pairs_contrib", ctypes.c_int64),
                 ("loss", ctypes.c_float), ("view_omega", ctypes.c_float * MAX_VIEWS)]
+
+
+class KernelTimeS(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
 EXPORTS = ["gps_abi_version", "gps_status_string", "gps_render_cfg_default", "gps_workspace_size",
            "gps_workspace_reset", "gps_fuse", "gps_raycast", "gps_render_fwd", "gps_render_bwd",
-           "gps_adam_step", "gps_device_status", "gps_read_stats"]
+           "gps_adam_step", "gps_device_status", "gps_read_stats", "gps_profile_start", "gps_profile_stop",
+           "gps_profile_read"]
 
 _lib = None
 
@@ -103,6 +109,9 @@ def lib():
         L.gps_adam_step.argtypes = [P, I32, I32, P, F, F, F, P]
         L.gps_device_status.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(I32), P]
         L.gps_read_stats.argtypes = [P, ctypes.c_size_t, P, P]
+        L.gps_profile_start.argtypes = []
+        L.gps_profile_stop.argtypes = []
+        L.gps_profile_read.argtypes = [P, I32, ctypes.POINTER(I32)]
         for n in EXPORTS:
             if n not in ("gps_render_cfg_default", "gps_status_string", "gps_abi_version"):
                 getattr(L, n).restype = I32
@@ -275,6 +284,25 @@ def raycast(vol: Volume, cams, z_near=0.2, step=0.0, out=None, stream=None):
 
 
 # --------------------------------------------------------------------------- #
+# Per-kernel timing (HIP events on the launch stream, thread-local)            #
+# --------------------------------------------------------------------------- #
+def profile_start():
+    _check(lib().gps_profile_start(), "gps_profile_start")
+
+
+def profile_stop():
+    _check(lib().gps_profile_stop(), "gps_profile_stop")
+
+
+def profile_read() -> dict:
+    """{kernel name: (launches, total ms)} since profile_start (synchronises the recorded events)."""
+    arr = (KernelTimeS * 32)()
+    n = ctypes.c_int32(0)
+    _check(lib().gps_profile_read(arr, 32, ctypes.byref(n)), "gps_profile_read")
+    return {arr[i].name.decode(): (int(arr[i].launches), float(arr[i].total_ms)) for i in range(n.value)}
+
+
+# --------------------------------------------------------------------------- #
 # Render                                                                       #
 # --------------------------------------------------------------------------- #
 @dataclass
@@ -338,6 +366,7 @@ class Workspace:
         _check(lib().gps_read_stats(self.ptr(), self.nbytes, ctypes.byref(s), _stream(stream)), "gps_read_stats")
         return {"status": s.status, "n_views": s.n_views, "n_instances": s.n_instances, "capacity": s.capacity,
                 "sort_fallback": s.sort_fallback, "n_tiles": s.n_tiles, "loss": s.loss,
+                "pairs_eval": s.pairs_eval, "pairs_contrib": s.pairs_contrib,
                 "view_omega": list(s.view_omega)[:max(s.n_views, 0)]}
 
 
