@@ -131,7 +131,9 @@ typedef struct gps_adam_group {
 typedef struct gps_stats {
     int32_t status;            /* sticky status word                              */
     int32_t n_views;
-    int64_t n_instances;       /* tile instances emitted by the last forward      */
+    int64_t n_instances;       /* tile slots of the last forward: the screen tiles
+                                  covered by the support boxes (before the depth
+                                  cull); the capacity bounds this number          */
     int64_t capacity;          /* instances the workspace holds                   */
     int64_t sort_fallback;     /* tiles longer than the LDS sort holds            */
     int64_t n_tiles;

@@ -14,8 +14,11 @@ enum KernelId {
     K_PREP,
     K_PROJECT,
     K_SCAN,
+    K_TILE_COUNT,
+    K_SCAN_TILES,
     K_EMIT,
     K_TILE_SORT,
+    K_TILE_SORT_LARGE,
     K_COMPOSITE_FWD,
     K_LOSS_REDUCE,
     K_COMPOSITE_BWD,

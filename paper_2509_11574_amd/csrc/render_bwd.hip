@@ -22,12 +22,13 @@ template <int TW, int TH, int B, int PPT>
 __global__ void __launch_bounds__(TW * TH / PPT)
     k_composite_bwd(ViewTable vt, RParams rp, WsPtrs w, int explicit_up, const float* loss_scale)
 {
-    constexpr int NT = TW * TH / PPT;
-    constexpr int NW = NT / 64;
-    constexpr int ROWS = TH / PPT;
+    using Lay = TileLayout<TW, TH, PPT>;
+    constexpr int NT = Lay::NT;
+    constexpr int NW = Lay::NW;
     __shared__ float4 srec[3 * B];
     __shared__ unsigned int sslot[B];
     __shared__ float slab[B * NW * kAdj];
+    __shared__ unsigned char sact[B * NW];  // 1 when the wavefront wrote its partial of record j
     if (w.hdr->n_inst > rp.cap) return;
     const int tile = blockIdx.x;
     const int v = find_view(vt, tile);
@@ -36,10 +37,13 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
     const int Wd = V.cam.W, Ht = V.cam.H;
     const size_t HW = (size_t)Wd * Ht;
-    const int px = tx * TW + (int)(threadIdx.x % TW);
-    const int py0 = ty * TH + (int)(threadIdx.x / TW);
-    const float fpx = (float)px;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int wx0 = tx * TW + Lay::wave_x0(wid), wy0 = ty * TH + Lay::wave_y0(wid);
+    const float fwx0 = (float)wx0, fwx1 = (float)(wx0 + Lay::WW - 1);
+    const float fwy0 = (float)wy0, fwy1 = (float)(wy0 + Lay::WH - 1);
+    const int px = wx0 + Lay::lane_x(lane);
+    const int py0 = wy0 + Lay::lane_y(lane);
+    const float fpx = (float)px;
 
     float sc = 1.0f;
     if (!explicit_up && loss_scale) sc = *loss_scale;
@@ -51,7 +55,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     bool done[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const int py = py0 + k * ROWS;
+        const int py = py0 + k * Lay::LROWS;
         const bool inb = px < Wd && py < Ht;
         const size_t p = inb ? (size_t)py * Wd + px : 0;
         const float dt = inb ? V.base_depth[p] : 0.0f;
@@ -107,80 +111,85 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         __syncthreads();
         const int n = (int)min((unsigned int)B, e - b);
         for (int j = 0; j < n; ++j) {
-            const float4 r0 = srec[3 * j], r1 = srec[3 * j + 1], r2 = srec[3 * j + 2];
-            const float c0 = r1.w, c1 = r2.x, c2 = r2.y, zi = r1.z;
+            const float4 r0 = srec[3 * j], r2 = srec[3 * j + 2];
+            bool act = false;
             float g[kAdj];
 #pragma unroll
             for (int q = 0; q < kAdj; ++q) g[q] = 0.0f;
-            bool act = false;
+            // Same wavefront-level skip as the forward: no pixel of this wavefront is in the box.
+            const bool miss = r0.x + r2.z < fwx0 || r0.x - r2.z > fwx1 || r0.y + r2.w < fwy0 || r0.y - r2.w > fwy1;
+            if (!miss) {
+                const float4 r1 = srec[3 * j + 1];
+                const float c0 = r1.w, c1 = r2.x, c2 = r2.y, zi = r1.z;
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                if (done[k]) continue;
-                if (!(zi < thr[k])) {
-                    done[k] = true;
-                    continue;
-                }
-                const AlphaEval ae = eval_alpha(fpx, (float)(py0 + k * ROWS), r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
-                float a, dal;
-                bool alpha_path;
-                if (rp.mode == 0) {
-                    a = fminf(rp.amax, ae.raw);
-                    if (a < rp.amin) continue;
-                    const float Tn = T[k] * (1.0f - a);
-                    if (Tn < rp.Tmin) {
+                for (int k = 0; k < PPT; ++k) {
+                    if (done[k]) continue;
+                    if (!(zi < thr[k])) {
                         done[k] = true;
                         continue;
                     }
-                    const float wgt = a * T[k];
-                    P0[k] = __builtin_fmaf(wgt, c0, P0[k]);
-                    P1[k] = __builtin_fmaf(wgt, c1, P1[k]);
-                    P2[k] = __builtin_fmaf(wgt, c2, P2[k]);
-                    PD[k] = __builtin_fmaf(wgt, zi, PD[k]);
-                    g[6] += wgt * G0[k];
-                    g[7] += wgt * G1[k];
-                    g[8] += wgt * G2[k];
-                    g[9] += wgt * GD[k];
-                    const float direct = G0[k] * c0 + G1[k] * c1 + G2[k] * c2 + GD[k] * zi;
-                    const float rest = G0[k] * (Cs0[k] - P0[k]) + G1[k] * (Cs1[k] - P1[k]) +
-                                       G2[k] * (Cs2[k] - P2[k]) + GD[k] * (Ds[k] - PD[k]);
-                    dal = T[k] * direct - rest / (1.0f - a);
-                    alpha_path = ae.raw <= rp.amax;
-                    T[k] = Tn;
-                } else {
-                    a = ae.raw;
-                    if (a < rp.amin) continue;
-                    const float inv = 1.0f / (1.0f + Wg[k]);
-                    const float ai = a * inv;
-                    g[6] += ai * G0[k];
-                    g[7] += ai * G1[k];
-                    g[8] += ai * G2[k];
-                    g[9] += ai * GD[k];
-                    dal = inv * (G0[k] * (c0 - Cs0[k]) + G1[k] * (c1 - Cs1[k]) + G2[k] * (c2 - Cs2[k]) +
-                                 GD[k] * (zi - Ds[k]));
-                    alpha_path = true;
-                }
-                act = true;
-                if (alpha_path) {
-                    const float dp = dal * a;  // d alpha / d power = alpha
-                    g[5] += dal * ae.e;        // d alpha / d sigma = exp(power)
-                    g[0] += dp * (r0.z * ae.dx + r0.w * ae.dy);
-                    g[1] += dp * (r0.w * ae.dx + r1.x * ae.dy);
-                    g[2] += -0.5f * dp * ae.dx * ae.dx;
-                    g[3] += -dp * ae.dx * ae.dy;
-                    g[4] += -0.5f * dp * ae.dy * ae.dy;
+                    const AlphaEval ae =
+                        eval_alpha(fpx, (float)(py0 + k * Lay::LROWS), r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
+                    float a, dal;
+                    bool alpha_path;
+                    if (rp.mode == 0) {
+                        a = fminf(rp.amax, ae.raw);
+                        if (a < rp.amin) continue;
+                        const float Tn = T[k] * (1.0f - a);
+                        if (Tn < rp.Tmin) {
+                            done[k] = true;
+                            continue;
+                        }
+                        const float wgt = a * T[k];
+                        P0[k] = __builtin_fmaf(wgt, c0, P0[k]);
+                        P1[k] = __builtin_fmaf(wgt, c1, P1[k]);
+                        P2[k] = __builtin_fmaf(wgt, c2, P2[k]);
+                        PD[k] = __builtin_fmaf(wgt, zi, PD[k]);
+                        g[6] += wgt * G0[k];
+                        g[7] += wgt * G1[k];
+                        g[8] += wgt * G2[k];
+                        g[9] += wgt * GD[k];
+                        const float direct = G0[k] * c0 + G1[k] * c1 + G2[k] * c2 + GD[k] * zi;
+                        const float rest = G0[k] * (Cs0[k] - P0[k]) + G1[k] * (Cs1[k] - P1[k]) +
+                                           G2[k] * (Cs2[k] - P2[k]) + GD[k] * (Ds[k] - PD[k]);
+                        dal = T[k] * direct - rest / (1.0f - a);
+                        alpha_path = ae.raw <= rp.amax;
+                        T[k] = Tn;
+                    } else {
+                        a = ae.raw;
+                        if (a < rp.amin) continue;
+                        const float inv = 1.0f / (1.0f + Wg[k]);
+                        const float ai = a * inv;
+                        g[6] += ai * G0[k];
+                        g[7] += ai * G1[k];
+                        g[8] += ai * G2[k];
+                        g[9] += ai * GD[k];
+                        dal = inv * (G0[k] * (c0 - Cs0[k]) + G1[k] * (c1 - Cs1[k]) + G2[k] * (c2 - Cs2[k]) +
+                                     GD[k] * (zi - Ds[k]));
+                        alpha_path = true;
+                    }
+                    act = true;
+                    if (alpha_path) {
+                        const float dp = dal * a;  // d alpha / d power = alpha
+                        g[5] += dal * ae.e;        // d alpha / d sigma = exp(power)
+                        g[0] += dp * (r0.z * ae.dx + r0.w * ae.dy);
+                        g[1] += dp * (r0.w * ae.dx + r1.x * ae.dy);
+                        g[2] += -0.5f * dp * ae.dx * ae.dx;
+                        g[3] += -dp * ae.dx * ae.dy;
+                        g[4] += -0.5f * dp * ae.dy * ae.dy;
+                    }
                 }
             }
-            float* dst = slab + (j * NW + wid) * kAdj;
-            if (wave_any(act)) {
+            const bool wact = wave_any(act);
+            if (wact) {
+                float* dst = slab + (j * NW + wid) * kAdj;
 #pragma unroll
                 for (int q = 0; q < kAdj; ++q) {
                     const float t = wave_sum_to_lane63(g[q]);
                     if (lane == 63) dst[q] = t;
                 }
-            } else if (lane == 0) {
-#pragma unroll
-                for (int q = 0; q < kAdj; ++q) dst[q] = 0.0f;
             }
+            if (lane == 0) sact[j * NW + wid] = wact ? 1 : 0;
         }
         __syncthreads();
         for (int t = threadIdx.x; t < n; t += NT) {
@@ -188,9 +197,11 @@ __global__ void __launch_bounds__(TW * TH / PPT)
 #pragma unroll
             for (int q = 0; q < kAdj; ++q) acc[q] = 0.0f;
 #pragma unroll
-            for (int ww = 0; ww < NW; ++ww)
+            for (int ww = 0; ww < NW; ++ww) {
+                if (!sact[t * NW + ww]) continue;
 #pragma unroll
                 for (int q = 0; q < kAdj; ++q) acc[q] += slab[(t * NW + ww) * kAdj + q];
+            }
             if (sslot[t] < rp.cap) {
                 float* out = w.partial + (size_t)sslot[t] * kAdj;
 #pragma unroll
@@ -268,13 +279,27 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(ViewTable vt, RParams rp, GP
         const unsigned int o = cnt ? w.off[vg] : 0u;
         if ((unsigned long long)o + cnt > w.hdr->n_inst) cnt = 0u;  // guard: stay inside the emitted slots
         if (cnt > 0) {
+            // The Gaussian's slots are its tile rectangle in row order; the slots of the
+            // tiles that passed the depth cull hold partials (the same test as the emission).
+            const DevView& VV = vt.v[v];
+            const float4 q0 = w.rec[3 * vg], q1 = w.rec[3 * vg + 1], q2 = w.rec[3 * vg + 2];
+            TileRect tr;
+            const bool has = rect_of(q0.x, q0.y, q2.z, q2.w, VV.cam.W, VV.cam.H, rp.tile_w, rp.tile_h, &tr);
             const float* part = w.partial + (size_t)o * kAdj;
             float A[kAdj];
 #pragma unroll
             for (int q = 0; q < kAdj; ++q) A[q] = 0.0f;
-            for (unsigned int k = 0; k < cnt; ++k)
+            if (has) {
+                unsigned int k = 0;
+                for (int tyy = tr.ty0; tyy <= tr.ty1; ++tyy)
+                    for (int txx = tr.tx0; txx <= tr.tx1; ++txx, ++k) {
+                        if (k >= cnt) break;
+                        const int tile = VV.tile_base + tyy * VV.tiles_x + txx;
+                        if (!(q1.z < w.tilemax[tile] + rp.eps)) continue;
 #pragma unroll
-                for (int q = 0; q < kAdj; ++q) A[q] += part[(size_t)k * kAdj + q];
+                        for (int q = 0; q < kAdj; ++q) A[q] += part[(size_t)k * kAdj + q];
+                    }
+            }
             const DevCam& c = vt.v[v].cam;
             const float* R = c.R;
             const float x = R[0] * m0 + R[1] * m1 + R[2] * m2 + c.t[0];

@@ -62,19 +62,45 @@ __device__ __forceinline__ float block_sum(float v)
     return t;
 }
 
-// Tile rectangle of a projected record: tiles [x0, x1] x [y0, y1] (empty if x0 > x1).
-__device__ __forceinline__ void rec_rect(float4 r2, int* x0, int* x1, int* y0, int* y1)
+// Tile rectangle [tx0, tx1] x [ty0, ty1] of a projected Gaussian from its centre
+// (mx, my) and padded pixel half-extents (rxp, ryp).  Every kernel that needs
+// the rectangle evaluates this same function on the same stored floats, so
+// they all agree on it.  Returns false when no pixel of the image is covered.
+struct TileRect {
+    int tx0, tx1, ty0, ty1;
+};
+
+__device__ __forceinline__ bool rect_of(float mx, float my, float rxp, float ryp, int W, int H, int tw, int th,
+                                        TileRect* r)
 {
-    unsigned int a = __float_as_uint(r2.z), b = __float_as_uint(r2.w);
-    *x0 = (int)(a & 0xffffu);
-    *x1 = (int)(a >> 16) - 1;
-    *y0 = (int)(b & 0xffffu);
-    *y1 = (int)(b >> 16) - 1;
+    const float xlo = fmaxf(mx - rxp, 0.0f), xhi = fminf(mx + rxp, (float)(W - 1));
+    const float ylo = fmaxf(my - ryp, 0.0f), yhi = fminf(my + ryp, (float)(H - 1));
+    if (!(xlo <= xhi) || !(ylo <= yhi)) return false;
+    const int px0 = (int)ceilf(xlo), px1 = (int)floorf(xhi), py0 = (int)ceilf(ylo), py1 = (int)floorf(yhi);
+    if (px0 > px1 || py0 > py1) return false;
+    r->tx0 = px0 / tw;
+    r->tx1 = px1 / tw;
+    r->ty0 = py0 / th;
+    r->ty1 = py1 / th;
+    return true;
 }
 
-__device__ __forceinline__ float pack_rect(int lo, int hi_plus1)
-{
-    return __uint_as_float((unsigned int)lo | ((unsigned int)hi_plus1 << 16));
-}
+// Pixel-to-lane layout of a tile: each wavefront covers a WW x WH block of the
+// tile (8x8 for one pixel per lane, 8x16 for two, 16x16 for four), so that a
+// Gaussian touching one corner of the tile activates few wavefronts.
+template <int TW, int TH, int PPT>
+struct TileLayout {
+    static constexpr int NT = TW * TH / PPT;
+    static constexpr int NW = NT / 64;
+    static constexpr int WW = (PPT == 4) ? 16 : 8;
+    static constexpr int WH = 64 * PPT / WW;
+    static constexpr int NWX = TW / WW;
+    static constexpr int LROWS = 64 / WW;  // rows between a lane's successive pixels
+    static_assert(NW * 64 == NT && NWX * WW == TW && (NW / NWX) * WH == TH, "tile layout");
+    __device__ static int wave_x0(int wid) { return (wid % NWX) * WW; }
+    __device__ static int wave_y0(int wid) { return (wid / NWX) * WH; }
+    __device__ static int lane_x(int lane) { return lane % WW; }
+    __device__ static int lane_y(int lane) { return lane / WW; }
+};
 
 }  // namespace gps

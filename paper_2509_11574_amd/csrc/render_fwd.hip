@@ -4,15 +4,19 @@
 //
 // Kernel sequence (one launch each, all grids sized from host-known shapes,
 // so the sequence is graph-capturable):
-//   k_prep       per screen tile: max of the SDF depth (invalid = +inf)
-//   k_project    per (view, Gaussian): projected record, tile rectangle,
-//                instance count after the exact tile depth cull, tile counts
-//   k_scan       one block: offsets of the per-block counts and of the tiles
-//   k_emit       per (view, Gaussian): instance slots and (depth, slot) keys
-//                scattered into their tile's range
-//   k_tile_sort  per tile: bitonic sort of its keys in LDS
+//   k_prep         per screen tile: max of the SDF depth (invalid = +inf)
+//   k_project      per (view, Gaussian): projected record and the number of
+//                  screen tiles its support box covers (one slot per tile)
+//   k_scan_blocks  one block: offsets of the per-block slot counts
+//   k_expand<0>    block-cooperative walk of the tile rectangles: per-tile
+//                  counts of the instances that pass the exact depth cull
+//   k_scan_tiles   one block: tile ranges
+//   k_expand<1>    the same walk: (depth, slot) keys scattered into tile ranges
+//   k_tile_sort_*  per tile: bitonic sort of its keys in LDS (one wavefront
+//                  for tiles of <= 512 instances, a 256-lane block above)
 //   k_composite_fwd<TW,TH,B,PPT>  per tile: LDS-staged batches of B records,
-//                front-to-back compositing, loss partial per tile
+//                  wavefronts skip records whose box misses their pixels,
+//                  front-to-back compositing, loss partial per tile
 //   k_loss_reduce  one block: per-view and total loss
 #include "prof.h"
 #include "render_common.h"
@@ -70,7 +74,7 @@ __device__ __forceinline__ ProjOut project_one(const DevView& V, const RParams& 
     o.valid = false;
     o.r0 = make_float4(0.f, 0.f, 0.f, 0.f);
     o.r1 = make_float4(0.f, 0.f, 0.f, 0.f);
-    o.r2 = make_float4(0.f, 0.f, pack_rect(0, 0), pack_rect(0, 0));
+    o.r2 = make_float4(0.f, 0.f, 0.f, 0.f);
     const int M = rp.M;
     const DevCam& c = V.cam;
     const float m0 = gp.mean[g], m1 = gp.mean[M + g], m2 = gp.mean[2 * M + g];
@@ -128,16 +132,12 @@ __device__ __forceinline__ ProjOut project_one(const DevView& V, const RParams& 
     if (!(sig > rp.amin)) return o;
     const float mx = c.fx * x * iz + c.cx, my = c.fy * y * iz + c.cy;
     const float kappa = 2.0f * __logf(sig / rp.amin);
-    const float rx = sqrtf(kappa * A), ry = sqrtf(kappa * C);
-    const float xlo = fmaxf(mx - rx - 1.0f, 0.0f), xhi = fminf(mx + rx + 1.0f, (float)(c.W - 1));
-    const float ylo = fmaxf(my - ry - 1.0f, 0.0f), yhi = fminf(my + ry + 1.0f, (float)(c.H - 1));
-    if (!(xlo <= xhi) || !(ylo <= yhi)) return o;
-    const int px0 = (int)ceilf(xlo), px1 = (int)floorf(xhi), py0 = (int)ceilf(ylo), py1 = (int)floorf(yhi);
-    if (px0 > px1 || py0 > py1) return o;
-    const int tx0 = px0 / rp.tile_w, tx1 = px1 / rp.tile_w, ty0 = py0 / rp.tile_h, ty1 = py1 / rp.tile_h;
+    // support half-extents padded by one pixel (covers the rounding of the opacity test)
+    const float rxp = sqrtf(kappa * A) + 1.0f, ryp = sqrtf(kappa * C) + 1.0f;
+    if (!(rxp < 1e7f) || !(ryp < 1e7f) || !(fabsf(mx) < 1e7f) || !(fabsf(my) < 1e7f)) return o;
     o.r0 = make_float4(mx, my, C * idet, -B * idet);
     o.r1 = make_float4(A * idet, sig, z, gp.rgb[g]);
-    o.r2 = make_float4(gp.rgb[M + g], gp.rgb[2 * M + g], pack_rect(tx0, tx1 + 1), pack_rect(ty0, ty1 + 1));
+    o.r2 = make_float4(gp.rgb[M + g], gp.rgb[2 * M + g], rxp, ryp);
     o.valid = true;
     return o;
 }
@@ -153,19 +153,9 @@ __global__ void __launch_bounds__(kBlk) k_project(ViewTable vt, RParams rp, GPar
         w.rec[3 * (size_t)vg + 0] = p.r0;
         w.rec[3 * (size_t)vg + 1] = p.r1;
         w.rec[3 * (size_t)vg + 2] = p.r2;
-        if (p.valid) {
-            int x0, x1, y0, y1;
-            rec_rect(p.r2, &x0, &x1, &y0, &y1);
-            const float z = p.r1.z;
-            for (int ty = y0; ty <= y1; ++ty)
-                for (int tx = x0; tx <= x1; ++tx) {
-                    const int tile = V.tile_base + ty * V.tiles_x + tx;
-                    if (z < w.tilemax[tile] + rp.eps) {  // exact tile-level depth cull
-                        ++count;
-                        atomicAdd(w.tile_cnt + tile, 1u);
-                    }
-                }
-        }
+        TileRect r;
+        if (p.valid && rect_of(p.r0.x, p.r0.y, p.r2.z, p.r2.w, V.cam.W, V.cam.H, rp.tile_w, rp.tile_h, &r))
+            count = (unsigned int)((r.tx1 - r.tx0 + 1) * (r.ty1 - r.ty0 + 1));  // one slot per covered tile
         w.cnt[vg] = count;
     }
     unsigned int tot;
@@ -222,11 +212,9 @@ __device__ unsigned long long scan_array_1024(const unsigned int* in, unsigned i
     return total;
 }
 
-__global__ void __launch_bounds__(1024) k_scan(RParams rp, WsPtrs w, int nblk_vg, int n_tiles)
+__global__ void __launch_bounds__(1024) k_scan_blocks(RParams rp, WsPtrs w, int nblk_vg, int n_tiles)
 {
     unsigned long long total = scan_array_1024(w.blk_sum, w.blk_off, nblk_vg, 0);
-    scan_array_1024(w.tile_cnt, w.tile_start, n_tiles, 1);
-    for (int i = threadIdx.x; i < n_tiles; i += 1024) w.tile_cursor[i] = w.tile_start[i];
     if (threadIdx.x == 0) {
         w.hdr->n_inst = total;
         w.hdr->cap = rp.cap;
@@ -235,78 +223,163 @@ __global__ void __launch_bounds__(1024) k_scan(RParams rp, WsPtrs w, int nblk_vg
     }
 }
 
-// ------------------------------------------------------------------- emit
-__global__ void __launch_bounds__(kBlk) k_emit(ViewTable vt, RParams rp, WsPtrs w)
+__global__ void __launch_bounds__(1024) k_scan_tiles(RParams rp, WsPtrs w, int n_tiles)
 {
     if (w.hdr->n_inst > rp.cap) return;
+    scan_array_1024(w.tile_cnt, w.tile_start, n_tiles, 1);
+    for (int i = threadIdx.x; i < n_tiles; i += 1024) w.tile_cursor[i] = w.tile_start[i];
+}
+
+// ------------------------------------------------------------ count / emit
+// Block-cooperative expansion of the instances of kBlk consecutive view-Gaussians:
+// the block's lanes walk the concatenation of their tile rectangles together
+// (instance i belongs to the lane whose prefix range holds i, found by binary
+// search in LDS), so one large Gaussian is spread over the whole block instead
+// of serialising one lane.  Instance i of block b has slot blk_off[b] + i.
+//   COUNT:  tiles that pass the exact depth cull get their tile count incremented;
+//           the per-view-Gaussian slot offsets are written.
+//   EMIT:   the same instances get a position in their tile's range and a key
+//           (depth bits << 32) | slot; slot -> view-Gaussian is recorded.
+template <bool EMIT>
+__global__ void __launch_bounds__(kBlk) k_expand(ViewTable vt, RParams rp, WsPtrs w)
+{
+    if (w.hdr->n_inst > rp.cap) return;
+    __shared__ unsigned int pre[kBlk + 1];
+    __shared__ float4 sbox[kBlk];  // mx, my, rxp, ryp
+    __shared__ float sz[kBlk];
+    __shared__ int4 sview[kBlk];   // tile_base, tiles_x, W, H
     const int vg = blockIdx.x * kBlk + threadIdx.x;
     const unsigned int c = vg < rp.nvg ? w.cnt[vg] : 0u;
     unsigned int tot;
     const unsigned int excl = block_excl_scan<kBlk>(c, &tot);
-    if (vg >= rp.nvg) return;
-    const unsigned int base = w.blk_off[blockIdx.x] + excl;
-    w.off[vg] = base;
-    if (c == 0) return;
-    const int v = vg / rp.M;
-    const DevView& V = vt.v[v];
-    const float4 r1 = w.rec[3 * (size_t)vg + 1];
-    const float4 r2 = w.rec[3 * (size_t)vg + 2];
-    const float z = r1.z;
-    const unsigned long long zkey = (unsigned long long)__float_as_uint(z) << 32;
-    int x0, x1, y0, y1;
-    rec_rect(r2, &x0, &x1, &y0, &y1);
-    unsigned int slot = base;
-    const unsigned int slot_end = base + c;  // the count the projection made
-    for (int ty = y0; ty <= y1; ++ty)
-        for (int tx = x0; tx <= x1; ++tx) {
-            const int tile = V.tile_base + ty * V.tiles_x + tx;
-            if (z < w.tilemax[tile] + rp.eps && slot < slot_end) {
-                w.inst_vg[slot] = (unsigned int)vg;
-                const unsigned int pos = atomicAdd(w.tile_cursor + tile, 1u);
-                if (pos < w.tile_start[tile + 1]) w.keys[pos] = zkey | slot;
-                ++slot;
-            }
+    pre[threadIdx.x] = excl;
+    if (threadIdx.x == kBlk - 1) pre[kBlk] = excl + c;
+    if (c > 0) {
+        const float4 r0 = w.rec[3 * (size_t)vg], r1 = w.rec[3 * (size_t)vg + 1], r2 = w.rec[3 * (size_t)vg + 2];
+        sbox[threadIdx.x] = make_float4(r0.x, r0.y, r2.z, r2.w);
+        sz[threadIdx.x] = r1.z;
+        const DevView& V = vt.v[vg / rp.M];
+        sview[threadIdx.x] = make_int4(V.tile_base, V.tiles_x, V.cam.W, V.cam.H);
+    }
+    const unsigned int base = w.blk_off[blockIdx.x];
+    if (!EMIT && vg < rp.nvg) w.off[vg] = base + excl;
+    __syncthreads();
+    for (unsigned int i = threadIdx.x; i < tot; i += kBlk) {
+        int lo = 0, hi = kBlk;  // pre[lo] <= i < pre[hi]
+#pragma unroll
+        for (int step = 0; step < 8; ++step) {
+            const int mid = (lo + hi) >> 1;
+            if (pre[mid] <= i) lo = mid;
+            else hi = mid;
         }
+        const unsigned int j = i - pre[lo];
+        const float4 bx = sbox[lo];
+        const int4 vw = sview[lo];
+        TileRect r;
+        if (!rect_of(bx.x, bx.y, bx.z, bx.w, vw.z, vw.w, rp.tile_w, rp.tile_h, &r)) continue;
+        const unsigned int wdt = (unsigned int)(r.tx1 - r.tx0 + 1);
+        const int tile = vw.x + (r.ty0 + (int)(j / wdt)) * vw.y + r.tx0 + (int)(j % wdt);
+        const float z = sz[lo];
+        if (!(z < w.tilemax[tile] + rp.eps)) continue;  // exact tile-level depth cull
+        if (!EMIT) {
+            atomicAdd(w.tile_cnt + tile, 1u);
+        } else {
+            const unsigned int slot = base + i;
+            w.inst_vg[slot] = (unsigned int)(blockIdx.x * kBlk + lo);
+            const unsigned int pos = atomicAdd(w.tile_cursor + tile, 1u);
+            if (pos < w.tile_start[tile + 1]) w.keys[pos] = ((unsigned long long)__float_as_uint(z) << 32) | slot;
+        }
+    }
 }
 
 // -------------------------------------------------------------- tile sort
-// Bitonic network in which every compare-exchange puts the smaller key at
-// the lower index (the first step of each merge compares mirrored pairs), so
+// Bitonic network in which every compare-exchange puts the smaller key at the
+// lower index (the first step of each merge compares mirrored pairs), so
 // padding with +inf keys never moves into the sorted range.
-__global__ void __launch_bounds__(256) k_tile_sort(RParams rp, WsPtrs w)
+//
+// k_tile_sort_small: each wavefront of a 256-lane block sorts one tile of at
+// most kSmallSort keys in its own 4 KiB of LDS (wavefront-local barriers only).
+// k_tile_sort_large: one block per tile for the longer tiles; tiles longer
+// than kSortCap use the same network in global memory.
+constexpr int kSmallSort = 512;
+
+__device__ __forceinline__ void cas_lds(unsigned long long* sh, int i, int j)
+{
+    const unsigned long long a = sh[i], b = sh[j];
+    if (a > b) {
+        sh[i] = b;
+        sh[j] = a;
+    }
+}
+
+// Wavefront-level LDS barrier: the 64 lanes run in lockstep; this orders the
+// LDS traffic of the step before against the step after.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ void __launch_bounds__(256) k_tile_sort_small(RParams rp, WsPtrs w, int n_tiles)
+{
+    __shared__ unsigned long long sh_all[4][kSmallSort];
+    if (w.hdr->n_inst > rp.cap) return;
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * 4 + wid;
+    if (tile >= n_tiles) return;
+    const unsigned int s = w.tile_start[tile], e = w.tile_start[tile + 1];
+    const int n = (int)(e - s);
+    if (n <= 1 || n > kSmallSort) return;
+    int P = 2;
+    while (P < n) P <<= 1;
+    unsigned long long* sh = sh_all[wid];
+    unsigned long long* key = w.keys + s;
+    for (int i = lane; i < P; i += 64) sh[i] = i < n ? key[i] : ~0ull;
+    wave_lds_sync();
+    for (int k = 2; k <= P; k <<= 1) {
+        const int half = k >> 1;
+        for (int c = lane; c < P / 2; c += 64) {
+            const int blk = c / half, wi = c - blk * half;
+            cas_lds(sh, blk * k + wi, blk * k + k - 1 - wi);
+        }
+        wave_lds_sync();
+        for (int jj = k >> 2; jj > 0; jj >>= 1) {
+            for (int c = lane; c < P / 2; c += 64) {
+                const int i = (c / jj) * 2 * jj + (c % jj);
+                cas_lds(sh, i, i + jj);
+            }
+            wave_lds_sync();
+        }
+    }
+    for (int i = lane; i < n; i += 64) key[i] = sh[i];
+}
+
+__global__ void __launch_bounds__(256) k_tile_sort_large(RParams rp, WsPtrs w)
 {
     if (w.hdr->n_inst > rp.cap) return;
     const int tile = blockIdx.x;
     const unsigned int s = w.tile_start[tile], e = w.tile_start[tile + 1];
     const int n = (int)(e - s);
-    if (n <= 1) return;
+    if (n <= kSmallSort) return;
     int P = 1;
     while (P < n) P <<= 1;
     unsigned long long* key = w.keys + s;
     if (n <= kSortCap) {
-        __shared__ unsigned long long sh[kSortCap];
+        extern __shared__ unsigned long long sh[];  // kSortCap keys (dynamic LDS)
         for (int i = threadIdx.x; i < P; i += 256) sh[i] = i < n ? key[i] : ~0ull;
         __syncthreads();
         for (int k = 2; k <= P; k <<= 1) {
             const int half = k >> 1;
             for (int c = threadIdx.x; c < P / 2; c += 256) {
                 const int blk = c / half, wi = c - blk * half;
-                const int i = blk * k + wi, j = blk * k + k - 1 - wi;
-                unsigned long long a = sh[i], b = sh[j];
-                if (a > b) {
-                    sh[i] = b;
-                    sh[j] = a;
-                }
+                cas_lds(sh, blk * k + wi, blk * k + k - 1 - wi);
             }
             __syncthreads();
             for (int jj = k >> 2; jj > 0; jj >>= 1) {
                 for (int c = threadIdx.x; c < P / 2; c += 256) {
-                    const int i = (c / jj) * 2 * jj + (c % jj), j = i + jj;
-                    unsigned long long a = sh[i], b = sh[j];
-                    if (a > b) {
-                        sh[i] = b;
-                        sh[j] = a;
-                    }
+                    const int i = (c / jj) * 2 * jj + (c % jj);
+                    cas_lds(sh, i, i + jj);
                 }
                 __syncthreads();
             }
@@ -351,8 +424,8 @@ __global__ void __launch_bounds__(256) k_tile_sort(RParams rp, WsPtrs w)
 template <int TW, int TH, int B, int PPT>
 __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(ViewTable vt, RParams rp, WsPtrs w)
 {
-    constexpr int NT = TW * TH / PPT;
-    constexpr int ROWS = TH / PPT;
+    using Lay = TileLayout<TW, TH, PPT>;
+    constexpr int NT = Lay::NT;
     __shared__ float4 srec[3 * B];
     if (w.hdr->n_inst > rp.cap) return;
     const int tile = blockIdx.x;
@@ -362,8 +435,12 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(ViewTable vt, R
     const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
     const int Wd = V.cam.W, Ht = V.cam.H;
     const size_t HW = (size_t)Wd * Ht;
-    const int px = tx * TW + (int)(threadIdx.x % TW);
-    const int py0 = ty * TH + (int)(threadIdx.x / TW);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int wx0 = tx * TW + Lay::wave_x0(wid), wy0 = ty * TH + Lay::wave_y0(wid);
+    const float fwx0 = (float)wx0, fwx1 = (float)(wx0 + Lay::WW - 1);
+    const float fwy0 = (float)wy0, fwy1 = (float)(wy0 + Lay::WH - 1);
+    const int px = wx0 + Lay::lane_x(lane);
+    const int py0 = wy0 + Lay::lane_y(lane);
     const float fpx = (float)px;
 
     float thr[PPT], T[PPT], ac0[PPT], ac1[PPT], ac2[PPT], ad[PPT];
@@ -371,7 +448,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(ViewTable vt, R
     unsigned int n_eval = 0, n_contrib = 0;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const int py = py0 + k * ROWS;
+        const int py = py0 + k * Lay::LROWS;
         const bool inb = px < Wd && py < Ht;
         float dt = inb ? V.base_depth[(size_t)py * Wd + px] : 0.0f;
         float dcull = dt > 0.0f ? dt : INFINITY;
@@ -398,7 +475,11 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(ViewTable vt, R
         __syncthreads();
         const int n = (int)min((unsigned int)B, e - b);
         for (int j = 0; j < n; ++j) {
-            const float4 r0 = srec[3 * j], r1 = srec[3 * j + 1], r2 = srec[3 * j + 2];
+            const float4 r0 = srec[3 * j], r2 = srec[3 * j + 2];
+            // The support box misses this wavefront's pixels: every opacity here is
+            // below alpha_min, so skipping the record changes nothing.
+            if (r0.x + r2.z < fwx0 || r0.x - r2.z > fwx1 || r0.y + r2.w < fwy0 || r0.y - r2.w > fwy1) continue;
+            const float4 r1 = srec[3 * j + 1];
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 if (done[k]) continue;
@@ -406,7 +487,8 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(ViewTable vt, R
                     done[k] = true;
                     continue;
                 }
-                const AlphaEval ae = eval_alpha(fpx, (float)(py0 + k * ROWS), r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
+                const AlphaEval ae =
+                    eval_alpha(fpx, (float)(py0 + k * Lay::LROWS), r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
                 ++n_eval;
                 if (rp.mode == 0) {
                     const float a = fminf(rp.amax, ae.raw);
@@ -441,7 +523,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(ViewTable vt, R
     float lc = 0.0f, ld = 0.0f, lo = 0.0f;
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
-        const int py = py0 + k * ROWS;
+        const int py = py0 + k * Lay::LROWS;
         if (!(px < Wd && py < Ht)) continue;
         const size_t p = (size_t)py * Wd + px;
         const float dt = V.base_depth[p];
@@ -582,9 +664,12 @@ gps_status launch_render_fwd(const gps_render_cfg* cfg, const RParams& rp, const
         if (!vt.v[v].target_rgb) has_loss = 0;
     GPS_LAUNCH(K_PREP, s, k_prep, dim3(L.n_tiles), dim3(256), 0, s, vt, rp, w);
     if (L.nblk_vg > 0) GPS_LAUNCH(K_PROJECT, s, k_project, dim3(L.nblk_vg), dim3(kBlk), 0, s, vt, rp, gp, w);
-    GPS_LAUNCH(K_SCAN, s, k_scan, dim3(1), dim3(1024), 0, s, rp, w, L.nblk_vg, L.n_tiles);
-    if (L.nblk_vg > 0) GPS_LAUNCH(K_EMIT, s, k_emit, dim3(L.nblk_vg), dim3(kBlk), 0, s, vt, rp, w);
-    GPS_LAUNCH(K_TILE_SORT, s, k_tile_sort, dim3(L.n_tiles), dim3(256), 0, s, rp, w);
+    GPS_LAUNCH(K_SCAN, s, k_scan_blocks, dim3(1), dim3(1024), 0, s, rp, w, L.nblk_vg, L.n_tiles);
+    if (L.nblk_vg > 0) GPS_LAUNCH(K_TILE_COUNT, s, k_expand<false>, dim3(L.nblk_vg), dim3(kBlk), 0, s, vt, rp, w);
+    GPS_LAUNCH(K_SCAN_TILES, s, k_scan_tiles, dim3(1), dim3(1024), 0, s, rp, w, L.n_tiles);
+    if (L.nblk_vg > 0) GPS_LAUNCH(K_EMIT, s, k_expand<true>, dim3(L.nblk_vg), dim3(kBlk), 0, s, vt, rp, w);
+    GPS_LAUNCH(K_TILE_SORT, s, k_tile_sort_small, dim3((L.n_tiles + 3) / 4), dim3(256), 0, s, rp, w, L.n_tiles);
+    GPS_LAUNCH(K_TILE_SORT_LARGE, s, k_tile_sort_large, dim3(L.n_tiles), dim3(256), kSortCap * sizeof(unsigned long long), s, rp, w);
     if (!dispatch_cfwd(cfg, vt, rp, w, L.n_tiles, s)) return GPS_ERR_UNSUPPORTED_CONFIG;
     GPS_LAUNCH(K_LOSS_REDUCE, s, k_loss_reduce, dim3(1), dim3(256), 0, s, vt, rp, w, out_loss, has_loss);
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
