@@ -411,7 +411,9 @@ def test_long_tile_lists(P, O, M):
     """Tiles holding more than 512 (LDS block sort) and more than 8192 (global-memory sort)
     instances composite in the same order as the reference."""
     say(f"long tile lists: M={M}")
-    case = tiny_case(40, M=M, W=32, H=24, f=30.0, log_scale=-1.6, invalid_frac=0.0)
+    # M > 8192 on a single 16x16 tile puts every instance into that tile's list
+    W, H = (32, 24) if M <= 8192 else (16, 16)
+    case = tiny_case(40, M=M, W=W, H=H, f=30.0, log_scale=-1.6, invalid_frac=0.0)
     case["base_depth"][:] = 3.0
     gc, oc = cfg_pair(P, O, eps=0.03)
     views, ws, gd, _ = _render_gpu(P, gc, case["gauss"], [case])
