@@ -16,6 +16,7 @@ constexpr int kSortCap = 8192;        // longest tile list sorted in LDS (64 KiB
 constexpr int kRecFloats = 12;        // projected record: 48 bytes
 constexpr int kAdj = 10;              // screen-space adjoints per instance
 constexpr int kBlk = 256;             // threads per block of the per-Gaussian kernels
+constexpr int kFlush = 32;            // records between flushes of the backward's per-wavefront partials
 
 // ---------------------------------------------------------------------------
 // Camera / view tables passed by value as kernel arguments.

@@ -27,8 +27,9 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     constexpr int NW = Lay::NW;
     __shared__ float4 srec[3 * B];
     __shared__ unsigned int sslot[B];
-    __shared__ float slab[B * NW * kAdj];
-    __shared__ unsigned char sact[B * NW];  // 1 when the wavefront wrote its partial of record j
+    constexpr int S = kFlush;                // records per flush of the per-wavefront partials
+    __shared__ float slab[S * NW * kAdj];
+    __shared__ unsigned char sact[S * NW];  // 1 when the wavefront wrote its partial of record j
     if (w.hdr->n_inst > rp.cap) return;
     const int tile = blockIdx.x;
     const int v = find_view(vt, tile);
@@ -92,8 +93,8 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     }
 
     const unsigned int s = w.tile_start[tile], e = w.tile_start[tile + 1];
-    unsigned int b = s;
-    for (; b < e; b += B) {
+    unsigned int stop = s;  // first position whose partial has not been written
+    for (unsigned int b = s; b < e; b += B) {
         int alive = 0;
 #pragma unroll
         for (int k = 0; k < PPT; ++k) alive |= !done[k];
@@ -110,108 +111,120 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         }
         __syncthreads();
         const int n = (int)min((unsigned int)B, e - b);
-        for (int j = 0; j < n; ++j) {
-            const float4 r0 = srec[3 * j], r2 = srec[3 * j + 2];
-            bool act = false;
-            float g[kAdj];
+        int alive_now = 1;
+        for (int j0 = 0; j0 < n && alive_now; j0 += S) {
+            const int j1 = min(j0 + S, n);
+            for (int j = j0; j < j1; ++j) {
+                const float4 r0 = srec[3 * j], r2 = srec[3 * j + 2];
+                bool act = false;
+                float g[kAdj];
 #pragma unroll
-            for (int q = 0; q < kAdj; ++q) g[q] = 0.0f;
-            // Same wavefront-level skip as the forward: no pixel of this wavefront is in the box.
-            const bool miss = r0.x + r2.z < fwx0 || r0.x - r2.z > fwx1 || r0.y + r2.w < fwy0 || r0.y - r2.w > fwy1;
-            if (!miss) {
-                const float4 r1 = srec[3 * j + 1];
-                const float c0 = r1.w, c1 = r2.x, c2 = r2.y, zi = r1.z;
+                for (int q = 0; q < kAdj; ++q) g[q] = 0.0f;
+                // Same wavefront-level skip as the forward: no pixel of this wavefront is in the box.
+                const bool miss =
+                    r0.x + r2.z < fwx0 || r0.x - r2.z > fwx1 || r0.y + r2.w < fwy0 || r0.y - r2.w > fwy1;
+                if (!miss) {
+                    const float4 r1 = srec[3 * j + 1];
+                    const float c0 = r1.w, c1 = r2.x, c2 = r2.y, zi = r1.z;
 #pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    if (done[k]) continue;
-                    if (!(zi < thr[k])) {
-                        done[k] = true;
-                        continue;
-                    }
-                    const AlphaEval ae =
-                        eval_alpha(fpx, (float)(py0 + k * Lay::LROWS), r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
-                    float a, dal;
-                    bool alpha_path;
-                    if (rp.mode == 0) {
-                        a = fminf(rp.amax, ae.raw);
-                        if (a < rp.amin) continue;
-                        const float Tn = T[k] * (1.0f - a);
-                        if (Tn < rp.Tmin) {
+                    for (int k = 0; k < PPT; ++k) {
+                        if (done[k]) continue;
+                        if (!(zi < thr[k])) {
                             done[k] = true;
                             continue;
                         }
-                        const float wgt = a * T[k];
-                        P0[k] = __builtin_fmaf(wgt, c0, P0[k]);
-                        P1[k] = __builtin_fmaf(wgt, c1, P1[k]);
-                        P2[k] = __builtin_fmaf(wgt, c2, P2[k]);
-                        PD[k] = __builtin_fmaf(wgt, zi, PD[k]);
-                        g[6] += wgt * G0[k];
-                        g[7] += wgt * G1[k];
-                        g[8] += wgt * G2[k];
-                        g[9] += wgt * GD[k];
-                        const float direct = G0[k] * c0 + G1[k] * c1 + G2[k] * c2 + GD[k] * zi;
-                        const float rest = G0[k] * (Cs0[k] - P0[k]) + G1[k] * (Cs1[k] - P1[k]) +
-                                           G2[k] * (Cs2[k] - P2[k]) + GD[k] * (Ds[k] - PD[k]);
-                        dal = T[k] * direct - rest / (1.0f - a);
-                        alpha_path = ae.raw <= rp.amax;
-                        T[k] = Tn;
-                    } else {
-                        a = ae.raw;
-                        if (a < rp.amin) continue;
-                        const float inv = 1.0f / (1.0f + Wg[k]);
-                        const float ai = a * inv;
-                        g[6] += ai * G0[k];
-                        g[7] += ai * G1[k];
-                        g[8] += ai * G2[k];
-                        g[9] += ai * GD[k];
-                        dal = inv * (G0[k] * (c0 - Cs0[k]) + G1[k] * (c1 - Cs1[k]) + G2[k] * (c2 - Cs2[k]) +
-                                     GD[k] * (zi - Ds[k]));
-                        alpha_path = true;
-                    }
-                    act = true;
-                    if (alpha_path) {
-                        const float dp = dal * a;  // d alpha / d power = alpha
-                        g[5] += dal * ae.e;        // d alpha / d sigma = exp(power)
-                        g[0] += dp * (r0.z * ae.dx + r0.w * ae.dy);
-                        g[1] += dp * (r0.w * ae.dx + r1.x * ae.dy);
-                        g[2] += -0.5f * dp * ae.dx * ae.dx;
-                        g[3] += -dp * ae.dx * ae.dy;
-                        g[4] += -0.5f * dp * ae.dy * ae.dy;
+                        const AlphaEval ae =
+                            eval_alpha(fpx, (float)(py0 + k * Lay::LROWS), r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
+                        float a, dal;
+                        bool alpha_path;
+                        if (rp.mode == 0) {
+                            a = fminf(rp.amax, ae.raw);
+                            if (a < rp.amin) continue;
+                            const float Tn = T[k] * (1.0f - a);
+                            if (Tn < rp.Tmin) {
+                                done[k] = true;
+                                continue;
+                            }
+                            const float wgt = a * T[k];
+                            P0[k] = __builtin_fmaf(wgt, c0, P0[k]);
+                            P1[k] = __builtin_fmaf(wgt, c1, P1[k]);
+                            P2[k] = __builtin_fmaf(wgt, c2, P2[k]);
+                            PD[k] = __builtin_fmaf(wgt, zi, PD[k]);
+                            g[6] += wgt * G0[k];
+                            g[7] += wgt * G1[k];
+                            g[8] += wgt * G2[k];
+                            g[9] += wgt * GD[k];
+                            const float direct = G0[k] * c0 + G1[k] * c1 + G2[k] * c2 + GD[k] * zi;
+                            const float rest = G0[k] * (Cs0[k] - P0[k]) + G1[k] * (Cs1[k] - P1[k]) +
+                                               G2[k] * (Cs2[k] - P2[k]) + GD[k] * (Ds[k] - PD[k]);
+                            dal = T[k] * direct - rest / (1.0f - a);
+                            alpha_path = ae.raw <= rp.amax;
+                            T[k] = Tn;
+                        } else {
+                            a = ae.raw;
+                            if (a < rp.amin) continue;
+                            const float inv = 1.0f / (1.0f + Wg[k]);
+                            const float ai = a * inv;
+                            g[6] += ai * G0[k];
+                            g[7] += ai * G1[k];
+                            g[8] += ai * G2[k];
+                            g[9] += ai * GD[k];
+                            dal = inv * (G0[k] * (c0 - Cs0[k]) + G1[k] * (c1 - Cs1[k]) + G2[k] * (c2 - Cs2[k]) +
+                                         GD[k] * (zi - Ds[k]));
+                            alpha_path = true;
+                        }
+                        act = true;
+                        if (alpha_path) {
+                            const float dp = dal * a;  // d alpha / d power = alpha
+                            g[5] += dal * ae.e;        // d alpha / d sigma = exp(power)
+                            g[0] += dp * (r0.z * ae.dx + r0.w * ae.dy);
+                            g[1] += dp * (r0.w * ae.dx + r1.x * ae.dy);
+                            g[2] += -0.5f * dp * ae.dx * ae.dx;
+                            g[3] += -dp * ae.dx * ae.dy;
+                            g[4] += -0.5f * dp * ae.dy * ae.dy;
+                        }
                     }
                 }
-            }
-            const bool wact = wave_any(act);
-            if (wact) {
-                float* dst = slab + (j * NW + wid) * kAdj;
+                const bool wact = wave_any(act);
+                if (wact) {
+                    float* dst = slab + ((j - j0) * NW + wid) * kAdj;
 #pragma unroll
-                for (int q = 0; q < kAdj; ++q) {
-                    const float t = wave_sum_to_lane63(g[q]);
-                    if (lane == 63) dst[q] = t;
+                    for (int q = 0; q < kAdj; ++q) {
+                        const float t = wave_sum_to_lane63(g[q]);
+                        if (lane == 63) dst[q] = t;
+                    }
+                }
+                if (lane == 0) sact[(j - j0) * NW + wid] = wact ? 1 : 0;
+            }
+            int alive = 0;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) alive |= !done[k];
+            alive_now = __syncthreads_count(alive);
+            for (int t = threadIdx.x; t < j1 - j0; t += NT) {
+                float acc[kAdj];
+#pragma unroll
+                for (int q = 0; q < kAdj; ++q) acc[q] = 0.0f;
+#pragma unroll
+                for (int ww = 0; ww < NW; ++ww) {
+                    if (!sact[t * NW + ww]) continue;
+#pragma unroll
+                    for (int q = 0; q < kAdj; ++q) acc[q] += slab[(t * NW + ww) * kAdj + q];
+                }
+                const unsigned int slot = sslot[j0 + t];
+                if (slot < rp.cap) {
+                    float* out = w.partial + (size_t)slot * kAdj;
+#pragma unroll
+                    for (int q = 0; q < kAdj; ++q) out[q] = acc[q];
                 }
             }
-            if (lane == 0) sact[j * NW + wid] = wact ? 1 : 0;
+            __syncthreads();
+            stop = b + (unsigned int)j1;  // positions before this were written
         }
-        __syncthreads();
-        for (int t = threadIdx.x; t < n; t += NT) {
-            float acc[kAdj];
-#pragma unroll
-            for (int q = 0; q < kAdj; ++q) acc[q] = 0.0f;
-#pragma unroll
-            for (int ww = 0; ww < NW; ++ww) {
-                if (!sact[t * NW + ww]) continue;
-#pragma unroll
-                for (int q = 0; q < kAdj; ++q) acc[q] += slab[(t * NW + ww) * kAdj + q];
-            }
-            if (sslot[t] < rp.cap) {
-                float* out = w.partial + (size_t)sslot[t] * kAdj;
-#pragma unroll
-                for (int q = 0; q < kAdj; ++q) out[q] = acc[q];
-            }
-        }
+        if (!alive_now) break;
     }
     // Instances after the point where every pixel of the tile had stopped
     // contribute nothing; their slots still need zeros.
-    for (unsigned int pos = b + threadIdx.x; pos < e; pos += NT) {
+    for (unsigned int pos = stop + threadIdx.x; pos < e; pos += NT) {
         const unsigned int slot = (unsigned int)w.keys[pos];
         if (slot >= rp.cap) continue;
         float* out = w.partial + (size_t)slot * kAdj;
@@ -279,27 +292,16 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(ViewTable vt, RParams rp, GP
         const unsigned int o = cnt ? w.off[vg] : 0u;
         if ((unsigned long long)o + cnt > w.hdr->n_inst) cnt = 0u;  // guard: stay inside the emitted slots
         if (cnt > 0) {
-            // The Gaussian's slots are its tile rectangle in row order; the slots of the
-            // tiles that passed the depth cull hold partials (the same test as the emission).
-            const DevView& VV = vt.v[v];
-            const float4 q0 = w.rec[3 * vg], q1 = w.rec[3 * vg + 1], q2 = w.rec[3 * vg + 2];
-            TileRect tr;
-            const bool has = rect_of(q0.x, q0.y, q2.z, q2.w, VV.cam.W, VV.cam.H, rp.tile_w, rp.tile_h, &tr);
+            // Slots of tiles removed by the depth cull were zeroed by the emission, so the
+            // whole contiguous range is summed, in order.
             const float* part = w.partial + (size_t)o * kAdj;
             float A[kAdj];
 #pragma unroll
             for (int q = 0; q < kAdj; ++q) A[q] = 0.0f;
-            if (has) {
-                unsigned int k = 0;
-                for (int tyy = tr.ty0; tyy <= tr.ty1; ++tyy)
-                    for (int txx = tr.tx0; txx <= tr.tx1; ++txx, ++k) {
-                        if (k >= cnt) break;
-                        const int tile = VV.tile_base + tyy * VV.tiles_x + txx;
-                        if (!(q1.z < w.tilemax[tile] + rp.eps)) continue;
+#pragma unroll 4
+            for (unsigned int k = 0; k < cnt; ++k)
 #pragma unroll
-                        for (int q = 0; q < kAdj; ++q) A[q] += part[(size_t)k * kAdj + q];
-                    }
-            }
+                for (int q = 0; q < kAdj; ++q) A[q] += part[(size_t)k * kAdj + q];
             const DevCam& c = vt.v[v].cam;
             const float* R = c.R;
             const float x = R[0] * m0 + R[1] * m1 + R[2] * m2 + c.t[0];

@@ -280,7 +280,14 @@ __global__ void __launch_bounds__(kBlk) k_expand(ViewTable vt, RParams rp, WsPtr
         const unsigned int wdt = (unsigned int)(r.tx1 - r.tx0 + 1);
         const int tile = vw.x + (r.ty0 + (int)(j / wdt)) * vw.y + r.tx0 + (int)(j % wdt);
         const float z = sz[lo];
-        if (!(z < w.tilemax[tile] + rp.eps)) continue;  // exact tile-level depth cull
+        if (!(z < w.tilemax[tile] + rp.eps)) {  // exact tile-level depth cull
+            if (EMIT) {  // the backward sums every slot of a Gaussian: culled slots hold zeros
+                float* pz = w.partial + (size_t)(base + i) * kAdj;
+#pragma unroll
+                for (int q = 0; q < kAdj; ++q) pz[q] = 0.0f;
+            }
+            continue;
+        }
         if (!EMIT) {
             atomicAdd(w.tile_cnt + tile, 1u);
         } else {
