@@ -50,7 +50,9 @@ def parse():
     ap.add_argument("--gaussians", type=int, default=100_000)
     ap.add_argument("--res", type=str, default="1280x720")
     ap.add_argument("--volume", type=int, default=256)
-    ap.add_argument("--tile", type=str, default="16x16x256x1", help="tile_w x tile_h x batch x pixels_per_lane")
+    ap.add_argument("--tile", type=str, default="auto",
+                    help="tile_w x tile_h x batch x pixels_per_lane, or 'auto' (autotuned on the first frame)")
+    ap.add_argument("--graph", type=int, default=1, help="replay the iteration as a captured HIP graph")
     ap.add_argument("--mode", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -73,7 +75,6 @@ def main():
     dev = "cuda:0"
     torch.cuda.set_device(0)
     W_img, H_img = (int(x) for x in args.res.split("x"))
-    tw, th, tb, ppt = (int(x) for x in args.tile.split("x"))
     K, Wu, M = args.steps, args.warmup, args.gaussians
     n_frames = Wu + 2 * K  # warmup, timed pass, profiled pass
 
@@ -92,9 +93,8 @@ def main():
         f"{args.volume}^3 volume")
 
     vol = P.Volume(scene.dims, scene.origin, scene.voxel, scene.trunc, device=dev)
-    cfg = P.RenderCfg(tile_w=tw, tile_h=th, batch=tb, pix_per_thread=ppt, mode=args.mode, eps_cull=scene.voxel)
+    cfg = P.RenderCfg(mode=args.mode, eps_cull=scene.voxel)
     cam0 = cams[0].as_dict()
-    ws = P.Workspace(cfg, M, [cam0], device=dev)
     base_depth = torch.empty(H_img, W_img, device=dev)
     base_rgb = torch.empty(3, H_img, W_img, device=dev)
     out_rgb = torch.empty(3, H_img, W_img, device=dev)
@@ -104,19 +104,52 @@ def main():
     dpose = torch.zeros(1, 6, device=dev)
     opt = P.Adam(params)
 
-    def frame_step(k):
+    def frame_prep(k):
         cam = cams[k].as_dict()
         depth, rgb = frames[k]
         P.fuse(vol, cam, depth, rgb)
         P.raycast(vol, [cam], z_near=cfg.z_near, out=[(base_depth, base_rgb)])
-        view = P.View(cam, base_rgb, base_depth, rgb, depth, out_rgb=out_rgb, out_depth=out_depth)
+        return P.View(cam, base_rgb, base_depth, rgb, depth, out_rgb=out_rgb, out_depth=out_depth)
+
+    tune_ms = None
+    if args.tile == "auto":
+        from paper_2509_11574_amd import autotune
+        view = frame_prep(0)
+        snapshot = {k: v.clone() for k, v in params.items()}  # tuning runs forward+backward only
+        cfg, tune_ms = autotune.autotune(cfg, params, [view], reps=5, use_cache=False)
+        torch.cuda.synchronize()
+        for k in params:
+            params[k].copy_(snapshot[k])
+        vol = P.Volume(scene.dims, scene.origin, scene.voxel, scene.trunc, device=dev)  # start the map afresh
+        log(f"autotuned: {cfg.tile_w}x{cfg.tile_h}x{cfg.batch}x{cfg.pix_per_thread} ({tune_ms})")
+    else:
+        tw, th, tb, ppt = (int(x) for x in args.tile.split("x"))
+        cfg = P.RenderCfg(tile_w=tw, tile_h=th, batch=tb, pix_per_thread=ppt, mode=args.mode,
+                          eps_cull=scene.voxel)
+    ws = P.Workspace(cfg, M, [cam0], device=dev)
+
+    def frame_step_eager(k):
+        view = frame_prep(k)
         for _ in range(ITERS_PER_FRAME):
             P.render_fwd(cfg, params, [view], ws, out_loss=loss)
             P.render_bwd(cfg, params, [view], ws, grads, dpose)
             opt.step(grads)
 
+    graph = None
+
+    def frame_step_graph(k):
+        view = frame_prep(k)
+        graph.set_views([view])
+        for _ in range(ITERS_PER_FRAME):
+            graph.replay()
+
+    frame_step = frame_step_eager
     for k in range(Wu):
         frame_step(k)
+    if args.graph:
+        from paper_2509_11574_amd.graph import IterationGraph
+        graph = IterationGraph(cfg, params, [frame_prep(Wu - 1)], ws, grads, opt, loss, dpose)
+        frame_step = frame_step_graph
     torch.cuda.synchronize()
     st0 = ws.stats()
     if st0["status"] != 0:
@@ -148,8 +181,8 @@ def main():
     if not args.no_profile:
         stp0 = ws.stats()
         P.gps.profile_start()
-        for k in range(Wu + K, Wu + 2 * K):
-            frame_step(k)
+        for k in range(Wu + K, Wu + 2 * K):  # the same kernels, launched eagerly so events bracket each
+            frame_step_eager(k)
         torch.cuda.synchronize()
         P.gps.profile_stop()
         kernels = P.gps.profile_read()
@@ -184,8 +217,9 @@ def main():
                   + 392 * M)                         # Adam: 14 scalars x 28 B
     iter_ms = None
     if kernels:
-        it_kernels = ("prep", "project", "scan", "emit", "tile_sort", "composite_fwd", "loss_reduce",
-                      "composite_bwd", "gauss_bwd", "pose_reduce", "adam", "step_incr")
+        it_kernels = ("upload_views", "prep", "project", "scan", "count", "scan_tiles", "emit", "tile_sort",
+                      "tile_sort_large", "composite_fwd", "loss_reduce", "composite_bwd", "gauss_bwd",
+                      "pose_reduce", "adam", "step_incr")
         iter_ms = sum(kernels[n][1] for n in it_kernels if n in kernels) / (K * ITERS_PER_FRAME)
     hbm_gbs = bytes_iter / (iter_ms / 1e3) / 1e9 if iter_ms else None
 
@@ -199,8 +233,10 @@ def main():
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": f"plain per-frame mapping: {args.volume}^3 TSDF at {scene.voxel * 100:.3g} cm, "
                                   f"{W_img}x{H_img} orbit frames, {M} Gaussians, {ITERS_PER_FRAME} iterations/frame",
-                      "tile": args.tile, "mode": "sorted" if args.mode == 0 else "sort-free",
-                      "graph": False},
+                      "tile": f"{cfg.tile_w}x{cfg.tile_h}x{cfg.batch}x{cfg.pix_per_thread}",
+                      "autotuned": args.tile == "auto",
+                      "mode": "sorted" if args.mode == 0 else "sort-free", "graph": bool(args.graph)},
+           "autotune_ms_fwd_bwd": tune_ms,
            "ms_per_frame": round(ms_per_frame, 4),
            "ms_per_iteration_kernels": round(iter_ms, 4) if iter_ms else None,
            "hbm_gbs_iteration": round(hbm_gbs, 1) if hbm_gbs else None,

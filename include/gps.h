@@ -113,9 +113,19 @@ typedef struct gps_render_cfg {
     float alpha_max;         /* opacity cap of sorted mode (0.99)                  */
     float T_min;             /* transmittance stop of sorted mode (1e-4, 0 = off)   */
     float z_near;            /* centres nearer than this are culled (0.2 m)        */
-    int64_t max_instances;   /* capacity for (view, tile, Gaussian) instances;
+    int64_t max_instances;   /* capacity for (view, tile, Gaussian) slots;
                                 0 = 32 per view-Gaussian, at least 2^20            */
+    int32_t flags;           /* GPS_RENDER_VIEWS_PRESET or 0                       */
 } gps_render_cfg;
+
+/* The render kernels read the view table (cameras and image pointers) from the
+ * workspace.  By default gps_render_fwd and gps_render_bwd first write the
+ * table of their `views` argument there.  With this flag they launch no such
+ * upload and use the table written by the last gps_views_upload on the
+ * workspace; the `views` argument must then describe views of the same sizes
+ * (it still sizes the launches).  This lets one captured forward + backward +
+ * Adam iteration be replayed for new camera poses: upload, then replay. */
+#define GPS_RENDER_VIEWS_PRESET 1
 
 /* One Adam parameter group. */
 typedef struct gps_adam_group {
@@ -220,6 +230,14 @@ gps_status gps_render_fwd(const gps_render_cfg* cfg, const gps_gaussians* g, con
 gps_status gps_render_bwd(const gps_render_cfg* cfg, const gps_gaussians* g, const gps_view* views, int32_t n_views,
                           const float* const* dL_drgb, const float* const* dL_ddepth, const float* loss_scale,
                           gps_gaussians* grads, float* dpose, void* ws, size_t ws_bytes, void* stream);
+
+/* Writes the view table of `views` (and, for an explicit-adjoint backward,
+ * the per-view dL_drgb / dL_ddepth device pointers; both may be NULL) into the
+ * workspace, for calls made with GPS_RENDER_VIEWS_PRESET.  Same argument
+ * checks as gps_render_fwd; one small kernel is launched on `stream`. */
+gps_status gps_views_upload(const gps_render_cfg* cfg, const gps_gaussians* g, const gps_view* views,
+                            int32_t n_views, const float* const* dL_drgb, const float* const* dL_ddepth, void* ws,
+                            size_t ws_bytes, void* stream);
 
 /* Adam over n_groups (<= 8) parameter groups in one launch (groups: host
  * array), with the per-attribute learning rates of Appendix C supplied by the

@@ -49,6 +49,7 @@ static gps_status compute_layout(const gps_render_cfg* cfg, int M, const gps_cam
     if (cfg->mode != 0 && cfg->mode != 1) return GPS_ERR_INVALID_ARG;
     if (!tile_config_supported(cfg)) return GPS_ERR_UNSUPPORTED_CONFIG;
     if (cfg->max_instances < 0) return GPS_ERR_INVALID_ARG;
+    if (cfg->flags & ~GPS_RENDER_VIEWS_PRESET) return GPS_ERR_INVALID_ARG;
     const float consts[7] = {cfg->eps_cull, cfg->lambda_depth, cfg->dilation, cfg->alpha_min,
                              cfg->alpha_max, cfg->T_min, cfg->z_near};
     for (float c : consts)
@@ -78,6 +79,8 @@ static gps_status compute_layout(const gps_render_cfg* cfg, int M, const gps_cam
     size_t o = 0;
     L->hdr = o;
     o = align_up(o + 1024);
+    L->vtab = o;
+    o = align_up(o + sizeof(ViewTable));
     L->tilemax = o;
     o = align_up(o + 4 * (size_t)n_tiles);
     L->tile_cnt = o;
@@ -221,6 +224,7 @@ void gps_render_cfg_default(gps_render_cfg* c)
     c->T_min = 1e-4f;
     c->z_near = 0.2f;
     c->max_instances = 0;
+    c->flags = 0;
 }
 
 gps_status gps_workspace_size(const gps_render_cfg* cfg, int32_t n_gaussians, const gps_camera* cams,
@@ -316,6 +320,29 @@ gps_status gps_render_bwd(const gps_render_cfg* cfg, const gps_gaussians* g, con
     if (st != GPS_OK) return st;
     return launch_render_bwd(cfg, rp, g, vt, L, static_cast<char*>(ws), explicit_up, loss_scale, grads, dpose,
                              (hipStream_t)stream);
+}
+
+gps_status gps_views_upload(const gps_render_cfg* cfg, const gps_gaussians* g, const gps_view* views,
+                            int32_t n_views, const float* const* dL_drgb, const float* const* dL_ddepth, void* ws,
+                            size_t ws_bytes, void* stream)
+{
+    ViewTable vt;
+    RParams rp;
+    WsLayout L;
+    gps_status st = build_tables(cfg, g, views, n_views, &vt, &rp, &L);
+    if (st != GPS_OK) return st;
+    if (!ws || ((uintptr_t)ws & 255)) return GPS_ERR_INVALID_ARG;
+    if (ws_bytes < L.total) return GPS_ERR_WORKSPACE_TOO_SMALL;
+    for (int v = 0; v < n_views; ++v) {
+        if (dL_drgb) {
+            if (!dL_drgb[v]) return GPS_ERR_INVALID_ARG;
+            vt.v[v].g_rgb = dL_drgb[v];
+            vt.v[v].g_depth = dL_ddepth ? dL_ddepth[v] : nullptr;
+        }
+    }
+    st = check_device();
+    if (st != GPS_OK) return st;
+    return launch_views_upload(vt, L, static_cast<char*>(ws), (hipStream_t)stream);
 }
 
 gps_status gps_adam_step(const gps_adam_group* groups, int32_t n_groups, int32_t step, int32_t* step_counter,

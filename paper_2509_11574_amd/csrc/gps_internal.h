@@ -81,7 +81,7 @@ struct WsHeader {
 
 struct WsLayout {
     size_t total;
-    size_t hdr, tilemax, tile_cnt, tile_start, tile_cursor, tile_loss, pix_aux, rec, cnt, off, blk_sum, blk_off,
+    size_t hdr, vtab, tilemax, tile_cnt, tile_start, tile_cursor, tile_loss, pix_aux, rec, cnt, off, blk_sum, blk_off,
         keys, inst_vg, partial, pose_part;
     int n_tiles, nvg, nblk_vg, nblk_g;
     unsigned long long cap;
@@ -249,6 +249,7 @@ gps_status launch_render_fwd(const gps_render_cfg* cfg, const RParams& rp, const
 gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const gps_gaussians* g,
                              const ViewTable& vt, const WsLayout& L, char* ws, int explicit_upstream,
                              const float* loss_scale, gps_gaussians* grads, float* dpose, hipStream_t s);
+gps_status launch_views_upload(const ViewTable& vt, const WsLayout& L, char* ws, hipStream_t s);
 gps_status launch_adam(const gps_adam_group* groups, int n_groups, int step, int* step_counter, float b1, float b2,
                        float eps, hipStream_t s);
 gps_status launch_ws_reset(char* ws, hipStream_t s);

@@ -27,6 +27,7 @@ enum KernelId {
     K_ADAM,
     K_STEP_INCR,
     K_WS_RESET,
+    K_UPLOAD,
     K_COUNT
 };
 

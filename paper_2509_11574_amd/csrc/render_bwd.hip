@@ -20,8 +20,9 @@ __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.0f) - (x 
 
 template <int TW, int TH, int B, int PPT>
 __global__ void __launch_bounds__(TW * TH / PPT)
-    k_composite_bwd(ViewTable vt, RParams rp, WsPtrs w, int explicit_up, const float* loss_scale)
+    k_composite_bwd(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w, int explicit_up, const float* loss_scale)
 {
+    const ViewTable& vt = *vtp;
     using Lay = TileLayout<TW, TH, PPT>;
     constexpr int NT = Lay::NT;
     constexpr int NW = Lay::NW;
@@ -236,8 +237,9 @@ __global__ void __launch_bounds__(TW * TH / PPT)
 // ------------------------------------------------------------- gauss bwd
 // EWA chain rule of one Gaussian in one view.  A[10] = dL/d(mx, my, a, b, c,
 // sigma, r, g, b, d) where (a, b, c) is the conic and b multiplies 2 dx dy.
-__global__ void __launch_bounds__(kBlk) k_gauss_bwd(ViewTable vt, RParams rp, GParams gp, GGrads gg, WsPtrs w)
+__global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict__ vtp, RParams rp, GParams gp, GGrads gg, WsPtrs w)
 {
+    const ViewTable& vt = *vtp;
     const int M = rp.M;
     const int g = blockIdx.x * kBlk + threadIdx.x;
     const bool live = g < M;
@@ -475,7 +477,7 @@ __global__ void __launch_bounds__(256) k_pose_reduce(RParams rp, WsPtrs w, int n
 
 // ----------------------------------------------------------------- launch
 template <int TW, int TH, int B, int PPT>
-static void launch_cbwd(const ViewTable& vt, const RParams& rp, const WsPtrs& w, int n_tiles, int explicit_up,
+static void launch_cbwd(const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles, int explicit_up,
                         const float* loss_scale, hipStream_t s)
 {
     GPS_LAUNCH(K_COMPOSITE_BWD, s, (k_composite_bwd<TW, TH, B, PPT>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, vt, rp, w,
@@ -501,7 +503,7 @@ static void launch_cbwd(const ViewTable& vt, const RParams& rp, const WsPtrs& w,
     X(16, 32, 256, 4)         \
     X(16, 32, 512, 4)
 
-static bool dispatch_cbwd(const gps_render_cfg* cfg, const ViewTable& vt, const RParams& rp, const WsPtrs& w,
+static bool dispatch_cbwd(const gps_render_cfg* cfg, const ViewTable* vt, const RParams& rp, const WsPtrs& w,
                           int n_tiles, int explicit_up, const float* loss_scale, hipStream_t s)
 {
 #define X(tw, th, b, ppt)                                                                              \
@@ -521,9 +523,14 @@ gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const
     WsPtrs w = ws_ptrs(ws, L);
     GParams gp{g->mean, g->log_scale, g->quat, g->opacity_logit, g->rgb};
     GGrads gg{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->rgb};
-    if (!dispatch_cbwd(cfg, vt, rp, w, L.n_tiles, explicit_upstream, loss_scale, s)) return GPS_ERR_UNSUPPORTED_CONFIG;
+    const ViewTable* dvt = reinterpret_cast<const ViewTable*>(ws + L.vtab);
+    if (!(cfg->flags & GPS_RENDER_VIEWS_PRESET)) {
+        gps_status st = launch_views_upload(vt, L, ws, s);
+        if (st != GPS_OK) return st;
+    }
+    if (!dispatch_cbwd(cfg, dvt, rp, w, L.n_tiles, explicit_upstream, loss_scale, s)) return GPS_ERR_UNSUPPORTED_CONFIG;
     if (L.nblk_g > 0) {
-        GPS_LAUNCH(K_GAUSS_BWD, s, k_gauss_bwd, dim3(L.nblk_g), dim3(kBlk), 0, s, vt, rp, gp, gg, w);
+        GPS_LAUNCH(K_GAUSS_BWD, s, k_gauss_bwd, dim3(L.nblk_g), dim3(kBlk), 0, s, dvt, rp, gp, gg, w);
         if (dpose) GPS_LAUNCH(K_POSE_REDUCE, s, k_pose_reduce, dim3(vt.n), dim3(256), 0, s, rp, w, L.nblk_g, dpose);
     }
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;

@@ -24,8 +24,9 @@
 namespace gps {
 
 // ------------------------------------------------------------------- prep
-__global__ void __launch_bounds__(256) k_prep(ViewTable vt, RParams rp, WsPtrs w)
+__global__ void __launch_bounds__(256) k_prep(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w)
 {
+    const ViewTable& vt = *vtp;
     const int tile = blockIdx.x;
     if (tile == 0 && threadIdx.x == 0) {
         w.hdr->n_inst = 0ull;
@@ -142,8 +143,9 @@ __device__ __forceinline__ ProjOut project_one(const DevView& V, const RParams& 
     return o;
 }
 
-__global__ void __launch_bounds__(kBlk) k_project(ViewTable vt, RParams rp, GParams gp, WsPtrs w)
+__global__ void __launch_bounds__(kBlk) k_project(const ViewTable* __restrict__ vtp, RParams rp, GParams gp, WsPtrs w)
 {
+    const ViewTable& vt = *vtp;
     const int vg = blockIdx.x * kBlk + threadIdx.x;
     unsigned int count = 0;
     if (vg < rp.nvg) {
@@ -241,8 +243,9 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(RParams rp, WsPtrs w, int n
 //   EMIT:   the same instances get a position in their tile's range and a key
 //           (depth bits << 32) | slot; slot -> view-Gaussian is recorded.
 template <bool EMIT>
-__global__ void __launch_bounds__(kBlk) k_expand(ViewTable vt, RParams rp, WsPtrs w)
+__global__ void __launch_bounds__(kBlk) k_expand(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w)
 {
+    const ViewTable& vt = *vtp;
     if (w.hdr->n_inst > rp.cap) return;
     __shared__ unsigned int pre[kBlk + 1];
     __shared__ float4 sbox[kBlk];  // mx, my, rxp, ryp
@@ -429,8 +432,9 @@ __global__ void __launch_bounds__(256) k_tile_sort_large(RParams rp, WsPtrs w)
 
 // ---------------------------------------------------------- composite fwd
 template <int TW, int TH, int B, int PPT>
-__global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(ViewTable vt, RParams rp, WsPtrs w)
+__global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w)
 {
+    const ViewTable& vt = *vtp;
     using Lay = TileLayout<TW, TH, PPT>;
     constexpr int NT = Lay::NT;
     __shared__ float4 srec[3 * B];
@@ -580,9 +584,10 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(ViewTable vt, R
 }
 
 // ------------------------------------------------------------ loss reduce
-__global__ void __launch_bounds__(256) k_loss_reduce(ViewTable vt, RParams rp, WsPtrs w, float* out_loss,
+__global__ void __launch_bounds__(256) k_loss_reduce(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w, float* out_loss,
                                                      int has_loss)
 {
+    const ViewTable& vt = *vtp;
     float L = 0.0f;
     for (int v = 0; v < vt.n; ++v) {
         const DevView& V = vt.v[v];
@@ -613,9 +618,25 @@ __global__ void __launch_bounds__(256) k_loss_reduce(ViewTable vt, RParams rp, W
     }
 }
 
+// ------------------------------------------------------------ view table
+// Copies the by-value view table into the workspace, so that a replayed
+// sequence of kernels reads whatever table was uploaded last.
+__global__ void __launch_bounds__(256) k_upload_views(ViewTable vt, ViewTable* dst)
+{
+    const unsigned int* src = reinterpret_cast<const unsigned int*>(&vt);
+    unsigned int* d = reinterpret_cast<unsigned int*>(dst);
+    for (int i = threadIdx.x; i < (int)(sizeof(ViewTable) / 4); i += 256) d[i] = src[i];
+}
+
+gps_status launch_views_upload(const ViewTable& vt, const WsLayout& L, char* ws, hipStream_t s)
+{
+    GPS_LAUNCH(K_UPLOAD, s, k_upload_views, dim3(1), dim3(256), 0, s, vt, reinterpret_cast<ViewTable*>(ws + L.vtab));
+    return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
+}
+
 // ----------------------------------------------------------------- launch
 template <int TW, int TH, int B, int PPT>
-static void launch_cfwd(const ViewTable& vt, const RParams& rp, const WsPtrs& w, int n_tiles, hipStream_t s)
+static void launch_cfwd(const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles, hipStream_t s)
 {
     GPS_LAUNCH(K_COMPOSITE_FWD, s, (k_composite_fwd<TW, TH, B, PPT>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, vt, rp, w);
 }
@@ -639,7 +660,7 @@ static void launch_cfwd(const ViewTable& vt, const RParams& rp, const WsPtrs& w,
     X(16, 32, 256, 4)       \
     X(16, 32, 512, 4)
 
-static bool dispatch_cfwd(const gps_render_cfg* cfg, const ViewTable& vt, const RParams& rp, const WsPtrs& w,
+static bool dispatch_cfwd(const gps_render_cfg* cfg, const ViewTable* vt, const RParams& rp, const WsPtrs& w,
                           int n_tiles, hipStream_t s)
 {
 #define X(tw, th, b, ppt)                                                                                  \
@@ -669,16 +690,20 @@ gps_status launch_render_fwd(const gps_render_cfg* cfg, const RParams& rp, const
     int has_loss = 1;
     for (int v = 0; v < vt.n; ++v)
         if (!vt.v[v].target_rgb) has_loss = 0;
-    GPS_LAUNCH(K_PREP, s, k_prep, dim3(L.n_tiles), dim3(256), 0, s, vt, rp, w);
-    if (L.nblk_vg > 0) GPS_LAUNCH(K_PROJECT, s, k_project, dim3(L.nblk_vg), dim3(kBlk), 0, s, vt, rp, gp, w);
+    // the kernels read the view table from the workspace
+    const ViewTable* dvt = reinterpret_cast<const ViewTable*>(ws + L.vtab);
+    if (!(cfg->flags & GPS_RENDER_VIEWS_PRESET))
+        GPS_LAUNCH(K_UPLOAD, s, k_upload_views, dim3(1), dim3(256), 0, s, vt, const_cast<ViewTable*>(dvt));
+    GPS_LAUNCH(K_PREP, s, k_prep, dim3(L.n_tiles), dim3(256), 0, s, dvt, rp, w);
+    if (L.nblk_vg > 0) GPS_LAUNCH(K_PROJECT, s, k_project, dim3(L.nblk_vg), dim3(kBlk), 0, s, dvt, rp, gp, w);
     GPS_LAUNCH(K_SCAN, s, k_scan_blocks, dim3(1), dim3(1024), 0, s, rp, w, L.nblk_vg, L.n_tiles);
-    if (L.nblk_vg > 0) GPS_LAUNCH(K_TILE_COUNT, s, k_expand<false>, dim3(L.nblk_vg), dim3(kBlk), 0, s, vt, rp, w);
+    if (L.nblk_vg > 0) GPS_LAUNCH(K_TILE_COUNT, s, k_expand<false>, dim3(L.nblk_vg), dim3(kBlk), 0, s, dvt, rp, w);
     GPS_LAUNCH(K_SCAN_TILES, s, k_scan_tiles, dim3(1), dim3(1024), 0, s, rp, w, L.n_tiles);
-    if (L.nblk_vg > 0) GPS_LAUNCH(K_EMIT, s, k_expand<true>, dim3(L.nblk_vg), dim3(kBlk), 0, s, vt, rp, w);
+    if (L.nblk_vg > 0) GPS_LAUNCH(K_EMIT, s, k_expand<true>, dim3(L.nblk_vg), dim3(kBlk), 0, s, dvt, rp, w);
     GPS_LAUNCH(K_TILE_SORT, s, k_tile_sort_small, dim3((L.n_tiles + 3) / 4), dim3(256), 0, s, rp, w, L.n_tiles);
     GPS_LAUNCH(K_TILE_SORT_LARGE, s, k_tile_sort_large, dim3(L.n_tiles), dim3(256), kSortCap * sizeof(unsigned long long), s, rp, w);
-    if (!dispatch_cfwd(cfg, vt, rp, w, L.n_tiles, s)) return GPS_ERR_UNSUPPORTED_CONFIG;
-    GPS_LAUNCH(K_LOSS_REDUCE, s, k_loss_reduce, dim3(1), dim3(256), 0, s, vt, rp, w, out_loss, has_loss);
+    if (!dispatch_cfwd(cfg, dvt, rp, w, L.n_tiles, s)) return GPS_ERR_UNSUPPORTED_CONFIG;
+    GPS_LAUNCH(K_LOSS_REDUCE, s, k_loss_reduce, dim3(1), dim3(256), 0, s, dvt, rp, w, out_loss, has_loss);
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
 }
 

@@ -59,7 +59,7 @@ class RenderCfgS(ctypes.Structure):
                 ("pix_per_thread", ctypes.c_int32), ("mode", ctypes.c_int32), ("eps_cull", ctypes.c_float),
                 ("lambda_depth", ctypes.c_float), ("dilation", ctypes.c_float), ("alpha_min", ctypes.c_float),
                 ("alpha_max", ctypes.c_float), ("T_min", ctypes.c_float), ("z_near", ctypes.c_float),
-                ("max_instances", ctypes.c_int64)]
+                ("max_instances", ctypes.c_int64), ("flags", ctypes.c_int32)]
 
 
 class AdamGroupS(ctypes.Structure):
@@ -81,7 +81,7 @@ class KernelTimeS(ctypes.Structure):
 EXPORTS = ["gps_abi_version", "gps_status_string", "gps_render_cfg_default", "gps_workspace_size",
            "gps_workspace_reset", "gps_fuse", "gps_raycast", "gps_render_fwd", "gps_render_bwd",
            "gps_adam_step", "gps_device_status", "gps_read_stats", "gps_profile_start", "gps_profile_stop",
-           "gps_profile_read"]
+           "gps_profile_read", "gps_views_upload"]
 
 _lib = None
 
@@ -109,6 +109,7 @@ def lib():
         L.gps_adam_step.argtypes = [P, I32, I32, P, F, F, F, P]
         L.gps_device_status.argtypes = [P, ctypes.c_size_t, ctypes.POINTER(I32), P]
         L.gps_read_stats.argtypes = [P, ctypes.c_size_t, P, P]
+        L.gps_views_upload.argtypes = [P, P, P, I32, P, P, P, ctypes.c_size_t, P]
         L.gps_profile_start.argtypes = []
         L.gps_profile_stop.argtypes = []
         L.gps_profile_read.argtypes = [P, I32, ctypes.POINTER(I32)]
@@ -243,11 +244,12 @@ class RenderCfg:
     T_min: float = 1e-4
     z_near: float = 0.2
     max_instances: int = 0
+    views_preset: bool = False  # read the view table uploaded by views_upload (for graph replay)
 
     def struct(self) -> RenderCfgS:
         return RenderCfgS(self.tile_w, self.tile_h, self.batch, self.pix_per_thread, self.mode, self.eps_cull,
                           self.lambda_depth, self.dilation, self.alpha_min, self.alpha_max, self.T_min,
-                          self.z_near, int(self.max_instances))
+                          self.z_near, int(self.max_instances), 1 if self.views_preset else 0)
 
 
 # Tile / batch / pixels-per-lane combinations compiled into libgps.
@@ -385,6 +387,22 @@ def render_fwd(cfg: RenderCfg, gauss: dict, views, ws: Workspace, out_loss: torc
     _check(lib().gps_render_fwd(ctypes.byref(cs), ctypes.byref(gs), va, len(views), ws.ptr(), ws.nbytes,
                                 _ptr(out_loss, "out_loss", 1) if out_loss is not None else None, _stream(stream)),
            "gps_render_fwd")
+
+
+def views_upload(cfg: RenderCfg, gauss: dict, views, ws: Workspace, dL_drgb=None, dL_ddepth=None, stream=None):
+    """Write the view table into the workspace for calls made with cfg.views_preset."""
+    cs = cfg.struct()
+    gs = gaussians_struct(gauss)
+    va = _views_array(views)
+    V = len(views)
+    rgb_arr = dep_arr = None
+    if dL_drgb is not None:
+        rgb_arr = (ctypes.c_void_p * V)(*[_ptr(t, "dL_drgb").value for t in dL_drgb])
+        if dL_ddepth is not None:
+            dep_arr = (ctypes.c_void_p * V)(*[_ptr(t, "dL_ddepth").value if t is not None else None
+                                             for t in dL_ddepth])
+    _check(lib().gps_views_upload(ctypes.byref(cs), ctypes.byref(gs), va, V, rgb_arr, dep_arr, ws.ptr(), ws.nbytes,
+                                  _stream(stream)), "gps_views_upload")
 
 
 def render_bwd(cfg: RenderCfg, gauss: dict, views, ws: Workspace, grads: dict, dpose: torch.Tensor | None = None,

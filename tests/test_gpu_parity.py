@@ -431,3 +431,59 @@ def test_long_tile_lists(P, O, M):
     ref = O.render_bwd(oc, case["gauss"], case["cam"], case["base_rgb"], case["base_depth"], gC, gD)
     for k in KEYS:
         assert normwise(got[k], ref[k]) < 1e-3, (k, normwise(got[k], ref[k]))
+
+
+# ------------------------------------------------------------- graph / tuner
+def test_graph_replay_matches_eager(P, O):
+    """A captured iteration (forward + backward + Adam) replayed several times, with eager work and
+    synchronisation between replays, gives bitwise the eager parameters after every replay, also
+    after a new camera pose is uploaded."""
+    from paper_2509_11574_amd.graph import IterationGraph
+    case = tiny_case(7, M=80, W=53, H=37, log_scale=-2.4)
+    gc, _ = cfg_pair(P, O, eps=0.03)
+    cam2 = dict(case["cam"])
+    cam2["t"] = (case["cam"]["t"] + np.array([0.01, -0.02, 0.015])).astype(np.float32)
+
+    def setup():
+        params = gauss_dev(case["gauss"])
+        view = P.View(case["cam"], t(case["base_rgb"]), t(case["base_depth"]), t(case["target_rgb"]),
+                      t(case["target_depth"]))
+        view2 = P.View(cam2, view.base_rgb, view.base_depth, view.target_rgb, view.target_depth)
+        ws = P.Workspace(gc, 80, [case["cam"]], device=DEV)
+        return params, view, view2, ws, P.zeros_like_gaussians(params), P.Adam(params), torch.zeros(1, device=DEV)
+
+    params, view, view2, ws, grads, opt, loss = setup()
+    snaps = []
+    for i in range(5):
+        v = view if i < 3 else view2
+        P.render_fwd(gc, params, [v], ws, out_loss=loss)
+        P.render_bwd(gc, params, [v], ws, grads)
+        opt.step(grads)
+        snaps.append({k: h(x) for k, x in params.items()})
+    params, view, view2, ws, grads, opt, loss = setup()
+    g = IterationGraph(gc, params, [view], ws, grads, opt, loss)
+    for i in range(5):
+        if i == 3:
+            g.set_views([view2])
+        g.replay()
+        torch.cuda.synchronize()
+        _ = torch.randn(4096, device=DEV).sum().item()  # eager work between replays
+        assert ws.status() == 0
+        for k in KEYS:
+            np.testing.assert_array_equal(h(params[k]), snaps[i][k])
+
+
+def test_autotune_picks_a_compiled_config(P, O, tmp_path, monkeypatch):
+    from paper_2509_11574_amd import autotune
+    monkeypatch.setenv("GPS_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    case = tiny_case(8, M=80, W=53, H=37)
+    gc, _ = cfg_pair(P, O, eps=0.03)
+    params = gauss_dev(case["gauss"])
+    view = P.View(case["cam"], t(case["base_rgb"]), t(case["base_depth"]), t(case["target_rgb"]),
+                  t(case["target_depth"]))
+    cfgs = [(16, 16, 256, 1), (8, 8, 128, 1), (16, 16, 256, 4)]
+    best, ms = autotune.autotune(gc, params, [view], configs=cfgs, reps=2)
+    assert (best.tile_w, best.tile_h, best.batch, best.pix_per_thread) in cfgs and len(ms) == 3
+    best2, _ = autotune.autotune(gc, params, [view], configs=cfgs, reps=2)  # from the cache
+    assert (best2.tile_w, best2.tile_h, best2.batch, best2.pix_per_thread) == \
+        (best.tile_w, best.tile_h, best.batch, best.pix_per_thread)
