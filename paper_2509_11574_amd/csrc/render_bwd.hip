@@ -32,7 +32,17 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     __shared__ float slab[S * NW * kAdj];
     __shared__ unsigned char sact[S * NW];  // 1 when the wavefront wrote its partial of record j
     if (w.hdr->n_inst > rp.cap) return;
-    const int tile = blockIdx.x;
+    // Persistent: resident blocks take tiles from the queue (longest first)
+    // until it is empty; every block reaches the exit when the ticket passes
+    // the number of tiles.
+    __shared__ unsigned int s_next;
+    for (;;) {
+    if (threadIdx.x == 0) s_next = atomicAdd(&w.hdr->q_bwd, 1u);
+    __syncthreads();
+    const unsigned int qi = s_next;
+    __syncthreads();
+    if (qi >= (unsigned int)vt.n_tiles) break;
+    const int tile = (int)w.tile_queue[qi];
     const int v = find_view(vt, tile);
     const DevView& V = vt.v[v];
     const int lt = tile - V.tile_base;
@@ -232,6 +242,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
 #pragma unroll
         for (int q = 0; q < kAdj; ++q) out[q] = 0.0f;
     }
+    }  // tile loop
 }
 
 // ------------------------------------------------------------- gauss bwd
@@ -243,6 +254,7 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
     const int M = rp.M;
     const int g = blockIdx.x * kBlk + threadIdx.x;
     const bool live = g < M;
+    if (blockIdx.x == 0 && threadIdx.x == 0) w.hdr->q_bwd = 0u;  // the compositing backward has finished
     float gmean[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.0f, grgb[3] = {0, 0, 0};
     __shared__ float pred[kBlk / 64][6];
 
@@ -480,7 +492,9 @@ template <int TW, int TH, int B, int PPT>
 static void launch_cbwd(const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles, int explicit_up,
                         const float* loss_scale, hipStream_t s)
 {
-    GPS_LAUNCH(K_COMPOSITE_BWD, s, (k_composite_bwd<TW, TH, B, PPT>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, vt, rp, w,
+    static int per_cu = 0;  // resident blocks per CU of this instantiation
+    const int grid = persistent_grid((const void*)k_composite_bwd<TW, TH, B, PPT>, TW * TH / PPT, &per_cu, n_tiles);
+    GPS_LAUNCH(K_COMPOSITE_BWD, s, (k_composite_bwd<TW, TH, B, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, s, vt, rp, w,
                        explicit_up, loss_scale);
 }
 

@@ -31,8 +31,7 @@ __global__ void __launch_bounds__(256) k_prep(const ViewTable* __restrict__ vtp,
     if (tile == 0 && threadIdx.x == 0) {
         w.hdr->n_inst = 0ull;
         w.hdr->n_fallback = 0ull;
-        w.hdr->queue_ctr = 0u;
-        w.hdr->done_ctr = 0u;
+        w.hdr->q_fwd = 0u;
         w.hdr->n_views = rp.V;
     }
     const int v = find_view(vt, tile);
@@ -225,11 +224,34 @@ __global__ void __launch_bounds__(1024) k_scan_blocks(RParams rp, WsPtrs w, int 
     }
 }
 
+// Also orders the tiles for the persistent compositing kernels, longest first:
+// tiles are bucketed by floor(log2(count + 1)) and the buckets laid out in
+// descending order.  The order inside a bucket is arbitrary; it affects only
+// which block processes a tile, never a result.
 __global__ void __launch_bounds__(1024) k_scan_tiles(RParams rp, WsPtrs w, int n_tiles)
 {
     if (w.hdr->n_inst > rp.cap) return;
     scan_array_1024(w.tile_cnt, w.tile_start, n_tiles, 1);
-    for (int i = threadIdx.x; i < n_tiles; i += 1024) w.tile_cursor[i] = w.tile_start[i];
+    __shared__ unsigned int hist[33], cur[33];
+    if (threadIdx.x < 33) hist[threadIdx.x] = 0u;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_tiles; i += 1024) {
+        w.tile_cursor[i] = w.tile_start[i];
+        atomicAdd(&hist[31 - __clz(w.tile_cnt[i] + 1u)], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned int o = 0;
+        for (int bkt = 32; bkt >= 0; --bkt) {
+            cur[bkt] = o;
+            o += hist[bkt];
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n_tiles; i += 1024) {
+        const unsigned int pos = atomicAdd(&cur[31 - __clz(w.tile_cnt[i] + 1u)], 1u);
+        w.tile_queue[pos] = (unsigned int)i;
+    }
 }
 
 // ------------------------------------------------------------ count / emit
@@ -439,7 +461,17 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
     constexpr int NT = Lay::NT;
     __shared__ float4 srec[3 * B];
     if (w.hdr->n_inst > rp.cap) return;
-    const int tile = blockIdx.x;
+    // Persistent: resident blocks take tiles from the queue (longest first)
+    // until it is empty; every block reaches the exit when the ticket passes
+    // the number of tiles.
+    __shared__ unsigned int s_next;
+    for (;;) {
+    if (threadIdx.x == 0) s_next = atomicAdd(&w.hdr->q_fwd, 1u);
+    __syncthreads();
+    const unsigned int qi = s_next;
+    __syncthreads();
+    if (qi >= (unsigned int)vt.n_tiles) break;
+    const int tile = (int)w.tile_queue[qi];
     const int v = find_view(vt, tile);
     const DevView& V = vt.v[v];
     const int lt = tile - V.tile_base;
@@ -581,6 +613,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
         atomicAdd(&w.hdr->pairs_eval, (unsigned long long)tot_eval);  // integer: order-independent
         atomicAdd(&w.hdr->pairs_contrib, (unsigned long long)tot_contrib);
     }
+    }  // tile loop
 }
 
 // ------------------------------------------------------------ loss reduce
@@ -612,6 +645,7 @@ __global__ void __launch_bounds__(256) k_loss_reduce(const ViewTable* __restrict
         }
     }
     if (threadIdx.x == 0) {
+        w.hdr->q_bwd = 0u;  // ticket of the next backward's persistent compositing
         L = L / (float)vt.n;
         w.hdr->loss = has_loss ? L : 0.0f;
         if (out_loss && has_loss) *out_loss = L;
@@ -638,7 +672,9 @@ gps_status launch_views_upload(const ViewTable& vt, const WsLayout& L, char* ws,
 template <int TW, int TH, int B, int PPT>
 static void launch_cfwd(const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles, hipStream_t s)
 {
-    GPS_LAUNCH(K_COMPOSITE_FWD, s, (k_composite_fwd<TW, TH, B, PPT>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s, vt, rp, w);
+    static int per_cu = 0;  // resident blocks per CU of this instantiation
+    const int grid = persistent_grid((const void*)k_composite_fwd<TW, TH, B, PPT>, TW * TH / PPT, &per_cu, n_tiles);
+    GPS_LAUNCH(K_COMPOSITE_FWD, s, (k_composite_fwd<TW, TH, B, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, s, vt, rp, w);
 }
 
 #define GPS_TILE_CONFIGS(X) \
