@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--mode", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="MiB copied (device to device, 3 times) before the workload, so that a counter run can "
+                         "scale FETCH_SIZE / WRITE_SIZE by a copy of known size")
     return ap.parse_args()
 
 
@@ -77,6 +80,15 @@ def main():
     W_img, H_img = (int(x) for x in args.res.split("x"))
     K, Wu, M = args.steps, args.warmup, args.gaussians
     n_frames = Wu + 2 * K  # warmup, timed pass, profiled pass
+
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # ---------------------------------------------------------------- inputs
     t0 = time.time()
