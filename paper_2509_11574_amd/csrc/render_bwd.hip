@@ -35,9 +35,12 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     // Persistent: resident blocks take tiles from the queue (longest first)
     // until it is empty; every block reaches the exit when the ticket passes
     // the number of tiles.
+    // The next ticket is fetched at the end of each tile, in the same thread-0 block
+    // that closes the tile, so the loop head starts with a barrier and no
+    // thread-dependent branch can be threaded across it.
     __shared__ unsigned int s_next;
-    for (;;) {
     if (threadIdx.x == 0) s_next = atomicAdd(&w.hdr->q_bwd, 1u);
+    for (;;) {
     __syncthreads();
     const unsigned int qi = s_next;
     __syncthreads();
@@ -242,6 +245,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
 #pragma unroll
         for (int q = 0; q < kAdj; ++q) out[q] = 0.0f;
     }
+    if (threadIdx.x == 0) s_next = atomicAdd(&w.hdr->q_bwd, 1u);  // next tile
     }  // tile loop
 }
 

@@ -464,9 +464,12 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
     // Persistent: resident blocks take tiles from the queue (longest first)
     // until it is empty; every block reaches the exit when the ticket passes
     // the number of tiles.
+    // The next ticket is fetched at the end of each tile, in the same thread-0 block
+    // that closes the tile, so the loop head starts with a barrier and no
+    // thread-dependent branch can be threaded across it.
     __shared__ unsigned int s_next;
-    for (;;) {
     if (threadIdx.x == 0) s_next = atomicAdd(&w.hdr->q_fwd, 1u);
+    for (;;) {
     __syncthreads();
     const unsigned int qi = s_next;
     __syncthreads();
@@ -612,6 +615,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
         w.tile_loss[tile] = make_float4(lc, ld, lo, 0.0f);
         atomicAdd(&w.hdr->pairs_eval, (unsigned long long)tot_eval);  // integer: order-independent
         atomicAdd(&w.hdr->pairs_contrib, (unsigned long long)tot_contrib);
+        s_next = atomicAdd(&w.hdr->q_fwd, 1u);  // next tile
     }
     }  // tile loop
 }
