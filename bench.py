@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--mode", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--batched", type=int, default=1,
+                    help="also time the 8-keyframe batch (one 8-view iteration) against 8 single-view iterations")
+    ap.add_argument("--large-frames", type=int, default=6,
+                    help="frames timed on the 512^3 / 1M-Gaussian / 4-keyframe workload (0 skips it)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB copied (device to device, 3 times) before the workload, so that a counter run can "
                          "scale FETCH_SIZE / WRITE_SIZE by a copy of known size")
@@ -235,6 +239,10 @@ def main():
         iter_ms = sum(kernels[n][1] for n in it_kernels if n in kernels) / (K * ITERS_PER_FRAME)
     hbm_gbs = bytes_iter / (iter_ms / 1e3) / 1e9 if iter_ms else None
 
+    # ----------------------------------- batched keyframes and the large map
+    batched = bench_batched(P, synth, dev, cfg, reps=20) if args.batched else None
+    large = bench_large(P, synth, dev, cfg, args.large_frames) if args.large_frames > 0 else None
+
     # ------------------------------- reference implementation on the host
     cpu = None
     if not args.no_cpu_baseline:
@@ -255,9 +263,158 @@ def main():
            "instances": I, "pairs": pairs,
            "loss_first_last": [round(first_loss, 6), round(last_loss, 6)],
            "roofline": roofline,
+           "batched_keyframes": batched,
+           "large_map": large,
            "kernels_ms_per_frame": {n: round(v[1] / K, 4) for n, v in sorted(kernels.items(), key=lambda x: -x[1][1])},
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
+
+
+def _window_views(P, synth, scene, vol, cams, frames, dev, cfg):
+    """Views of a window of keyframes: each frame fused into `vol`, then every
+    keyframe's SDF base image raycast from the fused map (cached for the window)."""
+    import torch
+    views = []
+    for cam, (depth, rgb) in zip(cams, frames):
+        P.fuse(vol, cam.as_dict(), depth, rgb)
+    for cam, (depth, rgb) in zip(cams, frames):
+        bd = torch.empty(cam.height, cam.width, device=dev)
+        bc = torch.empty(3, cam.height, cam.width, device=dev)
+        P.raycast(vol, [cam.as_dict()], z_near=cfg.z_near, out=[(bd, bc)])
+        views.append(P.View(cam.as_dict(), bc, bd, rgb, depth))
+    return views
+
+
+def bench_batched(P, synth, dev, cfg, reps=20, n_gauss=300_000):
+    """Eight keyframes of mixed resolution (3 x 1280x720, 3 x 640x480, 2 x 320x240 at
+    orbit frames 0, 12, ..., 87 of the room) sharing 300,000 Gaussians.  Batched: one
+    iteration renders, differentiates and steps all eight views (one forward and one
+    backward launch each, one graph).  Per-frame: eight single-view iterations in
+    sequence (eight graphs, eight Adam steps).  Both produce the same per-view
+    gradients; the batched form averages them into one step."""
+    import torch
+
+    from paper_2509_11574_amd.graph import IterationGraph
+    scene = synth.scene_room(256)
+    cams, frames = [], []
+    for (k, W, H) in synth.STANDARD_VIEWS:
+        cam = synth.orbit_cameras(0, W, H, frames=[k])[0]
+        cams.append(cam)
+        frames.append(synth.render_frame(scene, cam, noise_sigma_per_m2=1e-3, frame_index=k, device=dev,
+                                         as_torch=True))
+    seed_cams = synth.orbit_cameras(0, 1280, 720, frames=list(range(0, 100, 10)))
+    seed_depths = [synth.render_frame(scene, c, device=dev, as_torch=True)[0].cpu().numpy() for c in seed_cams]
+    params = P.gaussians_to_device(synth.seed_gaussians(scene, seed_cams, seed_depths, n_gauss), dev)
+    vol = P.Volume(scene.dims, scene.origin, scene.voxel, scene.trunc, device=dev)
+    views = _window_views(P, synth, scene, vol, cams, frames, dev, cfg)
+    grads = P.zeros_like_gaussians(params)
+
+    def timed(fn, n):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    opt_b = P.Adam(params)
+    ws_b = P.Workspace(cfg, n_gauss, [v.cam for v in views], device=dev)
+    loss_b = torch.zeros(1, device=dev)
+    g_b = IterationGraph(cfg, params, views, ws_b, grads, opt_b, loss_b, torch.zeros(len(views), 6, device=dev))
+    t_b = timed(g_b.replay, reps)
+    st = ws_b.stats()
+    if st["status"] != 0:
+        raise RuntimeError(f"batched keyframes: device status {st}")
+    inst_b = st["n_instances"]
+    del g_b, ws_b
+    opt_s = P.Adam(params)
+    graphs = []
+    for v in views:
+        ws = P.Workspace(cfg, n_gauss, [v.cam], device=dev)
+        graphs.append((IterationGraph(cfg, params, [v], ws, grads, opt_s, torch.zeros(1, device=dev),
+                                      torch.zeros(1, 6, device=dev)), ws))
+
+    def seq():
+        for g, _ in graphs:
+            g.replay()
+    t_s = timed(seq, reps)
+    for _, ws in graphs:
+        if ws.status() != 0:
+            raise RuntimeError("per-frame keyframes: device status")
+    nv = len(views)
+    log(f"keyframe batch: batched {1e3 * t_b:.3f} ms per 8-view iteration, sequential {1e3 * t_s:.3f} ms "
+        f"for 8 single-view iterations")
+    return {"workload": "8 keyframes (3x1280x720, 3x640x480, 2x320x240), 300000 Gaussians, 256^3 room",
+            "instances": inst_b,
+            "batched_ms_per_iteration": round(1e3 * t_b, 4),
+            "sequential_ms_per_8_iterations": round(1e3 * t_s, 4),
+            "batched_view_iters_per_s": round(nv / t_b, 1),
+            "sequential_view_iters_per_s": round(nv / t_s, 1),
+            "speedup": round(t_s / t_b, 3)}
+
+
+def bench_large(P, synth, dev, cfg, n_frames, n_gauss=1_000_000, warm=2):
+    """Large map: the room at 5 mm (512^3 lattice, 3.2 GB of volume), 1280x720 orbit
+    frames fused every frame, 1,000,000 Gaussians, and per frame 10 batched
+    iterations over the latest 4 keyframes (one keyframe every 10 frames; a new
+    keyframe's base image is raycast when it enters the window)."""
+    import torch
+
+    from paper_2509_11574_amd.graph import IterationGraph
+    scene = synth.scene_room(512)
+    W, H = 1280, 720
+    total = warm + n_frames
+    first = 40  # the window starts full: keyframes at frames 10, 20, 30, 40
+    idx = list(range(first - 30, first + 1 + total))  # frames 10 .. 41 + total
+    cams = synth.orbit_cameras(0, W, H, frames=idx)
+    frames = [synth.render_frame(scene, c, noise_sigma_per_m2=1e-3, frame_index=k, device=dev, as_torch=True)
+              for k, c in zip(idx, cams)]
+    seed_cams = synth.orbit_cameras(0, W, H, frames=list(range(0, 100, 10)))
+    seed_depths = [synth.render_frame(scene, c, device=dev, as_torch=True)[0].cpu().numpy() for c in seed_cams]
+    params = P.gaussians_to_device(synth.seed_gaussians(scene, seed_cams, seed_depths, n_gauss), dev)
+    vol = P.Volume(scene.dims, scene.origin, scene.voxel, scene.trunc, device=dev)
+    kf = [30, 0, 10, 20]  # frames 40, 10, 20, 30: window slot (frame / 10) mod 4 holds that keyframe
+    views = _window_views(P, synth, scene, vol, [cams[i] for i in kf], [frames[i] for i in kf], dev, cfg)
+    grads = P.zeros_like_gaussians(params)
+    opt = P.Adam(params)
+    ws = P.Workspace(cfg, n_gauss, [v.cam for v in views], device=dev)
+    g = IterationGraph(cfg, params, views, ws, grads, opt, torch.zeros(1, device=dev),
+                       torch.zeros(len(views), 6, device=dev))
+    ring = [(v.base_depth, v.base_rgb) for v in views]
+
+    def frame(i):
+        cam = cams[i]
+        depth, rgb = frames[i]
+        P.fuse(vol, cam.as_dict(), depth, rgb)
+        if idx[i] % 10 == 0:  # new keyframe: raycast its base into the oldest slot
+            slot = (idx[i] // 10) % 4
+            bd, bc = ring[slot]
+            P.raycast(vol, [cam.as_dict()], z_near=cfg.z_near, out=[(bd, bc)])
+            views[slot] = P.View(cam.as_dict(), bc, bd, rgb, depth)
+            g.set_views(views)
+        for _ in range(ITERS_PER_FRAME):
+            g.replay()
+
+    for i in range(31, 31 + warm):
+        frame(i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(31 + warm, 31 + warm + n_frames):
+        frame(i)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / n_frames
+    st = ws.stats()
+    if st["status"] != 0:
+        raise RuntimeError(f"large map: device status {st}")
+    log(f"large map: {1e3 * dt:.3f} ms per frame, {ITERS_PER_FRAME / dt:.1f} batched iterations/s")
+    return {"workload": "512^3 TSDF at 5 mm, 1280x720 frames fused every frame, 1000000 Gaussians, "
+                        "10 batched iterations per frame over the latest 4 keyframes",
+            "frames": n_frames, "ms_per_frame": round(1e3 * dt, 3),
+            "batched_iters_per_s": round(ITERS_PER_FRAME / dt, 2),
+            "view_iters_per_s": round(4 * ITERS_PER_FRAME / dt, 1),
+            "instances": st["n_instances"]}
 
 
 def cpu_baseline(scene, cam, frame, gauss_np, cfg):

@@ -166,28 +166,33 @@ __device__ __forceinline__ float d32_lerp(float a, float b, float f)
 // ---------------------------------------------------------------------------
 // Opacity of a projected Gaussian at a pixel, Eq. 3:
 //   alpha = sigma * exp(-0.5 * (a dx^2 + 2 b dx dy + c dy^2)).
-// Written with explicit fused operations so that the forward and the backward
-// kernels evaluate bit-identical values (the backward recomputes the
-// transmittance and must stop at the same Gaussian as the forward).
+// The projection stores the conic pre-scaled for a base-2 exponential,
+//   A' = -0.5 log2(e) a,  B' = -log2(e) b,  C' = -0.5 log2(e) c,
+// and log2(sigma), so that
+//   alpha = exp2(A' dx^2 + B' dx dy + C' dy^2 + log2 sigma)
+// costs three products, three fused multiply-adds and one v_exp_f32.  The
+// squares dx^2, dx dy, dy^2 are kept: the backward reuses them.  The
+// operations are written out with explicit fused multiply-adds so that the
+// forward and the backward kernels evaluate bit-identical values (the
+// backward recomputes the transmittance and must stop at the same Gaussian).
 // ---------------------------------------------------------------------------
 struct AlphaEval {
-    float raw;    // sigma * e
-    float e;      // exp(power)
-    float dx, dy;
+    float raw;  // alpha before the cap
+    float dx, dy, dxx, dxy, dyy;
 };
 
-__device__ __forceinline__ AlphaEval eval_alpha(float px, float py, float mx, float my, float ca, float cb,
-                                                float cc, float sigma)
+__device__ __forceinline__ AlphaEval eval_alpha(float px, float py, float mx, float my, float A, float B, float C,
+                                                float log2_sigma)
 {
 #pragma clang fp contract(off)
     AlphaEval r;
     r.dx = px - mx;
     r.dy = py - my;
-    float q = __builtin_fmaf(ca * r.dx, r.dx, cc * r.dy * r.dy);
-    q = __builtin_fmaf(2.0f * cb * r.dx, r.dy, q);
-    float power = -0.5f * q;
-    r.e = __expf(power);
-    r.raw = sigma * r.e;
+    r.dxx = r.dx * r.dx;
+    r.dxy = r.dx * r.dy;
+    r.dyy = r.dy * r.dy;
+    const float pw = __builtin_fmaf(A, r.dxx, __builtin_fmaf(B, r.dxy, __builtin_fmaf(C, r.dyy, log2_sigma)));
+    r.raw = __builtin_amdgcn_exp2f(pw);
     return r;
 }
 
@@ -210,6 +215,34 @@ __device__ __forceinline__ float wave_sum_to_lane63(float v)
     v += dpp_f<0x142, 0xa, 0xf, false>(v);  // row_bcast:15 into rows 1 and 3
     v += dpp_f<0x143, 0xc, 0xf, false>(v);  // row_bcast:31 into rows 2 and 3
     return v;
+}
+
+// Sums each of ten per-lane values over each 16-lane row of the wavefront and
+// stores the row totals at dst[row * 10 + q] (LDS, 40 floats).  A transpose-
+// reduction within rows, DPP only: the pairs (q, q+5) are exchanged between
+// lanes i and i^8 (row_ror:8), then pairs of the five results between i and
+// 7-i within each half-row (row_half_mirror), then between i and i^2 and i^1
+// (quad_perm).  Each exchange keeps one value of the pair, sends the other and
+// adds the partner's: 15 + 7 + 4 + 3 = 29 VALU operations, against 40 for ten
+// independent row reductions.  Lane bits (b3 b2 b1 b0) of the row then hold
+// value (b1 ? 2 : 0) + b2 + 5 b3 when b0 = 0 and value 4 + 5 b3 when b0 = 1 (written
+// from the lanes with b1 = b2 = 0).  Every lane must be active; the summation
+// order is fixed.
+__device__ __forceinline__ void wave_rows_sum10_store(const float (&g)[10], float* dst, int lane)
+{
+    const int i = lane & 15;
+    const bool s3 = (i & 8) != 0, s2 = (i & 4) != 0, s1 = (i & 2) != 0, s0 = (i & 1) != 0;
+    float h[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) h[q] = (s3 ? g[q + 5] : g[q]) + dpp_f<0x128>(s3 ? g[q] : g[q + 5]);  // row_ror:8
+    const float p0 = (s2 ? h[1] : h[0]) + dpp_f<0x141>(s2 ? h[0] : h[1]);  // row_half_mirror
+    const float p1 = (s2 ? h[3] : h[2]) + dpp_f<0x141>(s2 ? h[2] : h[3]);
+    const float p2 = h[4] + dpp_f<0x141>(h[4]);
+    const float r0 = (s1 ? p1 : p0) + dpp_f<0x4E>(s1 ? p0 : p1);  // quad_perm [2,3,0,1]
+    const float r1 = p2 + dpp_f<0x4E>(p2);
+    const float f = (s0 ? r1 : r0) + dpp_f<0xB1>(s0 ? r0 : r1);  // quad_perm [1,0,3,2]
+    const int idx = s0 ? 4 + 5 * (int)s3 : (s1 ? 2 : 0) + (int)s2 + 5 * (int)s3;
+    if (!s0 || (!s1 && !s2)) dst[(lane >> 4) * 10 + idx] = f;
 }
 
 // Sum over the 64 lanes, result uniform across the wave.

@@ -2,10 +2,12 @@
 //
 //   k_composite_bwd<TW,TH,B,PPT>  per tile: recompute the front-to-back
 //       traversal of every pixel (transmittance T_i and prefix colour/depth
-//       P_i), form dL/d{centre, conic, sigma, colour, depth} of each
-//       contributor, reduce them over the tile's pixels (DPP within each
-//       wavefront, LDS across wavefronts, fixed order) and write ONE 10-float
-//       partial per (tile, Gaussian) instance into that instance's slot.
+//       P_i), form the adjoints of each contributor's centre, conic, opacity,
+//       colour and depth (the first six in the base-2 form of the opacity, see
+//       k_gauss_bwd), reduce them over the tile's pixels (a DPP
+//       transpose-reduction within each 16-lane row, LDS across rows and
+//       wavefronts, fixed order) and write ONE 10-float partial per (tile, Gaussian) instance
+//       into that instance's slot.
 //   k_gauss_bwd   per Gaussian: sum its instance partials (a contiguous slot
 //       range per view, summed in order), apply the EWA chain rule to the
 //       parameters and form the per-Gaussian pose terms, reduced per block.
@@ -18,7 +20,7 @@ namespace gps {
 
 __device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.0f) - (x < 0.0f)); }
 
-template <int TW, int TH, int B, int PPT>
+template <int TW, int TH, int B, int PPT, int MODE>
 __global__ void __launch_bounds__(TW * TH / PPT)
     k_composite_bwd(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w, int explicit_up, const float* loss_scale)
 {
@@ -28,8 +30,9 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     constexpr int NW = Lay::NW;
     __shared__ float4 srec[3 * B];
     __shared__ unsigned int sslot[B];
+    __shared__ unsigned char smask[B];
     constexpr int S = kFlush;                // records per flush of the per-wavefront partials
-    __shared__ float slab[S * NW * kAdj];
+    __shared__ float slab[S * NW * 4 * kAdj];  // per record and wavefront: four row partials
     __shared__ unsigned char sact[S * NW];  // 1 when the wavefront wrote its partial of record j
     if (w.hdr->n_inst > rp.cap) return;
     // Persistent: resident blocks take tiles from the queue (longest first)
@@ -54,8 +57,6 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     const size_t HW = (size_t)Wd * Ht;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int wx0 = tx * TW + Lay::wave_x0(wid), wy0 = ty * TH + Lay::wave_y0(wid);
-    const float fwx0 = (float)wx0, fwx1 = (float)(wx0 + Lay::WW - 1);
-    const float fwy0 = (float)wy0, fwy1 = (float)(wy0 + Lay::WH - 1);
     const int px = wx0 + Lay::lane_x(lane);
     const int py0 = wy0 + Lay::lane_y(lane);
     const float fpx = (float)px;
@@ -67,7 +68,8 @@ __global__ void __launch_bounds__(TW * TH / PPT)
 
     float thr[PPT], T[PPT], G0[PPT], G1[PPT], G2[PPT], GD[PPT], Cs0[PPT], Cs1[PPT], Cs2[PPT], Ds[PPT];
     float P0[PPT], P1[PPT], P2[PPT], PD[PPT], Wg[PPT];
-    bool done[PPT];
+    // thr as in the forward: -inf once a pixel has stopped for a reason other
+    // than the depth test (which every deeper record fails as well)
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int py = py0 + k * Lay::LROWS;
@@ -75,7 +77,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         const size_t p = inb ? (size_t)py * Wd + px : 0;
         const float dt = inb ? V.base_depth[p] : 0.0f;
         const bool dvalid = dt > 0.0f;
-        thr[k] = (dvalid ? dt : INFINITY) + rp.eps;
+        thr[k] = inb ? (dvalid ? dt : INFINITY) + rp.eps : -INFINITY;
         T[k] = 1.0f;
         P0[k] = P1[k] = P2[k] = PD[k] = 0.0f;
         Cs0[k] = Cs1[k] = Cs2[k] = Ds[k] = 0.0f;
@@ -86,7 +88,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
             Cs1[k] = V.out_rgb[HW + p];
             Cs2[k] = V.out_rgb[2 * HW + p];
             Ds[k] = V.out_depth[p];
-            if (rp.mode == 1) Wg[k] = w.pix_aux[(size_t)V.pix_base + p];
+            if (MODE == 1) Wg[k] = w.pix_aux[(size_t)V.pix_base + p];
             if (explicit_up) {
                 G0[k] = V.g_rgb[p];
                 G1[k] = V.g_rgb[HW + p];
@@ -103,24 +105,28 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                 }
             }
         }
-        done[k] = !inb;
     }
 
     const unsigned int s = w.tile_start[tile], e = w.tile_start[tile + 1];
+    const int tx0 = tx * TW, ty0 = ty * TH;
     unsigned int stop = s;  // first position whose partial has not been written
+    bool wave_alive = true;  // some pixel of this wavefront still takes records
     for (unsigned int b = s; b < e; b += B) {
-        int alive = 0;
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) alive |= !done[k];
-        if (__syncthreads_count(alive) == 0) break;
-        for (int j = threadIdx.x; j < B && b + j < e; j += NT) {
-            const unsigned int slot = (unsigned int)w.keys[b + j];
-            unsigned int vg = slot < rp.cap ? w.inst_vg[slot] : 0u;
-            if (vg >= (unsigned int)rp.nvg) vg = 0u;  // guard: never read outside the records
-            const float4* r = w.rec + 3 * (size_t)vg;
-            srec[3 * j + 0] = r[0];
-            srec[3 * j + 1] = r[1];
-            srec[3 * j + 2] = r[2];
+        if (__syncthreads_count(wave_alive && lane == 0) == 0) break;
+        for (int j = threadIdx.x; j < B; j += NT) {
+            unsigned int mk = 0u, slot = 0xffffffffu;
+            if (b + j < e) {
+                slot = (unsigned int)w.keys[b + j];
+                unsigned int vg = slot < rp.cap ? w.inst_vg[slot] : 0u;
+                if (vg >= (unsigned int)rp.nvg) vg = 0u;  // guard: never read outside the records
+                const float4* r = w.rec + 3 * (size_t)vg;
+                const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+                srec[3 * j + 0] = r0;
+                srec[3 * j + 1] = r1;
+                srec[3 * j + 2] = r2;
+                mk = wave_box_mask<Lay>(r0.x, r0.y, r2.z, r2.w, tx0, ty0);
+            }
+            smask[j] = (unsigned char)mk;
             sslot[j] = slot;
         }
         __syncthreads();
@@ -128,108 +134,109 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         int alive_now = 1;
         for (int j0 = 0; j0 < n && alive_now; j0 += S) {
             const int j1 = min(j0 + S, n);
-            for (int j = j0; j < j1; ++j) {
-                const float4 r0 = srec[3 * j], r2 = srec[3 * j + 2];
+            // Records of this window whose box touches this wavefront (as in the forward).
+            const int jl = j0 + lane;
+            unsigned long long m =
+                __builtin_amdgcn_ballot_w64(wave_alive && lane < S && jl < j1 && ((smask[jl] >> wid) & 1u));
+            unsigned long long written = 0ull;  // window records whose partial this wavefront wrote
+            while (m) {
+                const int jw = (int)__builtin_ctzll(m);
+                m &= m - 1ull;
+                const int j = j0 + jw;
+                const float4 r0 = srec[3 * j], r1 = srec[3 * j + 1], r2 = srec[3 * j + 2];
+                const float c0 = r1.w, c1 = r2.x, c2 = r2.y, zi = r1.z;
+                const float A2 = r0.z + r0.z, C2 = r1.x + r1.x;
                 bool act = false;
+                // g: (d/dm_x, d/dm_y) of the base-2 exponent's accumulations, the
+                // three conic terms, d alpha * alpha (sigma), colour, depth.
                 float g[kAdj];
 #pragma unroll
                 for (int q = 0; q < kAdj; ++q) g[q] = 0.0f;
-                // Same wavefront-level skip as the forward: no pixel of this wavefront is in the box.
-                const bool miss =
-                    r0.x + r2.z < fwx0 || r0.x - r2.z > fwx1 || r0.y + r2.w < fwy0 || r0.y - r2.w > fwy1;
-                if (!miss) {
-                    const float4 r1 = srec[3 * j + 1];
-                    const float c0 = r1.w, c1 = r2.x, c2 = r2.y, zi = r1.z;
+                unsigned long long any_live = 0ull;
 #pragma unroll
-                    for (int k = 0; k < PPT; ++k) {
-                        if (done[k]) continue;
-                        if (!(zi < thr[k])) {
-                            done[k] = true;
-                            continue;
-                        }
-                        const AlphaEval ae =
-                            eval_alpha(fpx, (float)(py0 + k * Lay::LROWS), r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
-                        float a, dal;
-                        bool alpha_path;
-                        if (rp.mode == 0) {
-                            a = fminf(rp.amax, ae.raw);
-                            if (a < rp.amin) continue;
-                            const float Tn = T[k] * (1.0f - a);
-                            if (Tn < rp.Tmin) {
-                                done[k] = true;
-                                continue;
-                            }
-                            const float wgt = a * T[k];
-                            P0[k] = __builtin_fmaf(wgt, c0, P0[k]);
-                            P1[k] = __builtin_fmaf(wgt, c1, P1[k]);
-                            P2[k] = __builtin_fmaf(wgt, c2, P2[k]);
-                            PD[k] = __builtin_fmaf(wgt, zi, PD[k]);
-                            g[6] += wgt * G0[k];
-                            g[7] += wgt * G1[k];
-                            g[8] += wgt * G2[k];
-                            g[9] += wgt * GD[k];
-                            const float direct = G0[k] * c0 + G1[k] * c1 + G2[k] * c2 + GD[k] * zi;
-                            const float rest = G0[k] * (Cs0[k] - P0[k]) + G1[k] * (Cs1[k] - P1[k]) +
-                                               G2[k] * (Cs2[k] - P2[k]) + GD[k] * (Ds[k] - PD[k]);
-                            dal = T[k] * direct - rest / (1.0f - a);
-                            alpha_path = ae.raw <= rp.amax;
-                            T[k] = Tn;
-                        } else {
-                            a = ae.raw;
-                            if (a < rp.amin) continue;
-                            const float inv = 1.0f / (1.0f + Wg[k]);
-                            const float ai = a * inv;
-                            g[6] += ai * G0[k];
-                            g[7] += ai * G1[k];
-                            g[8] += ai * G2[k];
-                            g[9] += ai * GD[k];
-                            dal = inv * (G0[k] * (c0 - Cs0[k]) + G1[k] * (c1 - Cs1[k]) + G2[k] * (c2 - Cs2[k]) +
-                                         GD[k] * (zi - Ds[k]));
-                            alpha_path = true;
-                        }
-                        act = true;
-                        if (alpha_path) {
-                            const float dp = dal * a;  // d alpha / d power = alpha
-                            g[5] += dal * ae.e;        // d alpha / d sigma = exp(power)
-                            g[0] += dp * (r0.z * ae.dx + r0.w * ae.dy);
-                            g[1] += dp * (r0.w * ae.dx + r1.x * ae.dy);
-                            g[2] += -0.5f * dp * ae.dx * ae.dx;
-                            g[3] += -dp * ae.dx * ae.dy;
-                            g[4] += -0.5f * dp * ae.dy * ae.dy;
-                        }
+                for (int k = 0; k < PPT; ++k) {
+                    // the forward's decisions, in the same order and arithmetic
+                    const bool live = zi < thr[k];
+                    any_live |= __builtin_amdgcn_ballot_w64(live);
+                    const AlphaEval ae =
+                        eval_alpha(fpx, (float)(py0 + k * Lay::LROWS), r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
+                    bool use;
+                    float a, Tn = 0.0f;
+                    if (MODE == 0) {
+                        a = fminf(ae.raw, rp.amax);
+                        const bool ok = live && a >= rp.amin;
+                        Tn = T[k] * (1.0f - a);
+                        const bool stop = ok && Tn < rp.Tmin;
+                        use = ok && !stop;
+                        thr[k] = stop ? -INFINITY : thr[k];
+                    } else {
+                        a = ae.raw;
+                        use = live && a >= rp.amin;
                     }
-                }
-                const bool wact = wave_any(act);
-                if (wact) {
-                    float* dst = slab + ((j - j0) * NW + wid) * kAdj;
-#pragma unroll
-                    for (int q = 0; q < kAdj; ++q) {
-                        const float t = wave_sum_to_lane63(g[q]);
-                        if (lane == 63) dst[q] = t;
+                    if (!use) continue;
+                    float dal;
+                    bool alpha_path;
+                    if (MODE == 0) {
+                        const float wgt = a * T[k];
+                        P0[k] = __builtin_fmaf(wgt, c0, P0[k]);
+                        P1[k] = __builtin_fmaf(wgt, c1, P1[k]);
+                        P2[k] = __builtin_fmaf(wgt, c2, P2[k]);
+                        PD[k] = __builtin_fmaf(wgt, zi, PD[k]);
+                        g[6] = __builtin_fmaf(wgt, G0[k], g[6]);
+                        g[7] = __builtin_fmaf(wgt, G1[k], g[7]);
+                        g[8] = __builtin_fmaf(wgt, G2[k], g[8]);
+                        g[9] = __builtin_fmaf(wgt, GD[k], g[9]);
+                        const float direct = G0[k] * c0 + G1[k] * c1 + G2[k] * c2 + GD[k] * zi;
+                        const float rest = G0[k] * (Cs0[k] - P0[k]) + G1[k] * (Cs1[k] - P1[k]) +
+                                           G2[k] * (Cs2[k] - P2[k]) + GD[k] * (Ds[k] - PD[k]);
+                        dal = T[k] * direct - rest * __builtin_amdgcn_rcpf(1.0f - a);  // v_rcp_f32, 1 ulp
+                        alpha_path = ae.raw <= rp.amax;  // a capped opacity has no gradient
+                        T[k] = Tn;
+                    } else {
+                        const float inv = __builtin_amdgcn_rcpf(1.0f + Wg[k]);
+                        const float ai = a * inv;
+                        g[6] = __builtin_fmaf(ai, G0[k], g[6]);
+                        g[7] = __builtin_fmaf(ai, G1[k], g[7]);
+                        g[8] = __builtin_fmaf(ai, G2[k], g[8]);
+                        g[9] = __builtin_fmaf(ai, GD[k], g[9]);
+                        dal = inv * (G0[k] * (c0 - Cs0[k]) + G1[k] * (c1 - Cs1[k]) + G2[k] * (c2 - Cs2[k]) +
+                                     GD[k] * (zi - Ds[k]));
+                        alpha_path = true;
                     }
+                    act = true;
+                    // alpha = exp2(pw): d alpha / d pw = alpha ln 2; the constant
+                    // factors are applied once per Gaussian.
+                    const float u = alpha_path ? dal * a : 0.0f;
+                    g[5] += u;
+                    g[0] = __builtin_fmaf(u, __builtin_fmaf(A2, ae.dx, r0.w * ae.dy), g[0]);
+                    g[1] = __builtin_fmaf(u, __builtin_fmaf(C2, ae.dy, r0.w * ae.dx), g[1]);
+                    g[2] = __builtin_fmaf(u, ae.dxx, g[2]);
+                    g[3] = __builtin_fmaf(u, ae.dxy, g[3]);
+                    g[4] = __builtin_fmaf(u, ae.dyy, g[4]);
                 }
-                if (lane == 0) sact[(j - j0) * NW + wid] = wact ? 1 : 0;
+                if (wave_any(act)) {
+                    wave_rows_sum10_store(g, slab + (jw * NW + wid) * 4 * kAdj, lane);
+                    written |= 1ull << jw;
+                }
+                if (!any_live) {  // this record and all deeper ones fail every pixel
+                    wave_alive = false;
+                    break;
+                }
             }
-            int alive = 0;
+            if (lane < S) sact[lane * NW + wid] = (unsigned char)((written >> lane) & 1ull);
+            alive_now = __syncthreads_count(wave_alive && lane == 0);
+            // one thread per (record, component): sum the wavefront partials in order
+            for (int t = threadIdx.x; t < (j1 - j0) * kAdj; t += NT) {
+                const int jr = t / kAdj, q = t - jr * kAdj;
+                float acc = 0.0f;
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) alive |= !done[k];
-            alive_now = __syncthreads_count(alive);
-            for (int t = threadIdx.x; t < j1 - j0; t += NT) {
-                float acc[kAdj];
-#pragma unroll
-                for (int q = 0; q < kAdj; ++q) acc[q] = 0.0f;
-#pragma unroll
-                for (int ww = 0; ww < NW; ++ww) {
-                    if (!sact[t * NW + ww]) continue;
-#pragma unroll
-                    for (int q = 0; q < kAdj; ++q) acc[q] += slab[(t * NW + ww) * kAdj + q];
-                }
-                const unsigned int slot = sslot[j0 + t];
-                if (slot < rp.cap) {
-                    float* out = w.partial + (size_t)slot * kAdj;
-#pragma unroll
-                    for (int q = 0; q < kAdj; ++q) out[q] = acc[q];
-                }
+                for (int ww = 0; ww < NW; ++ww)
+                    if (sact[jr * NW + ww]) {
+                        const float* sp = slab + (jr * NW + ww) * 4 * kAdj + q;
+                        acc += (sp[0] + sp[kAdj]) + (sp[2 * kAdj] + sp[3 * kAdj]);
+                    }
+                const unsigned int slot = sslot[j0 + jr];
+                if (slot < rp.cap) w.partial[(size_t)slot * kAdj + q] = acc;
             }
             __syncthreads();
             stop = b + (unsigned int)j1;  // positions before this were written
@@ -250,8 +257,9 @@ __global__ void __launch_bounds__(TW * TH / PPT)
 }
 
 // ------------------------------------------------------------- gauss bwd
-// EWA chain rule of one Gaussian in one view.  A[10] = dL/d(mx, my, a, b, c,
-// sigma, r, g, b, d) where (a, b, c) is the conic and b multiplies 2 dx dy.
+// EWA chain rule of one Gaussian in one view.  The summed instance partials are
+// first turned into A[10] = dL/d(mx, my, a, b, c), sigma dL/dsigma, dL/d(r, g, b, d),
+// where (a, b, c) is the conic and b multiplies 2 dx dy.
 __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict__ vtp, RParams rp, GParams gp, GGrads gg, WsPtrs w)
 {
     const ViewTable& vt = *vtp;
@@ -320,6 +328,18 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
             for (unsigned int k = 0; k < cnt; ++k)
 #pragma unroll
                 for (int q = 0; q < kAdj; ++q) A[q] += part[(size_t)k * kAdj + q];
+            // The compositing kernel accumulates, with u = dL/dalpha * alpha, the sums
+            // of u d(pw)/d(-m), u dx^2, u dx dy, u dy^2 and u, where alpha = exp2(pw) and
+            // pw = A' dx^2 + B' dx dy + C' dy^2 + log2 sigma, (A', B', C') =
+            // (-0.5 a, -b, -0.5 c) log2 e.  Since d alpha / d pw = alpha ln 2 and
+            // ln 2 log2 e = 1: dL/dm = -ln 2 A[0..1], dL/da = -0.5 A[2], dL/db = -A[3],
+            // dL/dc = -0.5 A[4], and dL/dsigma sigma = A[5].
+            constexpr float kLn2 = 0.6931471805599453f;
+            A[0] *= -kLn2;
+            A[1] *= -kLn2;
+            A[2] *= -0.5f;
+            A[3] = -A[3];
+            A[4] *= -0.5f;
             const DevCam& c = vt.v[v].cam;
             const float* R = c.R;
             const float x = R[0] * m0 + R[1] * m1 + R[2] * m2 + c.t[0];
@@ -349,7 +369,7 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
             grgb[0] += A[6];
             grgb[1] += A[7];
             grgb[2] += A[8];
-            gop += A[5] * sig * (1.0f - sig);
+            gop += A[5] * (1.0f - sig);  // dL/dsigma * sigma (1 - sigma)
             // G2 = -Q Gq Q with Gq = [[A2, A3/2], [A3/2, A4]]
             const float h = 0.5f * A[3];
             const float T00 = qa * A[2] + qb * h, T01 = qa * h + qb * A[4];
@@ -492,14 +512,23 @@ __global__ void __launch_bounds__(256) k_pose_reduce(RParams rp, WsPtrs w, int n
 }
 
 // ----------------------------------------------------------------- launch
+template <int TW, int TH, int B, int PPT, int MODE>
+static void launch_cbwd_mode(const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles, int explicit_up,
+                             const float* loss_scale, hipStream_t s)
+{
+    static int per_cu = 0;  // resident blocks per CU of this instantiation
+    const int grid =
+        persistent_grid((const void*)k_composite_bwd<TW, TH, B, PPT, MODE>, TW * TH / PPT, &per_cu, n_tiles);
+    GPS_LAUNCH(K_COMPOSITE_BWD, s, (k_composite_bwd<TW, TH, B, PPT, MODE>), dim3(grid), dim3(TW * TH / PPT), 0, s, vt,
+               rp, w, explicit_up, loss_scale);
+}
+
 template <int TW, int TH, int B, int PPT>
 static void launch_cbwd(const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles, int explicit_up,
                         const float* loss_scale, hipStream_t s)
 {
-    static int per_cu = 0;  // resident blocks per CU of this instantiation
-    const int grid = persistent_grid((const void*)k_composite_bwd<TW, TH, B, PPT>, TW * TH / PPT, &per_cu, n_tiles);
-    GPS_LAUNCH(K_COMPOSITE_BWD, s, (k_composite_bwd<TW, TH, B, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, s, vt, rp, w,
-                       explicit_up, loss_scale);
+    if (rp.mode == 0) launch_cbwd_mode<TW, TH, B, PPT, 0>(vt, rp, w, n_tiles, explicit_up, loss_scale, s);
+    else launch_cbwd_mode<TW, TH, B, PPT, 1>(vt, rp, w, n_tiles, explicit_up, loss_scale, s);
 }
 
 #define GPS_TILE_CONFIGS_B(X) \

@@ -103,4 +103,24 @@ struct TileLayout {
     __device__ static int lane_y(int lane) { return lane / WW; }
 };
 
+// Wavefronts of a tile (origin tx0, ty0) whose pixel rectangle meets the
+// support box [mx - rx, mx + rx] x [my - ry, my + ry]: bit w for wavefront w.
+// A record outside a wavefront's rectangle has opacity below alpha_min at every
+// one of its pixels, so the wavefront may skip it.
+template <class Lay>
+__device__ __forceinline__ unsigned int wave_box_mask(float mx, float my, float rx, float ry, int tx0, int ty0)
+{
+    static_assert(Lay::NW <= 8, "wavefront mask is one byte");
+    unsigned int mk = 0u;
+#pragma unroll
+    for (int wv = 0; wv < Lay::NW; ++wv) {
+        const int x0 = tx0 + Lay::wave_x0(wv), y0 = ty0 + Lay::wave_y0(wv);
+        const float fx0 = (float)x0, fx1 = (float)(x0 + Lay::WW - 1);
+        const float fy0 = (float)y0, fy1 = (float)(y0 + Lay::WH - 1);
+        const bool miss = mx + rx < fx0 || mx - rx > fx1 || my + ry < fy0 || my - ry > fy1;
+        if (!miss) mk |= 1u << wv;
+    }
+    return mk;
+}
+
 }  // namespace gps

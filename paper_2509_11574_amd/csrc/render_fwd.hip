@@ -60,6 +60,10 @@ __global__ void __launch_bounds__(256) k_prep(const ViewTable* __restrict__ vtp,
 // EWA projection of one Gaussian into one view (Eq. 3; 3DGS convention):
 //   p_c = R mu + t, Sigma_3D = R_q diag(s^2) R_q^T, J the pinhole Jacobian,
 //   Sigma_2D = (J R) Sigma_3D (J R)^T + dilation I, conic = Sigma_2D^-1.
+// Record of 12 floats: r0 = (m_x, m_y, A', B'), r1 = (C', log2 sigma, z, red),
+// r2 = (green, blue, half-width, half-height of the support box), where
+// (A', B', C') = (-0.5 a, -b, -0.5 c) log2(e) for the conic (a, b, c), the
+// opacity then being exp2(A' dx^2 + B' dx dy + C' dy^2 + log2 sigma).
 // The support ellipse where sigma exp(-q/2) >= alpha_min has the bounding box
 // m +- sqrt(kappa Sigma_xx), sqrt(kappa Sigma_yy), kappa = 2 ln(sigma/alpha_min);
 // it is padded by one pixel and turned into a tile rectangle.
@@ -135,8 +139,10 @@ __device__ __forceinline__ ProjOut project_one(const DevView& V, const RParams& 
     // support half-extents padded by one pixel (covers the rounding of the opacity test)
     const float rxp = sqrtf(kappa * A) + 1.0f, ryp = sqrtf(kappa * C) + 1.0f;
     if (!(rxp < 1e7f) || !(ryp < 1e7f) || !(fabsf(mx) < 1e7f) || !(fabsf(my) < 1e7f)) return o;
-    o.r0 = make_float4(mx, my, C * idet, -B * idet);
-    o.r1 = make_float4(A * idet, sig, z, gp.rgb[g]);
+    // conic (a, b, c) = (C, -B, A) / det, pre-scaled for the base-2 exponential
+    constexpr float kL2E = 1.4426950408889634f;
+    o.r0 = make_float4(mx, my, (-0.5f * kL2E) * (C * idet), kL2E * (B * idet));
+    o.r1 = make_float4((-0.5f * kL2E) * (A * idet), __log2f(sig), z, gp.rgb[g]);
     o.r2 = make_float4(gp.rgb[M + g], gp.rgb[2 * M + g], rxp, ryp);
     o.valid = true;
     return o;
@@ -453,13 +459,14 @@ __global__ void __launch_bounds__(256) k_tile_sort_large(RParams rp, WsPtrs w)
 }
 
 // ---------------------------------------------------------- composite fwd
-template <int TW, int TH, int B, int PPT>
+template <int TW, int TH, int B, int PPT, int MODE>
 __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w)
 {
     const ViewTable& vt = *vtp;
     using Lay = TileLayout<TW, TH, PPT>;
     constexpr int NT = Lay::NT;
     __shared__ float4 srec[3 * B];
+    __shared__ unsigned char smask[B];
     if (w.hdr->n_inst > rp.cap) return;
     // Persistent: resident blocks take tiles from the queue (longest first)
     // until it is empty; every block reaches the exit when the ticket passes
@@ -483,83 +490,97 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
     const size_t HW = (size_t)Wd * Ht;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int wx0 = tx * TW + Lay::wave_x0(wid), wy0 = ty * TH + Lay::wave_y0(wid);
-    const float fwx0 = (float)wx0, fwx1 = (float)(wx0 + Lay::WW - 1);
-    const float fwy0 = (float)wy0, fwy1 = (float)(wy0 + Lay::WH - 1);
     const int px = wx0 + Lay::lane_x(lane);
     const int py0 = wy0 + Lay::lane_y(lane);
     const float fpx = (float)px;
 
+    // thr: the depth test of Eq. 1-2 passes while d_i < D_t + eps.  The list is
+    // depth-ordered, so once a record fails it every later record fails too; a
+    // pixel that stops for another reason (outside the image, transmittance
+    // below T_min) gets thr = -inf, so the one comparison carries every stop.
     float thr[PPT], T[PPT], ac0[PPT], ac1[PPT], ac2[PPT], ad[PPT];
-    bool done[PPT];
-    unsigned int n_eval = 0, n_contrib = 0;
+    unsigned int n_eval = 0, n_contrib = 0;  // per wavefront (uniform)
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int py = py0 + k * Lay::LROWS;
         const bool inb = px < Wd && py < Ht;
         float dt = inb ? V.base_depth[(size_t)py * Wd + px] : 0.0f;
         float dcull = dt > 0.0f ? dt : INFINITY;
-        thr[k] = dcull + rp.eps;
-        T[k] = rp.mode == 0 ? 1.0f : 0.0f;
+        thr[k] = inb ? dcull + rp.eps : -INFINITY;
+        T[k] = MODE == 0 ? 1.0f : 0.0f;
         ac0[k] = ac1[k] = ac2[k] = ad[k] = 0.0f;
-        done[k] = !inb;
     }
     const unsigned int s = w.tile_start[tile], e = w.tile_start[tile + 1];
+    const int tx0 = tx * TW, ty0 = ty * TH;
+    bool wave_alive = true;  // some pixel of this wavefront still takes records
     for (unsigned int b = s; b < e; b += B) {
-        int alive = 0;
-#pragma unroll
-        for (int k = 0; k < PPT; ++k) alive |= !done[k];
-        if (__syncthreads_count(alive) == 0) break;
-        for (int j = threadIdx.x; j < B && b + j < e; j += NT) {
-            const unsigned int slot = (unsigned int)w.keys[b + j];
-            unsigned int vg = slot < rp.cap ? w.inst_vg[slot] : 0u;
-            if (vg >= (unsigned int)rp.nvg) vg = 0u;  // guard: never read outside the records
-            const float4* r = w.rec + 3 * (size_t)vg;
-            srec[3 * j + 0] = r[0];
-            srec[3 * j + 1] = r[1];
-            srec[3 * j + 2] = r[2];
+        if (__syncthreads_count(wave_alive && lane == 0) == 0) break;
+        // Stage B records; each also gets the set of wavefronts whose pixels its
+        // support box touches (the box test runs once per record, not once per
+        // record and wavefront).
+        for (int j = threadIdx.x; j < B; j += NT) {
+            unsigned int mk = 0u;
+            if (b + j < e) {
+                const unsigned int slot = (unsigned int)w.keys[b + j];
+                unsigned int vg = slot < rp.cap ? w.inst_vg[slot] : 0u;
+                if (vg >= (unsigned int)rp.nvg) vg = 0u;  // guard: never read outside the records
+                const float4* r = w.rec + 3 * (size_t)vg;
+                const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+                srec[3 * j + 0] = r0;
+                srec[3 * j + 1] = r1;
+                srec[3 * j + 2] = r2;
+                mk = wave_box_mask<Lay>(r0.x, r0.y, r2.z, r2.w, tx0, ty0);
+            }
+            smask[j] = (unsigned char)mk;
         }
         __syncthreads();
         const int n = (int)min((unsigned int)B, e - b);
-        for (int j = 0; j < n; ++j) {
-            const float4 r0 = srec[3 * j], r2 = srec[3 * j + 2];
-            // The support box misses this wavefront's pixels: every opacity here is
-            // below alpha_min, so skipping the record changes nothing.
-            if (r0.x + r2.z < fwx0 || r0.x - r2.z > fwx1 || r0.y + r2.w < fwy0 || r0.y - r2.w > fwy1) continue;
-            const float4 r1 = srec[3 * j + 1];
+        for (int c0 = 0; c0 < n && wave_alive; c0 += 64) {
+            // The records of this chunk whose box touches this wavefront; the
+            // others have opacity below alpha_min at all its pixels.
+            const int jl = c0 + lane;
+            unsigned long long m = __builtin_amdgcn_ballot_w64(jl < n && ((smask[jl] >> wid) & 1u));
+            while (m) {
+                const int j = c0 + (int)__builtin_ctzll(m);
+                m &= m - 1ull;
+                const float4 r0 = srec[3 * j], r1 = srec[3 * j + 1], r2 = srec[3 * j + 2];
+                unsigned long long any_live = 0ull;
 #pragma unroll
-            for (int k = 0; k < PPT; ++k) {
-                if (done[k]) continue;
-                if (!(r1.z < thr[k])) {  // depth test of Eq. 1-2; the list is depth-ordered
-                    done[k] = true;
-                    continue;
-                }
-                const AlphaEval ae =
-                    eval_alpha(fpx, (float)(py0 + k * Lay::LROWS), r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
-                ++n_eval;
-                if (rp.mode == 0) {
-                    const float a = fminf(rp.amax, ae.raw);
-                    if (a < rp.amin) continue;
-                    const float Tn = T[k] * (1.0f - a);
-                    if (Tn < rp.Tmin) {
-                        done[k] = true;
-                        continue;
+                for (int k = 0; k < PPT; ++k) {
+                    const bool live = r1.z < thr[k];
+                    const AlphaEval ae =
+                        eval_alpha(fpx, (float)(py0 + k * Lay::LROWS), r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
+                    bool use;
+                    if (MODE == 0) {
+                        const float a = fminf(ae.raw, rp.amax);
+                        const bool ok = live && a >= rp.amin;
+                        const float Tn = T[k] * (1.0f - a);
+                        const bool stop = ok && Tn < rp.Tmin;  // 3DGS transmittance stop
+                        use = ok && !stop;
+                        const float wgt = use ? a * T[k] : 0.0f;
+                        ac0[k] = __builtin_fmaf(wgt, r1.w, ac0[k]);
+                        ac1[k] = __builtin_fmaf(wgt, r2.x, ac1[k]);
+                        ac2[k] = __builtin_fmaf(wgt, r2.y, ac2[k]);
+                        ad[k] = __builtin_fmaf(wgt, r1.z, ad[k]);
+                        T[k] = use ? Tn : T[k];
+                        thr[k] = stop ? -INFINITY : thr[k];
+                    } else {
+                        use = live && ae.raw >= rp.amin;
+                        const float a = use ? ae.raw : 0.0f;
+                        T[k] += a;  // W_G
+                        ac0[k] = __builtin_fmaf(a, r1.w, ac0[k]);
+                        ac1[k] = __builtin_fmaf(a, r2.x, ac1[k]);
+                        ac2[k] = __builtin_fmaf(a, r2.y, ac2[k]);
+                        ad[k] = __builtin_fmaf(a, r1.z, ad[k]);
                     }
-                    ++n_contrib;
-                    const float wgt = a * T[k];
-                    ac0[k] = __builtin_fmaf(wgt, r1.w, ac0[k]);
-                    ac1[k] = __builtin_fmaf(wgt, r2.x, ac1[k]);
-                    ac2[k] = __builtin_fmaf(wgt, r2.y, ac2[k]);
-                    ad[k] = __builtin_fmaf(wgt, r1.z, ad[k]);
-                    T[k] = Tn;
-                } else {
-                    const float a = ae.raw;
-                    if (a < rp.amin) continue;
-                    ++n_contrib;
-                    T[k] += a;  // W_G
-                    ac0[k] = __builtin_fmaf(a, r1.w, ac0[k]);
-                    ac1[k] = __builtin_fmaf(a, r2.x, ac1[k]);
-                    ac2[k] = __builtin_fmaf(a, r2.y, ac2[k]);
-                    ad[k] = __builtin_fmaf(a, r1.z, ad[k]);
+                    const unsigned long long lm = __builtin_amdgcn_ballot_w64(live);
+                    any_live |= lm;
+                    n_eval += (unsigned int)__builtin_popcountll(lm);
+                    n_contrib += (unsigned int)__builtin_popcountll(__builtin_amdgcn_ballot_w64(use));
+                }
+                if (!any_live) {  // this record and all deeper ones fail every pixel
+                    wave_alive = false;
+                    break;
                 }
             }
         }
@@ -576,7 +597,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
         const bool dvalid = dt > 0.0f;
         float Cs[3], Ds;
         const float ct0 = V.base_rgb[p], ct1 = V.base_rgb[HW + p], ct2 = V.base_rgb[2 * HW + p];
-        if (rp.mode == 0) {
+        if (MODE == 0) {
             Cs[0] = __builtin_fmaf(T[k], ct0, ac0[k]);
             Cs[1] = __builtin_fmaf(T[k], ct1, ac1[k]);
             Cs[2] = __builtin_fmaf(T[k], ct2, ac2[k]);
@@ -608,9 +629,9 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
     lc = block_sum<NT>(lc);
     ld = block_sum<NT>(ld);
     lo = block_sum<NT>(lo);
-    unsigned int tot_eval, tot_contrib;
-    block_excl_scan<NT>(n_eval, &tot_eval);
-    block_excl_scan<NT>(n_contrib, &tot_contrib);
+    unsigned int tot_eval, tot_contrib;  // the counts are per wavefront: lane 0 carries them
+    block_excl_scan<NT>(lane == 0 ? n_eval : 0u, &tot_eval);
+    block_excl_scan<NT>(lane == 0 ? n_contrib : 0u, &tot_contrib);
     if (threadIdx.x == 0) {
         w.tile_loss[tile] = make_float4(lc, ld, lo, 0.0f);
         atomicAdd(&w.hdr->pairs_eval, (unsigned long long)tot_eval);  // integer: order-independent
@@ -673,12 +694,21 @@ gps_status launch_views_upload(const ViewTable& vt, const WsLayout& L, char* ws,
 }
 
 // ----------------------------------------------------------------- launch
+template <int TW, int TH, int B, int PPT, int MODE>
+static void launch_cfwd_mode(const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles, hipStream_t s)
+{
+    static int per_cu = 0;  // resident blocks per CU of this instantiation
+    const int grid =
+        persistent_grid((const void*)k_composite_fwd<TW, TH, B, PPT, MODE>, TW * TH / PPT, &per_cu, n_tiles);
+    GPS_LAUNCH(K_COMPOSITE_FWD, s, (k_composite_fwd<TW, TH, B, PPT, MODE>), dim3(grid), dim3(TW * TH / PPT), 0, s, vt,
+               rp, w);
+}
+
 template <int TW, int TH, int B, int PPT>
 static void launch_cfwd(const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles, hipStream_t s)
 {
-    static int per_cu = 0;  // resident blocks per CU of this instantiation
-    const int grid = persistent_grid((const void*)k_composite_fwd<TW, TH, B, PPT>, TW * TH / PPT, &per_cu, n_tiles);
-    GPS_LAUNCH(K_COMPOSITE_FWD, s, (k_composite_fwd<TW, TH, B, PPT>), dim3(grid), dim3(TW * TH / PPT), 0, s, vt, rp, w);
+    if (rp.mode == 0) launch_cfwd_mode<TW, TH, B, PPT, 0>(vt, rp, w, n_tiles, s);
+    else launch_cfwd_mode<TW, TH, B, PPT, 1>(vt, rp, w, n_tiles, s);
 }
 
 #define GPS_TILE_CONFIGS(X) \
