@@ -32,8 +32,15 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     __shared__ unsigned int sslot[B];
     __shared__ unsigned char smask[B];
     constexpr int S = kFlush;                // records per flush of the per-wavefront partials
-    __shared__ float slab[S * NW * 4 * kAdj];  // per record and wavefront: four row partials
-    __shared__ unsigned char sact[S * NW];  // 1 when the wavefront wrote its partial of record j
+    // Per record: NW wavefronts x 4 row partials x kAdj, padded so that successive
+    // records start 10 banks apart (the flush reads (record, component) pairs).
+    constexpr int kRecStride = NW * 4 * kAdj + ((10 - (NW * 4 * kAdj) % 32) + 32) % 32;
+    __shared__ float slab[S * kRecStride];
+    // Bit j of swritten[w]: wavefront w wrote its partial of window record j.  One
+    // 64-bit word per wavefront, written by its lane 0: flags of different
+    // wavefronts never share an LDS dword (sub-dword stores from different
+    // wavefronts into one dword are not used anywhere).
+    __shared__ unsigned long long swritten[NW];
     if (w.hdr->n_inst > rp.cap) return;
     // Persistent: resident blocks take tiles from the queue (longest first)
     // until it is empty; every block reaches the exit when the ticket passes
@@ -66,10 +73,13 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     const float invV = 1.0f / (float)rp.V;
     const float om = w.hdr->view_stats[v][2];
 
-    float thr[PPT], T[PPT], G0[PPT], G1[PPT], G2[PPT], GD[PPT], Cs0[PPT], Cs1[PPT], Cs2[PPT], Ds[PPT];
-    float P0[PPT], P1[PPT], P2[PPT], PD[PPT], Wg[PPT];
+    // Per pixel: the upstream adjoint G = (dL/dC*, dL/dD*), CG = G . (C*, D*) and
+    // the running PG = G . P_i, where P_i is the composited prefix through
+    // Gaussian i.  The remainder term of dL/dalpha_i only ever needs
+    // G . (C* - P_i) = CG - PG, so the prefix colours are not kept.
     // thr as in the forward: -inf once a pixel has stopped for a reason other
-    // than the depth test (which every deeper record fails as well)
+    // than the depth test (which every deeper record fails as well).
+    float thr[PPT], T[PPT], G0[PPT], G1[PPT], G2[PPT], GD[PPT], CG[PPT], PG[PPT], invW[PPT];
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int py = py0 + k * Lay::LROWS;
@@ -79,16 +89,16 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         const bool dvalid = dt > 0.0f;
         thr[k] = inb ? (dvalid ? dt : INFINITY) + rp.eps : -INFINITY;
         T[k] = 1.0f;
-        P0[k] = P1[k] = P2[k] = PD[k] = 0.0f;
-        Cs0[k] = Cs1[k] = Cs2[k] = Ds[k] = 0.0f;
+        PG[k] = 0.0f;
         G0[k] = G1[k] = G2[k] = GD[k] = 0.0f;
-        Wg[k] = 0.0f;
+        float cs0 = 0.0f, cs1 = 0.0f, cs2 = 0.0f, ds = 0.0f;
+        invW[k] = 1.0f;
         if (inb) {
-            Cs0[k] = V.out_rgb[p];
-            Cs1[k] = V.out_rgb[HW + p];
-            Cs2[k] = V.out_rgb[2 * HW + p];
-            Ds[k] = V.out_depth[p];
-            if (MODE == 1) Wg[k] = w.pix_aux[(size_t)V.pix_base + p];
+            cs0 = V.out_rgb[p];
+            cs1 = V.out_rgb[HW + p];
+            cs2 = V.out_rgb[2 * HW + p];
+            ds = V.out_depth[p];
+            if (MODE == 1) invW[k] = 1.0f / (1.0f + w.pix_aux[(size_t)V.pix_base + p]);
             if (explicit_up) {
                 G0[k] = V.g_rgb[p];
                 G1[k] = V.g_rgb[HW + p];
@@ -96,15 +106,16 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                 GD[k] = (V.g_depth && dvalid) ? V.g_depth[p] : 0.0f;
             } else {
                 const float cn = sc * invV / (3.0f * (float)HW);
-                G0[k] = cn * sgnf(Cs0[k] - V.target_rgb[p]);
-                G1[k] = cn * sgnf(Cs1[k] - V.target_rgb[HW + p]);
-                G2[k] = cn * sgnf(Cs2[k] - V.target_rgb[2 * HW + p]);
+                G0[k] = cn * sgnf(cs0 - V.target_rgb[p]);
+                G1[k] = cn * sgnf(cs1 - V.target_rgb[HW + p]);
+                G2[k] = cn * sgnf(cs2 - V.target_rgb[2 * HW + p]);
                 if (V.target_depth && dvalid && om > 0.0f) {
                     const float dobs = V.target_depth[p];
-                    if (dobs > 0.0f) GD[k] = sc * invV * rp.lambda / om * sgnf(Ds[k] - dobs);
+                    if (dobs > 0.0f) GD[k] = sc * invV * rp.lambda / om * sgnf(ds - dobs);
                 }
             }
         }
+        CG[k] = G0[k] * cs0 + G1[k] * cs1 + G2[k] * cs2 + GD[k] * ds;
     }
 
     const unsigned int s = w.tile_start[tile], e = w.tile_start[tile + 1];
@@ -146,76 +157,81 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                 const float4 r0 = srec[3 * j], r1 = srec[3 * j + 1], r2 = srec[3 * j + 2];
                 const float c0 = r1.w, c1 = r2.x, c2 = r2.y, zi = r1.z;
                 const float A2 = r0.z + r0.z, C2 = r1.x + r1.x;
-                bool act = false;
-                // g: (d/dm_x, d/dm_y) of the base-2 exponent's accumulations, the
-                // three conic terms, d alpha * alpha (sigma), colour, depth.
-                float g[kAdj];
-#pragma unroll
-                for (int q = 0; q < kAdj; ++q) g[q] = 0.0f;
-                unsigned long long any_live = 0ull;
+                // the forward's decisions, in the same order and arithmetic
+                unsigned long long any_live = 0ull, any_use = 0ull;
+                AlphaEval ae[PPT];
+                float av[PPT], Tn[PPT];
+                bool use[PPT];
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
-                    // the forward's decisions, in the same order and arithmetic
                     const bool live = zi < thr[k];
                     any_live |= __builtin_amdgcn_ballot_w64(live);
-                    const AlphaEval ae =
-                        eval_alpha(fpx, (float)(py0 + k * Lay::LROWS), r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
-                    bool use;
-                    float a, Tn = 0.0f;
+                    ae[k] = eval_alpha(fpx, (float)(py0 + k * Lay::LROWS), r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
                     if (MODE == 0) {
-                        a = fminf(ae.raw, rp.amax);
-                        const bool ok = live && a >= rp.amin;
-                        Tn = T[k] * (1.0f - a);
-                        const bool stop = ok && Tn < rp.Tmin;
-                        use = ok && !stop;
+                        av[k] = fminf(ae[k].raw, rp.amax);
+                        const bool ok = live && av[k] >= rp.amin;
+                        Tn[k] = T[k] * (1.0f - av[k]);
+                        const bool stop = ok && Tn[k] < rp.Tmin;
+                        use[k] = ok && !stop;
                         thr[k] = stop ? -INFINITY : thr[k];
                     } else {
-                        a = ae.raw;
-                        use = live && a >= rp.amin;
+                        av[k] = ae[k].raw;
+                        Tn[k] = 0.0f;
+                        use[k] = live && av[k] >= rp.amin;
                     }
-                    if (!use) continue;
-                    float dal;
-                    bool alpha_path;
-                    if (MODE == 0) {
-                        const float wgt = a * T[k];
-                        P0[k] = __builtin_fmaf(wgt, c0, P0[k]);
-                        P1[k] = __builtin_fmaf(wgt, c1, P1[k]);
-                        P2[k] = __builtin_fmaf(wgt, c2, P2[k]);
-                        PD[k] = __builtin_fmaf(wgt, zi, PD[k]);
-                        g[6] = __builtin_fmaf(wgt, G0[k], g[6]);
-                        g[7] = __builtin_fmaf(wgt, G1[k], g[7]);
-                        g[8] = __builtin_fmaf(wgt, G2[k], g[8]);
-                        g[9] = __builtin_fmaf(wgt, GD[k], g[9]);
-                        const float direct = G0[k] * c0 + G1[k] * c1 + G2[k] * c2 + GD[k] * zi;
-                        const float rest = G0[k] * (Cs0[k] - P0[k]) + G1[k] * (Cs1[k] - P1[k]) +
-                                           G2[k] * (Cs2[k] - P2[k]) + GD[k] * (Ds[k] - PD[k]);
-                        dal = T[k] * direct - rest * __builtin_amdgcn_rcpf(1.0f - a);  // v_rcp_f32, 1 ulp
-                        alpha_path = ae.raw <= rp.amax;  // a capped opacity has no gradient
-                        T[k] = Tn;
-                    } else {
-                        const float inv = __builtin_amdgcn_rcpf(1.0f + Wg[k]);
-                        const float ai = a * inv;
-                        g[6] = __builtin_fmaf(ai, G0[k], g[6]);
-                        g[7] = __builtin_fmaf(ai, G1[k], g[7]);
-                        g[8] = __builtin_fmaf(ai, G2[k], g[8]);
-                        g[9] = __builtin_fmaf(ai, GD[k], g[9]);
-                        dal = inv * (G0[k] * (c0 - Cs0[k]) + G1[k] * (c1 - Cs1[k]) + G2[k] * (c2 - Cs2[k]) +
-                                     GD[k] * (zi - Ds[k]));
-                        alpha_path = true;
-                    }
-                    act = true;
-                    // alpha = exp2(pw): d alpha / d pw = alpha ln 2; the constant
-                    // factors are applied once per Gaussian.
-                    const float u = alpha_path ? dal * a : 0.0f;
-                    g[5] += u;
-                    g[0] = __builtin_fmaf(u, __builtin_fmaf(A2, ae.dx, r0.w * ae.dy), g[0]);
-                    g[1] = __builtin_fmaf(u, __builtin_fmaf(C2, ae.dy, r0.w * ae.dx), g[1]);
-                    g[2] = __builtin_fmaf(u, ae.dxx, g[2]);
-                    g[3] = __builtin_fmaf(u, ae.dxy, g[3]);
-                    g[4] = __builtin_fmaf(u, ae.dyy, g[4]);
+                    any_use |= __builtin_amdgcn_ballot_w64(use[k]);
                 }
-                if (wave_any(act)) {
-                    wave_rows_sum10_store(g, slab + (jw * NW + wid) * 4 * kAdj, lane);
+                if (any_use) {
+                    // Adjoints of the contributing lanes; the others carry zero
+                    // weight, so no accumulator needs clearing.
+                    float g[kAdj];
+#pragma unroll
+                    for (int k = 0; k < PPT; ++k) {
+                        const float direct = G0[k] * c0 + G1[k] * c1 + G2[k] * c2 + GD[k] * zi;  // G . (c_i, d_i)
+                        float wgt, dal;
+                        bool apath;
+                        if (MODE == 0) {
+                            wgt = use[k] ? av[k] * T[k] : 0.0f;  // w_i = alpha_i T_i
+                            PG[k] = __builtin_fmaf(wgt, direct, PG[k]);
+                            // dL/dalpha_i = T_i G.(c_i,d_i) - G.(C* - P_i) / (1 - alpha_i)
+                            dal = T[k] * direct - (CG[k] - PG[k]) * __builtin_amdgcn_rcpf(1.0f - av[k]);
+                            apath = use[k] && ae[k].raw <= rp.amax;  // a capped opacity has no gradient
+                            T[k] = use[k] ? Tn[k] : T[k];
+                        } else {
+                            wgt = use[k] ? av[k] * invW[k] : 0.0f;  // d C* / d c_i = alpha_i / (1 + W_G)
+                            dal = invW[k] * (direct - CG[k]);
+                            apath = use[k];
+                        }
+                        // alpha = exp2(pw): d alpha / d pw = alpha ln 2; the constant
+                        // factors are applied once per Gaussian.
+                        const float u = apath ? dal * av[k] : 0.0f;
+                        const float t0 = u * __builtin_fmaf(A2, ae[k].dx, r0.w * ae[k].dy);
+                        const float t1 = u * __builtin_fmaf(C2, ae[k].dy, r0.w * ae[k].dx);
+                        if (k == 0) {
+                            g[0] = t0;
+                            g[1] = t1;
+                            g[2] = u * ae[k].dxx;
+                            g[3] = u * ae[k].dxy;
+                            g[4] = u * ae[k].dyy;
+                            g[5] = u;
+                            g[6] = wgt * G0[k];
+                            g[7] = wgt * G1[k];
+                            g[8] = wgt * G2[k];
+                            g[9] = wgt * GD[k];
+                        } else {
+                            g[0] += t0;
+                            g[1] += t1;
+                            g[2] = __builtin_fmaf(u, ae[k].dxx, g[2]);
+                            g[3] = __builtin_fmaf(u, ae[k].dxy, g[3]);
+                            g[4] = __builtin_fmaf(u, ae[k].dyy, g[4]);
+                            g[5] += u;
+                            g[6] = __builtin_fmaf(wgt, G0[k], g[6]);
+                            g[7] = __builtin_fmaf(wgt, G1[k], g[7]);
+                            g[8] = __builtin_fmaf(wgt, G2[k], g[8]);
+                            g[9] = __builtin_fmaf(wgt, GD[k], g[9]);
+                        }
+                    }
+                    wave_rows_sum10_store(g, slab + jw * kRecStride + wid * 4 * kAdj, lane);
                     written |= 1ull << jw;
                 }
                 if (!any_live) {  // this record and all deeper ones fail every pixel
@@ -223,7 +239,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                     break;
                 }
             }
-            if (lane < S) sact[lane * NW + wid] = (unsigned char)((written >> lane) & 1ull);
+            if (lane == 0) swritten[wid] = written;
             alive_now = __syncthreads_count(wave_alive && lane == 0);
             // one thread per (record, component): sum the wavefront partials in order
             for (int t = threadIdx.x; t < (j1 - j0) * kAdj; t += NT) {
@@ -231,8 +247,8 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                 float acc = 0.0f;
 #pragma unroll
                 for (int ww = 0; ww < NW; ++ww)
-                    if (sact[jr * NW + ww]) {
-                        const float* sp = slab + (jr * NW + ww) * 4 * kAdj + q;
+                    if ((swritten[ww] >> jr) & 1ull) {
+                        const float* sp = slab + jr * kRecStride + ww * 4 * kAdj + q;
                         acc += (sp[0] + sp[kAdj]) + (sp[2 * kAdj] + sp[3 * kAdj]);
                     }
                 const unsigned int slot = sslot[j0 + jr];
