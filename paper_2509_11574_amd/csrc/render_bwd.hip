@@ -30,7 +30,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     constexpr int NW = Lay::NW;
     __shared__ float4 srec[3 * B];
     __shared__ unsigned int sslot[B];
-    __shared__ unsigned char smask[B];
+    __shared__ unsigned int smask[B];  // wavefront mask per staged record (32-bit: no byte stores in LDS)
     constexpr int S = kFlush;                // records per flush of the per-wavefront partials
     // Per record: NW wavefronts x 4 row partials x kAdj, padded so that successive
     // records start 10 banks apart (the flush reads (record, component) pairs).
@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                 srec[3 * j + 2] = r2;
                 mk = wave_box_mask<Lay>(r0.x, r0.y, r2.z, r2.w, tx0, ty0);
             }
-            smask[j] = (unsigned char)mk;
+            smask[j] = mk;
             sslot[j] = slot;
         }
         __syncthreads();

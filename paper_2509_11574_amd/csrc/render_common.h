@@ -110,7 +110,7 @@ struct TileLayout {
 template <class Lay>
 __device__ __forceinline__ unsigned int wave_box_mask(float mx, float my, float rx, float ry, int tx0, int ty0)
 {
-    static_assert(Lay::NW <= 8, "wavefront mask is one byte");
+    static_assert(Lay::NW <= 32, "wavefront mask fits 32 bits");
     unsigned int mk = 0u;
 #pragma unroll
     for (int wv = 0; wv < Lay::NW; ++wv) {

@@ -466,7 +466,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
     using Lay = TileLayout<TW, TH, PPT>;
     constexpr int NT = Lay::NT;
     __shared__ float4 srec[3 * B];
-    __shared__ unsigned char smask[B];
+    __shared__ unsigned int smask[B];  // wavefront mask per staged record (32-bit: no byte stores in LDS)
     if (w.hdr->n_inst > rp.cap) return;
     // Persistent: resident blocks take tiles from the queue (longest first)
     // until it is empty; every block reaches the exit when the ticket passes
@@ -531,7 +531,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
                 srec[3 * j + 2] = r2;
                 mk = wave_box_mask<Lay>(r0.x, r0.y, r2.z, r2.w, tx0, ty0);
             }
-            smask[j] = (unsigned char)mk;
+            smask[j] = mk;
         }
         __syncthreads();
         const int n = (int)min((unsigned int)B, e - b);

@@ -189,6 +189,16 @@ def test_keyframe_batch_sampled(P, O):
     for k in KEYS:
         assert normwise(h(grads[k]), refs[k]) < 1e-3, k
     assert normwise(h(dpose), refs["pose"]) < 1e-3
+    # The backward is bitwise reproducible: no floating-point atomics, fixed
+    # reduction orders, and no data race between the wavefronts of a block.
+    for _ in range(3):
+        g2 = P.zeros_like_gaussians(gd)
+        dp2 = torch.zeros(8, 6, device=DEV)
+        P.render_bwd(gc, gd, views, ws, g2, dp2, dL_drgb=ups_rgb, dL_ddepth=ups_dep)
+        torch.cuda.synchronize()
+        for k in KEYS:
+            assert torch.equal(g2[k], grads[k]), k
+        assert torch.equal(dp2, dpose)
 
 
 def test_room_5mm_fusion_every_point(P, O):
