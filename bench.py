@@ -42,6 +42,41 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# HBM traffic of a kernel comes from rocprofv3 counter runs (FETCH_SIZE, WRITE_SIZE),
+# recorded in profiles/traffic.json with the SHA-256 of the kernel's source files at
+# the time of the measurement; it is reported only while those sources are unchanged.
+KERNEL_SOURCES = {
+    "composite_bwd": ("render_bwd.hip", "render_common.h", "gps_internal.h"),
+    "composite_fwd": ("render_fwd.hip", "render_common.h", "gps_internal.h"),
+}
+
+
+def sources_sha256(kernel: str):
+    import hashlib
+    files = KERNEL_SOURCES.get(kernel)
+    if not files:
+        return None
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2509_11574_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, tile: str, mode: int):
+    """HBM bytes per launch of `kernel` at `tile`, or None when not measured for the current sources."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            table = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = table.get(f"{kernel} {tile} mode{mode}")
+    if not e or e.get("sources_sha256") != sources_sha256(kernel):
+        return None
+    return e.get("hbm_bytes_per_launch")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,8 +250,10 @@ def main():
             per = FLOPS_CONTRIB_FWD if dom == "composite_fwd" else FLOPS_CONTRIB_BWD
             flops = FLOPS_EVAL * pairs["eval_per_launch"] + per * pairs["contrib_per_launch"]
             ach = flops / avg_s / 1e12
+            tile_s = f"{cfg.tile_w}x{cfg.tile_h}x{cfg.batch}x{cfg.pix_per_thread}"
             roofline = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS,
-                        "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                        "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4),
+                        "traffic": measured_traffic(dom, tile_s, args.mode),
                         "avg_launch_ms": round(avg_s * 1e3, 4), "flops_per_launch": flops}
         else:
             roofline = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",

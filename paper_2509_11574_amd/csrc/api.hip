@@ -43,26 +43,6 @@ static gps_status check_device()
     return st == 1 ? GPS_OK : GPS_ERR_UNSUPPORTED_DEVICE;
 }
 
-int persistent_grid(const void* kernel, int block, int* per_cu, int work)
-{
-    if (*per_cu <= 0) {
-        int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block, 0) != hipSuccess || n < 1) n = 1;
-        *per_cu = n;
-    }
-    static std::atomic<int> n_cu{0};
-    int cus = n_cu.load(std::memory_order_relaxed);
-    if (cus <= 0) {
-        int dev = 0;
-        hipDeviceProp_t p;
-        cus = (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&p, dev) == hipSuccess) ? p.multiProcessorCount
-                                                                                                  : 256;
-        n_cu.store(cus, std::memory_order_relaxed);
-    }
-    const long long g = (long long)(*per_cu) * cus;
-    return (int)(g < work ? g : (work > 0 ? work : 1));
-}
-
 static gps_status compute_layout(const gps_render_cfg* cfg, int M, const gps_camera* cams, int V, WsLayout* L)
 {
     if (!cfg || !cams || !L || M < 0 || V < 1 || V > GPS_MAX_VIEWS) return GPS_ERR_INVALID_ARG;
@@ -113,6 +93,8 @@ static gps_status compute_layout(const gps_render_cfg* cfg, int M, const gps_cam
     o = align_up(o + 4 * (size_t)n_tiles);
     L->tile_loss = o;
     o = align_up(o + 16 * (size_t)n_tiles);
+    L->tile_pairs = o;
+    o = align_up(o + 8 * (size_t)n_tiles);
     L->pix_aux = o;
     o = align_up(o + 4 * (size_t)npix);
     L->rec = o;

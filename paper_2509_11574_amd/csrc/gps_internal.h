@@ -65,8 +65,6 @@ struct RParams {
 struct WsHeader {
     int status;                    // sticky gps_status of device-side failures
     int adam_step;                 // optional Adam step counter
-    unsigned int q_bwd;            // work-queue ticket of the backward compositing
-    unsigned int q_fwd;            // work-queue ticket of the forward compositing
     unsigned long long n_inst;     // instances emitted by the last forward
     unsigned long long n_fallback; // tiles sorted by the global-memory fallback
     unsigned long long cap;        // instance capacity of the last forward
@@ -81,7 +79,8 @@ struct WsHeader {
 
 struct WsLayout {
     size_t total;
-    size_t hdr, vtab, tilemax, tile_cnt, tile_start, tile_cursor, tile_queue, tile_loss, pix_aux, rec, cnt, off, blk_sum, blk_off,
+    size_t hdr, vtab, tilemax, tile_cnt, tile_start, tile_cursor, tile_queue, tile_loss, tile_pairs, pix_aux, rec, cnt, off,
+        blk_sum, blk_off,
         keys, inst_vg, partial, pose_part;
     int n_tiles, nvg, nblk_vg, nblk_g;
     unsigned long long cap;
@@ -95,6 +94,7 @@ struct WsPtrs {
     unsigned int* tile_cursor;
     unsigned int* tile_queue;   // tiles in processing order (longest first)
     float4* tile_loss;          // per tile: colour L1 sum, depth L1 sum, |Omega| count, 0
+    uint2* tile_pairs;          // per tile: evaluated and composited (pixel, instance) pairs
     float* pix_aux;             // per pixel: T_final (sorted) or W_G (sort-free)
     float4* rec;                // 3 float4 per view-Gaussian
     unsigned int* cnt;
@@ -117,6 +117,7 @@ inline WsPtrs ws_ptrs(char* ws, const WsLayout& L)
     p.tile_cursor = reinterpret_cast<unsigned int*>(ws + L.tile_cursor);
     p.tile_queue = reinterpret_cast<unsigned int*>(ws + L.tile_queue);
     p.tile_loss = reinterpret_cast<float4*>(ws + L.tile_loss);
+    p.tile_pairs = reinterpret_cast<uint2*>(ws + L.tile_pairs);
     p.pix_aux = reinterpret_cast<float*>(ws + L.pix_aux);
     p.rec = reinterpret_cast<float4*>(ws + L.rec);
     p.cnt = reinterpret_cast<unsigned int*>(ws + L.cnt);
@@ -272,9 +273,6 @@ __device__ __forceinline__ int find_view(const ViewTable& vt, int tile)
     return v;
 }
 
-// Grid of a persistent kernel: the blocks that fit on the device at once
-// (occupancy x CUs), at most `work`; `per_cu` caches the occupancy query.
-int persistent_grid(const void* kernel, int block, int* per_cu, int work);
 
 // ---------------------------------------------------------------------------
 // Host-side launch entry points (defined in the .hip files).

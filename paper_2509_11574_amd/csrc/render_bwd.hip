@@ -42,20 +42,8 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     // wavefronts into one dword are not used anywhere).
     __shared__ unsigned long long swritten[NW];
     if (w.hdr->n_inst > rp.cap) return;
-    // Persistent: resident blocks take tiles from the queue (longest first)
-    // until it is empty; every block reaches the exit when the ticket passes
-    // the number of tiles.
-    // The next ticket is fetched at the end of each tile, in the same thread-0 block
-    // that closes the tile, so the loop head starts with a barrier and no
-    // thread-dependent branch can be threaded across it.
-    __shared__ unsigned int s_next;
-    if (threadIdx.x == 0) s_next = atomicAdd(&w.hdr->q_bwd, 1u);
-    for (;;) {
-    __syncthreads();
-    const unsigned int qi = s_next;
-    __syncthreads();
-    if (qi >= (unsigned int)vt.n_tiles) break;
-    const int tile = (int)w.tile_queue[qi];
+    // One block per tile, in queue order (longest tile lists first).
+    const int tile = (int)w.tile_queue[blockIdx.x];
     const int v = find_view(vt, tile);
     const DevView& V = vt.v[v];
     const int lt = tile - V.tile_base;
@@ -156,7 +144,6 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                 const int j = j0 + jw;
                 const float4 r0 = srec[3 * j], r1 = srec[3 * j + 1], r2 = srec[3 * j + 2];
                 const float c0 = r1.w, c1 = r2.x, c2 = r2.y, zi = r1.z;
-                const float A2 = r0.z + r0.z, C2 = r1.x + r1.x;
                 // the forward's decisions, in the same order and arithmetic
                 unsigned long long any_live = 0ull, any_use = 0ull;
                 AlphaEval ae[PPT];
@@ -205,8 +192,8 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                         // alpha = exp2(pw): d alpha / d pw = alpha ln 2; the constant
                         // factors are applied once per Gaussian.
                         const float u = apath ? dal * av[k] : 0.0f;
-                        const float t0 = u * __builtin_fmaf(A2, ae[k].dx, r0.w * ae[k].dy);
-                        const float t1 = u * __builtin_fmaf(C2, ae[k].dy, r0.w * ae[k].dx);
+                        const float t0 = u * ae[k].dx;
+                        const float t1 = u * ae[k].dy;
                         if (k == 0) {
                             g[0] = t0;
                             g[1] = t1;
@@ -268,8 +255,6 @@ __global__ void __launch_bounds__(TW * TH / PPT)
 #pragma unroll
         for (int q = 0; q < kAdj; ++q) out[q] = 0.0f;
     }
-    if (threadIdx.x == 0) s_next = atomicAdd(&w.hdr->q_bwd, 1u);  // next tile
-    }  // tile loop
 }
 
 // ------------------------------------------------------------- gauss bwd
@@ -282,7 +267,6 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
     const int M = rp.M;
     const int g = blockIdx.x * kBlk + threadIdx.x;
     const bool live = g < M;
-    if (blockIdx.x == 0 && threadIdx.x == 0) w.hdr->q_bwd = 0u;  // the compositing backward has finished
     float gmean[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.0f, grgb[3] = {0, 0, 0};
     __shared__ float pred[kBlk / 64][6];
 
@@ -345,14 +329,12 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
 #pragma unroll
                 for (int q = 0; q < kAdj; ++q) A[q] += part[(size_t)k * kAdj + q];
             // The compositing kernel accumulates, with u = dL/dalpha * alpha, the sums
-            // of u d(pw)/d(-m), u dx^2, u dx dy, u dy^2 and u, where alpha = exp2(pw) and
-            // pw = A' dx^2 + B' dx dy + C' dy^2 + log2 sigma, (A', B', C') =
+            // of u dx, u dy, u dx^2, u dx dy, u dy^2 and u, where alpha = exp2(pw),
+            // pw = A' dx^2 + B' dx dy + C' dy^2 + log2 sigma and (A', B', C') =
             // (-0.5 a, -b, -0.5 c) log2 e.  Since d alpha / d pw = alpha ln 2 and
-            // ln 2 log2 e = 1: dL/dm = -ln 2 A[0..1], dL/da = -0.5 A[2], dL/db = -A[3],
-            // dL/dc = -0.5 A[4], and dL/dsigma sigma = A[5].
-            constexpr float kLn2 = 0.6931471805599453f;
-            A[0] *= -kLn2;
-            A[1] *= -kLn2;
+            // ln 2 log2 e = 1: dL/dm = conic (sum u dx, sum u dy) (applied below, once the
+            // conic is known), dL/da = -0.5 A[2], dL/db = -A[3], dL/dc = -0.5 A[4], and
+            // dL/dsigma sigma = A[5].
             A[2] *= -0.5f;
             A[3] = -A[3];
             A[4] *= -0.5f;
@@ -381,6 +363,11 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
             const float SC = WS[3] * Wm[3] + WS[4] * Wm[4] + WS[5] * Wm[5] + rp.dil;
             const float idet = 1.0f / (SA * SC - SB * SB);
             const float qa = SC * idet, qb = -SB * idet, qc = SA * idet;
+            {
+                const float sx = A[0], sy = A[1];  // sum u dx, sum u dy
+                A[0] = qa * sx + qb * sy;          // dL/dm_x
+                A[1] = qb * sx + qc * sy;          // dL/dm_y
+            }
 
             grgb[0] += A[6];
             grgb[1] += A[7];
@@ -532,11 +519,8 @@ template <int TW, int TH, int B, int PPT, int MODE>
 static void launch_cbwd_mode(const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles, int explicit_up,
                              const float* loss_scale, hipStream_t s)
 {
-    static int per_cu = 0;  // resident blocks per CU of this instantiation
-    const int grid =
-        persistent_grid((const void*)k_composite_bwd<TW, TH, B, PPT, MODE>, TW * TH / PPT, &per_cu, n_tiles);
-    GPS_LAUNCH(K_COMPOSITE_BWD, s, (k_composite_bwd<TW, TH, B, PPT, MODE>), dim3(grid), dim3(TW * TH / PPT), 0, s, vt,
-               rp, w, explicit_up, loss_scale);
+    GPS_LAUNCH(K_COMPOSITE_BWD, s, (k_composite_bwd<TW, TH, B, PPT, MODE>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s,
+               vt, rp, w, explicit_up, loss_scale);
 }
 
 template <int TW, int TH, int B, int PPT>

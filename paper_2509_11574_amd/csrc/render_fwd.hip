@@ -31,7 +31,6 @@ __global__ void __launch_bounds__(256) k_prep(const ViewTable* __restrict__ vtp,
     if (tile == 0 && threadIdx.x == 0) {
         w.hdr->n_inst = 0ull;
         w.hdr->n_fallback = 0ull;
-        w.hdr->q_fwd = 0u;
         w.hdr->n_views = rp.V;
     }
     const int v = find_view(vt, tile);
@@ -230,7 +229,7 @@ __global__ void __launch_bounds__(1024) k_scan_blocks(RParams rp, WsPtrs w, int 
     }
 }
 
-// Also orders the tiles for the persistent compositing kernels, longest first:
+// Also orders the tiles for the compositing kernels, longest first:
 // tiles are bucketed by floor(log2(count + 1)) and the buckets laid out in
 // descending order.  The order inside a bucket is arbitrary; it affects only
 // which block processes a tile, never a result.
@@ -459,6 +458,44 @@ __global__ void __launch_bounds__(256) k_tile_sort_large(RParams rp, WsPtrs w)
 }
 
 // ---------------------------------------------------------- composite fwd
+// One record at one pixel: the opacity test (alpha >= alpha_min), the
+// transmittance stop (sorted mode) and the accumulation of colour and depth.
+// `live` is the depth test of Eq. 1-2; a pixel that stops gets thr = -inf.
+template <int MODE>
+__device__ __forceinline__ void composite_step(bool live, float raw, const float4& r1, const float4& r2,
+                                               const RParams& rp, float& T, float& thr, float& ac0, float& ac1,
+                                               float& ac2, float& ad, unsigned int& n_eval,
+                                               unsigned int& n_contrib, unsigned long long& live_mask)
+{
+    bool use;
+    if (MODE == 0) {
+        const float a = fminf(raw, rp.amax);
+        const bool ok = live && a >= rp.amin;
+        const float Tn = T * (1.0f - a);
+        const bool stop = ok && Tn < rp.Tmin;  // 3DGS transmittance stop
+        use = ok && !stop;
+        const float wgt = use ? a * T : 0.0f;
+        ac0 = __builtin_fmaf(wgt, r1.w, ac0);
+        ac1 = __builtin_fmaf(wgt, r2.x, ac1);
+        ac2 = __builtin_fmaf(wgt, r2.y, ac2);
+        ad = __builtin_fmaf(wgt, r1.z, ad);
+        T = use ? Tn : T;
+        thr = stop ? -INFINITY : thr;
+    } else {
+        use = live && raw >= rp.amin;
+        const float a = use ? raw : 0.0f;
+        T += a;  // W_G
+        ac0 = __builtin_fmaf(a, r1.w, ac0);
+        ac1 = __builtin_fmaf(a, r2.x, ac1);
+        ac2 = __builtin_fmaf(a, r2.y, ac2);
+        ad = __builtin_fmaf(a, r1.z, ad);
+    }
+    const unsigned long long lm = __builtin_amdgcn_ballot_w64(live);
+    live_mask |= lm;
+    n_eval += (unsigned int)__builtin_popcountll(lm);
+    n_contrib += (unsigned int)__builtin_popcountll(__builtin_amdgcn_ballot_w64(use));
+}
+
 template <int TW, int TH, int B, int PPT, int MODE>
 __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w)
 {
@@ -468,20 +505,10 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
     __shared__ float4 srec[3 * B];
     __shared__ unsigned int smask[B];  // wavefront mask per staged record (32-bit: no byte stores in LDS)
     if (w.hdr->n_inst > rp.cap) return;
-    // Persistent: resident blocks take tiles from the queue (longest first)
-    // until it is empty; every block reaches the exit when the ticket passes
-    // the number of tiles.
-    // The next ticket is fetched at the end of each tile, in the same thread-0 block
-    // that closes the tile, so the loop head starts with a barrier and no
-    // thread-dependent branch can be threaded across it.
-    __shared__ unsigned int s_next;
-    if (threadIdx.x == 0) s_next = atomicAdd(&w.hdr->q_fwd, 1u);
-    for (;;) {
-    __syncthreads();
-    const unsigned int qi = s_next;
-    __syncthreads();
-    if (qi >= (unsigned int)vt.n_tiles) break;
-    const int tile = (int)w.tile_queue[qi];
+    // One block per tile, in queue order (longest tile lists first): the
+    // hardware dispatches blocks in index order as resources free up, which
+    // balances tiles of very different lengths without any global counter.
+    const int tile = (int)w.tile_queue[blockIdx.x];
     const int v = find_view(vt, tile);
     const DevView& V = vt.v[v];
     const int lt = tile - V.tile_base;
@@ -540,45 +567,34 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
             // others have opacity below alpha_min at all its pixels.
             const int jl = c0 + lane;
             unsigned long long m = __builtin_amdgcn_ballot_w64(jl < n && ((smask[jl] >> wid) & 1u));
+            // Records are taken two at a time: the opacities of both are independent
+            // of the transmittance, so their evaluation overlaps; the compositing then
+            // applies them in list order.  When the set has an odd count the second is
+            // a copy of the first that no lane takes (its depth test is forced false).
             while (m) {
-                const int j = c0 + (int)__builtin_ctzll(m);
+                const int ja = c0 + (int)__builtin_ctzll(m);
                 m &= m - 1ull;
-                const float4 r0 = srec[3 * j], r1 = srec[3 * j + 1], r2 = srec[3 * j + 2];
-                unsigned long long any_live = 0ull;
+                const bool hb = m != 0ull;
+                const int jb = hb ? c0 + (int)__builtin_ctzll(m) : ja;
+                if (hb) m &= m - 1ull;
+                const float4 a0 = srec[3 * ja], a1 = srec[3 * ja + 1], a2 = srec[3 * ja + 2];
+                const float4 b0 = srec[3 * jb], b1 = srec[3 * jb + 1], b2 = srec[3 * jb + 2];
+                unsigned long long live_a = 0ull, live_b = 0ull;
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
-                    const bool live = r1.z < thr[k];
-                    const AlphaEval ae =
-                        eval_alpha(fpx, (float)(py0 + k * Lay::LROWS), r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
-                    bool use;
-                    if (MODE == 0) {
-                        const float a = fminf(ae.raw, rp.amax);
-                        const bool ok = live && a >= rp.amin;
-                        const float Tn = T[k] * (1.0f - a);
-                        const bool stop = ok && Tn < rp.Tmin;  // 3DGS transmittance stop
-                        use = ok && !stop;
-                        const float wgt = use ? a * T[k] : 0.0f;
-                        ac0[k] = __builtin_fmaf(wgt, r1.w, ac0[k]);
-                        ac1[k] = __builtin_fmaf(wgt, r2.x, ac1[k]);
-                        ac2[k] = __builtin_fmaf(wgt, r2.y, ac2[k]);
-                        ad[k] = __builtin_fmaf(wgt, r1.z, ad[k]);
-                        T[k] = use ? Tn : T[k];
-                        thr[k] = stop ? -INFINITY : thr[k];
-                    } else {
-                        use = live && ae.raw >= rp.amin;
-                        const float a = use ? ae.raw : 0.0f;
-                        T[k] += a;  // W_G
-                        ac0[k] = __builtin_fmaf(a, r1.w, ac0[k]);
-                        ac1[k] = __builtin_fmaf(a, r2.x, ac1[k]);
-                        ac2[k] = __builtin_fmaf(a, r2.y, ac2[k]);
-                        ad[k] = __builtin_fmaf(a, r1.z, ad[k]);
-                    }
-                    const unsigned long long lm = __builtin_amdgcn_ballot_w64(live);
-                    any_live |= lm;
-                    n_eval += (unsigned int)__builtin_popcountll(lm);
-                    n_contrib += (unsigned int)__builtin_popcountll(__builtin_amdgcn_ballot_w64(use));
+                    const float fpy = (float)(py0 + k * Lay::LROWS);
+                    const AlphaEval ea = eval_alpha(fpx, fpy, a0.x, a0.y, a0.z, a0.w, a1.x, a1.y);
+                    const AlphaEval eb = eval_alpha(fpx, fpy, b0.x, b0.y, b0.z, b0.w, b1.x, b1.y);
+                    const bool la = a1.z < thr[k];  // depth test of Eq. 1-2
+                    composite_step<MODE>(la, ea.raw, a1, a2, rp, T[k], thr[k], ac0[k], ac1[k], ac2[k], ad[k],
+                                         n_eval, n_contrib, live_a);
+                    const bool lb = hb && b1.z < thr[k];  // after a's update: a may have stopped the pixel
+                    composite_step<MODE>(lb, eb.raw, b1, b2, rp, T[k], thr[k], ac0[k], ac1[k], ac2[k], ad[k],
+                                         n_eval, n_contrib, live_b);
                 }
-                if (!any_live) {  // this record and all deeper ones fail every pixel
+                // A record that no lane passes ends the wavefront's list: every later
+                // record is deeper.
+                if (!live_a || (hb && !live_b)) {
                     wave_alive = false;
                     break;
                 }
@@ -634,11 +650,8 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
     block_excl_scan<NT>(lane == 0 ? n_contrib : 0u, &tot_contrib);
     if (threadIdx.x == 0) {
         w.tile_loss[tile] = make_float4(lc, ld, lo, 0.0f);
-        atomicAdd(&w.hdr->pairs_eval, (unsigned long long)tot_eval);  // integer: order-independent
-        atomicAdd(&w.hdr->pairs_contrib, (unsigned long long)tot_contrib);
-        s_next = atomicAdd(&w.hdr->q_fwd, 1u);  // next tile
+        w.tile_pairs[tile] = make_uint2(tot_eval, tot_contrib);  // summed by k_loss_reduce
     }
-    }  // tile loop
 }
 
 // ------------------------------------------------------------ loss reduce
@@ -669,8 +682,29 @@ __global__ void __launch_bounds__(256) k_loss_reduce(const ViewTable* __restrict
             L += a / npx + (c > 0.0f ? rp.lambda * b / c : 0.0f);
         }
     }
+    // Evaluated / composited pair counts of this forward, summed over the tiles in
+    // a fixed order and added to the cumulative counters of the header.
+    unsigned long long pe = 0ull, pc = 0ull;
+    if (w.hdr->n_inst <= rp.cap) {
+        for (int t = threadIdx.x; t < vt.n_tiles; t += 256) {
+            const uint2 q = w.tile_pairs[t];
+            pe += q.x;
+            pc += q.y;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        pe += __shfl_xor(pe, o, 64);
+        pc += __shfl_xor(pc, o, 64);
+    }
+    __shared__ unsigned long long spe[4], spc[4];
+    if ((threadIdx.x & 63) == 0) {
+        spe[threadIdx.x >> 6] = pe;
+        spc[threadIdx.x >> 6] = pc;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        w.hdr->q_bwd = 0u;  // ticket of the next backward's persistent compositing
+        w.hdr->pairs_eval += spe[0] + spe[1] + spe[2] + spe[3];
+        w.hdr->pairs_contrib += spc[0] + spc[1] + spc[2] + spc[3];
         L = L / (float)vt.n;
         w.hdr->loss = has_loss ? L : 0.0f;
         if (out_loss && has_loss) *out_loss = L;
@@ -697,11 +731,8 @@ gps_status launch_views_upload(const ViewTable& vt, const WsLayout& L, char* ws,
 template <int TW, int TH, int B, int PPT, int MODE>
 static void launch_cfwd_mode(const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles, hipStream_t s)
 {
-    static int per_cu = 0;  // resident blocks per CU of this instantiation
-    const int grid =
-        persistent_grid((const void*)k_composite_fwd<TW, TH, B, PPT, MODE>, TW * TH / PPT, &per_cu, n_tiles);
-    GPS_LAUNCH(K_COMPOSITE_FWD, s, (k_composite_fwd<TW, TH, B, PPT, MODE>), dim3(grid), dim3(TW * TH / PPT), 0, s, vt,
-               rp, w);
+    GPS_LAUNCH(K_COMPOSITE_FWD, s, (k_composite_fwd<TW, TH, B, PPT, MODE>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s,
+               vt, rp, w);
 }
 
 template <int TW, int TH, int B, int PPT>
