@@ -35,10 +35,16 @@ __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, 
 
 __global__ void __launch_bounds__(256) k_adam(AdamArgs a)
 {
-    const int t = a.step_ctr ? (*a.step_ctr + 1) : a.step;
-    // bias corrections in double: 1 - beta^t loses digits in binary32 for small t
-    const float ibc1 = (float)(1.0 / (1.0 - pow((double)a.b1, (double)t)));
-    const float ibc2 = (float)(1.0 / (1.0 - pow((double)a.b2, (double)t)));
+    // Bias corrections 1 / (1 - beta^t), in double (1 - beta^t loses digits in
+    // binary32 for small t), computed once per block and shared through LDS.
+    __shared__ float sbc[2];
+    if (threadIdx.x == 0) {
+        const int t = a.step_ctr ? (*a.step_ctr + 1) : a.step;
+        sbc[0] = (float)(1.0 / (1.0 - pow((double)a.b1, (double)t)));
+        sbc[1] = (float)(1.0 / (1.0 - pow((double)a.b2, (double)t)));
+    }
+    __syncthreads();
+    const float ibc1 = sbc[0], ibc2 = sbc[1];
     const long long total = a.start[a.ng];
     for (long long i = blockIdx.x * 256ll + threadIdx.x; i < total; i += (long long)gridDim.x * 256ll) {
         int k = 0;

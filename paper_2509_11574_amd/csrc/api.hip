@@ -87,8 +87,6 @@ static gps_status compute_layout(const gps_render_cfg* cfg, int M, const gps_cam
     o = align_up(o + 4 * (size_t)n_tiles);
     L->tile_start = o;
     o = align_up(o + 4 * (size_t)(n_tiles + 1));
-    L->tile_cursor = o;
-    o = align_up(o + 4 * (size_t)n_tiles);
     L->tile_queue = o;
     o = align_up(o + 4 * (size_t)n_tiles);
     L->tile_loss = o;

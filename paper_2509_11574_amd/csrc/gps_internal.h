@@ -16,6 +16,8 @@ constexpr int kSortCap = 8192;        // longest tile list sorted in LDS (64 KiB
 constexpr int kRecFloats = 12;        // projected record: 48 bytes
 constexpr int kAdj = 10;              // screen-space adjoints per instance
 constexpr int kBlk = 256;             // threads per block of the per-Gaussian kernels
+constexpr int kBlkLog2 = 8;
+static_assert((1 << kBlkLog2) == kBlk, "kBlkLog2");
 constexpr int kFlush = 32;            // records between flushes of the backward's per-wavefront partials
 
 // ---------------------------------------------------------------------------
@@ -79,7 +81,7 @@ struct WsHeader {
 
 struct WsLayout {
     size_t total;
-    size_t hdr, vtab, tilemax, tile_cnt, tile_start, tile_cursor, tile_queue, tile_loss, tile_pairs, pix_aux, rec, cnt, off,
+    size_t hdr, vtab, tilemax, tile_cnt, tile_start, tile_queue, tile_loss, tile_pairs, pix_aux, rec, cnt, off,
         blk_sum, blk_off,
         keys, inst_vg, partial, pose_part;
     int n_tiles, nvg, nblk_vg, nblk_g;
@@ -89,9 +91,8 @@ struct WsLayout {
 struct WsPtrs {
     WsHeader* hdr;
     float* tilemax;
-    unsigned int* tile_cnt;
+    unsigned int* tile_cnt;     // per tile: instances that pass the depth cull
     unsigned int* tile_start;   // n_tiles + 1
-    unsigned int* tile_cursor;
     unsigned int* tile_queue;   // tiles in processing order (longest first)
     float4* tile_loss;          // per tile: colour L1 sum, depth L1 sum, |Omega| count, 0
     uint2* tile_pairs;          // per tile: evaluated and composited (pixel, instance) pairs
@@ -102,7 +103,7 @@ struct WsPtrs {
     unsigned int* blk_sum;
     unsigned int* blk_off;
     unsigned long long* keys;   // (depth bits << 32) | slot, grouped by tile
-    unsigned int* inst_vg;      // slot -> view * M + Gaussian
+    unsigned int* inst_vg;      // slot -> view * M + Gaussian (between the two expansion passes: rank in tile)
     float* partial;             // [cap][kAdj]
     float* pose_part;           // [nblk_g][V][6]
 };
@@ -114,7 +115,6 @@ inline WsPtrs ws_ptrs(char* ws, const WsLayout& L)
     p.tilemax = reinterpret_cast<float*>(ws + L.tilemax);
     p.tile_cnt = reinterpret_cast<unsigned int*>(ws + L.tile_cnt);
     p.tile_start = reinterpret_cast<unsigned int*>(ws + L.tile_start);
-    p.tile_cursor = reinterpret_cast<unsigned int*>(ws + L.tile_cursor);
     p.tile_queue = reinterpret_cast<unsigned int*>(ws + L.tile_queue);
     p.tile_loss = reinterpret_cast<float4*>(ws + L.tile_loss);
     p.tile_pairs = reinterpret_cast<uint2*>(ws + L.tile_pairs);

@@ -240,10 +240,9 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(RParams rp, WsPtrs w, int n
     __shared__ unsigned int hist[33], cur[33];
     if (threadIdx.x < 33) hist[threadIdx.x] = 0u;
     __syncthreads();
-    for (int i = threadIdx.x; i < n_tiles; i += 1024) {
-        w.tile_cursor[i] = w.tile_start[i];
-        atomicAdd(&hist[31 - __clz(w.tile_cnt[i] + 1u)], 1u);
-    }
+    // tile counts from the scanned starts
+    for (int i = threadIdx.x; i < n_tiles; i += 1024)
+        atomicAdd(&hist[31 - __clz(w.tile_start[i + 1] - w.tile_start[i] + 1u)], 1u);
     __syncthreads();
     if (threadIdx.x == 0) {
         unsigned int o = 0;
@@ -254,7 +253,7 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(RParams rp, WsPtrs w, int n
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n_tiles; i += 1024) {
-        const unsigned int pos = atomicAdd(&cur[31 - __clz(w.tile_cnt[i] + 1u)], 1u);
+        const unsigned int pos = atomicAdd(&cur[31 - __clz(w.tile_start[i + 1] - w.tile_start[i] + 1u)], 1u);
         w.tile_queue[pos] = (unsigned int)i;
     }
 }
@@ -266,9 +265,11 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(RParams rp, WsPtrs w, int n
 // search in LDS), so one large Gaussian is spread over the whole block instead
 // of serialising one lane.  Instance i of block b has slot blk_off[b] + i.
 //   COUNT:  tiles that pass the exact depth cull get their tile count incremented;
-//           the per-view-Gaussian slot offsets are written.
-//   EMIT:   the same instances get a position in their tile's range and a key
-//           (depth bits << 32) | slot; slot -> view-Gaussian is recorded.
+//           the count before the increment (the instance's rank in its tile) is
+//           parked in inst_vg[slot]; the per-view-Gaussian slot offsets are written.
+//   EMIT:   the same instances (the cull is the same binary32 test on the same
+//           values) write the key (depth bits << 32) | slot at tile_start + rank,
+//           with no atomics, and replace the rank by slot -> view-Gaussian.
 template <bool EMIT>
 __global__ void __launch_bounds__(kBlk) k_expand(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w)
 {
@@ -297,7 +298,7 @@ __global__ void __launch_bounds__(kBlk) k_expand(const ViewTable* __restrict__ v
     for (unsigned int i = threadIdx.x; i < tot; i += kBlk) {
         int lo = 0, hi = kBlk;  // pre[lo] <= i < pre[hi]
 #pragma unroll
-        for (int step = 0; step < 8; ++step) {
+        for (int step = 0; step < kBlkLog2; ++step) {
             const int mid = (lo + hi) >> 1;
             if (pre[mid] <= i) lo = mid;
             else hi = mid;
@@ -310,20 +311,20 @@ __global__ void __launch_bounds__(kBlk) k_expand(const ViewTable* __restrict__ v
         const unsigned int wdt = (unsigned int)(r.tx1 - r.tx0 + 1);
         const int tile = vw.x + (r.ty0 + (int)(j / wdt)) * vw.y + r.tx0 + (int)(j % wdt);
         const float z = sz[lo];
+        const unsigned int slot = base + i;
         if (!(z < w.tilemax[tile] + rp.eps)) {  // exact tile-level depth cull
             if (EMIT) {  // the backward sums every slot of a Gaussian: culled slots hold zeros
-                float* pz = w.partial + (size_t)(base + i) * kAdj;
+                float* pz = w.partial + (size_t)slot * kAdj;
 #pragma unroll
                 for (int q = 0; q < kAdj; ++q) pz[q] = 0.0f;
             }
             continue;
         }
         if (!EMIT) {
-            atomicAdd(w.tile_cnt + tile, 1u);
+            w.inst_vg[slot] = atomicAdd(w.tile_cnt + tile, 1u);
         } else {
-            const unsigned int slot = base + i;
+            const unsigned int pos = w.tile_start[tile] + w.inst_vg[slot];
             w.inst_vg[slot] = (unsigned int)(blockIdx.x * kBlk + lo);
-            const unsigned int pos = atomicAdd(w.tile_cursor + tile, 1u);
             if (pos < w.tile_start[tile + 1]) w.keys[pos] = ((unsigned long long)__float_as_uint(z) << 32) | slot;
         }
     }
@@ -655,7 +656,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
 }
 
 // ------------------------------------------------------------ loss reduce
-__global__ void __launch_bounds__(256) k_loss_reduce(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w, float* out_loss,
+__global__ void __launch_bounds__(1024) k_loss_reduce(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w, float* out_loss,
                                                      int has_loss)
 {
     const ViewTable& vt = *vtp;
@@ -664,15 +665,15 @@ __global__ void __launch_bounds__(256) k_loss_reduce(const ViewTable* __restrict
         const DevView& V = vt.v[v];
         const int nt = V.tiles_x * V.tiles_y;
         float a = 0.0f, b = 0.0f, c = 0.0f;
-        for (int t = threadIdx.x; t < nt; t += 256) {
+        for (int t = threadIdx.x; t < nt; t += 1024) {
             const float4 q = w.tile_loss[V.tile_base + t];
             a += q.x;
             b += q.y;
             c += q.z;
         }
-        a = block_sum<256>(a);
-        b = block_sum<256>(b);
-        c = block_sum<256>(c);
+        a = block_sum<1024>(a);
+        b = block_sum<1024>(b);
+        c = block_sum<1024>(c);
         if (threadIdx.x == 0) {
             w.hdr->view_stats[v][0] = a;
             w.hdr->view_stats[v][1] = b;
@@ -686,7 +687,7 @@ __global__ void __launch_bounds__(256) k_loss_reduce(const ViewTable* __restrict
     // a fixed order and added to the cumulative counters of the header.
     unsigned long long pe = 0ull, pc = 0ull;
     if (w.hdr->n_inst <= rp.cap) {
-        for (int t = threadIdx.x; t < vt.n_tiles; t += 256) {
+        for (int t = threadIdx.x; t < vt.n_tiles; t += 1024) {
             const uint2 q = w.tile_pairs[t];
             pe += q.x;
             pc += q.y;
@@ -696,15 +697,20 @@ __global__ void __launch_bounds__(256) k_loss_reduce(const ViewTable* __restrict
         pe += __shfl_xor(pe, o, 64);
         pc += __shfl_xor(pc, o, 64);
     }
-    __shared__ unsigned long long spe[4], spc[4];
+    __shared__ unsigned long long spe[16], spc[16];
     if ((threadIdx.x & 63) == 0) {
         spe[threadIdx.x >> 6] = pe;
         spc[threadIdx.x >> 6] = pc;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        w.hdr->pairs_eval += spe[0] + spe[1] + spe[2] + spe[3];
-        w.hdr->pairs_contrib += spc[0] + spc[1] + spc[2] + spc[3];
+        unsigned long long te = 0ull, tc = 0ull;
+        for (int k = 0; k < 16; ++k) {
+            te += spe[k];
+            tc += spc[k];
+        }
+        w.hdr->pairs_eval += te;
+        w.hdr->pairs_contrib += tc;
         L = L / (float)vt.n;
         w.hdr->loss = has_loss ? L : 0.0f;
         if (out_loss && has_loss) *out_loss = L;
@@ -804,7 +810,7 @@ gps_status launch_render_fwd(const gps_render_cfg* cfg, const RParams& rp, const
     GPS_LAUNCH(K_TILE_SORT, s, k_tile_sort_small, dim3((L.n_tiles + 3) / 4), dim3(256), 0, s, rp, w, L.n_tiles);
     GPS_LAUNCH(K_TILE_SORT_LARGE, s, k_tile_sort_large, dim3(L.n_tiles), dim3(256), kSortCap * sizeof(unsigned long long), s, rp, w);
     if (!dispatch_cfwd(cfg, dvt, rp, w, L.n_tiles, s)) return GPS_ERR_UNSUPPORTED_CONFIG;
-    GPS_LAUNCH(K_LOSS_REDUCE, s, k_loss_reduce, dim3(1), dim3(256), 0, s, dvt, rp, w, out_loss, has_loss);
+    GPS_LAUNCH(K_LOSS_REDUCE, s, k_loss_reduce, dim3(1), dim3(1024), 0, s, dvt, rp, w, out_loss, has_loss);
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
 }
 
