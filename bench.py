@@ -46,8 +46,8 @@ def log(*a):
 # recorded in profiles/traffic.json with the SHA-256 of the kernel's source files at
 # the time of the measurement; it is reported only while those sources are unchanged.
 KERNEL_SOURCES = {
-    "composite_bwd": ("render_bwd.hip", "render_common.h", "gps_internal.h"),
-    "composite_fwd": ("render_fwd.hip", "render_common.h", "gps_internal.h"),
+    "composite_bwd": ("composite_bwd.hip", "render_common.h", "gps_internal.h"),
+    "composite_fwd": ("composite_fwd.hip", "render_common.h", "gps_internal.h"),
 }
 
 

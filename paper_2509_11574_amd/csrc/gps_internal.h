@@ -286,6 +286,10 @@ gps_status launch_render_fwd(const gps_render_cfg* cfg, const RParams& rp, const
 gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const gps_gaussians* g,
                              const ViewTable& vt, const WsLayout& L, char* ws, int explicit_upstream,
                              const float* loss_scale, gps_gaussians* grads, float* dpose, hipStream_t s);
+bool dispatch_cfwd(const gps_render_cfg* cfg, const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles,
+                   hipStream_t s);
+bool dispatch_cbwd(const gps_render_cfg* cfg, const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles,
+                   int explicit_up, const float* loss_scale, hipStream_t s);
 gps_status launch_views_upload(const ViewTable& vt, const WsLayout& L, char* ws, hipStream_t s);
 gps_status launch_adam(const gps_adam_group* groups, int n_groups, int step, int* step_counter, float b1, float b2,
                        float eps, hipStream_t s);

@@ -1,13 +1,7 @@
-// Backward render (analytic gradient of the forward in render_fwd.hip).
+// Backward render (analytic gradient of the forward render).
 //
-//   k_composite_bwd<TW,TH,B,PPT>  per tile: recompute the front-to-back
-//       traversal of every pixel (transmittance T_i and prefix colour/depth
-//       P_i), form the adjoints of each contributor's centre, conic, opacity,
-//       colour and depth (the first six in the base-2 form of the opacity, see
-//       k_gauss_bwd), reduce them over the tile's pixels (a DPP
-//       transpose-reduction within each 16-lane row, LDS across rows and
-//       wavefronts, fixed order) and write ONE 10-float partial per (tile, Gaussian) instance
-//       into that instance's slot.
+//   k_composite_bwd  (composite_bwd.hip) per tile: one 10-float partial per
+//       (tile, Gaussian) instance, written into that instance's slot.
 //   k_gauss_bwd   per Gaussian: sum its instance partials (a contiguous slot
 //       range per view, summed in order), apply the EWA chain rule to the
 //       parameters and form the per-Gaussian pose terms, reduced per block.
@@ -17,245 +11,6 @@
 #include "render_common.h"
 
 namespace gps {
-
-__device__ __forceinline__ float sgnf(float x) { return (float)((x > 0.0f) - (x < 0.0f)); }
-
-template <int TW, int TH, int B, int PPT, int MODE>
-__global__ void __launch_bounds__(TW * TH / PPT)
-    k_composite_bwd(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w, int explicit_up, const float* loss_scale)
-{
-    const ViewTable& vt = *vtp;
-    using Lay = TileLayout<TW, TH, PPT>;
-    constexpr int NT = Lay::NT;
-    constexpr int NW = Lay::NW;
-    __shared__ float4 srec[3 * B];
-    __shared__ unsigned int sslot[B];
-    __shared__ unsigned int smask[B];  // wavefront mask per staged record (32-bit: no byte stores in LDS)
-    constexpr int S = kFlush;                // records per flush of the per-wavefront partials
-    // Per record: NW wavefronts x 4 row partials x kAdj, padded so that successive
-    // records start 10 banks apart (the flush reads (record, component) pairs).
-    constexpr int kRecStride = NW * 4 * kAdj + ((10 - (NW * 4 * kAdj) % 32) + 32) % 32;
-    __shared__ float slab[S * kRecStride];
-    // Bit j of swritten[w]: wavefront w wrote its partial of window record j.  One
-    // 64-bit word per wavefront, written by its lane 0: flags of different
-    // wavefronts never share an LDS dword (sub-dword stores from different
-    // wavefronts into one dword are not used anywhere).
-    __shared__ unsigned long long swritten[NW];
-    if (w.hdr->n_inst > rp.cap) return;
-    // One block per tile, in queue order (longest tile lists first).
-    const int tile = (int)w.tile_queue[blockIdx.x];
-    const int v = find_view(vt, tile);
-    const DevView& V = vt.v[v];
-    const int lt = tile - V.tile_base;
-    const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
-    const int Wd = V.cam.W, Ht = V.cam.H;
-    const size_t HW = (size_t)Wd * Ht;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int wx0 = tx * TW + Lay::wave_x0(wid), wy0 = ty * TH + Lay::wave_y0(wid);
-    const int px = wx0 + Lay::lane_x(lane);
-    const int py0 = wy0 + Lay::lane_y(lane);
-    const float fpx = (float)px;
-
-    float sc = 1.0f;
-    if (!explicit_up && loss_scale) sc = *loss_scale;
-    const float invV = 1.0f / (float)rp.V;
-    const float om = w.hdr->view_stats[v][2];
-
-    // Per pixel: the upstream adjoint G = (dL/dC*, dL/dD*), CG = G . (C*, D*) and
-    // the running PG = G . P_i, where P_i is the composited prefix through
-    // Gaussian i.  The remainder term of dL/dalpha_i only ever needs
-    // G . (C* - P_i) = CG - PG, so the prefix colours are not kept.
-    // thr as in the forward: -inf once a pixel has stopped for a reason other
-    // than the depth test (which every deeper record fails as well).
-    float thr[PPT], T[PPT], G0[PPT], G1[PPT], G2[PPT], GD[PPT], CG[PPT], PG[PPT], invW[PPT];
-#pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int py = py0 + k * Lay::LROWS;
-        const bool inb = px < Wd && py < Ht;
-        const size_t p = inb ? (size_t)py * Wd + px : 0;
-        const float dt = inb ? V.base_depth[p] : 0.0f;
-        const bool dvalid = dt > 0.0f;
-        thr[k] = inb ? (dvalid ? dt : INFINITY) + rp.eps : -INFINITY;
-        T[k] = 1.0f;
-        PG[k] = 0.0f;
-        G0[k] = G1[k] = G2[k] = GD[k] = 0.0f;
-        float cs0 = 0.0f, cs1 = 0.0f, cs2 = 0.0f, ds = 0.0f;
-        invW[k] = 1.0f;
-        if (inb) {
-            cs0 = V.out_rgb[p];
-            cs1 = V.out_rgb[HW + p];
-            cs2 = V.out_rgb[2 * HW + p];
-            ds = V.out_depth[p];
-            if (MODE == 1) invW[k] = 1.0f / (1.0f + w.pix_aux[(size_t)V.pix_base + p]);
-            if (explicit_up) {
-                G0[k] = V.g_rgb[p];
-                G1[k] = V.g_rgb[HW + p];
-                G2[k] = V.g_rgb[2 * HW + p];
-                GD[k] = (V.g_depth && dvalid) ? V.g_depth[p] : 0.0f;
-            } else {
-                const float cn = sc * invV / (3.0f * (float)HW);
-                G0[k] = cn * sgnf(cs0 - V.target_rgb[p]);
-                G1[k] = cn * sgnf(cs1 - V.target_rgb[HW + p]);
-                G2[k] = cn * sgnf(cs2 - V.target_rgb[2 * HW + p]);
-                if (V.target_depth && dvalid && om > 0.0f) {
-                    const float dobs = V.target_depth[p];
-                    if (dobs > 0.0f) GD[k] = sc * invV * rp.lambda / om * sgnf(ds - dobs);
-                }
-            }
-        }
-        CG[k] = G0[k] * cs0 + G1[k] * cs1 + G2[k] * cs2 + GD[k] * ds;
-    }
-
-    const unsigned int s = w.tile_start[tile], e = w.tile_start[tile + 1];
-    const int tx0 = tx * TW, ty0 = ty * TH;
-    unsigned int stop = s;  // first position whose partial has not been written
-    bool wave_alive = true;  // some pixel of this wavefront still takes records
-    for (unsigned int b = s; b < e; b += B) {
-        if (__syncthreads_count(wave_alive && lane == 0) == 0) break;
-        for (int j = threadIdx.x; j < B; j += NT) {
-            unsigned int mk = 0u, slot = 0xffffffffu;
-            if (b + j < e) {
-                slot = (unsigned int)w.keys[b + j];
-                unsigned int vg = slot < rp.cap ? w.inst_vg[slot] : 0u;
-                if (vg >= (unsigned int)rp.nvg) vg = 0u;  // guard: never read outside the records
-                const float4* r = w.rec + 3 * (size_t)vg;
-                const float4 r0 = r[0], r1 = r[1], r2 = r[2];
-                srec[3 * j + 0] = r0;
-                srec[3 * j + 1] = r1;
-                srec[3 * j + 2] = r2;
-                mk = wave_box_mask<Lay>(r0.x, r0.y, r2.z, r2.w, tx0, ty0);
-            }
-            smask[j] = mk;
-            sslot[j] = slot;
-        }
-        __syncthreads();
-        const int n = (int)min((unsigned int)B, e - b);
-        int alive_now = 1;
-        for (int j0 = 0; j0 < n && alive_now; j0 += S) {
-            const int j1 = min(j0 + S, n);
-            // Records of this window whose box touches this wavefront (as in the forward).
-            const int jl = j0 + lane;
-            unsigned long long m =
-                __builtin_amdgcn_ballot_w64(wave_alive && lane < S && jl < j1 && ((smask[jl] >> wid) & 1u));
-            unsigned long long written = 0ull;  // window records whose partial this wavefront wrote
-            while (m) {
-                const int jw = (int)__builtin_ctzll(m);
-                m &= m - 1ull;
-                const int j = j0 + jw;
-                const float4 r0 = srec[3 * j], r1 = srec[3 * j + 1], r2 = srec[3 * j + 2];
-                const float c0 = r1.w, c1 = r2.x, c2 = r2.y, zi = r1.z;
-                // the forward's decisions, in the same order and arithmetic
-                unsigned long long any_live = 0ull, any_use = 0ull;
-                AlphaEval ae[PPT];
-                float av[PPT], Tn[PPT];
-                bool use[PPT];
-#pragma unroll
-                for (int k = 0; k < PPT; ++k) {
-                    const bool live = zi < thr[k];
-                    any_live |= __builtin_amdgcn_ballot_w64(live);
-                    ae[k] = eval_alpha(fpx, (float)(py0 + k * Lay::LROWS), r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
-                    if (MODE == 0) {
-                        av[k] = fminf(ae[k].raw, rp.amax);
-                        const bool ok = live && av[k] >= rp.amin;
-                        Tn[k] = T[k] * (1.0f - av[k]);
-                        const bool stop = ok && Tn[k] < rp.Tmin;
-                        use[k] = ok && !stop;
-                        thr[k] = stop ? -INFINITY : thr[k];
-                    } else {
-                        av[k] = ae[k].raw;
-                        Tn[k] = 0.0f;
-                        use[k] = live && av[k] >= rp.amin;
-                    }
-                    any_use |= __builtin_amdgcn_ballot_w64(use[k]);
-                }
-                if (any_use) {
-                    // Adjoints of the contributing lanes; the others carry zero
-                    // weight, so no accumulator needs clearing.
-                    float g[kAdj];
-#pragma unroll
-                    for (int k = 0; k < PPT; ++k) {
-                        const float direct = G0[k] * c0 + G1[k] * c1 + G2[k] * c2 + GD[k] * zi;  // G . (c_i, d_i)
-                        float wgt, dal;
-                        bool apath;
-                        if (MODE == 0) {
-                            wgt = use[k] ? av[k] * T[k] : 0.0f;  // w_i = alpha_i T_i
-                            PG[k] = __builtin_fmaf(wgt, direct, PG[k]);
-                            // dL/dalpha_i = T_i G.(c_i,d_i) - G.(C* - P_i) / (1 - alpha_i)
-                            dal = T[k] * direct - (CG[k] - PG[k]) * __builtin_amdgcn_rcpf(1.0f - av[k]);
-                            apath = use[k] && ae[k].raw <= rp.amax;  // a capped opacity has no gradient
-                            T[k] = use[k] ? Tn[k] : T[k];
-                        } else {
-                            wgt = use[k] ? av[k] * invW[k] : 0.0f;  // d C* / d c_i = alpha_i / (1 + W_G)
-                            dal = invW[k] * (direct - CG[k]);
-                            apath = use[k];
-                        }
-                        // alpha = exp2(pw): d alpha / d pw = alpha ln 2; the constant
-                        // factors are applied once per Gaussian.
-                        const float u = apath ? dal * av[k] : 0.0f;
-                        const float t0 = u * ae[k].dx;
-                        const float t1 = u * ae[k].dy;
-                        if (k == 0) {
-                            g[0] = t0;
-                            g[1] = t1;
-                            g[2] = u * ae[k].dxx;
-                            g[3] = u * ae[k].dxy;
-                            g[4] = u * ae[k].dyy;
-                            g[5] = u;
-                            g[6] = wgt * G0[k];
-                            g[7] = wgt * G1[k];
-                            g[8] = wgt * G2[k];
-                            g[9] = wgt * GD[k];
-                        } else {
-                            g[0] += t0;
-                            g[1] += t1;
-                            g[2] = __builtin_fmaf(u, ae[k].dxx, g[2]);
-                            g[3] = __builtin_fmaf(u, ae[k].dxy, g[3]);
-                            g[4] = __builtin_fmaf(u, ae[k].dyy, g[4]);
-                            g[5] += u;
-                            g[6] = __builtin_fmaf(wgt, G0[k], g[6]);
-                            g[7] = __builtin_fmaf(wgt, G1[k], g[7]);
-                            g[8] = __builtin_fmaf(wgt, G2[k], g[8]);
-                            g[9] = __builtin_fmaf(wgt, GD[k], g[9]);
-                        }
-                    }
-                    wave_rows_sum10_store(g, slab + jw * kRecStride + wid * 4 * kAdj, lane);
-                    written |= 1ull << jw;
-                }
-                if (!any_live) {  // this record and all deeper ones fail every pixel
-                    wave_alive = false;
-                    break;
-                }
-            }
-            if (lane == 0) swritten[wid] = written;
-            alive_now = __syncthreads_count(wave_alive && lane == 0);
-            // one thread per (record, component): sum the wavefront partials in order
-            for (int t = threadIdx.x; t < (j1 - j0) * kAdj; t += NT) {
-                const int jr = t / kAdj, q = t - jr * kAdj;
-                float acc = 0.0f;
-#pragma unroll
-                for (int ww = 0; ww < NW; ++ww)
-                    if ((swritten[ww] >> jr) & 1ull) {
-                        const float* sp = slab + jr * kRecStride + ww * 4 * kAdj + q;
-                        acc += (sp[0] + sp[kAdj]) + (sp[2 * kAdj] + sp[3 * kAdj]);
-                    }
-                const unsigned int slot = sslot[j0 + jr];
-                if (slot < rp.cap) w.partial[(size_t)slot * kAdj + q] = acc;
-            }
-            __syncthreads();
-            stop = b + (unsigned int)j1;  // positions before this were written
-        }
-        if (!alive_now) break;
-    }
-    // Instances after the point where every pixel of the tile had stopped
-    // contribute nothing; their slots still need zeros.
-    for (unsigned int pos = stop + threadIdx.x; pos < e; pos += NT) {
-        const unsigned int slot = (unsigned int)w.keys[pos];
-        if (slot >= rp.cap) continue;
-        float* out = w.partial + (size_t)slot * kAdj;
-#pragma unroll
-        for (int q = 0; q < kAdj; ++q) out[q] = 0.0f;
-    }
-}
 
 // ------------------------------------------------------------- gauss bwd
 // EWA chain rule of one Gaussian in one view.  The summed instance partials are
@@ -515,54 +270,6 @@ __global__ void __launch_bounds__(256) k_pose_reduce(RParams rp, WsPtrs w, int n
 }
 
 // ----------------------------------------------------------------- launch
-template <int TW, int TH, int B, int PPT, int MODE>
-static void launch_cbwd_mode(const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles, int explicit_up,
-                             const float* loss_scale, hipStream_t s)
-{
-    GPS_LAUNCH(K_COMPOSITE_BWD, s, (k_composite_bwd<TW, TH, B, PPT, MODE>), dim3(n_tiles), dim3(TW * TH / PPT), 0, s,
-               vt, rp, w, explicit_up, loss_scale);
-}
-
-template <int TW, int TH, int B, int PPT>
-static void launch_cbwd(const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles, int explicit_up,
-                        const float* loss_scale, hipStream_t s)
-{
-    if (rp.mode == 0) launch_cbwd_mode<TW, TH, B, PPT, 0>(vt, rp, w, n_tiles, explicit_up, loss_scale, s);
-    else launch_cbwd_mode<TW, TH, B, PPT, 1>(vt, rp, w, n_tiles, explicit_up, loss_scale, s);
-}
-
-#define GPS_TILE_CONFIGS_B(X) \
-    X(8, 8, 128, 1)           \
-    X(8, 8, 256, 1)           \
-    X(8, 8, 512, 1)           \
-    X(16, 16, 128, 1)         \
-    X(16, 16, 256, 1)         \
-    X(16, 16, 128, 2)         \
-    X(16, 16, 256, 2)         \
-    X(16, 16, 512, 2)         \
-    X(16, 16, 128, 4)         \
-    X(16, 16, 256, 4)         \
-    X(16, 16, 512, 4)         \
-    X(16, 32, 128, 1)         \
-    X(16, 32, 128, 2)         \
-    X(16, 32, 256, 2)         \
-    X(16, 32, 128, 4)         \
-    X(16, 32, 256, 4)         \
-    X(16, 32, 512, 4)
-
-static bool dispatch_cbwd(const gps_render_cfg* cfg, const ViewTable* vt, const RParams& rp, const WsPtrs& w,
-                          int n_tiles, int explicit_up, const float* loss_scale, hipStream_t s)
-{
-#define X(tw, th, b, ppt)                                                                              \
-    if (cfg->tile_w == tw && cfg->tile_h == th && cfg->batch == b && cfg->pix_per_thread == ppt) {   \
-        launch_cbwd<tw, th, b, ppt>(vt, rp, w, n_tiles, explicit_up, loss_scale, s);                 \
-        return true;                                                                                 \
-    }
-    GPS_TILE_CONFIGS_B(X)
-#undef X
-    return false;
-}
-
 gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const gps_gaussians* g,
                              const ViewTable& vt, const WsLayout& L, char* ws, int explicit_upstream,
                              const float* loss_scale, gps_gaussians* grads, float* dpose, hipStream_t s)

@@ -123,4 +123,25 @@ __device__ __forceinline__ unsigned int wave_box_mask(float mx, float my, float 
     return mk;
 }
 
+// Tile configurations (tile width, height, staged batch, pixels per lane) for
+// which both compositing kernels are instantiated.
+#define GPS_TILE_CONFIGS(X) \
+    X(8, 8, 128, 1)         \
+    X(8, 8, 256, 1)         \
+    X(8, 8, 512, 1)         \
+    X(16, 16, 128, 1)       \
+    X(16, 16, 256, 1)       \
+    X(16, 16, 128, 2)       \
+    X(16, 16, 256, 2)       \
+    X(16, 16, 512, 2)       \
+    X(16, 16, 128, 4)       \
+    X(16, 16, 256, 4)       \
+    X(16, 16, 512, 4)       \
+    X(16, 32, 128, 1)       \
+    X(16, 32, 128, 2)       \
+    X(16, 32, 256, 2)       \
+    X(16, 32, 128, 4)       \
+    X(16, 32, 256, 4)       \
+    X(16, 32, 512, 4)
+
 }  // namespace gps
