@@ -84,7 +84,7 @@ static gps_status compute_layout(const gps_render_cfg* cfg, int M, const gps_cam
     L->tilemax = o;
     o = align_up(o + 4 * (size_t)n_tiles);
     L->tile_cnt = o;
-    o = align_up(o + 4 * (size_t)n_tiles);
+    o = align_up(o + 4 * (size_t)kCntSplit * n_tiles);
     L->tile_start = o;
     o = align_up(o + 4 * (size_t)(n_tiles + 1));
     L->tile_queue = o;

@@ -16,8 +16,12 @@ constexpr int kSortCap = 8192;        // longest tile list sorted in LDS (64 KiB
 constexpr int kRecFloats = 12;        // projected record: 48 bytes
 constexpr int kAdj = 10;              // screen-space adjoints per instance
 constexpr int kBlk = 256;             // threads per block of the per-Gaussian kernels
-constexpr int kBlkLog2 = 8;
-static_assert((1 << kBlkLog2) == kBlk, "kBlkLog2");
+constexpr int kExpG = 64;             // view-Gaussians per block of the instance expansion (kBlk lanes walk
+                                      // their tile rectangles: about kBlk / kExpG lanes per Gaussian)
+constexpr int kExpGLog2 = 6;
+static_assert((1 << kExpGLog2) == kExpG && kBlk % kExpG == 0, "expansion share");
+constexpr int kCntSplit = 4;          // sub-counters per tile for the count pass's atomics (block index mod 4):
+                                      // fewer increments queue on one address
 constexpr int kFlush = 32;            // records between flushes of the backward's per-wavefront partials
 
 // ---------------------------------------------------------------------------
@@ -91,7 +95,8 @@ struct WsLayout {
 struct WsPtrs {
     WsHeader* hdr;
     float* tilemax;
-    unsigned int* tile_cnt;     // per tile: instances that pass the depth cull
+    unsigned int* tile_cnt;     // [kCntSplit][n_tiles]: instances that pass the depth cull, per sub-counter;
+                                // after the tile scan, the start of each sub-counter's range
     unsigned int* tile_start;   // n_tiles + 1
     unsigned int* tile_queue;   // tiles in processing order (longest first)
     float4* tile_loss;          // per tile: colour L1 sum, depth L1 sum, |Omega| count, 0

@@ -52,8 +52,8 @@ __global__ void __launch_bounds__(256) k_prep(const ViewTable* __restrict__ vtp,
     __syncthreads();
     if (threadIdx.x == 0) {
         w.tilemax[tile] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
-        w.tile_cnt[tile] = 0u;
     }
+    if (threadIdx.x < kCntSplit) w.tile_cnt[(size_t)threadIdx.x * vt.n_tiles + tile] = 0u;
 }
 
 // ---------------------------------------------------------------- project
@@ -237,7 +237,26 @@ __global__ void __launch_bounds__(1024) k_scan_blocks(RParams rp, WsPtrs w, int 
 __global__ void __launch_bounds__(1024) k_scan_tiles(RParams rp, WsPtrs w, int n_tiles)
 {
     if (w.hdr->n_inst > rp.cap) return;
-    scan_array_1024(w.tile_cnt, w.tile_start, n_tiles, 1);
+    // tile totals over the sub-counters, scanned in place into tile ranges
+    for (int i = threadIdx.x; i < n_tiles; i += 1024) {
+        unsigned int t = 0u;
+#pragma unroll
+        for (int k = 0; k < kCntSplit; ++k) t += w.tile_cnt[(size_t)k * n_tiles + i];
+        w.tile_start[i] = t;
+    }
+    __syncthreads();
+    scan_array_1024(w.tile_start, w.tile_start, n_tiles, 1);
+    // each sub-counter's range inside its tile's range, in sub-counter order
+    for (int i = threadIdx.x; i < n_tiles; i += 1024) {
+        unsigned int run = w.tile_start[i];
+#pragma unroll
+        for (int k = 0; k < kCntSplit; ++k) {
+            unsigned int* c = w.tile_cnt + (size_t)k * n_tiles + i;
+            const unsigned int n = *c;
+            *c = run;
+            run += n;
+        }
+    }
     __shared__ unsigned int hist[33], cur[33];
     if (threadIdx.x < 33) hist[threadIdx.x] = 0u;
     __syncthreads();
@@ -260,46 +279,60 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(RParams rp, WsPtrs w, int n
 }
 
 // ------------------------------------------------------------ count / emit
-// Block-cooperative expansion of the instances of kBlk consecutive view-Gaussians:
-// the block's lanes walk the concatenation of their tile rectangles together
-// (instance i belongs to the lane whose prefix range holds i, found by binary
-// search in LDS), so one large Gaussian is spread over the whole block instead
-// of serialising one lane.  Instance i of block b has slot blk_off[b] + i.
-//   COUNT:  tiles that pass the exact depth cull get their tile count incremented;
-//           the count before the increment (the instance's rank in its tile) is
-//           parked in inst_vg[slot]; the per-view-Gaussian slot offsets are written.
+// Block-cooperative expansion of the instances of kExpG consecutive
+// view-Gaussians (a share of one projection block of kBlk): the block's kBlk
+// lanes walk the concatenation of their tile rectangles together (instance i
+// belongs to the Gaussian whose prefix range holds i, found by binary search in
+// LDS), so one large Gaussian, or a run of dense ones, is spread over several
+// lanes per Gaussian instead of serialising one lane.  Slots are numbered per
+// projection block: instance i of projection block b has slot blk_off[b] + i,
+// whichever expansion block handles it.
+//   COUNT:  tiles that pass the exact depth cull get one of their kCntSplit
+//           sub-counters (chosen by block index) incremented; the count before
+//           the increment (the instance's rank in that sub-counter) is parked in
+//           inst_vg[slot]; the per-view-Gaussian slot offsets are written.
 //   EMIT:   the same instances (the cull is the same binary32 test on the same
-//           values) write the key (depth bits << 32) | slot at tile_start + rank,
-//           with no atomics, and replace the rank by slot -> view-Gaussian.
+//           values, the block index the same) write the key
+//           (depth bits << 32) | slot at the sub-counter's start + rank, with no
+//           atomics, and replace the rank by slot -> view-Gaussian.
 template <bool EMIT>
 __global__ void __launch_bounds__(kBlk) k_expand(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w)
 {
+    constexpr int kSplit = kBlk / kExpG;  // expansion blocks per projection block
     const ViewTable& vt = *vtp;
     if (w.hdr->n_inst > rp.cap) return;
-    __shared__ unsigned int pre[kBlk + 1];
-    __shared__ float4 sbox[kBlk];  // mx, my, rxp, ryp
-    __shared__ float sz[kBlk];
-    __shared__ int4 sview[kBlk];   // tile_base, tiles_x, W, H
-    const int vg = blockIdx.x * kBlk + threadIdx.x;
+    __shared__ unsigned int pre[kExpG + 1];
+    __shared__ float4 sbox[kExpG];  // mx, my, rxp, ryp
+    __shared__ float sz[kExpG];
+    __shared__ int4 sview[kExpG];   // tile_base, tiles_x, W, H
+    const int pb = blockIdx.x / kSplit;
+    const int g0 = (blockIdx.x % kSplit) * kExpG;  // first lane (Gaussian) of this block's share
+    const int vg = pb * kBlk + threadIdx.x;         // lane k: Gaussian k of the projection block
     const unsigned int c = vg < rp.nvg ? w.cnt[vg] : 0u;
     unsigned int tot;
-    const unsigned int excl = block_excl_scan<kBlk>(c, &tot);
-    pre[threadIdx.x] = excl;
-    if (threadIdx.x == kBlk - 1) pre[kBlk] = excl + c;
-    if (c > 0) {
-        const float4 r0 = w.rec[3 * (size_t)vg], r1 = w.rec[3 * (size_t)vg + 1], r2 = w.rec[3 * (size_t)vg + 2];
-        sbox[threadIdx.x] = make_float4(r0.x, r0.y, r2.z, r2.w);
-        sz[threadIdx.x] = r1.z;
-        const DevView& V = vt.v[vg / rp.M];
-        sview[threadIdx.x] = make_int4(V.tile_base, V.tiles_x, V.cam.W, V.cam.H);
+    const unsigned int excl = block_excl_scan<kBlk>(c, &tot);  // prefix within the projection block
+    const int k = threadIdx.x - g0;
+    if (k >= 0 && k < kExpG) {
+        pre[k] = excl;
+        if (k == kExpG - 1) pre[kExpG] = excl + c;
+        if (c > 0) {
+            const float4 r0 = w.rec[3 * (size_t)vg], r1 = w.rec[3 * (size_t)vg + 1], r2 = w.rec[3 * (size_t)vg + 2];
+            sbox[k] = make_float4(r0.x, r0.y, r2.z, r2.w);
+            sz[k] = r1.z;
+            const DevView& V = vt.v[vg / rp.M];
+            sview[k] = make_int4(V.tile_base, V.tiles_x, V.cam.W, V.cam.H);
+        }
+        if (!EMIT && vg < rp.nvg) w.off[vg] = w.blk_off[pb] + excl;
     }
-    const unsigned int base = w.blk_off[blockIdx.x];
-    if (!EMIT && vg < rp.nvg) w.off[vg] = base + excl;
+    const unsigned int base = w.blk_off[pb];
+    // sub-counter of this block: the same block index, so the same sub-counter, in both passes
+    const size_t sub = (size_t)(blockIdx.x % kCntSplit) * vt.n_tiles;
     __syncthreads();
-    for (unsigned int i = threadIdx.x; i < tot; i += kBlk) {
-        int lo = 0, hi = kBlk;  // pre[lo] <= i < pre[hi]
+    const unsigned int first = pre[0], last = pre[kExpG];
+    for (unsigned int i = first + threadIdx.x; i < last; i += kBlk) {
+        int lo = 0, hi = kExpG;  // pre[lo] <= i < pre[hi]
 #pragma unroll
-        for (int step = 0; step < kBlkLog2; ++step) {
+        for (int step = 0; step < kExpGLog2; ++step) {
             const int mid = (lo + hi) >> 1;
             if (pre[mid] <= i) lo = mid;
             else hi = mid;
@@ -322,10 +355,10 @@ __global__ void __launch_bounds__(kBlk) k_expand(const ViewTable* __restrict__ v
             continue;
         }
         if (!EMIT) {
-            w.inst_vg[slot] = atomicAdd(w.tile_cnt + tile, 1u);
+            w.inst_vg[slot] = atomicAdd(w.tile_cnt + sub + tile, 1u);
         } else {
-            const unsigned int pos = w.tile_start[tile] + w.inst_vg[slot];
-            w.inst_vg[slot] = (unsigned int)(blockIdx.x * kBlk + lo);
+            const unsigned int pos = w.tile_cnt[sub + tile] + w.inst_vg[slot];
+            w.inst_vg[slot] = (unsigned int)(pb * kBlk + g0 + lo);
             if (pos < w.tile_start[tile + 1]) w.keys[pos] = ((unsigned long long)__float_as_uint(z) << 32) | slot;
         }
     }
@@ -553,9 +586,11 @@ gps_status launch_render_fwd(const gps_render_cfg* cfg, const RParams& rp, const
     GPS_LAUNCH(K_PREP, s, k_prep, dim3(L.n_tiles), dim3(256), 0, s, dvt, rp, w);
     if (L.nblk_vg > 0) GPS_LAUNCH(K_PROJECT, s, k_project, dim3(L.nblk_vg), dim3(kBlk), 0, s, dvt, rp, gp, w);
     GPS_LAUNCH(K_SCAN, s, k_scan_blocks, dim3(1), dim3(1024), 0, s, rp, w, L.nblk_vg, L.n_tiles);
-    if (L.nblk_vg > 0) GPS_LAUNCH(K_TILE_COUNT, s, k_expand<false>, dim3(L.nblk_vg), dim3(kBlk), 0, s, dvt, rp, w);
+    if (L.nblk_vg > 0)
+        GPS_LAUNCH(K_TILE_COUNT, s, k_expand<false>, dim3(L.nblk_vg * (kBlk / kExpG)), dim3(kBlk), 0, s, dvt, rp, w);
     GPS_LAUNCH(K_SCAN_TILES, s, k_scan_tiles, dim3(1), dim3(1024), 0, s, rp, w, L.n_tiles);
-    if (L.nblk_vg > 0) GPS_LAUNCH(K_EMIT, s, k_expand<true>, dim3(L.nblk_vg), dim3(kBlk), 0, s, dvt, rp, w);
+    if (L.nblk_vg > 0)
+        GPS_LAUNCH(K_EMIT, s, k_expand<true>, dim3(L.nblk_vg * (kBlk / kExpG)), dim3(kBlk), 0, s, dvt, rp, w);
     GPS_LAUNCH(K_TILE_SORT, s, k_tile_sort_small, dim3((L.n_tiles + 3) / 4), dim3(256), 0, s, rp, w, L.n_tiles);
     GPS_LAUNCH(K_TILE_SORT_LARGE, s, k_tile_sort_large, dim3(L.n_tiles), dim3(256), kSortCap * sizeof(unsigned long long), s, rp, w);
     if (!dispatch_cfwd(cfg, dvt, rp, w, L.n_tiles, s)) return GPS_ERR_UNSUPPORTED_CONFIG;
