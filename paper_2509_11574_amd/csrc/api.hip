@@ -6,6 +6,7 @@
 #include <cstring>
 
 #include "gps_internal.h"
+#include "binning.h"
 #include "prof.h"
 
 namespace gps {

@@ -16,12 +16,6 @@ constexpr int kSortCap = 8192;        // longest tile list sorted in LDS (64 KiB
 constexpr int kRecFloats = 12;        // projected record: 48 bytes
 constexpr int kAdj = 10;              // screen-space adjoints per instance
 constexpr int kBlk = 256;             // threads per block of the per-Gaussian kernels
-constexpr int kExpG = 64;             // view-Gaussians per block of the instance expansion (kBlk lanes walk
-                                      // their tile rectangles: about kBlk / kExpG lanes per Gaussian)
-constexpr int kExpGLog2 = 6;
-static_assert((1 << kExpGLog2) == kExpG && kBlk % kExpG == 0, "expansion share");
-constexpr int kCntSplit = 4;          // sub-counters per tile for the count pass's atomics (block index mod 4):
-                                      // fewer increments queue on one address
 constexpr int kFlush = 32;            // records between flushes of the backward's per-wavefront partials
 
 // ---------------------------------------------------------------------------

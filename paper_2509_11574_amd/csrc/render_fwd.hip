@@ -19,6 +19,7 @@
 //                  misses their pixels, front-to-back compositing, loss
 //                  partial per tile
 //   k_loss_reduce  one block: per-view and total loss
+#include "binning.h"
 #include "prof.h"
 #include "render_common.h"
 
