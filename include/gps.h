@@ -41,7 +41,14 @@
 extern "C" {
 #endif
 
-#define GPS_ABI_VERSION 1
+#define GPS_ABI_VERSION 2
+
+/* Size in floats of gps_volume.brick_min for an nx x ny x nz lattice. */
+#define GPS_BRICKS_(n) (((n) + 7) / 8)
+#define GPS_SUPERBRICKS_(n) ((GPS_BRICKS_(n) + 3) / 4)
+#define GPS_BRICK_MIN_FLOATS(nx, ny, nz)                                                  \
+    ((size_t)GPS_BRICKS_(nx) * GPS_BRICKS_(ny) * GPS_BRICKS_(nz) +                        \
+     (size_t)GPS_SUPERBRICKS_(nx) * GPS_SUPERBRICKS_(ny) * GPS_SUPERBRICKS_(nz))
 #define GPS_MAX_VIEWS 16 /* views per render call */
 
 typedef int32_t gps_status;
@@ -73,8 +80,10 @@ typedef struct gps_volume {
     float* weight;     /* [N] fusion weight, initialise to 0                    */
     float* rgb;        /* [3][N] colour, initialise to 0                        */
     float* rgb_weight; /* [N] colour weight, initialise to 0                    */
-    float* brick_min;  /* optional [ceil(nx/8)*ceil(ny/8)*ceil(nz/8)] scratch
-                          for empty-space skipping in gps_raycast; NULL disables */
+    float* brick_min;  /* optional GPS_BRICK_MIN_FLOATS(nx, ny, nz) floats of
+                          scratch for empty-space skipping in gps_raycast (minima
+                          of 8^3-voxel bricks, then of 4^3-brick superbricks);
+                          NULL disables */
 } gps_volume;
 
 /* The Gaussian set G = {p_i, sigma_i, r_i, s_i, SH_i} (Sec. 3.1), with

@@ -138,6 +138,26 @@ struct BrickArgs {
     float* bmin;
 };
 
+// Superbricks of kSuper^3 bricks: the minimum of their bricks' minima, so a
+// superbrick above the threshold has every sample stencil based in it positive.
+constexpr int kSuper = 4;
+
+__global__ void __launch_bounds__(256) k_super_min(const float* __restrict__ bmin, float* __restrict__ smin, int bx,
+                                                   int by, int bz, int sx, int sy, int sz)
+{
+    const int t = blockIdx.x * 256 + threadIdx.x;
+    if (t >= sx * sy * sz) return;
+    const int jx = t % sx, jy = (t / sx) % sy, jz = t / (sx * sy);
+    float m = INFINITY;
+    for (int dz = 0; dz < kSuper; ++dz)
+        for (int dy = 0; dy < kSuper; ++dy)
+            for (int dx = 0; dx < kSuper; ++dx) {
+                const int x = jx * kSuper + dx, y = jy * kSuper + dy, z = jz * kSuper + dz;
+                if (x < bx && y < by && z < bz) m = fminf(m, bmin[x + bx * (y + by * z)]);
+            }
+    smin[t] = m;
+}
+
 __global__ void __launch_bounds__(256) k_brick_min(BrickArgs a)
 {
     const int b = blockIdx.x;
@@ -160,12 +180,14 @@ __global__ void __launch_bounds__(256) k_brick_min(BrickArgs a)
 struct RayArgs {
     int n[3];
     float origin[3];
-    float voxel, inv_voxel, h, z_near;
+    float voxel, inv_voxel, h, inv_h, z_near;
     int bx, by, bz;
+    int sx, sy;  // superbricks along x and y
     int max_steps;
     const float* tsdf;
     const float* rgb;
     const float* bmin;  // may be null
+    const float* smin;  // superbrick minima (null with bmin)
     size_t N;
     int n_views;
     DevCam cams[GPS_MAX_VIEWS];
@@ -303,11 +325,12 @@ __global__ void __launch_bounds__(256) k_raycast(RayArgs a)
     }
 
     // Lattice-space ray for brick exits (values only, never decides a crossing).
-    float g0[3], gd[3];
+    float g0[3], gd[3], igd[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         g0[k] = (o[k] - a.origin[k]) * a.inv_voxel;
         gd[k] = dh[k] * a.inv_voxel;
+        igd[k] = gd[k] != 0.0f ? 1.0f / gd[k] : 0.0f;
     }
 
     float Fprev = 0.0f;
@@ -333,20 +356,33 @@ __global__ void __launch_bounds__(256) k_raycast(RayArgs a)
             float b0 = floorf(g[0]), b1 = floorf(g[1]), b2 = floorf(g[2]);
             if (b0 >= 0.0f && b1 >= 0.0f && b2 >= 0.0f && b0 <= (float)(a.n[0] - 2) && b1 <= (float)(a.n[1] - 2) &&
                 b2 <= (float)(a.n[2] - 2)) {
-                int i0 = (int)b0 >> 3, i1 = (int)b1 >> 3, i2 = (int)b2 >> 3;
-                if (__ldg(a.bmin + i0 + a.bx * (i1 + a.by * i2)) > kBrickPositive) {
-                    // Every sample whose base lies in this brick is positive.  Samples at least
-                    // one step before the ray's exit from the brick's box are inside it.
+                const int i0 = (int)b0 >> 3, i1 = (int)b1 >> 3, i2 = (int)b2 >> 3;
+                const int j0 = i0 / kSuper, j1 = i1 / kSuper, j2 = i2 / kSuper;
+                int edge = 0, bb[3];
+                if (__ldg(a.smin + j0 + a.sx * (j1 + a.sy * j2)) > kBrickPositive) {
+                    edge = kBrick * kSuper;  // the whole superbrick is positive
+                    bb[0] = j0;
+                    bb[1] = j1;
+                    bb[2] = j2;
+                } else if (__ldg(a.bmin + i0 + a.bx * (i1 + a.by * i2)) > kBrickPositive) {
+                    edge = kBrick;
+                    bb[0] = i0;
+                    bb[1] = i1;
+                    bb[2] = i2;
+                }
+                if (edge) {
+                    // Every sample whose base lies in this box is positive.  Samples at least
+                    // one step before the ray's exit from the box are inside it (the exit and
+                    // the step count are values only: the step of margin covers their rounding).
                     float lam_exit = INFINITY;
-                    const int bb[3] = {i0, i1, i2};
 #pragma unroll
                     for (int k = 0; k < 3; ++k) {
                         if (gd[k] > 0.0f)
-                            lam_exit = fminf(lam_exit, ((float)((bb[k] + 1) * kBrick) - g0[k]) / gd[k]);
+                            lam_exit = fminf(lam_exit, ((float)((bb[k] + 1) * edge) - g0[k]) * igd[k]);
                         else if (gd[k] < 0.0f)
-                            lam_exit = fminf(lam_exit, ((float)(bb[k] * kBrick) - g0[k]) / gd[k]);
+                            lam_exit = fminf(lam_exit, ((float)(bb[k] * edge) - g0[k]) * igd[k]);
                     }
-                    int s_last = (int)floorf((lam_exit - lam0) / a.h) - 1;
+                    int s_last = (int)floorf((lam_exit - lam0) * a.inv_h) - 1;
                     if (s_last > nsteps) s_last = nsteps;
                     if (s_last < s) s_last = s;
                     s = s_last;
@@ -429,12 +465,17 @@ gps_status launch_raycast(const gps_volume* vol, const gps_camera* cams, int n_v
                                                    (double)vol->nz * vol->nz);
         a.max_steps = (int)std::min(diag / a.h + 4.0, 1.0e8);
     }
+    a.inv_h = 1.0f / a.h;
     a.bx = (vol->nx + kBrick - 1) / kBrick;
     a.by = (vol->ny + kBrick - 1) / kBrick;
     a.bz = (vol->nz + kBrick - 1) / kBrick;
+    a.sx = (a.bx + kSuper - 1) / kSuper;
+    a.sy = (a.by + kSuper - 1) / kSuper;
+    const int sz = (a.bz + kSuper - 1) / kSuper;
     a.tsdf = vol->tsdf;
     a.rgb = vol->rgb;
     a.bmin = vol->brick_min;
+    a.smin = vol->brick_min ? vol->brick_min + (size_t)a.bx * a.by * a.bz : nullptr;
     a.N = (size_t)vol->nx * vol->ny * vol->nz;
     a.n_views = n_views;
     int maxW = 0, maxH = 0;
@@ -448,6 +489,9 @@ gps_status launch_raycast(const gps_volume* vol, const gps_camera* cams, int n_v
     if (vol->brick_min) {
         BrickArgs b{vol->nx, vol->ny, vol->nz, a.bx, a.by, a.bz, vol->tsdf, vol->brick_min};
         GPS_LAUNCH(K_BRICK_MIN, s, k_brick_min, dim3(a.bx * a.by * a.bz), dim3(256), 0, s, b);
+        const int ns = a.sx * a.sy * sz;
+        GPS_LAUNCH(K_BRICK_MIN, s, k_super_min, dim3((ns + 255) / 256), dim3(256), 0, s, vol->brick_min,
+                   vol->brick_min + (size_t)a.bx * a.by * a.bz, a.bx, a.by, a.bz, a.sx, a.sy, sz);
         if (hipGetLastError() != hipSuccess) return GPS_ERR_HIP;
     }
     dim3 grid((maxW + 15) / 16, (maxH + 15) / 16, n_views);

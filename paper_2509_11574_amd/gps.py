@@ -190,7 +190,8 @@ class Volume:
         self.weight = torch.zeros(N, dtype=torch.float32, device=self.device)
         self.rgb = torch.zeros(3, N, dtype=torch.float32, device=self.device)
         self.rgb_weight = torch.zeros(N, dtype=torch.float32, device=self.device)
-        nb = math.ceil(nx / 8) * math.ceil(ny / 8) * math.ceil(nz / 8)
+        bx, by, bz = (math.ceil(d / 8) for d in (nx, ny, nz))
+        nb = bx * by * bz + math.ceil(bx / 4) * math.ceil(by / 4) * math.ceil(bz / 4)  # GPS_BRICK_MIN_FLOATS
         self.brick_min = torch.zeros(nb, dtype=torch.float32, device=self.device) if self.skip_bricks else None
 
     def struct(self) -> VolumeS:

@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(P):
 
 def test_abi_version_and_status_strings(P):
     L = P.lib()
-    assert L.gps_abi_version() == 1
+    assert L.gps_abi_version() == 2
     assert L.gps_status_string(0) == b"ok"
     assert b"capacity" in L.gps_status_string(-3)
 
