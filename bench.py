@@ -272,7 +272,7 @@ def main():
                   + 392 * M)                         # Adam: 14 scalars x 28 B
     iter_ms = None
     if kernels:
-        it_kernels = ("upload_views", "prep", "project", "scan", "count", "scan_tiles", "emit", "tile_sort",
+        it_kernels = ("project", "scan", "count", "scan_tiles", "emit", "tile_sort",
                       "tile_sort_large", "composite_fwd", "loss_reduce", "composite_bwd", "gauss_bwd",
                       "pose_reduce", "adam", "step_incr")
         iter_ms = sum(kernels[n][1] for n in it_kernels if n in kernels) / (K * ITERS_PER_FRAME)

@@ -128,12 +128,15 @@ typedef struct gps_render_cfg {
 } gps_render_cfg;
 
 /* The render kernels read the view table (cameras and image pointers) from the
- * workspace.  By default gps_render_fwd and gps_render_bwd first write the
- * table of their `views` argument there.  With this flag they launch no such
- * upload and use the table written by the last gps_views_upload on the
- * workspace; the `views` argument must then describe views of the same sizes
- * (it still sizes the launches).  This lets one captured forward + backward +
- * Adam iteration be replayed for new camera poses: upload, then replay. */
+ * workspace, with the per-tile maxima of the views' base depths that drive the
+ * tile-level depth cull.  By default gps_render_fwd writes the table of its
+ * `views` argument there and takes those maxima (gps_render_bwd writes the
+ * table only).  With this flag both launch no such upload and use the table
+ * and maxima written by the last gps_views_upload on the workspace; the
+ * `views` argument must then describe views of the same sizes (it still sizes
+ * the launches), and the base images must not have changed since that upload.
+ * This lets one captured forward + backward + Adam iteration be replayed for
+ * new camera poses or new base images: upload, then replay. */
 #define GPS_RENDER_VIEWS_PRESET 1
 
 /* One Adam parameter group. */
@@ -242,8 +245,10 @@ gps_status gps_render_bwd(const gps_render_cfg* cfg, const gps_gaussians* g, con
 
 /* Writes the view table of `views` (and, for an explicit-adjoint backward,
  * the per-view dL_drgb / dL_ddepth device pointers; both may be NULL) into the
- * workspace, for calls made with GPS_RENDER_VIEWS_PRESET.  Same argument
- * checks as gps_render_fwd; one small kernel is launched on `stream`. */
+ * workspace, and the per-tile maxima of the views' base depths (read now: call
+ * again after a base image changes), for calls made with
+ * GPS_RENDER_VIEWS_PRESET.  Same argument checks as gps_render_fwd; two
+ * kernels are launched on `stream`. */
 gps_status gps_views_upload(const gps_render_cfg* cfg, const gps_gaussians* g, const gps_view* views,
                             int32_t n_views, const float* const* dL_drgb, const float* const* dL_ddepth, void* ws,
                             size_t ws_bytes, void* stream);

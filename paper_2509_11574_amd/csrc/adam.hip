@@ -3,6 +3,7 @@
 // scalar reads param, grad, m, v and writes param, m, v (28 bytes).  Groups
 // whose arrays are 16-byte aligned with n % 4 == 0 are processed as float4.
 #include "gps_internal.h"
+#include "launch.h"
 #include "prof.h"
 
 namespace gps {

@@ -7,6 +7,7 @@
 
 #include "gps_internal.h"
 #include "binning.h"
+#include "launch.h"
 #include "prof.h"
 
 namespace gps {
@@ -345,7 +346,7 @@ gps_status gps_views_upload(const gps_render_cfg* cfg, const gps_gaussians* g, c
     }
     st = check_device();
     if (st != GPS_OK) return st;
-    return launch_views_upload(vt, L, static_cast<char*>(ws), (hipStream_t)stream);
+    return launch_views_upload(vt, rp, L, static_cast<char*>(ws), 1, (hipStream_t)stream);
 }
 
 gps_status gps_adam_step(const gps_adam_group* groups, int32_t n_groups, int32_t step, int32_t* step_counter,

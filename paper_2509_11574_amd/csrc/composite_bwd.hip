@@ -6,6 +6,7 @@
 // transpose-reduction within each 16-lane row, LDS across rows and wavefronts,
 // fixed order) and writes one 10-float partial per (tile, Gaussian) instance
 // into that instance's slot.  No floating-point atomics.
+#include "launch.h"
 #include "prof.h"
 #include "render_common.h"
 

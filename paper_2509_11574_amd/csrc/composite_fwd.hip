@@ -3,6 +3,7 @@
 // records whose support box misses its pixels and composites the rest front to
 // back over the SDF base colour and depth, with the loss partial of the tile
 // written in the epilogue.
+#include "launch.h"
 #include "prof.h"
 #include "render_common.h"
 

@@ -273,25 +273,4 @@ __device__ __forceinline__ int find_view(const ViewTable& vt, int tile)
 }
 
 
-// ---------------------------------------------------------------------------
-// Host-side launch entry points (defined in the .hip files).
-// ---------------------------------------------------------------------------
-gps_status launch_fuse(const gps_volume* vol, const gps_camera* cam, const float* depth, const float* rgb,
-                       hipStream_t s);
-gps_status launch_raycast(const gps_volume* vol, const gps_camera* cams, int n_views, float* const* out_depth,
-                          float* const* out_rgb, float z_near, float step, hipStream_t s);
-gps_status launch_render_fwd(const gps_render_cfg* cfg, const RParams& rp, const gps_gaussians* g,
-                             const ViewTable& vt, const WsLayout& L, char* ws, float* out_loss, hipStream_t s);
-gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const gps_gaussians* g,
-                             const ViewTable& vt, const WsLayout& L, char* ws, int explicit_upstream,
-                             const float* loss_scale, gps_gaussians* grads, float* dpose, hipStream_t s);
-bool dispatch_cfwd(const gps_render_cfg* cfg, const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles,
-                   hipStream_t s);
-bool dispatch_cbwd(const gps_render_cfg* cfg, const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles,
-                   int explicit_up, const float* loss_scale, hipStream_t s);
-gps_status launch_views_upload(const ViewTable& vt, const WsLayout& L, char* ws, hipStream_t s);
-gps_status launch_adam(const gps_adam_group* groups, int n_groups, int step, int* step_counter, float b1, float b2,
-                       float eps, hipStream_t s);
-gps_status launch_ws_reset(char* ws, hipStream_t s);
-
 }  // namespace gps

@@ -11,7 +11,7 @@ enum KernelId {
     K_FUSE = 0,
     K_BRICK_MIN,
     K_RAYCAST,
-    K_PREP,
+    K_TILEMAX,
     K_PROJECT,
     K_SCAN,
     K_TILE_COUNT,

@@ -8,7 +8,7 @@
 
 namespace gps {
 
-static const char* kNames[K_COUNT] = {"fuse", "brick_min", "raycast", "prep", "project", "scan", "count",
+static const char* kNames[K_COUNT] = {"fuse", "brick_min", "raycast", "tilemax", "project", "scan", "count",
                                       "scan_tiles", "emit", "tile_sort", "tile_sort_large", "composite_fwd", "loss_reduce", "composite_bwd", "gauss_bwd",
                                       "pose_reduce", "adam", "step_incr", "ws_reset",
                                       "upload_views"};

@@ -7,6 +7,7 @@
 //       parameters and form the per-Gaussian pose terms, reduced per block.
 //   k_pose_reduce per view: sum the block pose partials in order.
 // No floating-point atomics: results are bitwise reproducible.
+#include "launch.h"
 #include "prof.h"
 #include "render_common.h"
 
@@ -279,7 +280,7 @@ gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const
     GGrads gg{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->rgb};
     const ViewTable* dvt = reinterpret_cast<const ViewTable*>(ws + L.vtab);
     if (!(cfg->flags & GPS_RENDER_VIEWS_PRESET)) {
-        gps_status st = launch_views_upload(vt, L, ws, s);
+        gps_status st = launch_views_upload(vt, rp, L, ws, 0, s);
         if (st != GPS_OK) return st;
     }
     if (!dispatch_cbwd(cfg, dvt, rp, w, L.n_tiles, explicit_upstream, loss_scale, s)) return GPS_ERR_UNSUPPORTED_CONFIG;

@@ -4,9 +4,11 @@
 //
 // Kernel sequence (one launch each, all grids sized from host-known shapes,
 // so the sequence is graph-capturable):
-//   k_prep         per screen tile: max of the SDF depth (invalid = +inf)
+//   k_tilemax      per screen tile: max of the SDF depth (invalid = +inf); launched
+//                  with the view-table upload, not per forward
 //   k_project      per (view, Gaussian): projected record and the number of
-//                  screen tiles its support box covers (one slot per tile)
+//                  screen tiles its support box covers (one slot per tile);
+//                  also clears the per-tile counters of this forward
 //   k_scan_blocks  one block: offsets of the per-block slot counts
 //   k_expand<0>    block-cooperative walk of the tile rectangles: per-tile
 //                  counts of the instances that pass the exact depth cull
@@ -20,21 +22,19 @@
 //                  partial per tile
 //   k_loss_reduce  one block: per-view and total loss
 #include "binning.h"
+#include "launch.h"
 #include "prof.h"
 #include "render_common.h"
 
 namespace gps {
 
-// ------------------------------------------------------------------- prep
-__global__ void __launch_bounds__(256) k_prep(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w)
+// ---------------------------------------------------- tile depth maxima
+// Per screen tile: the maximum of the SDF base depth (invalid = +inf), taken
+// when the view table is uploaded (the base images are fixed until the next upload).
+__global__ void __launch_bounds__(256) k_tilemax(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w)
 {
     const ViewTable& vt = *vtp;
     const int tile = blockIdx.x;
-    if (tile == 0 && threadIdx.x == 0) {
-        w.hdr->n_inst = 0ull;
-        w.hdr->n_fallback = 0ull;
-        w.hdr->n_views = rp.V;
-    }
     const int v = find_view(vt, tile);
     const DevView& V = vt.v[v];
     const int lt = tile - V.tile_base;
@@ -51,10 +51,20 @@ __global__ void __launch_bounds__(256) k_prep(const ViewTable* __restrict__ vtp,
     __shared__ float red[4];
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        w.tilemax[tile] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    if (threadIdx.x == 0) w.tilemax[tile] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+// Per-forward resets (run by the first kernel of the forward, over its whole
+// grid): the per-tile sub-counters and the forward's header counters.
+__device__ __forceinline__ void forward_resets(const ViewTable& vt, const RParams& rp, const WsPtrs& w)
+{
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x, nth = gridDim.x * blockDim.x;
+    for (int i = gid; i < kCntSplit * vt.n_tiles; i += nth) w.tile_cnt[i] = 0u;
+    if (gid == 0) {
+        w.hdr->n_inst = 0ull;
+        w.hdr->n_fallback = 0ull;
+        w.hdr->n_views = rp.V;
     }
-    if (threadIdx.x < kCntSplit) w.tile_cnt[(size_t)threadIdx.x * vt.n_tiles + tile] = 0u;
 }
 
 // ---------------------------------------------------------------- project
@@ -152,6 +162,7 @@ __device__ __forceinline__ ProjOut project_one(const DevView& V, const RParams& 
 __global__ void __launch_bounds__(kBlk) k_project(const ViewTable* __restrict__ vtp, RParams rp, GParams gp, WsPtrs w)
 {
     const ViewTable& vt = *vtp;
+    forward_resets(vt, rp, w);
     const int vg = blockIdx.x * kBlk + threadIdx.x;
     unsigned int count = 0;
     if (vg < rp.nvg) {
@@ -220,8 +231,10 @@ __device__ unsigned long long scan_array_1024(const unsigned int* in, unsigned i
     return total;
 }
 
-__global__ void __launch_bounds__(1024) k_scan_blocks(RParams rp, WsPtrs w, int nblk_vg, int n_tiles)
+__global__ void __launch_bounds__(1024) k_scan_blocks(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w,
+                                                     int nblk_vg, int n_tiles, int resets)
 {
+    if (resets) forward_resets(*vtp, rp, w);  // no projection launch (no Gaussians): the resets are here
     unsigned long long total = scan_array_1024(w.blk_sum, w.blk_off, nblk_vg, 0);
     if (threadIdx.x == 0) {
         w.hdr->n_inst = total;
@@ -617,9 +630,14 @@ __global__ void __launch_bounds__(256) k_upload_views(ViewTable vt, ViewTable* d
     for (int i = threadIdx.x; i < (int)(sizeof(ViewTable) / 4); i += 256) d[i] = src[i];
 }
 
-gps_status launch_views_upload(const ViewTable& vt, const WsLayout& L, char* ws, hipStream_t s)
+// The table upload, then (with_tilemax) the tile depth maxima of its views.
+gps_status launch_views_upload(const ViewTable& vt, const RParams& rp, const WsLayout& L, char* ws, int with_tilemax,
+                               hipStream_t s)
 {
-    GPS_LAUNCH(K_UPLOAD, s, k_upload_views, dim3(1), dim3(256), 0, s, vt, reinterpret_cast<ViewTable*>(ws + L.vtab));
+    ViewTable* dvt = reinterpret_cast<ViewTable*>(ws + L.vtab);
+    GPS_LAUNCH(K_UPLOAD, s, k_upload_views, dim3(1), dim3(256), 0, s, vt, dvt);
+    if (with_tilemax && L.n_tiles > 0)
+        GPS_LAUNCH(K_TILEMAX, s, k_tilemax, dim3(L.n_tiles), dim3(256), 0, s, dvt, rp, ws_ptrs(ws, L));
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
 }
 
@@ -634,11 +652,13 @@ gps_status launch_render_fwd(const gps_render_cfg* cfg, const RParams& rp, const
         if (!vt.v[v].target_rgb) has_loss = 0;
     // the kernels read the view table from the workspace
     const ViewTable* dvt = reinterpret_cast<const ViewTable*>(ws + L.vtab);
-    if (!(cfg->flags & GPS_RENDER_VIEWS_PRESET))
-        GPS_LAUNCH(K_UPLOAD, s, k_upload_views, dim3(1), dim3(256), 0, s, vt, const_cast<ViewTable*>(dvt));
-    GPS_LAUNCH(K_PREP, s, k_prep, dim3(L.n_tiles), dim3(256), 0, s, dvt, rp, w);
+    if (!(cfg->flags & GPS_RENDER_VIEWS_PRESET)) {
+        const gps_status st = launch_views_upload(vt, rp, L, ws, 1, s);
+        if (st != GPS_OK) return st;
+    }
     if (L.nblk_vg > 0) GPS_LAUNCH(K_PROJECT, s, k_project, dim3(L.nblk_vg), dim3(kBlk), 0, s, dvt, rp, gp, w);
-    GPS_LAUNCH(K_SCAN, s, k_scan_blocks, dim3(1), dim3(1024), 0, s, rp, w, L.nblk_vg, L.n_tiles);
+    GPS_LAUNCH(K_SCAN, s, k_scan_blocks, dim3(1), dim3(1024), 0, s, dvt, rp, w, L.nblk_vg, L.n_tiles,
+               L.nblk_vg > 0 ? 0 : 1);
     if (L.nblk_vg > 0)
         GPS_LAUNCH(K_TILE_COUNT, s, k_expand<false>, dim3(L.nblk_vg * (kBlk / kExpG)), dim3(kBlk), 0, s, dvt, rp, w);
     GPS_LAUNCH(K_SCAN_TILES, s, k_scan_tiles, dim3(1), dim3(1024), 0, s, rp, w, L.n_tiles);

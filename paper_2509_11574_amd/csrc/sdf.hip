@@ -15,6 +15,7 @@
 #include <cmath>
 
 #include "gps_internal.h"
+#include "launch.h"
 #include "prof.h"
 
 namespace gps {
@@ -138,42 +139,40 @@ struct BrickArgs {
     float* bmin;
 };
 
-// Superbricks of kSuper^3 bricks: the minimum of their bricks' minima, so a
-// superbrick above the threshold has every sample stencil based in it positive.
+// Brick minima: one wavefront per 8^3 brick, over its 9^3 lattice points (the
+// brick and the first plane of its +x, +y, +z neighbours: every 2x2x2 sample
+// stencil based in the brick), four bricks per block.
+__global__ void __launch_bounds__(256) k_brick_min(BrickArgs a)
+{
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (b >= a.bx * a.by * a.bz) return;
+    const int bxi = b % a.bx, byi = (b / a.bx) % a.by, bzi = b / (a.bx * a.by);
+    const int x0 = bxi * kBrick, y0 = byi * kBrick, z0 = bzi * kBrick;
+    float m = INFINITY;
+    for (int k = lane; k < 9 * 9 * 9; k += 64) {
+        const int dx = k % 9, dy = (k / 9) % 9, dz = k / 81;
+        const int x = x0 + dx, y = y0 + dy, z = z0 + dz;
+        if (x < a.nx && y < a.ny && z < a.nz) m = fminf(m, a.tsdf[x + (size_t)a.nx * (y + (size_t)a.ny * z)]);
+    }
+    m = -wave_max(-m);
+    if (lane == 0) a.bmin[b] = m;
+}
+
+// Superbricks of kSuper^3 = 64 bricks: the minimum of their bricks' minima (one
+// wavefront each, a lane per brick), so a superbrick above the threshold has
+// every sample stencil based in it positive.
 constexpr int kSuper = 4;
 
 __global__ void __launch_bounds__(256) k_super_min(const float* __restrict__ bmin, float* __restrict__ smin, int bx,
                                                    int by, int bz, int sx, int sy, int sz)
 {
-    const int t = blockIdx.x * 256 + threadIdx.x;
+    const int t = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (t >= sx * sy * sz) return;
     const int jx = t % sx, jy = (t / sx) % sy, jz = t / (sx * sy);
-    float m = INFINITY;
-    for (int dz = 0; dz < kSuper; ++dz)
-        for (int dy = 0; dy < kSuper; ++dy)
-            for (int dx = 0; dx < kSuper; ++dx) {
-                const int x = jx * kSuper + dx, y = jy * kSuper + dy, z = jz * kSuper + dz;
-                if (x < bx && y < by && z < bz) m = fminf(m, bmin[x + bx * (y + by * z)]);
-            }
-    smin[t] = m;
-}
-
-__global__ void __launch_bounds__(256) k_brick_min(BrickArgs a)
-{
-    const int b = blockIdx.x;
-    const int bxi = b % a.bx, byi = (b / a.bx) % a.by, bzi = b / (a.bx * a.by);
-    const int x0 = bxi * kBrick, y0 = byi * kBrick, z0 = bzi * kBrick;
-    float m = INFINITY;
-    for (int k = threadIdx.x; k < 9 * 9 * 9; k += 256) {
-        int dx = k % 9, dy = (k / 9) % 9, dz = k / 81;
-        int x = x0 + dx, y = y0 + dy, z = z0 + dz;
-        if (x < a.nx && y < a.ny && z < a.nz) m = fminf(m, a.tsdf[x + (size_t)a.nx * (y + (size_t)a.ny * z)]);
-    }
-    m = wave_max(-m);
-    __shared__ float red[4];
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
-    __syncthreads();
-    if (threadIdx.x == 0) a.bmin[b] = -fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    const int x = jx * kSuper + (lane & 3), y = jy * kSuper + ((lane >> 2) & 3), z = jz * kSuper + (lane >> 4);
+    float m = (x < bx && y < by && z < bz) ? bmin[x + bx * (y + by * z)] : INFINITY;
+    m = -wave_max(-m);
+    if (lane == 0) smin[t] = m;
 }
 
 // ---------------------------------------------------------------- raycast
@@ -488,9 +487,9 @@ gps_status launch_raycast(const gps_volume* vol, const gps_camera* cams, int n_v
     }
     if (vol->brick_min) {
         BrickArgs b{vol->nx, vol->ny, vol->nz, a.bx, a.by, a.bz, vol->tsdf, vol->brick_min};
-        GPS_LAUNCH(K_BRICK_MIN, s, k_brick_min, dim3(a.bx * a.by * a.bz), dim3(256), 0, s, b);
+        GPS_LAUNCH(K_BRICK_MIN, s, k_brick_min, dim3((a.bx * a.by * a.bz + 3) / 4), dim3(256), 0, s, b);
         const int ns = a.sx * a.sy * sz;
-        GPS_LAUNCH(K_BRICK_MIN, s, k_super_min, dim3((ns + 255) / 256), dim3(256), 0, s, vol->brick_min,
+        GPS_LAUNCH(K_BRICK_MIN, s, k_super_min, dim3((ns + 3) / 4), dim3(256), 0, s, vol->brick_min,
                    vol->brick_min + (size_t)a.bx * a.by * a.bz, a.bx, a.by, a.bz, a.sx, a.sy, sz);
         if (hipGetLastError() != hipSuccess) return GPS_ERR_HIP;
     }

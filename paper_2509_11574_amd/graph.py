@@ -3,9 +3,9 @@ Adam -- captured once as a HIP graph (torch.cuda.CUDAGraph on ROCm) and
 replayed.
 
 The captured kernels read the view table (cameras and image pointers) from the
-workspace, so new camera poses or new target images are taken by uploading a
-table (`set_views`, outside the graph) before replaying; views must keep their
-sizes.  The Adam step counter lives on the device.  Nothing in the captured
+workspace, so new camera poses, base images or target images are taken by
+uploading a table (`set_views`, outside the graph; it also takes the per-tile
+maxima of the base depths) before replaying; views must keep their sizes.  The Adam step counter lives on the device.  Nothing in the captured
 sequence allocates memory or reads device data on the host.
 """
 from __future__ import annotations
