@@ -14,6 +14,8 @@
 namespace gps {
 
 // ------------------------------------------------------------- gauss bwd
+constexpr unsigned int kCoopSlots = 16;  // more slots than this: summed by the whole wavefront
+
 // EWA chain rule of one Gaussian in one view.  The summed instance partials are
 // first turned into A[10] = dL/d(mx, my, a, b, c), sigma dL/dsigma, dL/d(r, g, b, d),
 // where (a, b, c) is the conic and b multiplies 2 dx dy.
@@ -22,6 +24,7 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
     const ViewTable& vt = *vtp;
     const int M = rp.M;
     const int g = blockIdx.x * kBlk + threadIdx.x;
+    const int lane = threadIdx.x & 63;
     const bool live = g < M;
     float gmean[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.0f, grgb[3] = {0, 0, 0};
     __shared__ float pred[kBlk / 64][6];
@@ -73,17 +76,41 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
         unsigned int cnt = live ? w.cnt[vg] : 0u;
         const unsigned int o = cnt ? w.off[vg] : 0u;
         if ((unsigned long long)o + cnt > w.hdr->n_inst) cnt = 0u;  // guard: stay inside the emitted slots
-        if (cnt > 0) {
-            // Slots of tiles removed by the depth cull were zeroed by the emission, so the
-            // whole contiguous range is summed, in order.
-            const float* part = w.partial + (size_t)o * kAdj;
-            float A[kAdj];
+        // Slots of tiles removed by the depth cull were zeroed by the emission, so the
+        // whole contiguous range is summed (in a fixed order).
+        float A[kAdj];
 #pragma unroll
-            for (int q = 0; q < kAdj; ++q) A[q] = 0.0f;
+        for (int q = 0; q < kAdj; ++q) A[q] = 0.0f;
+        // A Gaussian with more than kCoopSlots slots is summed by its whole wavefront
+        // (lanes take its slots in strides of 64, then a fixed-order wave sum), so the
+        // few Gaussians that cover many tiles do not hold their wavefront up.
+        unsigned long long big = __ballot(cnt > kCoopSlots);
+        while (big) {
+            const int b = __ffsll(big) - 1;
+            const unsigned int ob = (unsigned int)__shfl((int)o, b, 64), cb = (unsigned int)__shfl((int)cnt, b, 64);
+            float acc[kAdj];
+#pragma unroll
+            for (int q = 0; q < kAdj; ++q) acc[q] = 0.0f;
+            for (unsigned int k = (unsigned int)lane; k < cb; k += 64) {
+                const float* ps = w.partial + (size_t)(ob + k) * kAdj;
+#pragma unroll
+                for (int q = 0; q < kAdj; ++q) acc[q] += ps[q];
+            }
+#pragma unroll
+            for (int q = 0; q < kAdj; ++q) {
+                const float t = wave_sum(acc[q]);
+                if (lane == b) A[q] = t;
+            }
+            big &= big - 1ull;
+        }
+        if (cnt > 0 && cnt <= kCoopSlots) {
+            const float* part = w.partial + (size_t)o * kAdj;
 #pragma unroll 4
             for (unsigned int k = 0; k < cnt; ++k)
 #pragma unroll
                 for (int q = 0; q < kAdj; ++q) A[q] += part[(size_t)k * kAdj + q];
+        }
+        if (cnt > 0) {
             // The compositing kernel accumulates, with u = dL/dalpha * alpha, the sums
             // of u dx, u dy, u dx^2, u dx dy, u dy^2 and u, where alpha = exp2(pw),
             // pw = A' dx^2 + B' dx dy + C' dy^2 + log2 sigma and (A', B', C') =
