@@ -5,7 +5,10 @@
 // the base-2 form of the opacity), reduces them over the tile's pixels (a DPP
 // transpose-reduction within each 16-lane row, LDS across rows and wavefronts,
 // fixed order) and writes one 10-float partial per (tile, Gaussian) instance
-// into that instance's slot.  No floating-point atomics.
+// into that instance's slot: the view-Gaussian's first slot plus the tile's
+// place in its tile rectangle.  Instances after the point where every pixel of
+// the tile has stopped keep the zeros the emission wrote.  No floating-point
+// atomics.
 #include "launch.h"
 #include "prof.h"
 #include "render_common.h"
@@ -102,22 +105,26 @@ __global__ void __launch_bounds__(TW * TH / PPT)
 
     const unsigned int s = w.tile_start[tile], e = w.tile_start[tile + 1];
     const int tx0 = tx * TW, ty0 = ty * TH;
-    unsigned int stop = s;  // first position whose partial has not been written
     bool wave_alive = true;  // some pixel of this wavefront still takes records
     for (unsigned int b = s; b < e; b += B) {
         if (__syncthreads_count(wave_alive && lane == 0) == 0) break;
         for (int j = threadIdx.x; j < B; j += NT) {
             unsigned int mk = 0u, slot = 0xffffffffu;
             if (b + j < e) {
-                slot = (unsigned int)w.keys[b + j];
-                unsigned int vg = slot < rp.cap ? w.inst_vg[slot] : 0u;
+                unsigned int vg = (unsigned int)w.keys[b + j];
                 if (vg >= (unsigned int)rp.nvg) vg = 0u;  // guard: never read outside the records
                 const float4* r = w.rec + 3 * (size_t)vg;
                 const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+                const unsigned int o = w.off[vg];
                 srec[3 * j + 0] = r0;
                 srec[3 * j + 1] = r1;
                 srec[3 * j + 2] = r2;
                 mk = wave_box_mask<Lay>(r0.x, r0.y, r2.z, r2.w, tx0, ty0);
+                // the instance's slot: its view-Gaussian's first slot plus this tile's
+                // place in the tile rectangle (the rectangle the expansion walked)
+                TileRect rr;
+                if (rect_of(r0.x, r0.y, r2.z, r2.w, Wd, Ht, rp.tile_w, rp.tile_h, &rr))
+                    slot = o + (unsigned int)((ty - rr.ty0) * (rr.tx1 - rr.tx0 + 1) + (tx - rr.tx0));
             }
             smask[j] = mk;
             sslot[j] = slot;
@@ -236,18 +243,8 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                 if (slot < rp.cap) w.partial[(size_t)slot * kAdj + q] = acc;
             }
             __syncthreads();
-            stop = b + (unsigned int)j1;  // positions before this were written
         }
         if (!alive_now) break;
-    }
-    // Instances after the point where every pixel of the tile had stopped
-    // contribute nothing; their slots still need zeros.
-    for (unsigned int pos = stop + threadIdx.x; pos < e; pos += NT) {
-        const unsigned int slot = (unsigned int)w.keys[pos];
-        if (slot >= rp.cap) continue;
-        float* out = w.partial + (size_t)slot * kAdj;
-#pragma unroll
-        for (int q = 0; q < kAdj; ++q) out[q] = 0.0f;
     }
 }
 

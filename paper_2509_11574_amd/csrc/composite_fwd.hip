@@ -100,8 +100,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
         for (int j = threadIdx.x; j < B; j += NT) {
             unsigned int mk = 0u;
             if (b + j < e) {
-                const unsigned int slot = (unsigned int)w.keys[b + j];
-                unsigned int vg = slot < rp.cap ? w.inst_vg[slot] : 0u;
+                unsigned int vg = (unsigned int)w.keys[b + j];
                 if (vg >= (unsigned int)rp.nvg) vg = 0u;  // guard: never read outside the records
                 const float4* r = w.rec + 3 * (size_t)vg;
                 const float4 r0 = r[0], r1 = r[1], r2 = r[2];

@@ -101,8 +101,8 @@ struct WsPtrs {
     unsigned int* off;
     unsigned int* blk_sum;
     unsigned int* blk_off;
-    unsigned long long* keys;   // (depth bits << 32) | slot, grouped by tile
-    unsigned int* inst_vg;      // slot -> view * M + Gaussian (between the two expansion passes: rank in tile)
+    unsigned long long* keys;   // (depth bits << 32) | view-Gaussian, grouped by tile
+    unsigned int* inst_vg;      // per slot: the instance's rank in its tile sub-counter (count -> emit)
     float* partial;             // [cap][kAdj]
     float* pose_part;           // [nblk_g][V][6]
 };

@@ -13,7 +13,7 @@
 //   k_expand<0>    block-cooperative walk of the tile rectangles: per-tile
 //                  counts of the instances that pass the exact depth cull
 //   k_scan_tiles   one block: tile ranges
-//   k_expand<1>    the same walk: (depth, slot) keys scattered into tile ranges
+//   k_expand<1>    the same walk: (depth, view-Gaussian) keys scattered into tile ranges
 //   k_tile_sort_*  per tile: bitonic sort of its keys in LDS (one wavefront
 //                  for tiles of <= 512 instances, a 256-lane block above)
 //   k_composite_fwd<TW,TH,B,PPT>  (composite_fwd.hip) per tile: LDS-staged
@@ -307,8 +307,12 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(RParams rp, WsPtrs w, int n
 //           inst_vg[slot]; the per-view-Gaussian slot offsets are written.
 //   EMIT:   the same instances (the cull is the same binary32 test on the same
 //           values, the block index the same) write the key
-//           (depth bits << 32) | slot at the sub-counter's start + rank, with no
-//           atomics, and replace the rank by slot -> view-Gaussian.
+//           (depth bits << 32) | view-Gaussian at the sub-counter's start + rank,
+//           with no atomics, and zero the instance partials of every slot.  A
+//           tile holds at most one instance of a view-Gaussian, and slots grow
+//           with the view-Gaussian index, so the keys sort as (depth, slot) would;
+//           the backward recovers the slot from the view-Gaussian's offset and the
+//           tile's place in its rectangle.
 template <bool EMIT>
 __global__ void __launch_bounds__(kBlk) k_expand(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w)
 {
@@ -360,20 +364,21 @@ __global__ void __launch_bounds__(kBlk) k_expand(const ViewTable* __restrict__ v
         const int tile = vw.x + (r.ty0 + (int)(j / wdt)) * vw.y + r.tx0 + (int)(j % wdt);
         const float z = sz[lo];
         const unsigned int slot = base + i;
-        if (!(z < w.tilemax[tile] + rp.eps)) {  // exact tile-level depth cull
-            if (EMIT) {  // the backward sums every slot of a Gaussian: culled slots hold zeros
-                float* pz = w.partial + (size_t)slot * kAdj;
+        if (EMIT) {
+            // The per-Gaussian reduce sums every slot of a Gaussian: all slots start at
+            // zero (culled ones, and those the backward's tiles stop before, stay so).
+            float* pz = w.partial + (size_t)slot * kAdj;
 #pragma unroll
-                for (int q = 0; q < kAdj; ++q) pz[q] = 0.0f;
-            }
-            continue;
+            for (int q = 0; q < kAdj; ++q) pz[q] = 0.0f;
         }
+        if (!(z < w.tilemax[tile] + rp.eps)) continue;  // exact tile-level depth cull
         if (!EMIT) {
             w.inst_vg[slot] = atomicAdd(w.tile_cnt + sub + tile, 1u);
         } else {
+            // key: depth bits, then the view-Gaussian (within a tile it orders as the slot does)
             const unsigned int pos = w.tile_cnt[sub + tile] + w.inst_vg[slot];
-            w.inst_vg[slot] = (unsigned int)(pb * kBlk + g0 + lo);
-            if (pos < w.tile_start[tile + 1]) w.keys[pos] = ((unsigned long long)__float_as_uint(z) << 32) | slot;
+            if (pos < w.tile_start[tile + 1])
+                w.keys[pos] = ((unsigned long long)__float_as_uint(z) << 32) | (unsigned int)(pb * kBlk + g0 + lo);
         }
     }
 }
