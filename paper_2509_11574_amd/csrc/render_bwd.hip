@@ -288,13 +288,20 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
 
 __global__ void __launch_bounds__(256) k_pose_reduce(RParams rp, WsPtrs w, int nblk, float* dpose)
 {
-    const int v = blockIdx.x;
+    // One block per view: the six components summed per lane over the blocks (in
+    // strides), per wavefront (DPP), then over the four wavefronts in order.
+    const int v = blockIdx.x, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __shared__ float red[4][6];
+#pragma unroll
     for (int q = 0; q < 6; ++q) {
         float t = 0.0f;
         for (int b = threadIdx.x; b < nblk; b += 256) t += w.pose_part[((size_t)b * rp.V + v) * 6 + q];
-        t = block_sum<256>(t);
-        if (threadIdx.x == 0) dpose[v * 6 + q] = t;
+        t = wave_sum(t);
+        if (lane == 0) red[wid][q] = t;
     }
+    __syncthreads();
+    if (threadIdx.x < 6) dpose[v * 6 + threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
+                                                      red[3][threadIdx.x];
 }
 
 // ----------------------------------------------------------------- launch

@@ -251,34 +251,66 @@ __global__ void __launch_bounds__(1024) k_scan_blocks(const ViewTable* __restric
 __global__ void __launch_bounds__(1024) k_scan_tiles(RParams rp, WsPtrs w, int n_tiles)
 {
     if (w.hdr->n_inst > rp.cap) return;
-    // tile totals over the sub-counters, scanned in place into tile ranges
-    for (int i = threadIdx.x; i < n_tiles; i += 1024) {
-        unsigned int t = 0u;
-#pragma unroll
-        for (int k = 0; k < kCntSplit; ++k) t += w.tile_cnt[(size_t)k * n_tiles + i];
-        w.tile_start[i] = t;
-    }
-    __syncthreads();
-    scan_array_1024(w.tile_start, w.tile_start, n_tiles, 1);
-    // each sub-counter's range inside its tile's range, in sub-counter order
-    for (int i = threadIdx.x; i < n_tiles; i += 1024) {
-        unsigned int run = w.tile_start[i];
-#pragma unroll
-        for (int k = 0; k < kCntSplit; ++k) {
-            unsigned int* c = w.tile_cnt + (size_t)k * n_tiles + i;
-            const unsigned int n = *c;
-            *c = run;
-            run += n;
-        }
-    }
-    __shared__ unsigned int hist[33], cur[33];
+    __shared__ unsigned int wsum[16], hist[33], cur[33];
+    __shared__ unsigned int carry_s;
     if (threadIdx.x < 33) hist[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) carry_s = 0u;
     __syncthreads();
-    // tile counts from the scanned starts
-    for (int i = threadIdx.x; i < n_tiles; i += 1024)
-        atomicAdd(&hist[31 - __clz(w.tile_start[i + 1] - w.tile_start[i] + 1u)], 1u);
-    __syncthreads();
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // One pass per chunk of 4 tiles per lane: the sub-counts are read once, their
+    // totals scanned over the block (chunks carried in order) into the tile
+    // ranges, each sub-counter replaced by the start of its range inside its
+    // tile's range, and the tile lengths counted into the histogram.
+    for (int base = 0; base < n_tiles; base += 4 * 1024) {
+        unsigned int c[4][kCntSplit], tot[4], sum = 0u;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int t = base + threadIdx.x * 4 + i;
+            tot[i] = 0u;
+#pragma unroll
+            for (int k = 0; k < kCntSplit; ++k) {
+                c[i][k] = t < n_tiles ? w.tile_cnt[(size_t)k * n_tiles + t] : 0u;
+                tot[i] += c[i][k];
+            }
+            sum += tot[i];
+        }
+        unsigned int x = sum;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wid] = x;
+        __syncthreads();
+        unsigned int before = 0u, total = 0u;
+        for (int k = 0; k < 16; ++k) {
+            if (k < wid) before += wsum[k];
+            total += wsum[k];
+        }
+        const unsigned int carry = carry_s;
+        unsigned int run = carry + before + x - sum;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int t = base + threadIdx.x * 4 + i;
+            if (t < n_tiles) {
+                w.tile_start[t] = run;
+                unsigned int r = run;
+#pragma unroll
+                for (int k = 0; k < kCntSplit; ++k) {
+                    w.tile_cnt[(size_t)k * n_tiles + t] = r;
+                    r += c[i][k];
+                }
+                atomicAdd(&hist[31 - __clz(tot[i] + 1u)], 1u);
+            }
+            run += tot[i];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s = carry + total;
+        __syncthreads();
+    }
+    // Longest-first order: buckets floor(log2(count + 1)) laid out in descending order.
     if (threadIdx.x == 0) {
+        w.tile_start[n_tiles] = carry_s;
         unsigned int o = 0;
         for (int bkt = 32; bkt >= 0; --bkt) {
             cur[bkt] = o;
@@ -568,7 +600,11 @@ __global__ void __launch_bounds__(1024) k_loss_reduce(const ViewTable* __restric
                                                      int has_loss)
 {
     const ViewTable& vt = *vtp;
-    float L = 0.0f;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // Per view: the colour L1 sum, depth L1 sum and |Omega| over its tiles, each
+    // summed per lane, then per wavefront (DPP), then over the wavefronts in order
+    // by one thread: one barrier for all views.
+    __shared__ float4 red[GPS_MAX_VIEWS][16];
     for (int v = 0; v < vt.n; ++v) {
         const DevView& V = vt.v[v];
         const int nt = V.tiles_x * V.tiles_y;
@@ -579,17 +615,10 @@ __global__ void __launch_bounds__(1024) k_loss_reduce(const ViewTable* __restric
             b += q.y;
             c += q.z;
         }
-        a = block_sum<1024>(a);
-        b = block_sum<1024>(b);
-        c = block_sum<1024>(c);
-        if (threadIdx.x == 0) {
-            w.hdr->view_stats[v][0] = a;
-            w.hdr->view_stats[v][1] = b;
-            w.hdr->view_stats[v][2] = c;
-            w.hdr->view_stats[v][3] = 0.0f;
-            const float npx = 3.0f * (float)V.cam.W * (float)V.cam.H;
-            L += a / npx + (c > 0.0f ? rp.lambda * b / c : 0.0f);
-        }
+        a = wave_sum(a);
+        b = wave_sum(b);
+        c = wave_sum(c);
+        if (lane == 0) red[v][wid] = make_float4(a, b, c, 0.0f);
     }
     // Evaluated / composited pair counts of this forward, summed over the tiles in
     // a fixed order and added to the cumulative counters of the header.
@@ -606,12 +635,27 @@ __global__ void __launch_bounds__(1024) k_loss_reduce(const ViewTable* __restric
         pc += __shfl_xor(pc, o, 64);
     }
     __shared__ unsigned long long spe[16], spc[16];
-    if ((threadIdx.x & 63) == 0) {
-        spe[threadIdx.x >> 6] = pe;
-        spc[threadIdx.x >> 6] = pc;
+    if (lane == 0) {
+        spe[wid] = pe;
+        spc[wid] = pc;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
+        float L = 0.0f;
+        for (int v = 0; v < vt.n; ++v) {
+            float a = 0.0f, b = 0.0f, c = 0.0f;
+            for (int k = 0; k < 16; ++k) {
+                a += red[v][k].x;
+                b += red[v][k].y;
+                c += red[v][k].z;
+            }
+            w.hdr->view_stats[v][0] = a;
+            w.hdr->view_stats[v][1] = b;
+            w.hdr->view_stats[v][2] = c;
+            w.hdr->view_stats[v][3] = 0.0f;
+            const float npx = 3.0f * (float)vt.v[v].cam.W * (float)vt.v[v].cam.H;
+            L += a / npx + (c > 0.0f ? rp.lambda * b / c : 0.0f);
+        }
         unsigned long long te = 0ull, tc = 0ull;
         for (int k = 0; k < 16; ++k) {
             te += spe[k];
