@@ -227,7 +227,7 @@ def main():
     iters_per_s = ITERS_PER_FRAME * K / t_wall
     last_loss = float(loss.item())
     log(f"timed {K} frames: {ms_per_frame:.3f} ms/frame (events {ms_event / K:.3f}), {iters_per_s:.1f} iters/s, "
-        f"loss {first_loss:.5f} -> {last_loss:.5f}, instances {st1['n_instances']}")
+        f"loss {first_loss:.5f} -> {last_loss:.6f}, instances {st1['n_instances']}")
 
     # --------------------------------------- per-kernel times (HIP events)
     kernels, pairs = {}, None
