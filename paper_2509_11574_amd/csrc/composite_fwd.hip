@@ -193,15 +193,35 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
             }
         }
     }
-    lc = block_sum<NT>(lc);
-    ld = block_sum<NT>(ld);
-    lo = block_sum<NT>(lo);
-    unsigned int tot_eval, tot_contrib;  // the counts are per wavefront: lane 0 carries them
-    block_excl_scan<NT>(lane == 0 ? n_eval : 0u, &tot_eval);
-    block_excl_scan<NT>(lane == 0 ? n_contrib : 0u, &tot_contrib);
+    // One barrier: wave sums (DPP) of the three loss partials, the pair counts
+    // (already uniform per wavefront), then the wavefronts in order by one thread.
+    constexpr int NW = Lay::NW;
+    __shared__ float sred[NW][3];
+    __shared__ unsigned int scnt[NW][2];
+    lc = wave_sum(lc);
+    ld = wave_sum(ld);
+    lo = wave_sum(lo);
+    if (lane == 0) {
+        sred[wid][0] = lc;
+        sred[wid][1] = ld;
+        sred[wid][2] = lo;
+        scnt[wid][0] = n_eval;
+        scnt[wid][1] = n_contrib;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        w.tile_loss[tile] = make_float4(lc, ld, lo, 0.0f);
-        w.tile_pairs[tile] = make_uint2(tot_eval, tot_contrib);  // summed by k_loss_reduce
+        float a = 0.0f, bsum = 0.0f, c = 0.0f;
+        unsigned int te = 0u, tc = 0u;
+#pragma unroll
+        for (int k = 0; k < NW; ++k) {
+            a += sred[k][0];
+            bsum += sred[k][1];
+            c += sred[k][2];
+            te += scnt[k][0];
+            tc += scnt[k][1];
+        }
+        w.tile_loss[tile] = make_float4(a, bsum, c, 0.0f);
+        w.tile_pairs[tile] = make_uint2(te, tc);  // summed by k_loss_reduce
     }
 }
 

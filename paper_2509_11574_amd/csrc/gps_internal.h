@@ -73,7 +73,7 @@ struct WsHeader {
     float loss;
     int n_views;
     int n_tiles;
-    int pad_;
+    unsigned int n_large;          // tiles longer than one wavefront sorts (block sort)
     float view_stats[GPS_MAX_VIEWS][4];  // per view: colour L1 sum, depth L1 sum, |Omega|, pad
 };
 

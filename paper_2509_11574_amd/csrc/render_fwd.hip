@@ -252,9 +252,12 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(RParams rp, WsPtrs w, int n
 {
     if (w.hdr->n_inst > rp.cap) return;
     __shared__ unsigned int wsum[16], hist[33], cur[33];
-    __shared__ unsigned int carry_s;
+    __shared__ unsigned int carry_s, n_large;
     if (threadIdx.x < 33) hist[threadIdx.x] = 0u;
-    if (threadIdx.x == 0) carry_s = 0u;
+    if (threadIdx.x == 0) {
+        carry_s = 0u;
+        n_large = 0u;
+    }
     __syncthreads();
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     // One pass per chunk of 4 tiles per lane: the sub-counts are read once, their
@@ -301,6 +304,7 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(RParams rp, WsPtrs w, int n
                     r += c[i][k];
                 }
                 atomicAdd(&hist[31 - __clz(tot[i] + 1u)], 1u);
+                if (tot[i] >= kLongTile) atomicAdd(&n_large, 1u);
             }
             run += tot[i];
         }
@@ -311,6 +315,7 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(RParams rp, WsPtrs w, int n
     // Longest-first order: buckets floor(log2(count + 1)) laid out in descending order.
     if (threadIdx.x == 0) {
         w.tile_start[n_tiles] = carry_s;
+        w.hdr->n_large = n_large;
         unsigned int o = 0;
         for (int bkt = 32; bkt >= 0; --bkt) {
             cur[bkt] = o;
@@ -428,7 +433,6 @@ __global__ void __launch_bounds__(kBlk) k_expand(const ViewTable* __restrict__ v
 // barriers.
 // k_tile_sort_large: one block per longer tile; tiles longer than kSortCap use
 // the same network in global memory.
-constexpr int kSmallSort = 512;
 
 __device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m)
 {
@@ -506,7 +510,7 @@ __global__ void __launch_bounds__(256) k_tile_sort_small(RParams rp, WsPtrs w, i
     if (tile >= n_tiles) return;
     const unsigned int s = w.tile_start[tile], e = w.tile_start[tile + 1];
     const int n = (int)(e - s);
-    if (n <= 1 || n > kSmallSort) return;
+    if (n <= 1 || (unsigned int)n >= kLongTile) return;
     unsigned long long* key = w.keys + s;
     if (n <= 64) wave_sort_regs<1>(key, n, lane);
     else if (n <= 128) wave_sort_regs<2>(key, n, lane);
@@ -523,7 +527,7 @@ __device__ __forceinline__ void cas_lds(unsigned long long* sh, int i, int j)
     }
 }
 
-// One block sorts the n > kSmallSort keys starting at keys[s].
+// One block sorts the n >= kLongTile keys starting at keys[s].
 __device__ void sort_tile_block(const WsPtrs& w, unsigned int s, int n)
 {
     int P = 1;
@@ -584,15 +588,16 @@ __device__ void sort_tile_block(const WsPtrs& w, unsigned int s, int n)
     }
 }
 
-// The tiles longer than kSmallSort lead the longest-first tile queue, so block
-// b takes queue position b; past the long tiles, blocks exit at once.
+// The tiles of at least kLongTile keys lead the longest-first tile queue (the
+// tile scan counts them), so block b takes queue position b; past them, blocks
+// exit after one header read.
 __global__ void __launch_bounds__(256) k_tile_sort_large(RParams rp, WsPtrs w)
 {
-    if (w.hdr->n_inst > rp.cap) return;
+    if (w.hdr->n_inst > rp.cap || blockIdx.x >= w.hdr->n_large) return;
     const int tile = (int)w.tile_queue[blockIdx.x];
     const unsigned int s = w.tile_start[tile], e = w.tile_start[tile + 1];
     const int n = (int)(e - s);
-    if (n > kSmallSort) sort_tile_block(w, s, n);
+    if ((unsigned int)n >= kLongTile) sort_tile_block(w, s, n);
 }
 
 // ------------------------------------------------------------ loss reduce
