@@ -120,7 +120,7 @@ def main():
     torch.cuda.set_device(0)
     W_img, H_img = (int(x) for x in args.res.split("x"))
     K, Wu, M = args.steps, args.warmup, args.gaussians
-    n_frames = Wu + 2 * K  # warmup, timed pass, profiled pass
+    n_frames = Wu + 3 * K  # warmup, timed pass (graph), eager timed pass, profiled pass
 
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 4
@@ -187,6 +187,7 @@ def main():
             P.render_fwd(cfg, params, [view], ws, out_loss=loss)
             P.render_bwd(cfg, params, [view], ws, grads, dpose)
             opt.step(grads)
+        return view
 
     graph = None
 
@@ -197,11 +198,13 @@ def main():
             graph.replay()
 
     frame_step = frame_step_eager
+    last_view = None
     for k in range(Wu):
-        frame_step(k)
+        last_view = frame_step(k)
     if args.graph:
         from paper_2509_11574_amd.graph import IterationGraph
-        graph = IterationGraph(cfg, params, [frame_prep(Wu - 1)], ws, grads, opt, loss, dpose)
+        # captured on the last warm-up frame's view (capturing runs nothing on the device)
+        graph = IterationGraph(cfg, params, [last_view], ws, grads, opt, loss, dpose)
         frame_step = frame_step_graph
     torch.cuda.synchronize()
     st0 = ws.stats()
@@ -214,8 +217,11 @@ def main():
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     t_start = time.perf_counter()
     ev0.record()
-    for k in range(Wu, Wu + K):
+    fev = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+    fev[0].record()
+    for i, k in enumerate(range(Wu, Wu + K)):
         frame_step(k)
+        fev[i + 1].record()
     ev1.record()
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_start
@@ -226,6 +232,21 @@ def main():
     ms_per_frame = 1000.0 * t_wall / K
     iters_per_s = ITERS_PER_FRAME * K / t_wall
     last_loss = float(loss.item())
+    per_frame = sorted(fev[i].elapsed_time(fev[i + 1]) for i in range(K))
+    pct = lambda q: per_frame[min(K - 1, int(round(q * (K - 1))))]
+    frame_ms_pct = {"p10": round(pct(0.1), 4), "p50": round(pct(0.5), 4), "p90": round(pct(0.9), 4)}
+
+    # ------------------------------------- the same frames, eager launches
+    eager = None
+    if args.graph:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(Wu + K, Wu + 2 * K):
+            frame_step_eager(k)
+        torch.cuda.synchronize()
+        te = time.perf_counter() - t1
+        eager = {"ms_per_frame": round(1000.0 * te / K, 4), "iters_per_s": round(ITERS_PER_FRAME * K / te, 1),
+                 "frames": "the %d frames after the timed ones, launched without the graph" % K}
     log(f"timed {K} frames: {ms_per_frame:.3f} ms/frame (events {ms_event / K:.3f}), {iters_per_s:.1f} iters/s, "
         f"loss {first_loss:.5f} -> {last_loss:.6f}, instances {st1['n_instances']}")
 
@@ -234,7 +255,7 @@ def main():
     if not args.no_profile:
         stp0 = ws.stats()
         P.gps.profile_start()
-        for k in range(Wu + K, Wu + 2 * K):  # the same kernels, launched eagerly so events bracket each
+        for k in range(Wu + 2 * K, Wu + 3 * K):  # the same kernels, launched eagerly so events bracket each
             frame_step_eager(k)
         torch.cuda.synchronize()
         P.gps.profile_stop()
@@ -305,6 +326,8 @@ def main():
            "instances": I, "pairs": pairs,
            "loss_first_last": [round(first_loss, 6), round(last_loss, 6)],
            "roofline": roofline,
+           "frame_ms_p10_p50_p90": frame_ms_pct,
+           "eager": eager,
            "sorted_vs_sort_free": modes,
            "batched_keyframes": batched,
            "large_map": large,

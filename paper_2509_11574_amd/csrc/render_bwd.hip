@@ -14,7 +14,7 @@
 namespace gps {
 
 // ------------------------------------------------------------- gauss bwd
-constexpr unsigned int kCoopSlots = 16;  // more slots than this: summed by the whole wavefront
+constexpr unsigned int kCoopSlots = 32;  // more slots than this: summed by the whole wavefront
 
 // EWA chain rule of one Gaussian in one view.  The summed instance partials are
 // first turned into A[10] = dL/d(mx, my, a, b, c), sigma dL/dsigma, dL/d(r, g, b, d),
