@@ -356,13 +356,14 @@ def bench_modes(P, cfg, params, view, M, cam0, reps=40):
     backward, per-Gaussian reduce, pose) of one room view, timed with HIP events, in the
     sorted mode and in the sort-free blend of Eq. 1-4 (mode 1).  Mode 1 runs the same
     binning and tile sort: the sort fixes the summation order, which keeps its results
-    bitwise reproducible.  Median of `reps` calls each."""
+    bitwise reproducible.  The third line is the sort-free mode with the per-Gaussian
+    backward over pixel chunks.  Median of `reps` calls each."""
     import statistics
     from dataclasses import replace
     import torch
     out = {}
-    for mode, name in ((0, "sorted"), (1, "sort_free")):
-        c = replace(cfg, mode=mode)
+    for mode, name, pg in ((0, "sorted", False), (1, "sort_free", False), (1, "sort_free_per_gaussian_bwd", True)):
+        c = replace(cfg, mode=mode, bwd_per_gaussian=pg)
         ws = P.Workspace(c, M, [cam0], device=view.base_depth.device)
         grads = P.zeros_like_gaussians(params)
         dpose = torch.zeros(1, 6, device=view.base_depth.device)

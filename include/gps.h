@@ -139,6 +139,13 @@ typedef struct gps_render_cfg {
  * new camera poses or new base images: upload, then replay. */
 #define GPS_RENDER_VIEWS_PRESET 1
 
+/* Sort-free mode (mode 1) only: gps_render_bwd forms each view-Gaussian's
+ * screen-space adjoints by walking the pixels of its support box itself, in
+ * chunks of a fixed number of pixels spread over the lanes of a block (the
+ * per-Gaussian backward of Sec. 3.1 and Appendix B), instead of reducing per
+ * tile.  Same results up to rounding; GPS_ERR_UNSUPPORTED_CONFIG in mode 0. */
+#define GPS_RENDER_BWD_PER_GAUSSIAN 2
+
 /* One Adam parameter group. */
 typedef struct gps_adam_group {
     float* param;

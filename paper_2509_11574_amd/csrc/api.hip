@@ -51,7 +51,7 @@ static gps_status compute_layout(const gps_render_cfg* cfg, int M, const gps_cam
     if (cfg->mode != 0 && cfg->mode != 1) return GPS_ERR_INVALID_ARG;
     if (!tile_config_supported(cfg)) return GPS_ERR_UNSUPPORTED_CONFIG;
     if (cfg->max_instances < 0) return GPS_ERR_INVALID_ARG;
-    if (cfg->flags & ~GPS_RENDER_VIEWS_PRESET) return GPS_ERR_INVALID_ARG;
+    if (cfg->flags & ~(GPS_RENDER_VIEWS_PRESET | GPS_RENDER_BWD_PER_GAUSSIAN)) return GPS_ERR_INVALID_ARG;
     const float consts[7] = {cfg->eps_cull, cfg->lambda_depth, cfg->dilation, cfg->alpha_min,
                              cfg->alpha_max, cfg->T_min, cfg->z_near};
     for (float c : consts)
@@ -97,6 +97,8 @@ static gps_status compute_layout(const gps_render_cfg* cfg, int M, const gps_cam
     o = align_up(o + 8 * (size_t)n_tiles);
     L->pix_aux = o;
     o = align_up(o + 4 * (size_t)npix);
+    L->pix_grad = o;
+    o = align_up(o + 32 * (size_t)npix);
     L->rec = o;
     o = align_up(o + 4 * kRecFloats * (size_t)nvg);
     L->cnt = o;

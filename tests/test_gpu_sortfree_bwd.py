@@ -1,0 +1,123 @@
+"""GPU parity of the per-Gaussian backward of the sort-free blend.
+
+With GPS_RENDER_BWD_PER_GAUSSIAN (sort-free mode only) each view-Gaussian sums
+its screen-space adjoints over the pixels of its support box, in fixed-size
+pixel chunks spread over a block's lanes, instead of per tile.  Checked against
+the FP64 reference implementation (explicit upstream adjoints, the fused loss,
+several views), against the tile backward of the same forward, for bitwise
+repeatability, and for the refusal in sorted mode.  Gradient tolerance 1e-3
+relative (normwise per tensor), as for the tile backward.
+"""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+import torch
+
+from tests.gpu_util import DEV, cfg_pair, h, normwise, say, t
+from tests.test_gpu_parity import KEYS, _explicit_upstream, _fused_small, _grads_gpu, _render_gpu
+from tests.tiny_cases import tiny_case
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2509_11574_amd as P
+    P.lib()
+    assert torch.cuda.is_available()
+    return P
+
+
+@pytest.fixture(scope="module")
+def O():
+    from oracle import oracle as O
+    O.lib()
+    return O
+
+
+@pytest.fixture(scope="module")
+def small():
+    return synth.workload_small()
+
+
+@pytest.mark.parametrize("tile", [(16, 16, 256, 1), (16, 32, 128, 2)])
+def test_per_gaussian_bwd_explicit(P, O, tile):
+    say(f"per-Gaussian sort-free bwd (explicit upstream): tile={tile}")
+    for seed in (0, 1):
+        case = tiny_case(seed, M=60, W=53, H=37, log_scale=-2.4)
+        gc, oc = cfg_pair(P, O, mode=1, eps=0.03, tile=tile)
+        views, ws, gd, _ = _render_gpu(P, gc, case["gauss"], [case])
+        r = O.render(oc, case["gauss"], case["cam"], case["base_rgb"], case["base_depth"])
+        gC, gD = _explicit_upstream(case, seed, r["flag"])
+        got = _grads_gpu(P, replace(gc, bwd_per_gaussian=True), gd, views, ws, up=[(gC, gD)])
+        ref = O.render_bwd(oc, case["gauss"], case["cam"], case["base_rgb"], case["base_depth"], gC, gD)
+        for k in KEYS:
+            assert normwise(got[k], ref[k]) < 1e-3, (k, normwise(got[k], ref[k]))
+        assert normwise(got["pose"][0], ref["pose"]) < 1e-3
+
+
+def test_per_gaussian_bwd_fused_loss(P, O, small):
+    say("per-Gaussian sort-free bwd (fused loss): 160x120")
+    sc, cam = small["scene"], small["cam"]
+    grid, ref = _fused_small(O, small)
+    rd, rc, _ = O.raycast(grid, ref["tsdf"].astype(np.float32), ref["rgb"].astype(np.float32), cam.as_dict())
+    vn = {"cam": cam.as_dict(), "base_rgb": rc.reshape(3, 120, 160).astype(np.float32),
+          "base_depth": rd.reshape(120, 160).astype(np.float32), "target_rgb": small["rgb"],
+          "target_depth": small["depth"]}
+    gc, oc = cfg_pair(P, O, mode=1, eps=sc.voxel)
+    views, ws, gd, loss = _render_gpu(P, gc, small["gauss"], [vn])
+    scale = torch.full((1,), 2.0, device=DEV)
+    got = _grads_gpu(P, replace(gc, bwd_per_gaussian=True), gd, views, ws, scale=scale)
+    r = O.render(oc, small["gauss"], cam.as_dict(), vn["base_rgb"], vn["base_depth"])
+    L, grgb, gdep, _ = O.loss(oc, 160, 120, r["rgb"], r["depth"], small["rgb"], small["depth"], vn["base_depth"],
+                              scale=2.0)
+    refg = O.render_bwd(oc, small["gauss"], cam.as_dict(), vn["base_rgb"], vn["base_depth"], grgb, gdep)
+    for k in KEYS:
+        assert normwise(got[k], refg[k]) < 1e-3, (k, normwise(got[k], refg[k]))
+    assert normwise(got["pose"][0], refg["pose"]) < 1e-3
+
+
+def test_per_gaussian_bwd_multiview(P, O):
+    say("per-Gaussian sort-free bwd: 3 views of different sizes")
+    cases = [tiny_case(20, M=50, W=53, H=37), tiny_case(21, M=50, W=40, H=30), tiny_case(22, M=50, W=71, H=19)]
+    g = cases[0]["gauss"]
+    gc, oc = cfg_pair(P, O, mode=1, eps=0.03)
+    views, ws, gd, loss = _render_gpu(P, gc, g, cases)
+    got = _grads_gpu(P, replace(gc, bwd_per_gaussian=True), gd, views, ws)
+    acc = None
+    for c in cases:
+        r = O.render(oc, g, c["cam"], c["base_rgb"], c["base_depth"])
+        _, grgb, gdep, _ = O.loss(oc, c["cam"]["width"], c["cam"]["height"], r["rgb"], r["depth"], c["target_rgb"],
+                                  c["target_depth"], c["base_depth"], scale=1.0 / 3)
+        rg = O.render_bwd(oc, g, c["cam"], c["base_rgb"], c["base_depth"], grgb, gdep)
+        acc = rg if acc is None else {k: acc[k] + rg[k] if k != "pose" else np.vstack([acc[k], rg[k]]) for k in acc}
+    for k in KEYS:
+        assert normwise(got[k], acc[k]) < 1e-3, k
+    assert normwise(got["pose"], acc["pose"].reshape(3, 6)) < 1e-3
+
+
+def test_per_gaussian_bwd_matches_tile_bwd_and_repeats(P, O, small):
+    """After a tile backward of the same forward (which leaves partials in every
+    slot), the per-Gaussian backward still gives its own result, repeatably,
+    and that result equals the tile backward's up to rounding."""
+    say("per-Gaussian sort-free bwd against the tile bwd, repeated")
+    case = tiny_case(7, M=400, W=160, H=120, log_scale=-2.2)
+    gc, _ = cfg_pair(P, O, mode=1, eps=0.03, tile=(16, 32, 128, 2))
+    views, ws, gd, _ = _render_gpu(P, gc, case["gauss"], [case])
+    tile_g = _grads_gpu(P, gc, gd, views, ws)
+    pg = replace(gc, bwd_per_gaussian=True)
+    a = _grads_gpu(P, pg, gd, views, ws)
+    b = _grads_gpu(P, pg, gd, views, ws)
+    for k in list(KEYS) + ["pose"]:
+        assert np.array_equal(a[k], b[k]), k
+        assert normwise(a[k], tile_g[k]) < 1e-4, (k, normwise(a[k], tile_g[k]))
+
+
+def test_per_gaussian_bwd_needs_sort_free_mode(P, O):
+    case = tiny_case(3, M=20, W=32, H=24)
+    gc, _ = cfg_pair(P, O, mode=0, eps=0.03)
+    views, ws, gd, _ = _render_gpu(P, gc, case["gauss"], [case])
+    with pytest.raises(P.gps.GpsError):
+        _grads_gpu(P, replace(gc, bwd_per_gaussian=True), gd, views, ws)
