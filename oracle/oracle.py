@@ -305,3 +305,46 @@ def adam(param, grad, m, v, lr, t, b1=0.9, b2=0.999, eps=1e-15):
 # Learning rates per attribute, Appendix C (position, SH0 -> rgb, alpha -> opacity
 # logit, scale -> log-scale, rotation -> quaternion).
 PAPER_LR = {"mean": 1.6e-4, "rgb": 2.5e-3, "opacity_logit": 0.05, "log_scale": 5e-3, "quat": 1e-3}
+
+
+# --------------------------------------------------------------------------- #
+# Gaussian removal (Sec. 3.2.2, Eq. 8).                                        #
+# --------------------------------------------------------------------------- #
+# A Gaussian is deleted when its opacity sigma = sigmoid(o) is below
+# delta_sigma, or its largest scale s = exp(l) is above delta_s_max, or its
+# largest scale is below delta_s_min.  Reading: sigmoid and exp are increasing,
+# so the tests are taken on the stored parameters, o < logit(delta_sigma) and
+# max(l) > ln(delta_s_max), max(l) < ln(delta_s_min), each in binary32 against
+# the threshold computed in binary64 and rounded to binary32 once -- the
+# precision in which the parameters are stored, so that the keep/delete
+# decision is a plain comparison of stored values.
+REMOVAL_DEFAULTS = {"min_opacity": 0.005, "max_scale": 0.1, "min_scale": 0.003}
+
+
+def removal_thresholds(min_opacity=0.005, max_scale=0.1, min_scale=0.003):
+    """(logit threshold, ln max scale, ln min scale), binary32."""
+    return (np.float32(np.log(min_opacity / (1.0 - min_opacity))), np.float32(np.log(max_scale)),
+            np.float32(np.log(min_scale)))
+
+
+def removal_keep(g, min_opacity=0.005, max_scale=0.1, min_scale=0.003):
+    """Boolean mask of the Gaussians Eq. 8 keeps (plain loop over Gaussians)."""
+    t_o, t_hi, t_lo = removal_thresholds(min_opacity, max_scale, min_scale)
+    o = np.asarray(g["opacity_logit"], np.float32).reshape(-1)
+    ls = np.asarray(g["log_scale"], np.float32).reshape(3, -1)
+    keep = np.zeros(o.size, bool)
+    for i in range(o.size):
+        lmax = max(ls[0, i], ls[1, i], ls[2, i])
+        delete = (o[i] < t_o) or (lmax > t_hi) or (lmax < t_lo)
+        keep[i] = not delete
+    return keep
+
+
+def remove_gaussians(g, companions=(), **thresholds):
+    """The kept Gaussians of `g`, in their original order, and the same rows of
+    every companion set (e.g. Adam moments); each a dict of [rows][n_kept] arrays."""
+    keep = removal_keep(g, **thresholds)
+    idx = np.nonzero(keep)[0]
+    pick = lambda s: {k: np.asarray(v).reshape(np.asarray(v).shape[0] if np.asarray(v).ndim > 1 else 1, -1)[:, idx]
+                      for k, v in s.items()}
+    return pick(g), [pick(c) for c in companions], idx
