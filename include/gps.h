@@ -270,6 +270,35 @@ gps_status gps_views_upload(const gps_render_cfg* cfg, const gps_gaussians* g, c
 gps_status gps_adam_step(const gps_adam_group* groups, int32_t n_groups, int32_t step, int32_t* step_counter,
                          float beta1, float beta2, float eps, void* stream);
 
+/* ---- Gaussian removal (Sec. 3.2.2, Eq. 8) ---------------------------------
+ * A Gaussian is removed when its opacity sigmoid(o) is below min_opacity, or its
+ * largest scale exp(l) is above max_scale or below min_scale (0.005, 0.1 and
+ * 0.003 in the paper).  The tests are taken on the stored parameters in
+ * binary32: o < logit(min_opacity), max(l) > ln(max_scale), max(l) <
+ * ln(min_scale), each threshold computed in binary64 and rounded once. */
+typedef struct gps_removal_cfg {
+    float min_opacity;
+    float max_scale;
+    float min_scale;
+} gps_removal_cfg;
+
+/* Fills `cfg` (host) with the paper's thresholds. */
+void gps_removal_cfg_default(gps_removal_cfg* cfg);
+
+/* Scratch bytes that gps_remove_gaussians needs for n_gaussians. */
+gps_status gps_removal_workspace_size(int32_t n_gaussians, size_t* out_bytes);
+
+/* Stable compaction.  sets_in[0] decides (n = sets_in[0].count); the kept
+ * Gaussians of every set sets_in[0 .. n_sets) (for example the parameters and
+ * their two Adam moments; every set has count n) are written in their original
+ * order to sets_out[k] as planar [rows][n_kept] arrays (row stride n_kept; each
+ * output array has room for rows * n floats), and n_kept to *out_count (a
+ * device int32).  Inputs and outputs must not overlap.  n_sets: 1 .. 4.
+ * ws: gps_removal_workspace_size bytes of device memory, 256-byte aligned.
+ * Three kernels on `stream`; nothing is read back on the host. */
+gps_status gps_remove_gaussians(const gps_removal_cfg* cfg, const gps_gaussians* sets_in, gps_gaussians* sets_out,
+                                int32_t n_sets, int32_t* out_count, void* ws, size_t ws_bytes, void* stream);
+
 /* Reads the sticky status word of a workspace (synchronises `stream`). */
 gps_status gps_device_status(const void* ws, size_t ws_bytes, int32_t* out_status, void* stream);
 

@@ -345,6 +345,6 @@ def remove_gaussians(g, companions=(), **thresholds):
     every companion set (e.g. Adam moments); each a dict of [rows][n_kept] arrays."""
     keep = removal_keep(g, **thresholds)
     idx = np.nonzero(keep)[0]
-    pick = lambda s: {k: np.asarray(v).reshape(np.asarray(v).shape[0] if np.asarray(v).ndim > 1 else 1, -1)[:, idx]
-                      for k, v in s.items()}
+    rows = {"mean": 3, "log_scale": 3, "quat": 4, "opacity_logit": 1, "rgb": 3}
+    pick = lambda s: {k: np.asarray(v).reshape(rows[k], keep.size)[:, idx] for k, v in s.items()}
     return pick(g), [pick(c) for c in companions], idx

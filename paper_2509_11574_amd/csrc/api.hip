@@ -368,6 +368,46 @@ gps_status gps_adam_step(const gps_adam_group* groups, int32_t n_groups, int32_t
     return launch_adam(groups, n_groups, step, step_counter, beta1, beta2, eps, (hipStream_t)stream);
 }
 
+void gps_removal_cfg_default(gps_removal_cfg* cfg)
+{
+    if (!cfg) return;
+    cfg->min_opacity = 0.005f;
+    cfg->max_scale = 0.1f;
+    cfg->min_scale = 0.003f;
+}
+
+gps_status gps_removal_workspace_size(int32_t n_gaussians, size_t* out_bytes)
+{
+    if (n_gaussians < 0 || !out_bytes) return GPS_ERR_INVALID_ARG;
+    *out_bytes = removal_workspace_bytes(n_gaussians);
+    return GPS_OK;
+}
+
+gps_status gps_remove_gaussians(const gps_removal_cfg* cfg, const gps_gaussians* sets_in, gps_gaussians* sets_out,
+                                int32_t n_sets, int32_t* out_count, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!cfg || !sets_in || !sets_out || n_sets < 1 || n_sets > 4) return GPS_ERR_INVALID_ARG;
+    if (!(cfg->min_opacity > 0.0f && cfg->min_opacity < 1.0f) || !(cfg->max_scale > 0.0f) ||
+        !(cfg->min_scale > 0.0f) || !(cfg->min_scale <= cfg->max_scale))
+        return GPS_ERR_INVALID_ARG;
+    const int M = sets_in[0].count;
+    if (M < 0) return GPS_ERR_INVALID_ARG;
+    for (int k = 0; k < n_sets; ++k) {
+        const gps_gaussians& gi = sets_in[k];
+        const gps_gaussians& go = sets_out[k];
+        if (gi.count != M) return GPS_ERR_INVALID_ARG;
+        if (M > 0 && (!gi.mean || !gi.log_scale || !gi.quat || !gi.opacity_logit || !gi.rgb || !go.mean ||
+                      !go.log_scale || !go.quat || !go.opacity_logit || !go.rgb))
+            return GPS_ERR_INVALID_ARG;
+    }
+    if (!ws || ((uintptr_t)ws & 255)) return GPS_ERR_INVALID_ARG;
+    if (ws_bytes < removal_workspace_bytes(M)) return GPS_ERR_WORKSPACE_TOO_SMALL;
+    gps_status st = check_device();
+    if (st != GPS_OK) return st;
+    return launch_remove_gaussians(cfg, sets_in, sets_out, n_sets, out_count, static_cast<char*>(ws),
+                                   (hipStream_t)stream);
+}
+
 gps_status gps_device_status(const void* ws, size_t ws_bytes, int32_t* out_status, void* stream)
 {
     if (!ws || ws_bytes < 1024 || !out_status) return GPS_ERR_INVALID_ARG;

@@ -28,5 +28,8 @@ gps_status launch_views_upload(const ViewTable& vt, const RParams& rp, const WsL
 gps_status launch_adam(const gps_adam_group* groups, int n_groups, int step, int* step_counter, float b1, float b2,
                        float eps, hipStream_t s);
 gps_status launch_ws_reset(char* ws, hipStream_t s);
+size_t removal_workspace_bytes(int M);
+gps_status launch_remove_gaussians(const gps_removal_cfg* cfg, const gps_gaussians* sets_in, gps_gaussians* sets_out,
+                                   int n_sets, int* out_count, char* ws, hipStream_t s);
 
 }  // namespace gps

@@ -28,6 +28,7 @@ enum KernelId {
     K_STEP_INCR,
     K_WS_RESET,
     K_UPLOAD,
+    K_REMOVE,
     K_COUNT
 };
 

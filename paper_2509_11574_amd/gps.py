@@ -62,6 +62,10 @@ class RenderCfgS(ctypes.Structure):
                 ("max_instances", ctypes.c_int64), ("flags", ctypes.c_int32)]
 
 
+class RemovalCfgS(ctypes.Structure):
+    _fields_ = [("min_opacity", ctypes.c_float), ("max_scale", ctypes.c_float), ("min_scale", ctypes.c_float)]
+
+
 class AdamGroupS(ctypes.Structure):
     _fields_ = [("param", ctypes.c_void_p), ("grad", ctypes.c_void_p), ("m", ctypes.c_void_p),
                 ("v", ctypes.c_void_p), ("n", ctypes.c_int64), ("lr", ctypes.c_float)]
@@ -81,7 +85,8 @@ class KernelTimeS(ctypes.Structure):
 EXPORTS = ["gps_abi_version", "gps_status_string", "gps_render_cfg_default", "gps_workspace_size",
            "gps_workspace_reset", "gps_fuse", "gps_raycast", "gps_render_fwd", "gps_render_bwd",
            "gps_adam_step", "gps_device_status", "gps_read_stats", "gps_profile_start", "gps_profile_stop",
-           "gps_profile_read", "gps_views_upload"]
+           "gps_profile_read", "gps_views_upload", "gps_removal_cfg_default", "gps_removal_workspace_size",
+           "gps_remove_gaussians"]
 
 _lib = None
 
@@ -113,8 +118,12 @@ def lib():
         L.gps_profile_start.argtypes = []
         L.gps_profile_stop.argtypes = []
         L.gps_profile_read.argtypes = [P, I32, ctypes.POINTER(I32)]
+        L.gps_removal_cfg_default.argtypes = [P]
+        L.gps_removal_cfg_default.restype = None
+        L.gps_removal_workspace_size.argtypes = [I32, ctypes.POINTER(ctypes.c_size_t)]
+        L.gps_remove_gaussians.argtypes = [P, P, P, I32, P, P, ctypes.c_size_t, P]
         for n in EXPORTS:
-            if n not in ("gps_render_cfg_default", "gps_status_string", "gps_abi_version"):
+            if n not in ("gps_render_cfg_default", "gps_status_string", "gps_abi_version", "gps_removal_cfg_default"):
                 getattr(L, n).restype = I32
         _lib = L
     return _lib
@@ -536,3 +545,33 @@ class Render(torch.autograd.Function):
             ddep.append((gd if gd is not None else torch.zeros_like(v.out_depth)).contiguous())
         render_bwd(s.cfg, g, s.views, s.ws, grads, dpose, dL_drgb=drgb, dL_ddepth=ddep)
         return grads["mean"], grads["log_scale"], grads["quat"], grads["opacity_logit"], grads["rgb"], dpose, None
+
+
+def remove_gaussians(params: dict, companions=(), min_opacity=0.005, max_scale=0.1, min_scale=0.003, stream=None):
+    """Gaussian removal of Eq. 8 (gps_remove_gaussians): returns the kept Gaussians of
+    `params` in their original order, the same rows of every companion set (for
+    example Adam moments), and the kept count.  Reads the count back (synchronises)."""
+    M = int(params["opacity_logit"].numel())
+    dev = params["opacity_logit"].device
+    sets = [params] + list(companions)
+    outs = [{k: torch.empty(GAUSS_ROWS[k], max(M, 1), dtype=torch.float32, device=dev) for k in GAUSS_KEYS}
+            for _ in sets]
+    arr_in = (GaussiansS * len(sets))(*[gaussians_struct(s) for s in sets])
+    arr_out = (GaussiansS * len(sets))()
+    for i, o in enumerate(outs):
+        arr_out[i].count = M
+        for k in GAUSS_KEYS:
+            setattr(arr_out[i], k, ctypes.c_void_p(o[k].data_ptr()))
+    nbytes = ctypes.c_size_t(0)
+    _check(lib().gps_removal_workspace_size(M, ctypes.byref(nbytes)), "gps_removal_workspace_size")
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    cfg = RemovalCfgS(min_opacity, max_scale, min_scale)
+    _check(lib().gps_remove_gaussians(ctypes.byref(cfg), arr_in, arr_out, len(sets),
+                                      ctypes.c_void_p(count.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                      nbytes.value, _stream(stream)), "gps_remove_gaussians")
+    n = int(count.item())
+    shaped = [{k: o[k].reshape(-1)[:GAUSS_ROWS[k] * n].view(GAUSS_ROWS[k], n) if GAUSS_ROWS[k] > 1
+               else o[k].reshape(-1)[:n] for k in GAUSS_KEYS} for o in outs]
+    return shaped[0], shaped[1:], n
+

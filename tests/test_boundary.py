@@ -130,3 +130,23 @@ def test_oracle_and_product_are_independent():
         if f.endswith((".py", ".c", ".h")):
             txt = open(os.path.join(ROOT, "oracle", f)).read()
             assert "paper_2509_11574_amd" not in txt and "gps.h" not in txt, f
+
+
+def test_removal_defaults_and_argument_checks(P):
+    """Gaussian removal (Eq. 8): the default thresholds are the paper's; bad
+    arguments are refused before anything is launched."""
+    L = P.lib()
+    c = P.gps.RemovalCfgS()
+    L.gps_removal_cfg_default(ctypes.byref(c))
+    assert (c.min_opacity, c.max_scale, c.min_scale) == pytest.approx((0.005, 0.1, 0.003))
+    n = ctypes.c_size_t(0)
+    assert L.gps_removal_workspace_size(1000, ctypes.byref(n)) == 0 and n.value >= 2 * 4 * 4
+    assert L.gps_removal_workspace_size(-1, ctypes.byref(n)) == -1
+    sets = (P.gps.GaussiansS * 1)()
+    outs = (P.gps.GaussiansS * 1)()
+    assert L.gps_remove_gaussians(ctypes.byref(c), sets, outs, 0, None, None, 0, None) == -1   # no set
+    assert L.gps_remove_gaussians(ctypes.byref(c), sets, outs, 5, None, None, 0, None) == -1   # too many sets
+    bad = P.gps.RemovalCfgS(0.005, 0.001, 0.003)                                             # min > max scale
+    assert L.gps_remove_gaussians(ctypes.byref(bad), sets, outs, 1, None, None, 0, None) == -1
+    sets[0].count = 10                                                                        # null arrays
+    assert L.gps_remove_gaussians(ctypes.byref(c), sets, outs, 1, None, None, 0, None) == -1
