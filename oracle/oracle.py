@@ -348,3 +348,104 @@ def remove_gaussians(g, companions=(), **thresholds):
     rows = {"mean": 3, "log_scale": 3, "quat": 4, "opacity_logit": 1, "rgb": 3}
     pick = lambda s: {k: np.asarray(v).reshape(rows[k], keep.size)[:, idx] for k, v in s.items()}
     return pick(g), [pick(c) for c in companions], idx
+
+
+# --------------------------------------------------------------------------- #
+# Gaussian insertion (Sec. 3.2.2, Eq. 6 and the paragraph after it; App. A).  #
+# --------------------------------------------------------------------------- #
+# Readings (the paper is silent on these):
+#  * colour error |C*(u) - C_k(u)|: the mean over the three channels of the
+#    absolute difference (the per-pixel L1 of the loss), tested as the binary32
+#    sum (|e0| + |e1|) + |e2| > 3 delta_c (threshold computed in binary64,
+#    rounded once); W_G(u) < delta_W in binary32; pixels where the SDF ray
+#    missed (D_t = 0) have no surface point and are left out of the mask;
+#  * the 25 % uniform sample: a pixel of the mask is taken when the caller's
+#    uniform number for it is below the fraction (binary32);
+#  * V*(u): the camera-frame point (u - c_x) d / f_x, (v - c_y) d / f_y, d of the
+#    SDF depth d = D_t(u), taken to the world frame; N*(u): the normalised cross
+#    product of the central differences of V* along x and along y, turned to
+#    face the camera; where a neighbour is missing, the direction to the camera;
+#  * App. A: the three mask vertices nearest to V*(u) are searched among the mask
+#    pixels of the (2R + 1)^2 window around u (R = 4; the whole mask would be a
+#    quadratic search), nearest first, ties by pixel index; s1 = min(0.1,
+#    sqrt(mean of their distances)), s2 = s1, s3 = 0.1 s1 (a disc whose short
+#    axis is the normal); with no such vertex, s1 = 0.1;
+#  * rotation: the quaternion (w, x, y, z) that turns the local z axis onto the
+#    normal, (1 + n_z, -n_y, n_x, 0) normalised, (0, 1, 0, 0) when n = -z;
+#  * opacity 0.5 (logit 0), colour C_k(u); new Gaussians in row-major pixel order.
+INSERT_DEFAULTS = {"delta_c": 0.05, "delta_w": 4.0, "fraction": 0.25, "radius": 4, "scale_cap": 0.1,
+                   "flat_ratio": 0.1, "opacity": 0.5}
+
+
+def insertion_mask(render_rgb, frame_rgb, weight, sdf_depth, delta_c=0.05, delta_w=4.0):
+    """Eq. 6 mask (binary32 decisions), [H][W] bool."""
+    C = np.asarray(render_rgb, np.float32)
+    K = np.asarray(frame_rgb, np.float32)
+    H, W = C.shape[1], C.shape[2]
+    t_c, t_w = np.float32(3.0 * delta_c), np.float32(delta_w)
+    Wg = np.asarray(weight, np.float32)
+    D = np.asarray(sdf_depth, np.float32)
+    mask = np.zeros((H, W), bool)
+    for j in range(H):
+        for i in range(W):
+            e = (np.float32(abs(C[0, j, i] - K[0, j, i])) + np.float32(abs(C[1, j, i] - K[1, j, i]))) + \
+                np.float32(abs(C[2, j, i] - K[2, j, i]))
+            mask[j, i] = D[j, i] > 0 and e > t_c and Wg[j, i] < t_w
+    return mask
+
+
+def _backproject(cam, i, j, d):
+    R = np.asarray(cam["R"], np.float64).reshape(3, 3)
+    t = np.asarray(cam["t"], np.float64).reshape(3)
+    xc = np.array([(i - cam["cx"]) / cam["fx"] * d, (j - cam["cy"]) / cam["fy"] * d, d])
+    return R.T @ (xc - t)
+
+
+def insert_gaussians(cam, render_rgb, frame_rgb, weight, sdf_depth, rand, delta_c=0.05, delta_w=4.0,
+                     fraction=0.25, radius=4, scale_cap=0.1, flat_ratio=0.1, opacity=0.5):
+    """New Gaussians for the sampled mask pixels (dict of [rows][n] float64 arrays) and
+    their pixel indices (row-major)."""
+    D = np.asarray(sdf_depth, np.float32)
+    H, W = D.shape
+    K = np.asarray(frame_rgb, np.float32)
+    mask = insertion_mask(render_rgb, frame_rgb, weight, sdf_depth, delta_c, delta_w)
+    take = mask & (np.asarray(rand, np.float32) < np.float32(fraction))
+    R = np.asarray(cam["R"], np.float64).reshape(3, 3)
+    center = -R.T @ np.asarray(cam["t"], np.float64).reshape(3)
+    V = np.zeros((H, W, 3))
+    for j in range(H):
+        for i in range(W):
+            if D[j, i] > 0:
+                V[j, i] = _backproject(cam, i, j, float(D[j, i]))
+    valid = D > 0
+    pix = [(j, i) for j in range(H) for i in range(W) if take[j, i]]
+    out = {"mean": [], "log_scale": [], "quat": [], "opacity_logit": [], "rgb": []}
+    for (j, i) in pix:
+        p = V[j, i]
+        if 0 < i < W - 1 and 0 < j < H - 1 and valid[j, i - 1] and valid[j, i + 1] and valid[j - 1, i] and valid[j + 1, i]:
+            n = np.cross(V[j, i + 1] - V[j, i - 1], V[j + 1, i] - V[j - 1, i])
+            nn = np.linalg.norm(n)
+            n = n / nn if nn > 0 else center - p
+        else:
+            n = center - p
+        n = n / np.linalg.norm(n)
+        if np.dot(n, center - p) < 0:
+            n = -n
+        cand = []
+        for jj in range(max(0, j - radius), min(H, j + radius + 1)):
+            for ii in range(max(0, i - radius), min(W, i + radius + 1)):
+                if (jj, ii) != (j, i) and mask[jj, ii]:
+                    cand.append((np.linalg.norm(V[jj, ii] - p), jj * W + ii))
+        cand.sort()
+        s1 = scale_cap if not cand else min(scale_cap, np.sqrt(np.mean([c[0] for c in cand[:3]])))
+        q = np.array([1.0 + n[2], -n[1], n[0], 0.0])
+        q = q / np.linalg.norm(q) if np.linalg.norm(q) > 1e-12 else np.array([0.0, 1.0, 0.0, 0.0])
+        out["mean"].append(p)
+        out["log_scale"].append(np.log([s1, s1, flat_ratio * s1]))
+        out["quat"].append(q)
+        out["opacity_logit"].append([np.log(opacity / (1.0 - opacity))])
+        out["rgb"].append(K[:, j, i].astype(np.float64))
+    rows = {"mean": 3, "log_scale": 3, "quat": 4, "opacity_logit": 1, "rgb": 3}
+    res = {k: np.array(v, np.float64).T.reshape(rows[k], len(pix)) if pix else np.zeros((rows[k], 0))
+           for k, v in out.items()}
+    return res, np.array([j * W + i for (j, i) in pix], np.int64)
