@@ -299,6 +299,50 @@ gps_status gps_removal_workspace_size(int32_t n_gaussians, size_t* out_bytes);
 gps_status gps_remove_gaussians(const gps_removal_cfg* cfg, const gps_gaussians* sets_in, gps_gaussians* sets_out,
                                 int32_t n_sets, int32_t* out_count, void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Gaussian insertion (Sec. 3.2.2, Eq. 6 and the paragraph after it; App. A)
+ * Mask: pixels with an SDF surface (D_t > 0) whose colour error is above delta_c
+ * and whose Gaussian weight W_G is below delta_W; the colour error is the mean
+ * of the three absolute channel differences, tested in binary32 as
+ * (|e0| + |e1|) + |e2| > 3 delta_c.  A mask pixel is taken when the caller's
+ * uniform number for it is below `fraction` (the 25 % sample).  Each taken
+ * pixel u gets a Gaussian at the SDF surface point V*(u) (its depth D_t
+ * back-projected), coloured C_k(u), opacity `opacity`, shaped as a disc whose
+ * short axis is the vertex-map normal N*(u) (normalised cross product of the
+ * central differences of V*, turned to face the camera; the direction to the
+ * camera where a neighbour has no surface): scales (s1, s1, flat_ratio s1),
+ * s1 = min(scale_cap, sqrt(mean distance to the three nearest mask vertices)),
+ * the nearest searched among the mask pixels of the (2 radius + 1)^2 window
+ * (ties by pixel index; none: s1 = scale_cap). */
+typedef struct gps_insert_cfg {
+    float delta_c;     /* 0.05 */
+    float delta_w;     /* 4 */
+    float fraction;    /* 0.25 */
+    int32_t radius;    /* 4 (at most 8) */
+    float scale_cap;   /* 0.1 */
+    float flat_ratio;  /* 0.1 */
+    float opacity;     /* 0.5 */
+} gps_insert_cfg;
+
+/* Fills `cfg` (host) with the paper's constants and a window radius of 4. */
+void gps_insert_cfg_default(gps_insert_cfg* cfg);
+
+/* Scratch bytes that gps_insert_gaussians needs for a width x height frame. */
+gps_status gps_insertion_workspace_size(int32_t width, int32_t height, size_t* out_bytes);
+
+/* New Gaussians for one frame.  Images (device, planar): render_rgb C* [3][H][W]
+ * and weight W_G [H][W] of the current Gaussians over the SDF image (sort-free
+ * forward), frame_rgb C_k [3][H][W], sdf_depth D_t [H][W] (0 = miss), rand
+ * [H][W] uniform numbers in [0, 1).  out: out->count = capacity, planar
+ * [rows][capacity] arrays; the taken pixels fill positions 0 .. in row-major
+ * pixel order, those past the capacity are dropped; out_pixel (optional,
+ * [capacity]) receives their pixel indices; *out_count (device int32) the
+ * number of taken pixels (possibly above the capacity).  ws:
+ * gps_insertion_workspace_size bytes, 256-byte aligned.  Three kernels. */
+gps_status gps_insert_gaussians(const gps_insert_cfg* cfg, const gps_camera* cam, const float* render_rgb,
+                                const float* frame_rgb, const float* weight, const float* sdf_depth, const float* rand,
+                                gps_gaussians* out, int32_t* out_pixel, int32_t* out_count, void* ws, size_t ws_bytes,
+                                void* stream);
+
 /* Reads the sticky status word of a workspace (synchronises `stream`). */
 gps_status gps_device_status(const void* ws, size_t ws_bytes, int32_t* out_status, void* stream);
 

@@ -408,6 +408,53 @@ gps_status gps_remove_gaussians(const gps_removal_cfg* cfg, const gps_gaussians*
                                    (hipStream_t)stream);
 }
 
+void gps_insert_cfg_default(gps_insert_cfg* cfg)
+{
+    if (!cfg) return;
+    cfg->delta_c = 0.05f;
+    cfg->delta_w = 4.0f;
+    cfg->fraction = 0.25f;
+    cfg->radius = 4;
+    cfg->scale_cap = 0.1f;
+    cfg->flat_ratio = 0.1f;
+    cfg->opacity = 0.5f;
+}
+
+static bool insert_frame_ok(int32_t W, int32_t H)
+{
+    return W > 0 && H > 0 && (int64_t)W * H <= (int64_t(1) << 30);
+}
+
+gps_status gps_insertion_workspace_size(int32_t width, int32_t height, size_t* out_bytes)
+{
+    if (!out_bytes || !insert_frame_ok(width, height)) return GPS_ERR_INVALID_ARG;
+    *out_bytes = insertion_workspace_bytes(width, height);
+    return GPS_OK;
+}
+
+gps_status gps_insert_gaussians(const gps_insert_cfg* cfg, const gps_camera* cam, const float* render_rgb,
+                                const float* frame_rgb, const float* weight, const float* sdf_depth, const float* rand,
+                                gps_gaussians* out, int32_t* out_pixel, int32_t* out_count, void* ws, size_t ws_bytes,
+                                void* stream)
+{
+    if (!cfg || !cam || !out || !cam_ok(*cam) || !insert_frame_ok(cam->width, cam->height)) return GPS_ERR_INVALID_ARG;
+    if (!(cfg->delta_c >= 0.0f) || !std::isfinite(cfg->delta_c) || !(cfg->delta_w > 0.0f) ||
+        !(cfg->fraction >= 0.0f && cfg->fraction <= 1.0f) || cfg->radius < 1 || cfg->radius > 8 ||
+        !(cfg->scale_cap > 0.0f) || !std::isfinite(cfg->scale_cap) || !(cfg->flat_ratio > 0.0f) ||
+        !(cfg->flat_ratio <= 1.0f) || !(cfg->opacity > 0.0f && cfg->opacity < 1.0f))
+        return GPS_ERR_INVALID_ARG;
+    if (!render_rgb || !frame_rgb || !weight || !sdf_depth || !rand || !out_count) return GPS_ERR_INVALID_ARG;
+    if (out->count < 0) return GPS_ERR_INVALID_ARG;
+    if (out->count > 0 && (!out->mean || !out->log_scale || !out->quat || !out->opacity_logit || !out->rgb))
+        return GPS_ERR_INVALID_ARG;
+    if (!ws || ((uintptr_t)ws & 255)) return GPS_ERR_INVALID_ARG;
+    if (ws_bytes < insertion_workspace_bytes(cam->width, cam->height)) return GPS_ERR_WORKSPACE_TOO_SMALL;
+    gps_status st = check_device();
+    if (st != GPS_OK) return st;
+    return launch_insert_gaussians(cfg, dev_cam(*cam), render_rgb, frame_rgb, weight, sdf_depth, rand, out, out_pixel,
+                                   out_count, static_cast<char*>(ws), (hipStream_t)stream);
+}
+
 gps_status gps_device_status(const void* ws, size_t ws_bytes, int32_t* out_status, void* stream)
 {
     if (!ws || ws_bytes < 1024 || !out_status) return GPS_ERR_INVALID_ARG;

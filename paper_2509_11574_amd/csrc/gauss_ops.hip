@@ -134,4 +134,246 @@ gps_status launch_remove_gaussians(const gps_removal_cfg* cfg, const gps_gaussia
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
 }
 
+// ------------------------------------------------------------------ insertion
+// Gaussian insertion (Sec. 3.2.2, Eq. 6; Appendix A).
+//   k_insert_flags  per pixel: mask (bit 0) and sample (bit 1) flags; per block
+//                   of 256 pixels, the number taken
+//   k_insert_scan   one block: block offsets, total taken -> out_count
+//   k_insert_init   per taken pixel: the new Gaussian at its row-major place
+struct InsertArgs {
+    DevCam cam;
+    const float* render_rgb;
+    const float* frame_rgb;
+    const float* weight;
+    const float* depth;
+    const float* rnd;
+    float* out[5];  // mean, log_scale, quat, opacity_logit, rgb: planar [rows][capacity]
+    int* out_pixel;
+    int* out_count;
+    int capacity, radius;
+    float t_c, t_w, t_frac, scale_cap, flat_ratio, logit_opacity;
+    unsigned int* flags;
+    unsigned int* blk_cnt;
+    unsigned int* blk_off;
+    unsigned int* total;
+};
+
+__global__ void __launch_bounds__(256) k_insert_flags(InsertArgs a)
+{
+    const int n = a.cam.W * a.cam.H;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    unsigned int f = 0u;
+    if (p < n) {
+        const size_t HW = (size_t)n;
+        const float e = (fabsf(a.render_rgb[p] - a.frame_rgb[p]) + fabsf(a.render_rgb[HW + p] - a.frame_rgb[HW + p])) +
+                        fabsf(a.render_rgb[2 * HW + p] - a.frame_rgb[2 * HW + p]);
+        const bool mask = a.depth[p] > 0.0f && e > a.t_c && a.weight[p] < a.t_w;
+        f = (mask ? 1u : 0u) | ((mask && a.rnd[p] < a.t_frac) ? 2u : 0u);
+        a.flags[p] = f;
+    }
+    unsigned int tot;
+    block_excl_scan<256>((f >> 1) & 1u, &tot);
+    if (threadIdx.x == 0) a.blk_cnt[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024) k_insert_scan(InsertArgs a, int nblk)
+{
+    __shared__ unsigned int wsum[16];
+    __shared__ unsigned int carry_s;
+    if (threadIdx.x == 0) carry_s = 0u;
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    for (int base = 0; base < nblk; base += 1024) {
+        const int i = base + threadIdx.x;
+        const unsigned int c = i < nblk ? a.blk_cnt[i] : 0u;
+        unsigned int x = c;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wid] = x;
+        __syncthreads();
+        unsigned int before = 0u, total = 0u;
+        for (int k = 0; k < 16; ++k) {
+            if (k < wid) before += wsum[k];
+            total += wsum[k];
+        }
+        const unsigned int carry = carry_s;
+        if (i < nblk) a.blk_off[i] = carry + before + x - c;
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s = carry + total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        *a.total = carry_s;
+        if (a.out_count) *a.out_count = (int)carry_s;
+    }
+}
+
+// Camera-frame point of pixel (i, j) at depth d.
+__device__ __forceinline__ void cam_point(const DevCam& c, int i, int j, float d, float x[3])
+{
+    x[0] = ((float)i - c.cx) / c.fx * d;
+    x[1] = ((float)j - c.cy) / c.fy * d;
+    x[2] = d;
+}
+
+// The normal and the neighbour distances are rotation- and translation-free, so
+// they are formed from camera-frame differences (no world-coordinate
+// cancellation in binary32); only the mean and the normal are rotated to the
+// world frame, x_w = R^T (x_c - t).
+__global__ void __launch_bounds__(256) k_insert_init(InsertArgs a)
+{
+    const int W = a.cam.W, H = a.cam.H, n = W * H;
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const bool take = p < n && (a.flags[p] & 2u);
+    unsigned int tot;
+    const unsigned int excl = block_excl_scan<256>(take ? 1u : 0u, &tot);
+    if (!take) return;
+    const unsigned int pos = a.blk_off[blockIdx.x] + excl;
+    if (pos >= (unsigned int)a.capacity) return;
+    const int i = p % W, j = p / W;
+    const DevCam& c = a.cam;
+    float X[3];
+    cam_point(c, i, j, a.depth[p], X);
+    // normal: central differences of the vertex map, facing the camera (at -X)
+    float nc[3] = {-X[0], -X[1], -X[2]};
+    if (i > 0 && i < W - 1 && j > 0 && j < H - 1 && a.depth[p - 1] > 0.0f && a.depth[p + 1] > 0.0f &&
+        a.depth[p - W] > 0.0f && a.depth[p + W] > 0.0f) {
+        float xm[3], xp[3], ym[3], yp[3];
+        cam_point(c, i - 1, j, a.depth[p - 1], xm);
+        cam_point(c, i + 1, j, a.depth[p + 1], xp);
+        cam_point(c, i, j - 1, a.depth[p - W], ym);
+        cam_point(c, i, j + 1, a.depth[p + W], yp);
+        const float dx[3] = {xp[0] - xm[0], xp[1] - xm[1], xp[2] - xm[2]};
+        const float dy[3] = {yp[0] - ym[0], yp[1] - ym[1], yp[2] - ym[2]};
+        const float cr[3] = {dx[1] * dy[2] - dx[2] * dy[1], dx[2] * dy[0] - dx[0] * dy[2], dx[0] * dy[1] - dx[1] * dy[0]};
+        if (cr[0] * cr[0] + cr[1] * cr[1] + cr[2] * cr[2] > 0.0f) {
+            nc[0] = cr[0];
+            nc[1] = cr[1];
+            nc[2] = cr[2];
+        }
+    }
+    const float inl = 1.0f / sqrtf(nc[0] * nc[0] + nc[1] * nc[1] + nc[2] * nc[2]);
+    const float sg = (nc[0] * X[0] + nc[1] * X[1] + nc[2] * X[2]) > 0.0f ? -inl : inl;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) nc[k] *= sg;
+    float nv[3], V[3];
+    const float xt[3] = {X[0] - c.t[0], X[1] - c.t[1], X[2] - c.t[2]};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        nv[k] = c.R[k] * nc[0] + c.R[3 + k] * nc[1] + c.R[6 + k] * nc[2];
+        V[k] = c.R[k] * xt[0] + c.R[3 + k] * xt[1] + c.R[6 + k] * xt[2];
+    }
+    // the three nearest mask vertices of the window
+    float best[3] = {INFINITY, INFINITY, INFINITY};
+    int nb = 0;
+    const int j0 = max(0, j - a.radius), j1 = min(H - 1, j + a.radius);
+    const int i0 = max(0, i - a.radius), i1 = min(W - 1, i + a.radius);
+    for (int jj = j0; jj <= j1; ++jj)
+        for (int ii = i0; ii <= i1; ++ii) {
+            const int q = jj * W + ii;
+            if (q == p || !(a.flags[q] & 1u)) continue;
+            float U[3];
+            cam_point(c, ii, jj, a.depth[q], U);
+            const float d = sqrtf((U[0] - X[0]) * (U[0] - X[0]) + (U[1] - X[1]) * (U[1] - X[1]) +
+                                  (U[2] - X[2]) * (U[2] - X[2]));
+            ++nb;
+            if (d < best[2]) {
+                if (d < best[1]) {
+                    best[2] = best[1];
+                    if (d < best[0]) {
+                        best[1] = best[0];
+                        best[0] = d;
+                    } else {
+                        best[1] = d;
+                    }
+                } else {
+                    best[2] = d;
+                }
+            }
+        }
+    float s1 = a.scale_cap;
+    if (nb > 0) {
+        const int m = nb < 3 ? nb : 3;
+        float sum = 0.0f;
+        for (int k = 0; k < m; ++k) sum += best[k];
+        s1 = fminf(a.scale_cap, sqrtf(sum / (float)m));
+    }
+    // shortest-arc rotation taking the local z axis onto the normal; for a normal
+    // near -z the scalar part 1 + n_z is formed as (n_x^2 + n_y^2) / (1 - n_z), its
+    // value on the unit sphere, so that the rounding of the normalisation cannot
+    // leave a spurious 1 + n_z against vanishing n_x, n_y
+    const float nxy2 = nv[0] * nv[0] + nv[1] * nv[1];
+    float q[4] = {nv[2] < 0.0f ? nxy2 / (1.0f - nv[2]) : 1.0f + nv[2], -nv[1], nv[0], 0.0f};
+    const float qn = sqrtf(q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+    if (qn > 0.0f) {
+        q[0] /= qn;
+        q[1] /= qn;
+        q[2] /= qn;
+    } else {
+        q[0] = 0.0f;
+        q[1] = 1.0f;
+        q[2] = 0.0f;
+    }
+    const size_t C = (size_t)a.capacity, HW = (size_t)n;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.out[0][k * C + pos] = V[k];
+    a.out[1][pos] = logf(s1);
+    a.out[1][C + pos] = logf(s1);
+    a.out[1][2 * C + pos] = logf(a.flat_ratio * s1);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) a.out[2][k * C + pos] = q[k];
+    a.out[3][pos] = a.logit_opacity;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) a.out[4][k * C + pos] = a.frame_rgb[k * HW + p];
+    if (a.out_pixel) a.out_pixel[pos] = p;
+}
+
+size_t insertion_workspace_bytes(int W, int H)
+{
+    const size_t n = (size_t)W * H, nblk = n > 0 ? (n + 255) / 256 : 1;
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    return al(4 * n) + 2 * al(4 * nblk) + 256;
+}
+
+gps_status launch_insert_gaussians(const gps_insert_cfg* cfg, const DevCam& cam, const float* render_rgb,
+                                   const float* frame_rgb, const float* weight, const float* sdf_depth,
+                                   const float* rnd, gps_gaussians* out, int* out_pixel, int* out_count, char* ws,
+                                   hipStream_t s)
+{
+    InsertArgs a;
+    a.cam = cam;
+    a.render_rgb = render_rgb;
+    a.frame_rgb = frame_rgb;
+    a.weight = weight;
+    a.depth = sdf_depth;
+    a.rnd = rnd;
+    a.out[0] = out->mean, a.out[1] = out->log_scale, a.out[2] = out->quat, a.out[3] = out->opacity_logit,
+    a.out[4] = out->rgb;
+    a.out_pixel = out_pixel;
+    a.out_count = out_count;
+    a.capacity = out->count;
+    a.radius = cfg->radius;
+    a.t_c = (float)(3.0 * (double)cfg->delta_c);
+    a.t_w = cfg->delta_w;
+    a.t_frac = cfg->fraction;
+    a.scale_cap = cfg->scale_cap;
+    a.flat_ratio = cfg->flat_ratio;
+    a.logit_opacity = (float)std::log((double)cfg->opacity / (1.0 - (double)cfg->opacity));
+    const size_t n = (size_t)cam.W * cam.H;
+    const int nblk = (int)((n + 255) / 256);
+    auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t nb = nblk > 0 ? (size_t)nblk : 1;
+    a.flags = reinterpret_cast<unsigned int*>(ws);
+    a.blk_cnt = reinterpret_cast<unsigned int*>(ws + al(4 * n));
+    a.blk_off = reinterpret_cast<unsigned int*>(ws + al(4 * n) + al(4 * nb));
+    a.total = reinterpret_cast<unsigned int*>(ws + al(4 * n) + 2 * al(4 * nb));
+    if (nblk > 0) GPS_LAUNCH(K_INSERT, s, k_insert_flags, dim3(nblk), dim3(256), 0, s, a);
+    GPS_LAUNCH(K_INSERT, s, k_insert_scan, dim3(1), dim3(1024), 0, s, a, nblk);
+    if (nblk > 0) GPS_LAUNCH(K_INSERT, s, k_insert_init, dim3(nblk), dim3(256), 0, s, a);
+    return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
+}
+
 }  // namespace gps

@@ -28,6 +28,20 @@ struct DevCam {
     int W, H;
 };
 
+inline DevCam dev_cam(const gps_camera& c)
+{
+    DevCam d;
+    d.fx = c.fx;
+    d.fy = c.fy;
+    d.cx = c.cx;
+    d.cy = c.cy;
+    for (int k = 0; k < 9; ++k) d.R[k] = c.R[k];
+    for (int k = 0; k < 3; ++k) d.t[k] = c.t[k];
+    d.W = c.width;
+    d.H = c.height;
+    return d;
+}
+
 struct DevView {
     DevCam cam;
     int tiles_x, tiles_y, tile_base;

@@ -31,5 +31,10 @@ gps_status launch_ws_reset(char* ws, hipStream_t s);
 size_t removal_workspace_bytes(int M);
 gps_status launch_remove_gaussians(const gps_removal_cfg* cfg, const gps_gaussians* sets_in, gps_gaussians* sets_out,
                                    int n_sets, int* out_count, char* ws, hipStream_t s);
+size_t insertion_workspace_bytes(int W, int H);
+gps_status launch_insert_gaussians(const gps_insert_cfg* cfg, const DevCam& cam, const float* render_rgb,
+                                   const float* frame_rgb, const float* weight, const float* sdf_depth,
+                                   const float* rnd, gps_gaussians* out, int* out_pixel, int* out_count, char* ws,
+                                   hipStream_t s);
 
 }  // namespace gps

@@ -29,6 +29,7 @@ enum KernelId {
     K_WS_RESET,
     K_UPLOAD,
     K_REMOVE,
+    K_INSERT,
     K_COUNT
 };
 

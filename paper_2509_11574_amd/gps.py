@@ -66,6 +66,12 @@ class RemovalCfgS(ctypes.Structure):
     _fields_ = [("min_opacity", ctypes.c_float), ("max_scale", ctypes.c_float), ("min_scale", ctypes.c_float)]
 
 
+class InsertCfgS(ctypes.Structure):
+    _fields_ = [("delta_c", ctypes.c_float), ("delta_w", ctypes.c_float), ("fraction", ctypes.c_float),
+                ("radius", ctypes.c_int32), ("scale_cap", ctypes.c_float), ("flat_ratio", ctypes.c_float),
+                ("opacity", ctypes.c_float)]
+
+
 class AdamGroupS(ctypes.Structure):
     _fields_ = [("param", ctypes.c_void_p), ("grad", ctypes.c_void_p), ("m", ctypes.c_void_p),
                 ("v", ctypes.c_void_p), ("n", ctypes.c_int64), ("lr", ctypes.c_float)]
@@ -86,7 +92,8 @@ EXPORTS = ["gps_abi_version", "gps_status_string", "gps_render_cfg_default", "gp
            "gps_workspace_reset", "gps_fuse", "gps_raycast", "gps_render_fwd", "gps_render_bwd",
            "gps_adam_step", "gps_device_status", "gps_read_stats", "gps_profile_start", "gps_profile_stop",
            "gps_profile_read", "gps_views_upload", "gps_removal_cfg_default", "gps_removal_workspace_size",
-           "gps_remove_gaussians"]
+           "gps_remove_gaussians", "gps_insert_cfg_default", "gps_insertion_workspace_size",
+           "gps_insert_gaussians"]
 
 _lib = None
 
@@ -122,8 +129,13 @@ def lib():
         L.gps_removal_cfg_default.restype = None
         L.gps_removal_workspace_size.argtypes = [I32, ctypes.POINTER(ctypes.c_size_t)]
         L.gps_remove_gaussians.argtypes = [P, P, P, I32, P, P, ctypes.c_size_t, P]
+        L.gps_insert_cfg_default.argtypes = [P]
+        L.gps_insert_cfg_default.restype = None
+        L.gps_insertion_workspace_size.argtypes = [I32, I32, ctypes.POINTER(ctypes.c_size_t)]
+        L.gps_insert_gaussians.argtypes = [P, P, P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P]
         for n in EXPORTS:
-            if n not in ("gps_render_cfg_default", "gps_status_string", "gps_abi_version", "gps_removal_cfg_default"):
+            if n not in ("gps_render_cfg_default", "gps_status_string", "gps_abi_version", "gps_removal_cfg_default",
+                         "gps_insert_cfg_default"):
                 getattr(L, n).restype = I32
         _lib = L
     return _lib
@@ -575,3 +587,35 @@ def remove_gaussians(params: dict, companions=(), min_opacity=0.005, max_scale=0
                else o[k].reshape(-1)[:n] for k in GAUSS_KEYS} for o in outs]
     return shaped[0], shaped[1:], n
 
+
+def insert_gaussians(cam, render_rgb, frame_rgb, weight, sdf_depth, rand, capacity=None, delta_c=0.05, delta_w=4.0,
+                     fraction=0.25, radius=4, scale_cap=0.1, flat_ratio=0.1, opacity=0.5, stream=None):
+    """Gaussian insertion of Eq. 6 and App. A (gps_insert_gaussians): the new Gaussians
+    (planar [rows][n] tensors, row-major pixel order), their pixel indices and the
+    number of sampled pixels n_taken (the output keeps min(n_taken, capacity));
+    `capacity` defaults to every pixel.  Reads the count back (synchronises)."""
+    c = camera(cam)
+    W, H = c.width, c.height
+    dev = frame_rgb.device
+    cap = W * H if capacity is None else int(capacity)
+    out = {k: torch.empty(GAUSS_ROWS[k], max(cap, 1), dtype=torch.float32, device=dev) for k in GAUSS_KEYS}
+    pix = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    g = GaussiansS()
+    g.count = cap
+    for k in GAUSS_KEYS:
+        setattr(g, k, ctypes.c_void_p(out[k].data_ptr()))
+    nbytes = ctypes.c_size_t(0)
+    _check(lib().gps_insertion_workspace_size(W, H, ctypes.byref(nbytes)), "gps_insertion_workspace_size")
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
+    count = torch.zeros(1, dtype=torch.int32, device=dev)
+    cfg = InsertCfgS(delta_c, delta_w, fraction, radius, scale_cap, flat_ratio, opacity)
+    _check(lib().gps_insert_gaussians(ctypes.byref(cfg), ctypes.byref(c), _ptr(render_rgb, "render_rgb", 3 * W * H),
+                                      _ptr(frame_rgb, "frame_rgb", 3 * W * H), _ptr(weight, "weight", W * H),
+                                      _ptr(sdf_depth, "sdf_depth", W * H), _ptr(rand, "rand", W * H),
+                                      ctypes.byref(g), ctypes.c_void_p(pix.data_ptr()),
+                                      ctypes.c_void_p(count.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                                      nbytes.value, _stream(stream)), "gps_insert_gaussians")
+    n_taken = int(count.item())
+    n = min(n_taken, cap)
+    res = {k: out[k][:, :n] if GAUSS_ROWS[k] > 1 else out[k].reshape(-1)[:n] for k in GAUSS_KEYS}
+    return res, pix[:n], n_taken

@@ -372,3 +372,22 @@ def workload_room_frames(n: int = 256, width: int = 1280, height: int = 720, fra
 # Views of the mixed-resolution keyframe batch: frame index and resolution.
 STANDARD_VIEWS = [(0, 1280, 720), (12, 1280, 720), (25, 1280, 720), (37, 640, 480), (50, 640, 480),
                   (62, 640, 480), (75, 320, 240), (87, 320, 240)]
+
+
+def insertion_inputs(scene: Scene, cam: Camera, seed: int = 5, hole_fraction: float = 0.02,
+                     noise_sigma_per_m2: float = 0.002, device="cpu"):
+    """Inputs of one Gaussian-insertion call for a frame of `scene` seen from `cam`: the
+    frame's depth (with noise and seeded holes, 0 = no surface) and colour, a stand-in for
+    the current map's rendering (the frame colour plus seeded per-pixel noise of sigma 0.05
+    and, on a quarter of 8x8 blocks, an offset of 0.15), a Gaussian weight uniform in
+    [0, 8) and the uniform draw in [0, 1).  All float32 numpy arrays, planar."""
+    depth, rgb = render_frame(scene, cam, noise_sigma_per_m2=noise_sigma_per_m2, device=device)
+    H, W = depth.shape
+    rng = np.random.Generator(np.random.PCG64(seed))
+    depth = np.where(rng.uniform(size=(H, W)) < hole_fraction, 0.0, depth).astype(np.float32)
+    blocks = rng.uniform(size=((H + 7) // 8, (W + 7) // 8)) < 0.25
+    offset = np.kron(blocks, np.ones((8, 8)))[:H, :W] * 0.15
+    render = (rgb + rng.normal(0.0, 0.05, size=rgb.shape) + offset[None]).astype(np.float32)
+    weight = rng.uniform(0.0, 8.0, size=(H, W)).astype(np.float32)
+    draw = rng.uniform(size=(H, W)).astype(np.float32)
+    return tuple(np.ascontiguousarray(a, np.float32) for a in (render, rgb, weight, depth, draw))

@@ -150,3 +150,36 @@ def test_removal_defaults_and_argument_checks(P):
     assert L.gps_remove_gaussians(ctypes.byref(bad), sets, outs, 1, None, None, 0, None) == -1
     sets[0].count = 10                                                                        # null arrays
     assert L.gps_remove_gaussians(ctypes.byref(c), sets, outs, 1, None, None, 0, None) == -1
+
+
+def test_insertion_defaults_and_argument_checks(P):
+    """Gaussian insertion (Eq. 6, App. A): the defaults are the paper's constants;
+    bad arguments are refused before anything is launched."""
+    L = P.lib()
+    c = P.gps.InsertCfgS()
+    L.gps_insert_cfg_default(ctypes.byref(c))
+    assert (c.delta_c, c.delta_w, c.fraction, c.radius, c.scale_cap, c.flat_ratio, c.opacity) == pytest.approx(
+        (0.05, 4.0, 0.25, 4, 0.1, 0.1, 0.5))
+    n = ctypes.c_size_t(0)
+    assert L.gps_insertion_workspace_size(64, 48, ctypes.byref(n)) == 0 and n.value >= 4 * 64 * 48
+    assert L.gps_insertion_workspace_size(0, 48, ctypes.byref(n)) == -1
+    assert L.gps_insertion_workspace_size(1 << 16, 1 << 16, ctypes.byref(n)) == -1    # beyond 2^30 pixels
+    cam = P.camera(_cam())
+    g = P.gps.GaussiansS()
+    buf = (ctypes.c_float * 4)()
+    img = ctypes.cast(buf, ctypes.c_void_p)
+    cnt = ctypes.c_int32(0)
+
+    def call(cfg, g=g, ws_bytes=1 << 20):
+        return L.gps_insert_gaussians(ctypes.byref(cfg), ctypes.byref(cam), img, img, img, img, img, ctypes.byref(g),
+                                      None, ctypes.byref(cnt), None, ws_bytes, None)
+    assert call(c) == -1                                                   # no workspace
+    for field, value in (("radius", 0), ("radius", 9), ("fraction", 1.5), ("opacity", 1.0), ("scale_cap", 0.0),
+                         ("delta_w", 0.0), ("delta_c", float("nan"))):
+        bad = P.gps.InsertCfgS.from_buffer_copy(c)
+        setattr(bad, field, value)
+        assert call(bad) == -1, field
+    g.count = 10                                                           # capacity without arrays
+    assert call(c) == -1
+    assert L.gps_insert_gaussians(ctypes.byref(c), ctypes.byref(cam), None, img, img, img, img, ctypes.byref(g),
+                                  None, ctypes.byref(cnt), None, 0, None) == -1
