@@ -87,7 +87,9 @@ def parse():
     ap.add_argument("--volume", type=int, default=256)
     ap.add_argument("--tile", type=str, default="auto",
                     help="tile_w x tile_h x batch x pixels_per_lane, or 'auto' (autotuned on the first frame)")
-    ap.add_argument("--graph", type=int, default=1, help="replay the iteration as a captured HIP graph")
+    ap.add_argument("--graph", type=int, default=0,
+                    help="time graph replay of the iteration (default: kernel-by-kernel launches, which are "
+                         "faster on this stack; the other mode is timed on the following frames)")
     ap.add_argument("--mode", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -97,6 +99,8 @@ def parse():
                     help="also time the 8-keyframe batch (one 8-view iteration) against 8 single-view iterations")
     ap.add_argument("--large-frames", type=int, default=6,
                     help="frames timed on the 512^3 / 1M-Gaussian / 4-keyframe workload (0 skips it)")
+    ap.add_argument("--maintenance", type=int, default=1,
+                    help="time Gaussian removal (Eq. 8) and insertion (Eq. 6) once the timed frames are done")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB copied (device to device, 3 times) before the workload, so that a counter run can "
                          "scale FETCH_SIZE / WRITE_SIZE by a copy of known size")
@@ -120,7 +124,7 @@ def main():
     torch.cuda.set_device(0)
     W_img, H_img = (int(x) for x in args.res.split("x"))
     K, Wu, M = args.steps, args.warmup, args.gaussians
-    n_frames = Wu + 3 * K  # warmup, timed pass (graph), eager timed pass, profiled pass
+    n_frames = Wu + 3 * K  # warmup, timed pass, the other launch mode, profiled pass
 
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 4
@@ -181,11 +185,17 @@ def main():
                           eps_cull=scene.voxel)
     ws = P.Workspace(cfg, M, [cam0], device=dev)
 
+    from dataclasses import replace
+    cfg_pre = replace(cfg, views_preset=True)
+
     def frame_step_eager(k):
+        # the view table (and its tile depth maxima) is uploaded once per frame; the
+        # iterations read it from the workspace, as the captured graph does
         view = frame_prep(k)
+        P.gps.views_upload(cfg, params, [view], ws)
         for _ in range(ITERS_PER_FRAME):
-            P.render_fwd(cfg, params, [view], ws, out_loss=loss)
-            P.render_bwd(cfg, params, [view], ws, grads, dpose)
+            P.render_fwd(cfg_pre, params, [view], ws, out_loss=loss)
+            P.render_bwd(cfg_pre, params, [view], ws, grads, dpose)
             opt.step(grads)
         return view
 
@@ -236,17 +246,23 @@ def main():
     pct = lambda q: per_frame[min(K - 1, int(round(q * (K - 1))))]
     frame_ms_pct = {"p10": round(pct(0.1), 4), "p50": round(pct(0.5), 4), "p90": round(pct(0.9), 4)}
 
-    # ------------------------------------- the same frames, eager launches
-    eager = None
+    # ------------------------- the next frames in the other launch mode
     if args.graph:
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for k in range(Wu + K, Wu + 2 * K):
-            frame_step_eager(k)
-        torch.cuda.synchronize()
-        te = time.perf_counter() - t1
-        eager = {"ms_per_frame": round(1000.0 * te / K, 4), "iters_per_s": round(ITERS_PER_FRAME * K / te, 1),
-                 "frames": "the %d frames after the timed ones, launched without the graph" % K}
+        alt_step, alt_mode = frame_step_eager, "eager"
+    else:
+        from paper_2509_11574_amd.graph import IterationGraph
+        graph = IterationGraph(cfg, params, [last_view], ws, grads, opt, loss, dpose)
+        alt_step, alt_mode = frame_step_graph, "graph"
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for k in range(Wu + K, Wu + 2 * K):
+        alt_step(k)
+    torch.cuda.synchronize()
+    te = time.perf_counter() - t1
+    alt = {"launch": alt_mode, "ms_per_frame": round(1000.0 * te / K, 4),
+           "iters_per_s": round(ITERS_PER_FRAME * K / te, 1),
+           "frames": "the %d frames after the timed ones, each iteration %s" %
+                     (K, "launched kernel by kernel" if alt_mode == "eager" else "replayed as one captured HIP graph")}
     log(f"timed {K} frames: {ms_per_frame:.3f} ms/frame (events {ms_event / K:.3f}), {iters_per_s:.1f} iters/s, "
         f"loss {first_loss:.5f} -> {last_loss:.6f}, instances {st1['n_instances']}")
 
@@ -306,6 +322,9 @@ def main():
     batched = bench_batched(P, synth, dev, cfg, reps=20) if args.batched else None
     large = bench_large(P, synth, dev, cfg, args.large_frames) if args.large_frames > 0 else None
 
+    # -------------------------------- map maintenance: removal and insertion
+    maint = bench_maintenance(P, synth, scene, cams[Wu], params, opt) if args.maintenance else None
+
     # ------------------------------- reference implementation on the host
     cpu = None
     if not args.no_cpu_baseline:
@@ -327,10 +346,11 @@ def main():
            "loss_first_last": [round(first_loss, 6), round(last_loss, 6)],
            "roofline": roofline,
            "frame_ms_p10_p50_p90": frame_ms_pct,
-           "eager": eager,
+           "other_launch_mode": alt,
            "sorted_vs_sort_free": modes,
            "batched_keyframes": batched,
            "large_map": large,
+           "map_maintenance": maint,
            "kernels_ms_per_frame": {n: round(v[1] / K, 4) for n, v in sorted(kernels.items(), key=lambda x: -x[1][1])},
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
@@ -392,6 +412,42 @@ def bench_modes(P, cfg, params, view, M, cam0, reps=40):
     out["note"] = ("median over %d calls, eager launches; the paper's Table 7 (RTX 4090, its own scenes): "
                    "with sort 0.97 / 1.87 ms, sort-free 0.87 / 1.51 ms (forward / backward)" % reps)
     return out
+
+
+def bench_maintenance(P, synth, scene, cam, params, opt, reps=20):
+    """Map maintenance of Sec. 3.2.2, kernel time per call (HIP events around each
+    launch): removal (Eq. 8) over the trained Gaussians with their two Adam moment
+    sets as companions (3 sets, out of place), and insertion (Eq. 6, App. A) on one
+    frame of the room with the seeded insertion inputs.  Algorithmic bytes: removal
+    reads the 16 B that decide each Gaussian, all 56 B rows of every set and writes
+    the kept rows; insertion reads 36 B per pixel and writes 60 B per new Gaussian
+    (its rows and pixel index)."""
+    import numpy as np
+    import torch
+    dev = params["mean"].device
+    M = int(params["opacity_logit"].numel())
+    imgs = [torch.as_tensor(np.ascontiguousarray(a)).to(dev) for a in synth.insertion_inputs(scene, cam, device=dev)]
+    cd = cam.as_dict()
+    for _ in range(2):
+        P.remove_gaussians(params, [opt.m, opt.v])
+        P.insert_gaussians(cd, *imgs)
+    torch.cuda.synchronize()
+    P.gps.profile_start()
+    for _ in range(reps):
+        _, _, kept = P.remove_gaussians(params, [opt.m, opt.v])
+        _, new, n_taken = P.insert_gaussians(cd, *imgs)
+    torch.cuda.synchronize()
+    P.gps.profile_stop()
+    kt = P.gps.profile_read()
+    rem_ms, ins_ms = kt["remove"][1] / reps, kt["insert"][1] / reps
+    px = cam.width * cam.height
+    rem_bytes = 16 * M + 3 * 56 * (M + kept)
+    ins_bytes = 36 * px + 60 * int(new.numel())
+    return {"removal": {"gaussians": M, "kept": kept, "sets": 3, "ms_per_call": round(rem_ms, 4),
+                        "algorithmic_bytes": rem_bytes, "gbs": round(rem_bytes / (rem_ms / 1e3) / 1e9, 1)},
+            "insertion": {"pixels": px, "new": n_taken, "ms_per_call": round(ins_ms, 4),
+                          "algorithmic_bytes": ins_bytes, "gbs": round(ins_bytes / (ins_ms / 1e3) / 1e9, 1)},
+            "launches_per_call": 3}
 
 
 def bench_batched(P, synth, dev, cfg, reps=20, n_gauss=300_000):
