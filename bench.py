@@ -88,8 +88,8 @@ def parse():
     ap.add_argument("--tile", type=str, default="auto",
                     help="tile_w x tile_h x batch x pixels_per_lane, or 'auto' (autotuned on the first frame)")
     ap.add_argument("--graph", type=int, default=0,
-                    help="time graph replay of the iteration (default: kernel-by-kernel launches, which are "
-                         "faster on this stack; the other mode is timed on the following frames)")
+                    help="time graph replay of the iteration (default: kernel-by-kernel launches with the view "
+                         "table uploaded once per frame); the other mode is timed on the same frames afterwards")
     ap.add_argument("--mode", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -101,6 +101,8 @@ def parse():
                     help="frames timed on the 512^3 / 1M-Gaussian / 4-keyframe workload (0 skips it)")
     ap.add_argument("--maintenance", type=int, default=1,
                     help="time Gaussian removal (Eq. 8) and insertion (Eq. 6) once the timed frames are done")
+    ap.add_argument("--tracking", type=int, default=1,
+                    help="time ICP tracking (Eq. 5) of one frame against the previous frame's raycast")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB copied (device to device, 3 times) before the workload, so that a counter run can "
                          "scale FETCH_SIZE / WRITE_SIZE by a copy of known size")
@@ -124,7 +126,10 @@ def main():
     torch.cuda.set_device(0)
     W_img, H_img = (int(x) for x in args.res.split("x"))
     K, Wu, M = args.steps, args.warmup, args.gaussians
-    n_frames = Wu + 3 * K  # warmup, timed pass, the other launch mode, profiled pass
+    # warm-up frames, then K frames that the timed pass, the pass in the other launch mode and
+    # the pass with per-kernel events each process in full (fusion, raycast, iterations),
+    # then one frame that is tracked against the raycast of the last one
+    n_frames = Wu + K + 1
 
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 4
@@ -255,13 +260,13 @@ def main():
         alt_step, alt_mode = frame_step_graph, "graph"
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    for k in range(Wu + K, Wu + 2 * K):
+    for k in range(Wu, Wu + K):
         alt_step(k)
     torch.cuda.synchronize()
     te = time.perf_counter() - t1
     alt = {"launch": alt_mode, "ms_per_frame": round(1000.0 * te / K, 4),
            "iters_per_s": round(ITERS_PER_FRAME * K / te, 1),
-           "frames": "the %d frames after the timed ones, each iteration %s" %
+           "frames": "the same %d frames again, each iteration %s" %
                      (K, "launched kernel by kernel" if alt_mode == "eager" else "replayed as one captured HIP graph")}
     log(f"timed {K} frames: {ms_per_frame:.3f} ms/frame (events {ms_event / K:.3f}), {iters_per_s:.1f} iters/s, "
         f"loss {first_loss:.5f} -> {last_loss:.6f}, instances {st1['n_instances']}")
@@ -271,7 +276,7 @@ def main():
     if not args.no_profile:
         stp0 = ws.stats()
         P.gps.profile_start()
-        for k in range(Wu + 2 * K, Wu + 3 * K):  # the same kernels, launched eagerly so events bracket each
+        for k in range(Wu, Wu + K):  # the same frames, launched eagerly so events bracket each kernel
             frame_step_eager(k)
         torch.cuda.synchronize()
         P.gps.profile_stop()
@@ -325,6 +330,13 @@ def main():
     # -------------------------------- map maintenance: removal and insertion
     maint = bench_maintenance(P, synth, scene, cams[Wu], params, opt) if args.maintenance else None
 
+    # ------------- camera tracking of the next frame against the last raycast
+    tracking = None
+    if args.tracking:
+        kl = Wu + K - 1
+        frame_prep(kl)  # base_depth: the SDF raycast of the last frame
+        tracking = bench_tracking(P, cams[kl].as_dict(), base_depth, cams[kl + 1].as_dict(), frames[kl + 1][0])
+
     # ------------------------------- reference implementation on the host
     cpu = None
     if not args.no_cpu_baseline:
@@ -351,6 +363,7 @@ def main():
            "batched_keyframes": batched,
            "large_map": large,
            "map_maintenance": maint,
+           "tracking": tracking,
            "kernels_ms_per_frame": {n: round(v[1] / K, 4) for n, v in sorted(kernels.items(), key=lambda x: -x[1][1])},
            "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
@@ -448,6 +461,46 @@ def bench_maintenance(P, synth, scene, cam, params, opt, reps=20):
             "insertion": {"pixels": px, "new": n_taken, "ms_per_call": round(ins_ms, 4),
                           "algorithmic_bytes": ins_bytes, "gbs": round(ins_bytes / (ins_ms / 1e3) / 1e9, 1)},
             "launches_per_call": 3}
+
+
+def bench_tracking(P, prev_cam, prev_depth, cur_cam, cur_depth, reps=10):
+    """Coarse-to-fine ICP (Eq. 5) of one frame against the SDF raycast of the frame
+    before it: three levels (4, 4 and 6 Gauss-Newton steps, coarsest first), the depth
+    hierarchy built inside each run; kernel time per tracked frame from HIP events
+    around each launch, and the pose error against the frame's true pose."""
+    import numpy as np
+    import torch
+    dev = cur_depth.device
+    pose0 = P.pose_tensor(prev_cam, dev)
+    pose = pose0.clone()
+    ws = P.gps.IcpWorkspace(cur_cam["width"], cur_cam["height"], device=dev)
+    P.icp_track(prev_cam, prev_depth, cur_cam, cur_depth, pose, ws=ws)
+    torch.cuda.synchronize()
+    P.gps.profile_start()
+    for _ in range(reps):
+        pose.copy_(pose0)
+        P.icp_track(prev_cam, prev_depth, cur_cam, cur_depth, pose, ws=ws)
+    torch.cuda.synchronize()
+    P.gps.profile_stop()
+    kt = P.gps.profile_read()
+    launches, total = kt["icp"]
+    p = pose.cpu().numpy().astype(np.float64)
+    R, t = p[:9].reshape(3, 3), p[9:]
+    RB, tB = np.asarray(cur_cam["R"], np.float64), np.asarray(cur_cam["t"], np.float64)
+    R0 = np.asarray(prev_cam["R"], np.float64)
+    t0 = np.asarray(prev_cam["t"], np.float64)
+    def err(R_, t_):
+        M = R_ @ RB.T
+        s = 0.5 * np.linalg.norm([M[2, 1] - M[1, 2], M[0, 2] - M[2, 0], M[1, 0] - M[0, 1]])
+        return float(np.linalg.norm(-R_.T @ t_ + RB.T @ tB)), float(np.arctan2(s, 0.5 * (np.trace(M) - 1)))
+    e0, e1 = err(R0, t0), err(R, t)
+    pairs = int(ws.sys[28].item())
+    return {"ms_per_frame": round(total / reps, 4), "launches_per_frame": launches // reps,
+            "levels": "%dx%d, %dx%d, %dx%d" % (cur_cam["width"] // 4, cur_cam["height"] // 4, cur_cam["width"] // 2,
+                                               cur_cam["height"] // 2, cur_cam["width"], cur_cam["height"]),
+            "gauss_newton_steps": [4, 4, 6], "pairs_last_step": pairs,
+            "start_error_mm_mrad": [round(e0[0] * 1e3, 3), round(e0[1] * 1e3, 3)],
+            "final_error_mm_mrad": [round(e1[0] * 1e3, 3), round(e1[1] * 1e3, 3)]}
 
 
 def bench_batched(P, synth, dev, cfg, reps=20, n_gauss=300_000):

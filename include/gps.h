@@ -343,6 +343,45 @@ gps_status gps_insert_gaussians(const gps_insert_cfg* cfg, const gps_camera* cam
                                 gps_gaussians* out, int32_t* out_pixel, int32_t* out_count, void* ws, size_t ws_bytes,
                                 void* stream);
 
+/* ---- Camera tracking (Sec. 3.2.1, "Camera tracking", Eq. 5): point-to-plane ICP.
+ * The pose being tracked is a device array `pose` [12] = R (row-major), t of the
+ * current camera, world to camera like gps_camera; the model is the previous
+ * frame's SDF raycast depth D_t (full resolution, 0 = miss) seen from `prev_cam`.
+ * A step: gps_icp_reduce on one level of the current depth hierarchy, then
+ * gps_icp_solve; every call only enqueues work and reads the pose from device
+ * memory, so a whole coarse-to-fine loop can be captured as a graph. */
+
+/* One level of the depth hierarchy: out [height/2][width/2] (integer division)
+ * holds the mean of the valid (> 0) depths of each 2x2 block, 0 when none is
+ * valid (sum and division in binary64, rounded once).  The level's intrinsics
+ * are f/2 and (c - 1/2)/2.  width, height >= 2. */
+gps_status gps_depth_downsample(const float* depth, int32_t width, int32_t height, float* out, void* stream);
+
+/* Scratch bytes for gps_icp_reduce on a level of width x height pixels. */
+gps_status gps_icp_workspace_size(int32_t width, int32_t height, size_t* out_bytes);
+
+/* The Gauss-Newton system of Eq. 5 at the device pose, for one level.
+ * level_cam: the level's size and intrinsics (its R and t are not read);
+ * level_depth [height][width] (device).  For every pixel with depth d > 0: the
+ * vertex V = ((i - cx) d / fx, (j - cy) d / fy, d), its world point p, the
+ * nearest pixel u^ of its projection into prev_cam, which must lie in the image
+ * with its four neighbours, all with a raycast surface; V*, the back-projection
+ * of D_t(u^), and N*, the normalised cross product of the central differences
+ * of the back-projected D_t; pairs farther apart than dist_thresh (m) are
+ * dropped.  r = (p - V*) . N*, J = (N*, p x N*) for the left perturbation
+ * T_{g,k} <- Exp(xi) T_{g,k} of the camera-to-world pose, xi = (rho, phi).
+ * out_sys (device, binary64 [29]): the upper triangle of H = sum J J^T
+ * (row-major, 21), g = sum J r (6), sum r^2, the pair count.  Sums in a fixed
+ * order (no atomics).  ws: gps_icp_workspace_size bytes, 256-byte aligned. */
+gps_status gps_icp_reduce(const gps_camera* prev_cam, const float* prev_depth, const gps_camera* level_cam,
+                          const float* level_depth, const float* pose, float dist_thresh, double* out_sys, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/* Solves H xi = -g (Cholesky, binary64) and applies T_{g,k} <- Exp(xi) T_{g,k}
+ * to the device pose in place; out_xi (optional, device [6]) receives xi.  With
+ * fewer than 6 pairs or H not positive definite the pose is kept and xi = 0. */
+gps_status gps_icp_solve(const double* sys, float* pose, float* out_xi, void* stream);
+
 /* Reads the sticky status word of a workspace (synchronises `stream`). */
 gps_status gps_device_status(const void* ws, size_t ws_bytes, int32_t* out_status, void* stream);
 

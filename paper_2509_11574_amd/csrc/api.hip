@@ -455,6 +455,52 @@ gps_status gps_insert_gaussians(const gps_insert_cfg* cfg, const gps_camera* cam
                                    out_count, static_cast<char*>(ws), (hipStream_t)stream);
 }
 
+gps_status gps_depth_downsample(const float* depth, int32_t width, int32_t height, float* out, void* stream)
+{
+    if (!depth || !out || width < 2 || height < 2 || (int64_t)width * height > (int64_t(1) << 30))
+        return GPS_ERR_INVALID_ARG;
+    gps_status st = check_device();
+    if (st != GPS_OK) return st;
+    return launch_depth_downsample(depth, width, height, out, (hipStream_t)stream);
+}
+
+gps_status gps_icp_workspace_size(int32_t width, int32_t height, size_t* out_bytes)
+{
+    if (!out_bytes || width <= 0 || height <= 0 || (int64_t)width * height > (int64_t(1) << 30))
+        return GPS_ERR_INVALID_ARG;
+    *out_bytes = icp_workspace_bytes(width, height);
+    return GPS_OK;
+}
+
+gps_status gps_icp_reduce(const gps_camera* prev_cam, const float* prev_depth, const gps_camera* level_cam,
+                          const float* level_depth, const float* pose, float dist_thresh, double* out_sys, void* ws,
+                          size_t ws_bytes, void* stream)
+{
+    if (!prev_cam || !level_cam || !prev_depth || !level_depth || !pose || !out_sys) return GPS_ERR_INVALID_ARG;
+    if (!cam_ok(*prev_cam) || !(level_cam->width > 0 && level_cam->height > 0) ||
+        !std::isfinite(level_cam->fx) || !std::isfinite(level_cam->fy) || !std::isfinite(level_cam->cx) ||
+        !std::isfinite(level_cam->cy) || level_cam->fx == 0.0f || level_cam->fy == 0.0f)
+        return GPS_ERR_INVALID_ARG;
+    if ((int64_t)level_cam->width * level_cam->height > (int64_t(1) << 30) ||
+        (int64_t)prev_cam->width * prev_cam->height > (int64_t(1) << 30))
+        return GPS_ERR_INVALID_ARG;
+    if (!(dist_thresh > 0.0f) || !std::isfinite(dist_thresh)) return GPS_ERR_INVALID_ARG;
+    if (!ws || ((uintptr_t)ws & 255)) return GPS_ERR_INVALID_ARG;
+    if (ws_bytes < icp_workspace_bytes(level_cam->width, level_cam->height)) return GPS_ERR_WORKSPACE_TOO_SMALL;
+    gps_status st = check_device();
+    if (st != GPS_OK) return st;
+    return launch_icp_reduce(*prev_cam, prev_depth, *level_cam, level_depth, pose, dist_thresh, out_sys,
+                             static_cast<char*>(ws), (hipStream_t)stream);
+}
+
+gps_status gps_icp_solve(const double* sys, float* pose, float* out_xi, void* stream)
+{
+    if (!sys || !pose) return GPS_ERR_INVALID_ARG;
+    gps_status st = check_device();
+    if (st != GPS_OK) return st;
+    return launch_icp_solve(sys, pose, out_xi, (hipStream_t)stream);
+}
+
 gps_status gps_device_status(const void* ws, size_t ws_bytes, int32_t* out_status, void* stream)
 {
     if (!ws || ws_bytes < 1024 || !out_status) return GPS_ERR_INVALID_ARG;

@@ -30,6 +30,7 @@ enum KernelId {
     K_UPLOAD,
     K_REMOVE,
     K_INSERT,
+    K_ICP,
     K_COUNT
 };
 

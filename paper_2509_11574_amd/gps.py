@@ -93,7 +93,8 @@ EXPORTS = ["gps_abi_version", "gps_status_string", "gps_render_cfg_default", "gp
            "gps_adam_step", "gps_device_status", "gps_read_stats", "gps_profile_start", "gps_profile_stop",
            "gps_profile_read", "gps_views_upload", "gps_removal_cfg_default", "gps_removal_workspace_size",
            "gps_remove_gaussians", "gps_insert_cfg_default", "gps_insertion_workspace_size",
-           "gps_insert_gaussians"]
+           "gps_insert_gaussians", "gps_depth_downsample", "gps_icp_workspace_size", "gps_icp_reduce",
+           "gps_icp_solve"]
 
 _lib = None
 
@@ -133,6 +134,10 @@ def lib():
         L.gps_insert_cfg_default.restype = None
         L.gps_insertion_workspace_size.argtypes = [I32, I32, ctypes.POINTER(ctypes.c_size_t)]
         L.gps_insert_gaussians.argtypes = [P, P, P, P, P, P, P, P, P, P, P, ctypes.c_size_t, P]
+        L.gps_depth_downsample.argtypes = [P, I32, I32, P, P]
+        L.gps_icp_workspace_size.argtypes = [I32, I32, ctypes.POINTER(ctypes.c_size_t)]
+        L.gps_icp_reduce.argtypes = [P, P, P, P, P, F, P, P, ctypes.c_size_t, P]
+        L.gps_icp_solve.argtypes = [P, P, P, P]
         for n in EXPORTS:
             if n not in ("gps_render_cfg_default", "gps_status_string", "gps_abi_version", "gps_removal_cfg_default",
                          "gps_insert_cfg_default"):
@@ -619,3 +624,81 @@ def insert_gaussians(cam, render_rgb, frame_rgb, weight, sdf_depth, rand, capaci
     n = min(n_taken, cap)
     res = {k: out[k][:, :n] if GAUSS_ROWS[k] > 1 else out[k].reshape(-1)[:n] for k in GAUSS_KEYS}
     return res, pix[:n], n_taken
+
+
+# --------------------------------------------------------------------------- #
+# Camera tracking (Eq. 5)                                                      #
+# --------------------------------------------------------------------------- #
+def level_camera(cam, level: int) -> dict:
+    """Size and intrinsics of a level of the depth hierarchy (f / 2, (c - 1/2) / 2 per level)."""
+    c = dict(cam)
+    for _ in range(level):
+        c["width"], c["height"] = c["width"] // 2, c["height"] // 2
+        c["fx"], c["fy"] = c["fx"] / 2.0, c["fy"] / 2.0
+        c["cx"], c["cy"] = (c["cx"] - 0.5) / 2.0, (c["cy"] - 0.5) / 2.0
+    return c
+
+
+def depth_downsample(depth: torch.Tensor, stream=None) -> torch.Tensor:
+    """One level of the depth hierarchy (gps_depth_downsample)."""
+    H, W = depth.shape
+    out = torch.empty(H // 2, W // 2, dtype=torch.float32, device=depth.device)
+    _check(lib().gps_depth_downsample(_ptr(depth, "depth", W * H), W, H, ctypes.c_void_p(out.data_ptr()),
+                                      _stream(stream)), "gps_depth_downsample")
+    return out
+
+
+def pose_tensor(cam, device="cuda") -> torch.Tensor:
+    """The [12] device pose (R row-major, t; world to camera) of a camera dict."""
+    R = np.asarray(cam["R"], np.float32).reshape(9)
+    t = np.asarray(cam["t"], np.float32).reshape(3)
+    return torch.as_tensor(np.concatenate([R, t])).to(device)
+
+
+class IcpWorkspace:
+    def __init__(self, width: int, height: int, device="cuda"):
+        n = ctypes.c_size_t(0)
+        _check(lib().gps_icp_workspace_size(width, height, ctypes.byref(n)), "gps_icp_workspace_size")
+        self.nbytes = n.value
+        self.buf = torch.empty(self.nbytes, dtype=torch.uint8, device=device)
+        self.sys = torch.zeros(29, dtype=torch.float64, device=device)
+        self.xi = torch.zeros(6, dtype=torch.float32, device=device)
+
+
+def icp_reduce(prev_cam, prev_depth, level_cam, level_depth, pose, dist_thresh, ws: IcpWorkspace, stream=None):
+    """Gauss-Newton system of Eq. 5 at the device pose (gps_icp_reduce) into ws.sys."""
+    pc, lc = camera(prev_cam), camera({**level_cam, "R": np.eye(3), "t": np.zeros(3)})
+    _check(lib().gps_icp_reduce(ctypes.byref(pc), _ptr(prev_depth, "prev_depth", pc.width * pc.height),
+                                ctypes.byref(lc), _ptr(level_depth, "level_depth", lc.width * lc.height),
+                                _ptr(pose, "pose", 12), float(dist_thresh), ctypes.c_void_p(ws.sys.data_ptr()),
+                                ctypes.c_void_p(ws.buf.data_ptr()), ws.nbytes, _stream(stream)), "gps_icp_reduce")
+    return ws.sys
+
+
+def icp_solve(sys: torch.Tensor, pose: torch.Tensor, xi: torch.Tensor | None = None, stream=None):
+    """Solve and apply one Gauss-Newton step to the device pose (gps_icp_solve)."""
+    _check(lib().gps_icp_solve(ctypes.c_void_p(sys.data_ptr()), _ptr(pose, "pose", 12),
+                               ctypes.c_void_p(xi.data_ptr()) if xi is not None else None, _stream(stream)),
+           "gps_icp_solve")
+
+
+def icp_track(prev_cam, prev_depth, cur_cam, cur_depth, pose: torch.Tensor, iters=(4, 4, 6),
+              dist_thresh=(0.1, 0.05, 0.02), ws: IcpWorkspace | None = None, pyramid=None, stream=None):
+    """Coarse-to-fine tracking of the current frame against the previous frame's raycast
+    depth; `pose` (device [12], world to camera) is refined in place.  iters and
+    dist_thresh list the levels from the coarsest to the finest.  Nothing is read
+    back to the host."""
+    L = len(iters)
+    if pyramid is None:
+        pyramid = [cur_depth]
+        for _ in range(L - 1):
+            pyramid.append(depth_downsample(pyramid[-1], stream))
+    if ws is None:
+        ws = IcpWorkspace(cur_cam["width"], cur_cam["height"], device=cur_depth.device)
+    for k in range(L):
+        lvl = L - 1 - k
+        lc = level_camera(cur_cam, lvl)
+        for _ in range(iters[k]):
+            icp_reduce(prev_cam, prev_depth, lc, pyramid[lvl], pose, dist_thresh[k], ws, stream)
+            icp_solve(ws.sys, pose, ws.xi, stream)
+    return pose

@@ -183,3 +183,24 @@ def test_insertion_defaults_and_argument_checks(P):
     assert call(c) == -1
     assert L.gps_insert_gaussians(ctypes.byref(c), ctypes.byref(cam), None, img, img, img, img, ctypes.byref(g),
                                   None, ctypes.byref(cnt), None, 0, None) == -1
+
+
+def test_icp_argument_checks(P):
+    """Camera tracking (Eq. 5): bad arguments are refused before anything is launched."""
+    L = P.lib()
+    n = ctypes.c_size_t(0)
+    assert L.gps_icp_workspace_size(160, 120, ctypes.byref(n)) == 0 and n.value >= 29 * 4 * 75
+    assert L.gps_icp_workspace_size(0, 120, ctypes.byref(n)) == -1
+    buf = (ctypes.c_float * 16)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+    assert L.gps_depth_downsample(p, 1, 4, p, None) == -1              # width below 2
+    assert L.gps_depth_downsample(None, 4, 4, p, None) == -1
+    cam = P.camera(_cam())
+    sysb = (ctypes.c_double * 29)()
+    sp = ctypes.cast(sysb, ctypes.c_void_p)
+    assert L.gps_icp_reduce(ctypes.byref(cam), p, ctypes.byref(cam), p, p, 0.1, sp, None, 1 << 20, None) == -1
+    assert L.gps_icp_reduce(ctypes.byref(cam), p, ctypes.byref(cam), p, p, 0.0, sp, p, 1 << 20, None) == -1
+    assert L.gps_icp_reduce(ctypes.byref(cam), None, ctypes.byref(cam), p, p, 0.1, sp, p, 1 << 20, None) == -1
+    bad = P.camera({**_cam(), "fx": 0.0})
+    assert L.gps_icp_reduce(ctypes.byref(cam), p, ctypes.byref(bad), p, p, 0.1, sp, p, 1 << 20, None) == -1
+    assert L.gps_icp_solve(None, p, None, None) == -1 and L.gps_icp_solve(sp, None, None, None) == -1

@@ -134,5 +134,7 @@ def test_tracking_recovers_the_true_pose():
     assert np.linalg.norm(c0 - cB) > 0.015
     R, t = I.track(camA, DA, camB, DB, R0, t0)
     c = -R.T @ t
-    ang = np.arccos(np.clip((np.trace(R @ RB.T) - 1) / 2, -1, 1))
+    M = R @ RB.T
+    ang = np.arctan2(0.5 * np.linalg.norm([M[2, 1] - M[1, 2], M[0, 2] - M[2, 0], M[1, 0] - M[0, 1]]),
+                     0.5 * (np.trace(M) - 1))
     assert np.linalg.norm(c - cB) < 1e-3 and ang < 2e-3, (np.linalg.norm(c - cB), ang)
