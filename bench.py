@@ -89,7 +89,7 @@ def parse():
                     help="tile_w x tile_h x batch x pixels_per_lane, or 'auto' (autotuned on the first frame)")
     ap.add_argument("--graph", type=int, default=0,
                     help="time graph replay of the iteration (default: kernel-by-kernel launches with the view "
-                         "table uploaded once per frame); the other mode is timed on the same frames afterwards")
+                         "table uploaded once per frame); the other mode is timed on later frames")
     ap.add_argument("--mode", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -101,6 +101,8 @@ def parse():
                     help="frames timed on the 512^3 / 1M-Gaussian / 4-keyframe workload (0 skips it)")
     ap.add_argument("--maintenance", type=int, default=1,
                     help="time Gaussian removal (Eq. 8) and insertion (Eq. 6) once the timed frames are done")
+    ap.add_argument("--other-mode", type=int, default=1,
+                    help="also time the other launch mode (graph replay or kernel-by-kernel) on later frames")
     ap.add_argument("--tracking", type=int, default=1,
                     help="time ICP tracking (Eq. 5) of one frame against the previous frame's raycast")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -126,10 +128,10 @@ def main():
     torch.cuda.set_device(0)
     W_img, H_img = (int(x) for x in args.res.split("x"))
     K, Wu, M = args.steps, args.warmup, args.gaussians
-    # warm-up frames, then K frames that the timed pass, the pass in the other launch mode and
-    # the pass with per-kernel events each process in full (fusion, raycast, iterations),
+    # warm-up frames, then K frames for each of: the timed pass, the pass with per-kernel
+    # events, the pass in the other launch mode (each frame new to the map, as in mapping),
     # then one frame that is tracked against the raycast of the last one
-    n_frames = Wu + K + 1
+    n_frames = Wu + 3 * K + 1
 
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 4
@@ -251,23 +253,6 @@ def main():
     pct = lambda q: per_frame[min(K - 1, int(round(q * (K - 1))))]
     frame_ms_pct = {"p10": round(pct(0.1), 4), "p50": round(pct(0.5), 4), "p90": round(pct(0.9), 4)}
 
-    # ------------------------- the next frames in the other launch mode
-    if args.graph:
-        alt_step, alt_mode = frame_step_eager, "eager"
-    else:
-        from paper_2509_11574_amd.graph import IterationGraph
-        graph = IterationGraph(cfg, params, [last_view], ws, grads, opt, loss, dpose)
-        alt_step, alt_mode = frame_step_graph, "graph"
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for k in range(Wu, Wu + K):
-        alt_step(k)
-    torch.cuda.synchronize()
-    te = time.perf_counter() - t1
-    alt = {"launch": alt_mode, "ms_per_frame": round(1000.0 * te / K, 4),
-           "iters_per_s": round(ITERS_PER_FRAME * K / te, 1),
-           "frames": "the same %d frames again, each iteration %s" %
-                     (K, "launched kernel by kernel" if alt_mode == "eager" else "replayed as one captured HIP graph")}
     log(f"timed {K} frames: {ms_per_frame:.3f} ms/frame (events {ms_event / K:.3f}), {iters_per_s:.1f} iters/s, "
         f"loss {first_loss:.5f} -> {last_loss:.6f}, instances {st1['n_instances']}")
 
@@ -276,7 +261,7 @@ def main():
     if not args.no_profile:
         stp0 = ws.stats()
         P.gps.profile_start()
-        for k in range(Wu, Wu + K):  # the same frames, launched eagerly so events bracket each kernel
+        for k in range(Wu + K, Wu + 2 * K):  # the next frames, launched eagerly so events bracket each kernel
             frame_step_eager(k)
         torch.cuda.synchronize()
         P.gps.profile_stop()
@@ -285,6 +270,28 @@ def main():
         n_fwd = kernels.get("composite_fwd", (1, 0))[0]
         pairs = {"eval_per_launch": (stp1["pairs_eval"] - stp0["pairs_eval"]) / n_fwd,
                  "contrib_per_launch": (stp1["pairs_contrib"] - stp0["pairs_contrib"]) / n_fwd}
+    # ------------------ the next frames in the other launch mode (wall clock)
+    alt = None
+    if not args.other_mode:
+        alt_step = None
+    elif args.graph:
+        alt_step, alt_mode = frame_step_eager, "eager"
+    else:
+        from paper_2509_11574_amd.graph import IterationGraph
+        graph = IterationGraph(cfg, params, [last_view], ws, grads, opt, loss, dpose)
+        alt_step, alt_mode = frame_step_graph, "graph"
+    if alt_step is not None:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(Wu + 2 * K, Wu + 3 * K):
+            alt_step(k)
+        torch.cuda.synchronize()
+        te = time.perf_counter() - t1
+        alt = {"launch": alt_mode, "ms_per_frame": round(1000.0 * te / K, 4),
+               "iters_per_s": round(ITERS_PER_FRAME * K / te, 1),
+               "frames": "the %d frames after the profiled ones, each iteration %s" %
+                         (K, "launched kernel by kernel" if alt_mode == "eager"
+                          else "replayed as one captured HIP graph")}
     roofline = None
     if kernels:
         dom = max(kernels, key=lambda n: kernels[n][1])
@@ -333,7 +340,7 @@ def main():
     # ------------- camera tracking of the next frame against the last raycast
     tracking = None
     if args.tracking:
-        kl = Wu + K - 1
+        kl = Wu + 3 * K - 1
         frame_prep(kl)  # base_depth: the SDF raycast of the last frame
         tracking = bench_tracking(P, cams[kl].as_dict(), base_depth, cams[kl + 1].as_dict(), frames[kl + 1][0])
 
@@ -460,7 +467,7 @@ def bench_maintenance(P, synth, scene, cam, params, opt, reps=20):
                         "algorithmic_bytes": rem_bytes, "gbs": round(rem_bytes / (rem_ms / 1e3) / 1e9, 1)},
             "insertion": {"pixels": px, "new": n_taken, "ms_per_call": round(ins_ms, 4),
                           "algorithmic_bytes": ins_bytes, "gbs": round(ins_bytes / (ins_ms / 1e3) / 1e9, 1)},
-            "launches_per_call": 3}
+            "launches_per_call": {"removal": 3, "insertion": 4}}
 
 
 def bench_tracking(P, prev_cam, prev_depth, cur_cam, cur_depth, reps=10):

@@ -337,7 +337,7 @@ gps_status gps_insertion_workspace_size(int32_t width, int32_t height, size_t* o
  * pixel order, those past the capacity are dropped; out_pixel (optional,
  * [capacity]) receives their pixel indices; *out_count (device int32) the
  * number of taken pixels (possibly above the capacity).  ws:
- * gps_insertion_workspace_size bytes, 256-byte aligned.  Three kernels. */
+ * gps_insertion_workspace_size bytes, 256-byte aligned.  Four kernels. */
 gps_status gps_insert_gaussians(const gps_insert_cfg* cfg, const gps_camera* cam, const float* render_rgb,
                                 const float* frame_rgb, const float* weight, const float* sdf_depth, const float* rand,
                                 gps_gaussians* out, int32_t* out_pixel, int32_t* out_count, void* ws, size_t ws_bytes,

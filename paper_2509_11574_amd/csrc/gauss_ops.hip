@@ -139,7 +139,10 @@ gps_status launch_remove_gaussians(const gps_removal_cfg* cfg, const gps_gaussia
 //   k_insert_flags  per pixel: mask (bit 0) and sample (bit 1) flags; per block
 //                   of 256 pixels, the number taken
 //   k_insert_scan   one block: block offsets, total taken -> out_count
-//   k_insert_init   per taken pixel: the new Gaussian at its row-major place
+//   k_insert_place  per taken pixel: its row-major output position
+//   k_insert_init   per new Gaussian: its surface point, normal, scale, rotation
+constexpr int kInsertMaxRadius = 8;  // the window radius the C ABI accepts
+
 struct InsertArgs {
     DevCam cam;
     const float* render_rgb;
@@ -156,6 +159,8 @@ struct InsertArgs {
     unsigned int* blk_cnt;
     unsigned int* blk_off;
     unsigned int* total;
+    int* list;     // pixel of each output position
+    float* mdepth; // depth of the mask pixels, 0 elsewhere
 };
 
 __global__ void __launch_bounds__(256) k_insert_flags(InsertArgs a)
@@ -170,6 +175,7 @@ __global__ void __launch_bounds__(256) k_insert_flags(InsertArgs a)
         const bool mask = a.depth[p] > 0.0f && e > a.t_c && a.weight[p] < a.t_w;
         f = (mask ? 1u : 0u) | ((mask && a.rnd[p] < a.t_frac) ? 2u : 0u);
         a.flags[p] = f;
+        a.mdepth[p] = mask ? a.depth[p] : 0.0f;
     }
     unsigned int tot;
     block_excl_scan<256>((f >> 1) & 1u, &tot);
@@ -223,16 +229,27 @@ __device__ __forceinline__ void cam_point(const DevCam& c, int i, int j, float d
 // they are formed from camera-frame differences (no world-coordinate
 // cancellation in binary32); only the mean and the normal are rotated to the
 // world frame, x_w = R^T (x_c - t).
-__global__ void __launch_bounds__(256) k_insert_init(InsertArgs a)
+// Per pixel: the output position of each sampled pixel (row-major order) into
+// the list, so that the initialisation runs one lane per new Gaussian.
+__global__ void __launch_bounds__(256) k_insert_place(InsertArgs a)
 {
-    const int W = a.cam.W, H = a.cam.H, n = W * H;
+    const int n = a.cam.W * a.cam.H;
     const int p = blockIdx.x * 256 + threadIdx.x;
     const bool take = p < n && (a.flags[p] & 2u);
     unsigned int tot;
     const unsigned int excl = block_excl_scan<256>(take ? 1u : 0u, &tot);
     if (!take) return;
     const unsigned int pos = a.blk_off[blockIdx.x] + excl;
-    if (pos >= (unsigned int)a.capacity) return;
+    if (pos < (unsigned int)a.capacity) a.list[pos] = p;
+}
+
+// Per new Gaussian (position pos < min(sampled, capacity)).
+__global__ void __launch_bounds__(256) k_insert_init(InsertArgs a)
+{
+    const int W = a.cam.W, H = a.cam.H, n = W * H;
+    const unsigned int pos = blockIdx.x * 256 + threadIdx.x;
+    if (pos >= *a.total || pos >= (unsigned int)a.capacity) return;
+    const int p = a.list[pos];
     const int i = p % W, j = p / W;
     const DevCam& c = a.cam;
     float X[3];
@@ -271,12 +288,22 @@ __global__ void __launch_bounds__(256) k_insert_init(InsertArgs a)
     int nb = 0;
     const int j0 = max(0, j - a.radius), j1 = min(H - 1, j + a.radius);
     const int i0 = max(0, i - a.radius), i1 = min(W - 1, i + a.radius);
-    for (int jj = j0; jj <= j1; ++jj)
-        for (int ii = i0; ii <= i1; ++ii) {
-            const int q = jj * W + ii;
-            if (q == p || !(a.flags[q] & 1u)) continue;
+    // one window row at a time: its (up to 17) mask depths are loaded together,
+    // then searched (the mask depth is > 0 exactly on the mask pixels)
+    for (int jj = j0; jj <= j1; ++jj) {
+        const float* row = a.mdepth + (size_t)jj * W;
+        float dv[2 * kInsertMaxRadius + 1];
+#pragma unroll
+        for (int t = 0; t < 2 * kInsertMaxRadius + 1; ++t) {
+            const int ii = i0 + t;
+            dv[t] = ii <= i1 ? row[ii] : 0.0f;
+        }
+#pragma unroll
+        for (int t = 0; t < 2 * kInsertMaxRadius + 1; ++t) {
+            const int ii = i0 + t;
+            if (!(dv[t] > 0.0f) || (jj == j && ii == i)) continue;
             float U[3];
-            cam_point(c, ii, jj, a.depth[q], U);
+            cam_point(c, ii, jj, dv[t], U);
             const float d = sqrtf((U[0] - X[0]) * (U[0] - X[0]) + (U[1] - X[1]) * (U[1] - X[1]) +
                                   (U[2] - X[2]) * (U[2] - X[2]));
             ++nb;
@@ -294,6 +321,7 @@ __global__ void __launch_bounds__(256) k_insert_init(InsertArgs a)
                 }
             }
         }
+    }
     float s1 = a.scale_cap;
     if (nb > 0) {
         const int m = nb < 3 ? nb : 3;
@@ -335,7 +363,7 @@ size_t insertion_workspace_bytes(int W, int H)
 {
     const size_t n = (size_t)W * H, nblk = n > 0 ? (n + 255) / 256 : 1;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    return al(4 * n) + 2 * al(4 * nblk) + 256;
+    return 3 * al(4 * n) + 2 * al(4 * nblk) + 256;
 }
 
 gps_status launch_insert_gaussians(const gps_insert_cfg* cfg, const DevCam& cam, const float* render_rgb,
@@ -370,9 +398,15 @@ gps_status launch_insert_gaussians(const gps_insert_cfg* cfg, const DevCam& cam,
     a.blk_cnt = reinterpret_cast<unsigned int*>(ws + al(4 * n));
     a.blk_off = reinterpret_cast<unsigned int*>(ws + al(4 * n) + al(4 * nb));
     a.total = reinterpret_cast<unsigned int*>(ws + al(4 * n) + 2 * al(4 * nb));
+    a.list = reinterpret_cast<int*>(ws + al(4 * n) + 2 * al(4 * nb) + 256);
+    a.mdepth = reinterpret_cast<float*>(ws + 2 * al(4 * n) + 2 * al(4 * nb) + 256);
     if (nblk > 0) GPS_LAUNCH(K_INSERT, s, k_insert_flags, dim3(nblk), dim3(256), 0, s, a);
     GPS_LAUNCH(K_INSERT, s, k_insert_scan, dim3(1), dim3(1024), 0, s, a, nblk);
-    if (nblk > 0) GPS_LAUNCH(K_INSERT, s, k_insert_init, dim3(nblk), dim3(256), 0, s, a);
+    const size_t cap = (size_t)a.capacity < n ? (size_t)a.capacity : n;
+    if (nblk > 0 && cap > 0) {
+        GPS_LAUNCH(K_INSERT, s, k_insert_place, dim3(nblk), dim3(256), 0, s, a);
+        GPS_LAUNCH(K_INSERT, s, k_insert_init, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, a);
+    }
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
 }
 

@@ -9,6 +9,7 @@
 //                  pixels the 29 sums (upper triangle of J J^T, J r, r^2, count)
 //                  in a fixed order
 //   k_icp_total    one block: the block sums in binary64, in a fixed order
+//                  (at most 1024 block partials: larger levels loop per lane)
 //   k_icp_solve    one lane: Cholesky solve of H xi = -g in binary64 and the
 //                  update T_{g,k} <- Exp(xi) T_{g,k} of the device pose
 // No atomics: the system is bitwise reproducible.  Every stage reads the pose
@@ -103,8 +104,10 @@ __global__ void __launch_bounds__(256) k_icp_pairs(IcpArgs a)
     float v[kIcpTerms];
 #pragma unroll
     for (int k = 0; k < kIcpTerms; ++k) v[k] = 0.0f;
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p < a.W * a.H) {
+    // each lane takes the pixels p, p + 256 * gridDim.x, ... (a fixed assignment, so
+    // the sums have a fixed order)
+    const int n = a.W * a.H;
+    for (int p = blockIdx.x * 256 + threadIdx.x; p < n; p += 256 * gridDim.x) {
         const float d = a.depth[p];
         const int i = p % a.W, j = p / a.W;
         bool ok = d > 0.0f;
@@ -167,11 +170,11 @@ __global__ void __launch_bounds__(256) k_icp_pairs(IcpArgs a)
 #pragma unroll
                 for (int r0 = 0; r0 < 6; ++r0)
 #pragma unroll
-                    for (int c0 = r0; c0 < 6; ++c0) v[k++] = J[r0] * J[c0];
+                    for (int c0 = r0; c0 < 6; ++c0) v[k++] += J[r0] * J[c0];
 #pragma unroll
-                for (int r0 = 0; r0 < 6; ++r0) v[21 + r0] = J[r0] * r;
-                v[27] = r * r;
-                v[28] = 1.0f;
+                for (int r0 = 0; r0 < 6; ++r0) v[21 + r0] += J[r0] * r;
+                v[27] += r * r;
+                v[28] += 1.0f;
             }
         }
     }
@@ -188,19 +191,17 @@ __global__ void __launch_bounds__(256) k_icp_pairs(IcpArgs a)
     }
 }
 
-__global__ void __launch_bounds__(256) k_icp_total(const float* __restrict__ part, int nblk, double* __restrict__ sys)
+// Wavefront w sums the terms w and w + 16 over the block partials: lane l takes
+// blocks l, l + 64, ... in binary64, then a fixed butterfly across the lanes.
+__global__ void __launch_bounds__(1024) k_icp_total(const float* __restrict__ part, int nblk, double* __restrict__ sys)
 {
-    __shared__ double red[4];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int k = 0; k < kIcpTerms; ++k) {
+    for (int k = wid; k < kIcpTerms; k += 16) {
         double s = 0.0;
-        for (int b = threadIdx.x; b < nblk; b += 256) s += (double)part[(size_t)k * nblk + b];
+        for (int b = lane; b < nblk; b += 64) s += (double)part[(size_t)k * nblk + b];
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-        if (lane == 0) red[wid] = s;
-        __syncthreads();
-        if (threadIdx.x == k % 64) sys[k] = ((red[0] + red[1]) + red[2]) + red[3];
-        __syncthreads();
+        if (lane == 0) sys[k] = s;
     }
 }
 
@@ -242,35 +243,48 @@ __device__ void icp_solve_one(const double* sys, const float* pose, float* res)
     // H from its upper triangle, Cholesky H = L L^T
     double Hm[36];
     int k = 0;
+#pragma unroll
     for (int r = 0; r < 6; ++r)
+#pragma unroll
         for (int c = r; c < 6; ++c) {
             Hm[6 * r + c] = sys[k];
             Hm[6 * c + r] = sys[k];
             ++k;
         }
-    for (int j = 0; j < 6 && ok; ++j) {
+    // (fully unrolled so that the arrays stay in registers; a non-positive pivot
+    // clears `ok` and is replaced by 1 to finish the factorisation harmlessly)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
         double s = Hm[6 * j + j];
+#pragma unroll
         for (int m = 0; m < j; ++m) s -= L[6 * j + m] * L[6 * j + m];
         if (!(s > 0.0)) {
             ok = false;
-            break;
+            s = 1.0;
         }
         L[6 * j + j] = sqrt(s);
+#pragma unroll
         for (int i = j + 1; i < 6; ++i) {
             double u = Hm[6 * i + j];
+#pragma unroll
             for (int m = 0; m < j; ++m) u -= L[6 * i + m] * L[6 * j + m];
             L[6 * i + j] = u / L[6 * j + j];
         }
     }
+#pragma unroll
     for (int m = 0; m < 6; ++m) xi[m] = 0.0;
     if (ok) {
+#pragma unroll
         for (int i = 0; i < 6; ++i) {  // L y = -g
             double u = -sys[21 + i];
+#pragma unroll
             for (int m = 0; m < i; ++m) u -= L[6 * i + m] * y[m];
             y[i] = u / L[6 * i + i];
         }
+#pragma unroll
         for (int i = 5; i >= 0; --i) {  // L^T xi = y
             double u = y[i];
+#pragma unroll
             for (int m = i + 1; m < 6; ++m) u -= L[6 * m + i] * xi[m];
             xi[i] = u / L[6 * i + i];
         }
@@ -338,10 +352,12 @@ gps_status launch_icp_reduce(const gps_camera& prev, const float* prev_depth, co
     a.depth = depth;
     a.pose = pose;
     a.dist2 = dist_thresh * dist_thresh;
-    a.nblk = (int)(((size_t)lvl.width * lvl.height + 255) / 256);
+    // at most 1024 blocks (four per compute unit); larger levels loop inside the block
+    const size_t want = ((size_t)lvl.width * lvl.height + 255) / 256;
+    a.nblk = (int)(want < 1024 ? want : 1024);
     a.part = reinterpret_cast<float*>(ws);
     GPS_LAUNCH(K_ICP, s, k_icp_pairs, dim3(a.nblk), dim3(256), 0, s, a);
-    GPS_LAUNCH(K_ICP, s, k_icp_total, dim3(1), dim3(256), 0, s, a.part, a.nblk, sys);
+    GPS_LAUNCH(K_ICP, s, k_icp_total, dim3(1), dim3(1024), 0, s, a.part, a.nblk, sys);
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
 }
 
