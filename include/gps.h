@@ -3,12 +3,13 @@
  * path of Gaussian-plus-SDF SLAM (Peng, Zhou, Shao, arXiv 2509.11574):
  * colourised-TSDF fusion, SDF raycast, the differentiable 3D-Gaussian overlay
  * composited over the SDF base image, its photometric + depth loss, the
- * analytic backward pass (Gaussian parameters and 6-DoF camera pose) and Adam.
+ * analytic backward pass (Gaussian parameters and 6-DoF camera pose) and Adam;
+ * around it, Gaussian removal and insertion and point-to-plane ICP tracking.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
- *  - Pointers are DEVICE pointers unless the comment says "host".  Every array
- *    is float32, planar (structure of arrays), C order.  Images are [H][W]
+ *  - Pointers are DEVICE pointers unless the comment says "host".  Arrays are
+ *    float32 unless stated otherwise, planar (structure of arrays), C order.  Images are [H][W]
  *    (depth) and [3][H][W] (colour); lattices are indexed
  *    x + nx*(y + ny*z); Gaussian attributes are [k][M] (one plane per
  *    component).

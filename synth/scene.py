@@ -259,7 +259,7 @@ def render_frame(scene: Scene, cam: Camera, noise_sigma_per_m2: float = 0.0, see
     rgb = col.T.reshape(3, H, W).to(torch.float32)
     if as_torch:
         return depth.contiguous(), rgb.contiguous()
-    return depth.cpu().numpy(), rgb.cpu().numpy()
+    return np.ascontiguousarray(depth.cpu().numpy()), np.ascontiguousarray(rgb.cpu().numpy())
 
 
 def surface_points(scene: Scene, cam: Camera, pix: np.ndarray, device="cpu"):

@@ -169,3 +169,33 @@ def test_icp_track_full_size(P):
     dc, ang = _pose_err(pose, camB)
     assert d0 > 0.015 and a0 > 0.02
     assert dc < 1e-3 and ang < 1e-3, (dc, ang)
+
+
+def test_icp_track_graph_replay(P):
+    """A whole coarse-to-fine tracking loop captured as one HIP graph: every replay (with
+    eager tracking runs and synchronisations between them) gives the eager pose bitwise."""
+    say("icp: tracking loop as a graph")
+    camA, DA, camB, DB = _room_pair(320, 240)
+    dA, dB = t(DA), t(DB)
+    pose0 = P.pose_tensor(camA)
+    ws = P.gps.IcpWorkspace(320, 240)
+    pyr = [dB]
+    for _ in range(2):
+        pyr.append(P.depth_downsample(pyr[-1]))
+    pose_e = pose0.clone()
+    P.icp_track(camA, dA, camB, dB, pose_e, ws=ws, pyramid=pyr)
+    torch.cuda.synchronize()
+    pose_g = pose0.clone()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        P.icp_track(camA, dA, camB, dB, pose_g, ws=ws, pyramid=pyr)
+    for _ in range(3):
+        pose_g.copy_(pose0)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(pose_g, pose_e)
+        pose_x = pose0.clone()
+        P.icp_track(camA, dA, camB, dB, pose_x, ws=ws, pyramid=pyr)
+        torch.cuda.synchronize()
+        assert torch.equal(pose_x, pose_e)
+    assert _pose_err(pose_g, camB)[0] < 1e-3
