@@ -47,7 +47,7 @@ def log(*a):
 # the time of the measurement; it is reported only while those sources are unchanged.
 KERNEL_SOURCES = {
     "composite_bwd": ("composite_bwd.hip", "render_common.h", "gps_internal.h"),
-    "composite_fwd": ("composite_fwd.hip", "render_common.h", "gps_internal.h"),
+    "composite_fwd": ("composite_fwd.hip", "binning.h", "render_common.h", "gps_internal.h"),
 }
 
 

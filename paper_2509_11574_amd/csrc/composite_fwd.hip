@@ -3,6 +3,7 @@
 // records whose support box misses its pixels and composites the rest front to
 // back over the SDF base colour and depth, with the loss partial of the tile
 // written in the epilogue.
+#include "binning.h"
 #include "launch.h"
 #include "prof.h"
 #include "render_common.h"
@@ -90,6 +91,13 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
         ac0[k] = ac1[k] = ac2[k] = ad[k] = 0.0f;
     }
     const unsigned int s = w.tile_start[tile], e = w.tile_start[tile + 1];
+    // Depth order: lists shorter than kLongTile are sorted here, in registers of
+    // the first wavefront (the longer ones by k_tile_sort_large before this
+    // kernel); the barrier publishes the sorted keys to the block.
+    if (e - s > 1u && e - s < kLongTile) {
+        if (wid == 0) wave_sort_tile(w.keys + s, (int)(e - s), lane);
+        __syncthreads();
+    }
     const int tx0 = tx * TW, ty0 = ty * TH;
     bool wave_alive = true;  // some pixel of this wavefront still takes records
     for (unsigned int b = s; b < e; b += B) {

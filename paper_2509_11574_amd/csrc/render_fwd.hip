@@ -421,102 +421,11 @@ __global__ void __launch_bounds__(kBlk) k_expand(const ViewTable* __restrict__ v
 }
 
 // -------------------------------------------------------------- tile sort
-// Bitonic network in which every compare-exchange puts the smaller key at the
-// lower index (the first step of each merge compares mirrored pairs: element e
-// with e ^ (k - 1) inside its aligned block of k), so padding with +inf keys
-// never moves into the sorted range.
-//
-// k_tile_sort_small: each wavefront sorts one tile of at most kSmallSort keys
-// in registers: element e = 64 r + lane sits in register r of that lane, so a
-// compare-exchange at distance < 64 is a lane exchange (shuffle) and one at
-// distance >= 64 a swap between two registers of the same lane.  No LDS and no
-// barriers.
-// k_tile_sort_large: one block per longer tile; tiles longer than kSortCap use
-// the same network in global memory.
-
-__device__ __forceinline__ unsigned long long shfl_xor_u64(unsigned long long v, int m)
-{
-    const unsigned int lo = __shfl_xor((unsigned int)v, m, 64);
-    const unsigned int hi = __shfl_xor((unsigned int)(v >> 32), m, 64);
-    return ((unsigned long long)hi << 32) | lo;
-}
-
-__device__ __forceinline__ unsigned long long min_u64(unsigned long long a, unsigned long long b) { return a < b ? a : b; }
-__device__ __forceinline__ unsigned long long max_u64(unsigned long long a, unsigned long long b) { return a < b ? b : a; }
-
-// Sorts the n <= 64 R keys at key[0..n) ascending; one wavefront, lane `lane`.
-template <int R>
-__device__ __forceinline__ void wave_sort_regs(unsigned long long* key, int n, int lane)
-{
-    constexpr int P = 64 * R;
-    unsigned long long x[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int e = 64 * r + lane;
-        x[r] = e < n ? key[e] : ~0ull;
-    }
-#pragma unroll
-    for (int k = 2; k <= P; k <<= 1) {
-        // mirrored step: e <-> e ^ (k - 1); e is the lower index when bit k/2 of e is clear
-        if (k <= 64) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-                const unsigned long long o = shfl_xor_u64(x[r], k - 1);
-                x[r] = (lane & (k >> 1)) == 0 ? min_u64(x[r], o) : max_u64(x[r], o);
-            }
-        } else {
-            const int jr = k / 64 - 1;  // partner: register r ^ jr of lane ^ 63
-            unsigned long long o[R];
-#pragma unroll
-            for (int r = 0; r < R; ++r) o[r] = shfl_xor_u64(x[r ^ jr], 63);
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-                x[r] = ((64 * r) & (k >> 1)) == 0 ? min_u64(x[r], o[r]) : max_u64(x[r], o[r]);
-        }
-        // half-cleaner steps: e <-> e ^ j, j = k/4 .. 1
-#pragma unroll
-        for (int j = k >> 2; j > 0; j >>= 1) {
-            if (j >= 64) {
-                const int jr = j / 64;
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    if ((r & jr) == 0) {
-                        const unsigned long long a = x[r], b = x[r | jr];
-                        x[r] = min_u64(a, b);
-                        x[r | jr] = max_u64(a, b);
-                    }
-                }
-            } else {
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const unsigned long long o = shfl_xor_u64(x[r], j);
-                    x[r] = (lane & j) == 0 ? min_u64(x[r], o) : max_u64(x[r], o);
-                }
-            }
-        }
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const int e = 64 * r + lane;
-        if (e < n) key[e] = x[r];
-    }
-}
-
-__global__ void __launch_bounds__(256) k_tile_sort_small(RParams rp, WsPtrs w, int n_tiles)
-{
-    if (w.hdr->n_inst > rp.cap) return;
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int tile = blockIdx.x * 4 + wid;
-    if (tile >= n_tiles) return;
-    const unsigned int s = w.tile_start[tile], e = w.tile_start[tile + 1];
-    const int n = (int)(e - s);
-    if (n <= 1 || (unsigned int)n >= kLongTile) return;
-    unsigned long long* key = w.keys + s;
-    if (n <= 64) wave_sort_regs<1>(key, n, lane);
-    else if (n <= 128) wave_sort_regs<2>(key, n, lane);
-    else if (n <= 256) wave_sort_regs<4>(key, n, lane);
-    else wave_sort_regs<8>(key, n, lane);
-}
+// Tiles of fewer than kLongTile keys are sorted in registers by the first
+// wavefront of their compositing block (wave_sort_tile, binning.h).
+// k_tile_sort_large: one block per longer tile (bitonic network in LDS, the
+// same compare-exchange order); tiles longer than kSortCap use the same network
+// in global memory.
 
 __device__ __forceinline__ void cas_lds(unsigned long long* sh, int i, int j)
 {
@@ -718,7 +627,6 @@ gps_status launch_render_fwd(const gps_render_cfg* cfg, const RParams& rp, const
     GPS_LAUNCH(K_SCAN_TILES, s, k_scan_tiles, dim3(1), dim3(1024), 0, s, rp, w, L.n_tiles);
     if (L.nblk_vg > 0)
         GPS_LAUNCH(K_EMIT, s, k_expand<true>, dim3(L.nblk_vg * (kBlk / kExpG)), dim3(kBlk), 0, s, dvt, rp, w);
-    GPS_LAUNCH(K_TILE_SORT, s, k_tile_sort_small, dim3((L.n_tiles + 3) / 4), dim3(256), 0, s, rp, w, L.n_tiles);
     GPS_LAUNCH(K_TILE_SORT_LARGE, s, k_tile_sort_large, dim3(L.n_tiles), dim3(256), kSortCap * sizeof(unsigned long long),
                s, rp, w);
     if (!dispatch_cfwd(cfg, dvt, rp, w, L.n_tiles, s)) return GPS_ERR_UNSUPPORTED_CONFIG;
