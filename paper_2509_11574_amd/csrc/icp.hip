@@ -5,11 +5,11 @@
 //                  association into the previous frame's raycast depth, the
 //                  model vertex and vertex-map normal there, the point-to-plane
 //                  residual r and its Jacobian J = (N, p x N) for a left
-//                  perturbation of the camera-to-world pose; per block of 256
-//                  pixels the 29 sums (upper triangle of J J^T, J r, r^2, count)
-//                  in a fixed order
+//                  perturbation of the camera-to-world pose; at most 1024
+//                  blocks of 256 lanes, each lane taking every (256 x blocks)-th
+//                  pixel; per block the 29 sums (upper triangle of J J^T, J r,
+//                  r^2, count) in a fixed order
 //   k_icp_total    one block: the block sums in binary64, in a fixed order
-//                  (at most 1024 block partials: larger levels loop per lane)
 //   k_icp_solve    one lane: Cholesky solve of H xi = -g in binary64 and the
 //                  update T_{g,k} <- Exp(xi) T_{g,k} of the device pose
 // No atomics: the system is bitwise reproducible.  Every stage reads the pose
