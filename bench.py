@@ -30,7 +30,7 @@ ITERS_PER_FRAME = 10
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 
-# Algorithmic operation counts of the compositing kernels (see DESIGN.md):
+# Algorithmic operation counts of the compositing kernels:
 # every evaluated (pixel, instance) pair costs 15 flops for the opacity of Eq. 3,
 # every composited pair 11 more in the forward and 66 more in the backward.
 FLOPS_EVAL = 15
@@ -114,7 +114,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported in this build "
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the path shards by view across GPUs by design, but no multi-GPU run is made).", file=sys.stderr)
         sys.exit(2)
     import numpy as np
