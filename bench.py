@@ -202,8 +202,7 @@ def main():
         P.gps.views_upload(cfg, params, [view], ws)
         for _ in range(ITERS_PER_FRAME):
             P.render_fwd(cfg_pre, params, [view], ws, out_loss=loss)
-            P.render_bwd(cfg_pre, params, [view], ws, grads, dpose)
-            opt.step(grads)
+            P.render_bwd_adam(cfg_pre, params, [view], ws, opt, dpose=dpose)  # backward with Adam fused in
         return view
 
     graph = None
@@ -221,7 +220,7 @@ def main():
     if args.graph:
         from paper_2509_11574_amd.graph import IterationGraph
         # captured on the last warm-up frame's view (capturing runs nothing on the device)
-        graph = IterationGraph(cfg, params, [last_view], ws, grads, opt, loss, dpose)
+        graph = IterationGraph(cfg, params, [last_view], ws, grads, opt, loss, dpose, fused_adam=True)
         frame_step = frame_step_graph
     torch.cuda.synchronize()
     st0 = ws.stats()
@@ -278,7 +277,7 @@ def main():
         alt_step, alt_mode = frame_step_eager, "eager"
     else:
         from paper_2509_11574_amd.graph import IterationGraph
-        graph = IterationGraph(cfg, params, [last_view], ws, grads, opt, loss, dpose)
+        graph = IterationGraph(cfg, params, [last_view], ws, grads, opt, loss, dpose, fused_adam=True)
         alt_step, alt_mode = frame_step_graph, "graph"
     if alt_step is not None:
         torch.cuda.synchronize()
@@ -317,8 +316,8 @@ def main():
                   + 12 * I + 8 * M + 16 * I          # emit (keys, slots), tile sort (read + write)
                   + 60 * I + 48 * Pp                 # composite fwd: keys/slots/records, base+target+out
                   + 60 * I + 40 * I + 64 * Pp        # composite bwd: instances, partials out, per-pixel in
-                  + 40 * I + 112 * M + 8 * M         # per-Gaussian reduce: partials, params in, grads out
-                  + 392 * M)                         # Adam: 14 scalars x 28 B
+                  + 40 * I + 56 * M + 8 * M          # per-Gaussian reduce: partials, params in, slot offsets
+                  + 336 * M)                         # Adam in its epilogue: 14 scalars x 24 B (p, m, v in + out)
     iter_ms = None
     if kernels:
         it_kernels = ("project", "scan", "count", "scan_tiles", "emit", "tile_sort",

@@ -271,6 +271,25 @@ gps_status gps_views_upload(const gps_render_cfg* cfg, const gps_gaussians* g, c
 gps_status gps_adam_step(const gps_adam_group* groups, int32_t n_groups, int32_t step, int32_t* step_counter,
                          float beta1, float beta2, float eps, void* stream);
 
+/* ---- Backward with the Adam step in its epilogue (one optimisation iteration's
+ * backward + Adam without the separate Adam launch).  The same as gps_render_bwd
+ * followed by gps_adam_step over the five attribute groups with the learning
+ * rates below, and bitwise the same parameters, moments and counter; `g` is
+ * updated in place after its gradient is formed.  grads may be NULL (the
+ * gradients are then not stored). */
+typedef struct gps_adam_fused {
+    gps_gaussians m, v;   /* first and second moments (device), same layout and count as g */
+    float lr_mean, lr_log_scale, lr_quat, lr_opacity, lr_rgb;
+    float beta1, beta2, eps;
+    int32_t step;         /* 1-based step, used when step_counter is NULL */
+    int32_t* step_counter;/* device int32 or NULL: t = *step_counter + 1, incremented afterwards */
+} gps_adam_fused;
+
+gps_status gps_render_bwd_adam(const gps_render_cfg* cfg, gps_gaussians* g, const gps_view* views, int32_t n_views,
+                               const float* const* dL_drgb, const float* const* dL_ddepth, const float* loss_scale,
+                               gps_gaussians* grads, float* dpose, const gps_adam_fused* adam, void* ws,
+                               size_t ws_bytes, void* stream);
+
 /* ---- Gaussian removal (Sec. 3.2.2, Eq. 8) ---------------------------------
  * A Gaussian is removed when its opacity sigmoid(o) is below min_opacity, or its
  * largest scale exp(l) is above max_scale or below min_scale (0.005, 0.1 and

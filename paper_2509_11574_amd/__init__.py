@@ -7,9 +7,9 @@ from . import gps
 from .gps import (Adam, Camera, GpsError, Render, RenderCfg, RenderLoss, Session, View, Volume, Workspace,
                   adam_step, camera, depth_downsample, fuse, gaussians_to_device, icp_reduce, icp_solve, icp_track,
                   insert_gaussians, lib, pose_tensor, raycast, remove_gaussians,
-                  render_bwd, render_fwd, workspace_size, zeros_like_gaussians, PAPER_LR, TILE_CONFIGS)
+                  render_bwd, render_bwd_adam, render_fwd, workspace_size, zeros_like_gaussians, PAPER_LR, TILE_CONFIGS)
 
 __all__ = ["gps", "Adam", "Camera", "GpsError", "Render", "RenderCfg", "RenderLoss", "Session", "View", "Volume",
            "Workspace", "adam_step", "camera", "depth_downsample", "fuse", "gaussians_to_device", "icp_reduce",
            "icp_solve", "icp_track", "insert_gaussians", "lib", "pose_tensor", "raycast",
-           "remove_gaussians", "render_bwd", "render_fwd", "workspace_size", "zeros_like_gaussians", "PAPER_LR", "TILE_CONFIGS"]
+           "remove_gaussians", "render_bwd", "render_bwd_adam", "render_fwd", "workspace_size", "zeros_like_gaussians", "PAPER_LR", "TILE_CONFIGS"]

@@ -2,6 +2,7 @@
 // rates of Appendix C are supplied by the caller).  HBM-streaming: every
 // scalar reads param, grad, m, v and writes param, m, v (28 bytes).  Groups
 // whose arrays are 16-byte aligned with n % 4 == 0 are processed as float4.
+#include "adam_math.h"
 #include "gps_internal.h"
 #include "launch.h"
 #include "prof.h"
@@ -25,25 +26,11 @@ struct AdamArgs {
     float b1, b2, eps;
 };
 
-__device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, float lr, float b1, float b2,
-                                         float eps, float ibc1, float ibc2)
-{
-    m = b1 * m + (1.0f - b1) * g;
-    v = b2 * v + (1.0f - b2) * g * g;
-    const float mh = m * ibc1, vh = v * ibc2;
-    p -= lr * mh / (sqrtf(vh) + eps);
-}
-
 __global__ void __launch_bounds__(256) k_adam(AdamArgs a)
 {
-    // Bias corrections 1 / (1 - beta^t), in double (1 - beta^t loses digits in
-    // binary32 for small t), computed once per block and shared through LDS.
+    // bias corrections, computed once per block and shared through LDS
     __shared__ float sbc[2];
-    if (threadIdx.x == 0) {
-        const int t = a.step_ctr ? (*a.step_ctr + 1) : a.step;
-        sbc[0] = (float)(1.0 / (1.0 - pow((double)a.b1, (double)t)));
-        sbc[1] = (float)(1.0 / (1.0 - pow((double)a.b2, (double)t)));
-    }
+    if (threadIdx.x == 0) adam_bias(a.step_ctr ? (*a.step_ctr + 1) : a.step, a.b1, a.b2, &sbc[0], &sbc[1]);
     __syncthreads();
     const float ibc1 = sbc[0], ibc2 = sbc[1];
     const long long total = a.start[a.ng];
@@ -112,6 +99,11 @@ gps_status launch_adam(const gps_adam_group* groups, int n_groups, int step, int
     }
     if (step_counter) GPS_LAUNCH(K_STEP_INCR, s, k_step_incr, dim3(1), dim3(64), 0, s, step_counter);
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
+}
+
+void launch_step_incr(int* step_counter, hipStream_t s)
+{
+    GPS_LAUNCH(K_STEP_INCR, s, k_step_incr, dim3(1), dim3(64), 0, s, step_counter);
 }
 
 }  // namespace gps

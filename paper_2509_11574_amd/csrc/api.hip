@@ -298,9 +298,10 @@ gps_status gps_render_fwd(const gps_render_cfg* cfg, const gps_gaussians* g, con
     return launch_render_fwd(cfg, rp, g, vt, L, static_cast<char*>(ws), out_loss, (hipStream_t)stream);
 }
 
-gps_status gps_render_bwd(const gps_render_cfg* cfg, const gps_gaussians* g, const gps_view* views, int32_t n_views,
-                          const float* const* dL_drgb, const float* const* dL_ddepth, const float* loss_scale,
-                          gps_gaussians* grads, float* dpose, void* ws, size_t ws_bytes, void* stream)
+static gps_status render_bwd_common(const gps_render_cfg* cfg, const gps_gaussians* g, const gps_view* views,
+                                    int32_t n_views, const float* const* dL_drgb, const float* const* dL_ddepth,
+                                    const float* loss_scale, gps_gaussians* grads, float* dpose,
+                                    const gps_adam_fused* adam, void* ws, size_t ws_bytes, void* stream)
 {
     ViewTable vt;
     RParams rp;
@@ -309,9 +310,24 @@ gps_status gps_render_bwd(const gps_render_cfg* cfg, const gps_gaussians* g, con
     if (st != GPS_OK) return st;
     if (!ws || ((uintptr_t)ws & 255)) return GPS_ERR_INVALID_ARG;
     if (ws_bytes < L.total) return GPS_ERR_WORKSPACE_TOO_SMALL;
-    if (!grads || grads->count != g->count) return GPS_ERR_INVALID_ARG;
-    if (g->count > 0 && (!grads->mean || !grads->log_scale || !grads->quat || !grads->opacity_logit || !grads->rgb))
+    if (!grads && !adam) return GPS_ERR_INVALID_ARG;
+    if (grads && (grads->count != g->count ||
+                  (g->count > 0 && (!grads->mean || !grads->log_scale || !grads->quat || !grads->opacity_logit ||
+                                    !grads->rgb))))
         return GPS_ERR_INVALID_ARG;
+    if (adam) {
+        const gps_gaussians* mv[2] = {&adam->m, &adam->v};
+        for (const gps_gaussians* x : mv)
+            if (x->count != g->count ||
+                (g->count > 0 && (!x->mean || !x->log_scale || !x->quat || !x->opacity_logit || !x->rgb)))
+                return GPS_ERR_INVALID_ARG;
+        const float lr[5] = {adam->lr_mean, adam->lr_log_scale, adam->lr_quat, adam->lr_opacity, adam->lr_rgb};
+        for (float x : lr)
+            if (!std::isfinite(x)) return GPS_ERR_INVALID_ARG;
+        if (!(adam->beta1 >= 0.0f && adam->beta1 < 1.0f) || !(adam->beta2 >= 0.0f && adam->beta2 < 1.0f) ||
+            !(adam->eps > 0.0f) || (!adam->step_counter && adam->step < 1))
+            return GPS_ERR_INVALID_ARG;
+    }
     const int explicit_up = dL_drgb != nullptr;
     for (int v = 0; v < n_views; ++v) {
         if (explicit_up) {
@@ -324,8 +340,27 @@ gps_status gps_render_bwd(const gps_render_cfg* cfg, const gps_gaussians* g, con
     }
     st = check_device();
     if (st != GPS_OK) return st;
-    return launch_render_bwd(cfg, rp, g, vt, L, static_cast<char*>(ws), explicit_up, loss_scale, grads, dpose,
+    return launch_render_bwd(cfg, rp, g, vt, L, static_cast<char*>(ws), explicit_up, loss_scale, grads, dpose, adam,
                              (hipStream_t)stream);
+}
+
+gps_status gps_render_bwd(const gps_render_cfg* cfg, const gps_gaussians* g, const gps_view* views, int32_t n_views,
+                          const float* const* dL_drgb, const float* const* dL_ddepth, const float* loss_scale,
+                          gps_gaussians* grads, float* dpose, void* ws, size_t ws_bytes, void* stream)
+{
+    if (!grads) return GPS_ERR_INVALID_ARG;
+    return render_bwd_common(cfg, g, views, n_views, dL_drgb, dL_ddepth, loss_scale, grads, dpose, nullptr, ws,
+                             ws_bytes, stream);
+}
+
+gps_status gps_render_bwd_adam(const gps_render_cfg* cfg, gps_gaussians* g, const gps_view* views, int32_t n_views,
+                               const float* const* dL_drgb, const float* const* dL_ddepth, const float* loss_scale,
+                               gps_gaussians* grads, float* dpose, const gps_adam_fused* adam, void* ws,
+                               size_t ws_bytes, void* stream)
+{
+    if (!adam) return GPS_ERR_INVALID_ARG;
+    return render_bwd_common(cfg, g, views, n_views, dL_drgb, dL_ddepth, loss_scale, grads, dpose, adam, ws,
+                             ws_bytes, stream);
 }
 
 gps_status gps_views_upload(const gps_render_cfg* cfg, const gps_gaussians* g, const gps_view* views,

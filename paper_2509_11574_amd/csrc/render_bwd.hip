@@ -6,7 +6,10 @@
 //       range per view, summed in order), apply the EWA chain rule to the
 //       parameters and form the per-Gaussian pose terms, reduced per block.
 //   k_pose_reduce per view: sum the block pose partials in order.
+//   With Adam in the epilogue (gps_render_bwd_adam), k_gauss_bwd also applies
+//   the Adam step to its Gaussian and k_pose_reduce advances the step counter.
 // No floating-point atomics: results are bitwise reproducible.
+#include "adam_math.h"
 #include "launch.h"
 #include "prof.h"
 #include "render_common.h"
@@ -19,7 +22,21 @@ constexpr unsigned int kCoopSlots = 32;  // more slots than this: summed by the 
 // EWA chain rule of one Gaussian in one view.  The summed instance partials are
 // first turned into A[10] = dL/d(mx, my, a, b, c), sigma dL/dsigma, dL/d(r, g, b, d),
 // where (a, b, c) is the conic and b multiplies 2 dx dy.
-__global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict__ vtp, RParams rp, GParams gp, GGrads gg, WsPtrs w)
+// Adam applied in the epilogue of k_gauss_bwd: the five attribute groups (mean,
+// log-scale, quaternion, opacity logit, rgb), each with its learning rate.
+struct AdamFuse {
+    float* p[5];
+    float* m[5];
+    float* v[5];
+    float lr[5];
+    const int* step_ctr;
+    int step;
+    float b1, b2, eps;
+    int on;
+};
+
+__global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict__ vtp, RParams rp, GParams gp, GGrads gg,
+                                                    WsPtrs w, AdamFuse af)
 {
     const ViewTable& vt = *vtp;
     const int M = rp.M;
@@ -28,6 +45,11 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
     const bool live = g < M;
     float gmean[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.0f, grgb[3] = {0, 0, 0};
     __shared__ float pred[kBlk / 64][6];
+    __shared__ float sbc[2];
+    if (af.on) {
+        if (threadIdx.x == 0) adam_bias(af.step_ctr ? (*af.step_ctr + 1) : af.step, af.b1, af.b2, &sbc[0], &sbc[1]);
+        __syncthreads();
+    }
 
     float m0 = 0, m1 = 0, m2 = 0, qw = 1, qx = 0, qy = 0, qz = 0, qn = 1, s[3] = {1, 1, 1}, sig = 0.5f;
     float Rq[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
@@ -268,7 +290,7 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
         }
         __syncthreads();
     }
-    if (live) {
+    if (live && gg.mean) {
         gg.mean[g] = gmean[0];
         gg.mean[M + g] = gmean[1];
         gg.mean[2 * M + g] = gmean[2];
@@ -284,10 +306,31 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
         gg.rgb[M + g] = grgb[1];
         gg.rgb[2 * M + g] = grgb[2];
     }
+    if (live && af.on) {
+        // this lane's Gaussian only: its parameters were read above by this lane alone
+        const float ibc1 = sbc[0], ibc2 = sbc[1];
+        const float* gr[5] = {gmean, gls, gq, &gop, grgb};
+        const int rows[5] = {3, 3, 4, 1, 3};
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r < rows[a]) {
+                    const size_t i = (size_t)r * M + g;
+                    float p = af.p[a][i], m = af.m[a][i], v = af.v[a][i];
+                    adam_one(p, gr[a][r], m, v, af.lr[a], af.b1, af.b2, af.eps, ibc1, ibc2);
+                    af.p[a][i] = p;
+                    af.m[a][i] = m;
+                    af.v[a][i] = v;
+                }
+    }
 }
 
-__global__ void __launch_bounds__(256) k_pose_reduce(RParams rp, WsPtrs w, int nblk, float* dpose)
+__global__ void __launch_bounds__(256) k_pose_reduce(RParams rp, WsPtrs w, int nblk, float* dpose, int* step_ctr)
 {
+    // the Adam step counter of a backward with Adam in its epilogue (one lane,
+    // vector memory path: the address depends on the lane id)
+    if (step_ctr && blockIdx.x == 0 && threadIdx.x == 0) step_ctr[threadIdx.x] += 1;
     // One block per view: the six components summed per lane over the blocks (in
     // strides), per wavefront (DPP), then over the four wavefronts in order.
     const int v = blockIdx.x, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -457,11 +500,32 @@ __global__ void __launch_bounds__(kBlk) k_gauss_pixel_bwd(const ViewTable* __res
 // ----------------------------------------------------------------- launch
 gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const gps_gaussians* g,
                              const ViewTable& vt, const WsLayout& L, char* ws, int explicit_upstream,
-                             const float* loss_scale, gps_gaussians* grads, float* dpose, hipStream_t s)
+                             const float* loss_scale, gps_gaussians* grads, float* dpose, const gps_adam_fused* adam,
+                             hipStream_t s)
 {
     WsPtrs w = ws_ptrs(ws, L);
     GParams gp{g->mean, g->log_scale, g->quat, g->opacity_logit, g->rgb};
-    GGrads gg{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->rgb};
+    GGrads gg{nullptr, nullptr, nullptr, nullptr, nullptr};
+    if (grads) gg = GGrads{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->rgb};
+    AdamFuse af{};
+    af.on = adam != nullptr;
+    if (adam) {
+        float* const pp[5] = {g->mean, g->log_scale, g->quat, g->opacity_logit, g->rgb};
+        float* const mm[5] = {adam->m.mean, adam->m.log_scale, adam->m.quat, adam->m.opacity_logit, adam->m.rgb};
+        float* const vv[5] = {adam->v.mean, adam->v.log_scale, adam->v.quat, adam->v.opacity_logit, adam->v.rgb};
+        const float lr[5] = {adam->lr_mean, adam->lr_log_scale, adam->lr_quat, adam->lr_opacity, adam->lr_rgb};
+        for (int k = 0; k < 5; ++k) {
+            af.p[k] = pp[k];
+            af.m[k] = mm[k];
+            af.v[k] = vv[k];
+            af.lr[k] = lr[k];
+        }
+        af.step_ctr = adam->step_counter;
+        af.step = adam->step;
+        af.b1 = adam->beta1;
+        af.b2 = adam->beta2;
+        af.eps = adam->eps;
+    }
     const ViewTable* dvt = reinterpret_cast<const ViewTable*>(ws + L.vtab);
     if (!(cfg->flags & GPS_RENDER_VIEWS_PRESET)) {
         gps_status st = launch_views_upload(vt, rp, L, ws, 0, s);
@@ -481,9 +545,13 @@ gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const
         return GPS_ERR_UNSUPPORTED_CONFIG;
     }
     if (L.nblk_g > 0) {
-        GPS_LAUNCH(K_GAUSS_BWD, s, k_gauss_bwd, dim3(L.nblk_g), dim3(kBlk), 0, s, dvt, rp, gp, gg, w);
-        if (dpose) GPS_LAUNCH(K_POSE_REDUCE, s, k_pose_reduce, dim3(vt.n), dim3(256), 0, s, rp, w, L.nblk_g, dpose);
+        GPS_LAUNCH(K_GAUSS_BWD, s, k_gauss_bwd, dim3(L.nblk_g), dim3(kBlk), 0, s, dvt, rp, gp, gg, w, af);
     }
+    int* ctr = adam ? adam->step_counter : nullptr;
+    if (dpose && L.nblk_g > 0)
+        GPS_LAUNCH(K_POSE_REDUCE, s, k_pose_reduce, dim3(vt.n), dim3(256), 0, s, rp, w, L.nblk_g, dpose, ctr);
+    else if (ctr)
+        launch_step_incr(ctr, s);
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
 }
 

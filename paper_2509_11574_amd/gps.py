@@ -94,7 +94,7 @@ EXPORTS = ["gps_abi_version", "gps_status_string", "gps_render_cfg_default", "gp
            "gps_profile_read", "gps_views_upload", "gps_removal_cfg_default", "gps_removal_workspace_size",
            "gps_remove_gaussians", "gps_insert_cfg_default", "gps_insertion_workspace_size",
            "gps_insert_gaussians", "gps_depth_downsample", "gps_icp_workspace_size", "gps_icp_reduce",
-           "gps_icp_solve"]
+           "gps_icp_solve", "gps_render_bwd_adam"]
 
 _lib = None
 
@@ -138,6 +138,7 @@ def lib():
         L.gps_icp_workspace_size.argtypes = [I32, I32, ctypes.POINTER(ctypes.c_size_t)]
         L.gps_icp_reduce.argtypes = [P, P, P, P, P, F, P, P, ctypes.c_size_t, P]
         L.gps_icp_solve.argtypes = [P, P, P, P]
+        L.gps_render_bwd_adam.argtypes = [P, P, P, I32, P, P, P, P, P, P, P, ctypes.c_size_t, P]
         for n in EXPORTS:
             if n not in ("gps_render_cfg_default", "gps_status_string", "gps_abi_version", "gps_removal_cfg_default",
                          "gps_insert_cfg_default"):
@@ -451,6 +452,41 @@ def render_bwd(cfg: RenderCfg, gauss: dict, views, ws: Workspace, grads: dict, d
                                 _ptr(loss_scale, "loss_scale", 1) if loss_scale is not None else None,
                                 ctypes.byref(gg), _ptr(dpose, "dpose", 6 * V) if dpose is not None else None,
                                 ws.ptr(), ws.nbytes, _stream(stream)), "gps_render_bwd")
+
+
+class AdamFusedS(ctypes.Structure):
+    _fields_ = [("m", GaussiansS), ("v", GaussiansS), ("lr_mean", ctypes.c_float), ("lr_log_scale", ctypes.c_float),
+                ("lr_quat", ctypes.c_float), ("lr_opacity", ctypes.c_float), ("lr_rgb", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("step", ctypes.c_int32), ("step_counter", ctypes.c_void_p)]
+
+
+def render_bwd_adam(cfg: RenderCfg, gauss: dict, views, ws: Workspace, opt: "Adam", grads: dict | None = None,
+                    dpose: torch.Tensor | None = None, dL_drgb=None, dL_ddepth=None,
+                    loss_scale: torch.Tensor | None = None, stream=None):
+    """Backward with the Adam step of `opt` applied in its epilogue (gps_render_bwd_adam):
+    the same parameters, moments and step counter as render_bwd followed by opt.step."""
+    cs = cfg.struct()
+    gs = gaussians_struct(gauss)
+    gg = gaussians_struct(grads) if grads is not None else None
+    va = _views_array(views)
+    V = len(views)
+    rgb_arr = dep_arr = None
+    if dL_drgb is not None:
+        rgb_arr = (ctypes.c_void_p * V)(*[_ptr(t, "dL_drgb").value for t in dL_drgb])
+        if dL_ddepth is not None:
+            dep_arr = (ctypes.c_void_p * V)(*[_ptr(t, "dL_ddepth").value if t is not None else None
+                                             for t in dL_ddepth])
+    opt.t += 1
+    af = AdamFusedS(gaussians_struct(opt.m), gaussians_struct(opt.v), float(opt.lr["mean"]),
+                    float(opt.lr["log_scale"]), float(opt.lr["quat"]), float(opt.lr["opacity_logit"]),
+                    float(opt.lr["rgb"]), opt.b1, opt.b2, opt.eps, opt.t,
+                    ctypes.c_void_p(opt.counter.data_ptr()) if opt.counter is not None else None)
+    _check(lib().gps_render_bwd_adam(ctypes.byref(cs), ctypes.byref(gs), va, V, rgb_arr, dep_arr,
+                                     _ptr(loss_scale, "loss_scale", 1) if loss_scale is not None else None,
+                                     ctypes.byref(gg) if gg is not None else None,
+                                     _ptr(dpose, "dpose", 6 * V) if dpose is not None else None,
+                                     ctypes.byref(af), ws.ptr(), ws.nbytes, _stream(stream)), "gps_render_bwd_adam")
 
 
 # Learning rates per attribute (Appendix C): position, SH0 (applied to rgb),

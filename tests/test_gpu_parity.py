@@ -434,7 +434,8 @@ def test_long_tile_lists(P, O, M):
 
 
 # ------------------------------------------------------------- graph / tuner
-def test_graph_replay_matches_eager(P, O):
+@pytest.mark.parametrize("fused_adam", [False, True])
+def test_graph_replay_matches_eager(P, O, fused_adam):
     """A captured iteration (forward + backward + Adam) replayed several times, with eager work and
     synchronisation between replays, gives bitwise the eager parameters after every replay, also
     after a new camera pose is uploaded."""
@@ -461,7 +462,7 @@ def test_graph_replay_matches_eager(P, O):
         opt.step(grads)
         snaps.append({k: h(x) for k, x in params.items()})
     params, view, view2, ws, grads, opt, loss = setup()
-    g = IterationGraph(gc, params, [view], ws, grads, opt, loss)
+    g = IterationGraph(gc, params, [view], ws, grads, opt, loss, fused_adam=fused_adam)
     for i in range(5):
         if i == 3:
             g.set_views([view2])
