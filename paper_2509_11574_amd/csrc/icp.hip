@@ -191,17 +191,30 @@ __global__ void __launch_bounds__(256) k_icp_pairs(IcpArgs a)
     }
 }
 
-// Wavefront w sums the terms w and w + 16 over the block partials: lane l takes
-// blocks l, l + 64, ... in binary64, then a fixed butterfly across the lanes.
+// Wavefront w sums the terms w and w + 16 over the block partials (both in one
+// pass, so their loads overlap): lane l takes blocks l, l + 64, ... in binary64,
+// then a fixed butterfly across the lanes.
 __global__ void __launch_bounds__(1024) k_icp_total(const float* __restrict__ part, int nblk, double* __restrict__ sys)
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    for (int k = wid; k < kIcpTerms; k += 16) {
-        double s = 0.0;
-        for (int b = lane; b < nblk; b += 64) s += (double)part[(size_t)k * nblk + b];
+    const int k0 = wid, k1 = wid + 16;
+    const bool two = k1 < kIcpTerms;
+    const float* p0 = part + (size_t)k0 * nblk;
+    const float* p1 = part + (size_t)(two ? k1 : k0) * nblk;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll 4
+    for (int b = lane; b < nblk; b += 64) {
+        s0 += (double)p0[b];
+        s1 += (double)p1[b];
+    }
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
-        if (lane == 0) sys[k] = s;
+    for (int o = 32; o > 0; o >>= 1) {
+        s0 += __shfl_xor(s0, o, 64);
+        s1 += __shfl_xor(s1, o, 64);
+    }
+    if (lane == 0) {
+        sys[k0] = s0;
+        if (two) sys[k1] = s1;
     }
 }
 
