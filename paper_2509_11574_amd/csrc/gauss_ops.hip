@@ -136,8 +136,9 @@ gps_status launch_remove_gaussians(const gps_removal_cfg* cfg, const gps_gaussia
 
 // ------------------------------------------------------------------ insertion
 // Gaussian insertion (Sec. 3.2.2, Eq. 6; Appendix A).
-//   k_insert_flags  per pixel: mask (bit 0) and sample (bit 1) flags; per block
-//                   of 256 pixels, the number taken
+//   k_insert_flags  per pixel: mask (bit 0) and sample (bit 1) flags and the
+//                   mask depth (the depth on mask pixels, 0 elsewhere); per
+//                   block of 256 pixels, the number taken
 //   k_insert_scan   one block: block offsets, total taken -> out_count
 //   k_insert_place  per taken pixel: its row-major output position
 //   k_insert_init   per new Gaussian: its surface point, normal, scale, rotation
