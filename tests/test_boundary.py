@@ -204,3 +204,36 @@ def test_icp_argument_checks(P):
     bad = P.camera({**_cam(), "fx": 0.0})
     assert L.gps_icp_reduce(ctypes.byref(cam), p, ctypes.byref(bad), p, p, 0.1, sp, p, 1 << 20, None) == -1
     assert L.gps_icp_solve(None, p, None, None) == -1 and L.gps_icp_solve(sp, None, None, None) == -1
+
+
+def test_fused_adam_argument_checks(P):
+    """The backward with Adam in its epilogue refuses a missing Adam block, moments of the
+    wrong count, non-finite learning rates and betas outside [0, 1) before any launch
+    (status -1).  Every call here fails its argument checks, so nothing reaches a device."""
+    L = P.lib()
+    rc = P.RenderCfg()
+    cfg = rc.struct()
+    g = P.gps.GaussiansS()
+    v = (P.gps.ViewS * 1)()
+    v[0].cam = P.camera(_cam())
+    img = ctypes.cast((ctypes.c_float * (4 * 64 * 48))(), ctypes.c_void_p)   # host stand-ins: never read
+    for f in ("base_rgb", "base_depth", "target_rgb", "target_depth", "out_rgb", "out_depth"):
+        setattr(v[0], f, img)
+    nbytes = P.workspace_size(rc, 0, [_cam()])
+    raw = (ctypes.c_uint8 * (nbytes + 256))()
+    wsp = ctypes.c_void_p((ctypes.addressof(raw) + 255) & ~255)
+
+    def call(af):
+        return L.gps_render_bwd_adam(ctypes.byref(cfg), ctypes.byref(g), v, 1, None, None, None, None, None,
+                                     ctypes.byref(af) if af is not None else None, wsp, nbytes, None)
+    assert call(None) == -1
+    good = P.gps.AdamFusedS()
+    good.lr_mean = good.lr_log_scale = good.lr_quat = good.lr_opacity = good.lr_rgb = 1e-3
+    good.beta1, good.beta2, good.eps, good.step = 0.9, 0.999, 1e-15, 1
+    for field, value in (("lr_quat", float("nan")), ("beta1", 1.0), ("beta2", -0.1), ("eps", 0.0), ("step", 0)):
+        bad = P.gps.AdamFusedS.from_buffer_copy(good)
+        setattr(bad, field, value)
+        assert call(bad) == -1, field
+    bad = P.gps.AdamFusedS.from_buffer_copy(good)
+    bad.m.count = 5                                        # moments of another size
+    assert call(bad) == -1
