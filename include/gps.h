@@ -42,7 +42,7 @@
 extern "C" {
 #endif
 
-#define GPS_ABI_VERSION 2
+#define GPS_ABI_VERSION 3
 
 /* Size in floats of gps_volume.brick_min for an nx x ny x nz lattice. */
 #define GPS_BRICKS_(n) (((n) + 7) / 8)
@@ -107,6 +107,14 @@ typedef struct gps_view {
     const float* target_depth; /* [H][W]    observed depth D_k (0 = invalid)       */
     float* out_rgb;            /* [3][H][W] rendered C* (written by render_fwd)    */
     float* out_depth;          /* [H][W]    rendered D* (0 where D_t is invalid)   */
+    const float* pose_xi;      /* [6] or NULL: xi = (rho, phi); the view is rendered
+                                  from Exp(xi) T_cw instead of the camera's T_cw
+                                  (read on the device when the view table is
+                                  written: by render_fwd / render_bwd, or by
+                                  gps_views_upload for GPS_RENDER_VIEWS_PRESET)  */
+    float* out_aux;            /* [H][W] or NULL: written by render_fwd with the
+                                  final transmittance T_final (mode 0) or the
+                                  Gaussian weight W_G of Eq. 2 (mode 1)          */
 } gps_view;
 
 /* Renderer constants (each is a reading of the paper where it is silent). */
@@ -234,7 +242,11 @@ gps_status gps_raycast(const gps_volume* vol, const gps_camera* cams, int32_t n_
 gps_status gps_render_fwd(const gps_render_cfg* cfg, const gps_gaussians* g, const gps_view* views, int32_t n_views,
                           void* ws, size_t ws_bytes, float* out_loss, void* stream);
 
-/* Backward of gps_render_fwd.  The upstream adjoint is either
+/* Backward of gps_render_fwd: the analytic gradient of the loss (Eq. 7 plus the
+ * depth term) through the blend (Eq. 1, 2, 4 in mode 1, front-to-back over the
+ * SDF image in mode 0) and the opacity of Eq. 3, to the Gaussian parameters and
+ * the camera pose (Sec. 3.1; the paper's backward for its blend is described
+ * after Eq. 4 and in Appendix B).  The upstream adjoint is either
  *   - the fused loss (dL_drgb == NULL): dL/dC*, dL/dD* of the loss above,
  *     scaled by *loss_scale (device float; NULL = 1), or
  *   - explicit per-view images (dL_drgb, dL_ddepth: host arrays of n_views
@@ -246,7 +258,12 @@ gps_status gps_render_fwd(const gps_render_cfg* cfg, const gps_gaussians* g, con
  * floating-point atomics are used.
  * grads: gradients with respect to every attribute of g (overwritten).
  * dpose: [n_views][6] gradient with respect to xi = (rho, phi) of the left
- * perturbation T_cw <- Exp(xi) T_cw at xi = 0 (may be NULL). */
+ * perturbation T_cw <- Exp(xi) T_cw (may be NULL): at xi = 0, or at the view's
+ * pose_xi when it is set (the gradient at the perturbed pose times the
+ * transposed left Jacobian of SE(3) at xi).
+ * After a capacity overflow of the forward (sticky GPS_ERR_CAPACITY) no slot is
+ * read: every gradient and dpose is zero (and gps_render_bwd_adam leaves the
+ * parameters, moments and step counter unchanged). */
 gps_status gps_render_bwd(const gps_render_cfg* cfg, const gps_gaussians* g, const gps_view* views, int32_t n_views,
                           const float* const* dL_drgb, const float* const* dL_ddepth, const float* loss_scale,
                           gps_gaussians* grads, float* dpose, void* ws, size_t ws_bytes, void* stream);
@@ -330,20 +347,21 @@ gps_status gps_remove_gaussians(const gps_removal_cfg* cfg, const gps_gaussians*
  * short axis is the vertex-map normal N*(u) (normalised cross product of the
  * central differences of V*, turned to face the camera; the direction to the
  * camera where a neighbour has no surface): scales (s1, s1, flat_ratio s1),
- * s1 = min(scale_cap, sqrt(mean distance to the three nearest mask vertices)),
- * the nearest searched among the mask pixels of the (2 radius + 1)^2 window
- * (ties by pixel index; none: s1 = scale_cap). */
+ * s1 = min(scale_cap, root mean square distance to the three mask vertices
+ * nearest to V*(u)), searched over the whole mask (u itself excluded; with
+ * fewer than three other mask vertices the mean runs over those there are,
+ * with none s1 = scale_cap).  App. A prints the square root of the mean
+ * distance; the root mean square distance is the reading used here. */
 typedef struct gps_insert_cfg {
     float delta_c;     /* 0.05 */
     float delta_w;     /* 4 */
     float fraction;    /* 0.25 */
-    int32_t radius;    /* 4 (at most 8) */
     float scale_cap;   /* 0.1 */
     float flat_ratio;  /* 0.1 */
     float opacity;     /* 0.5 */
 } gps_insert_cfg;
 
-/* Fills `cfg` (host) with the paper's constants and a window radius of 4. */
+/* Fills `cfg` (host) with the paper's constants. */
 void gps_insert_cfg_default(gps_insert_cfg* cfg);
 
 /* Scratch bytes that gps_insert_gaussians needs for a width x height frame. */
@@ -357,7 +375,7 @@ gps_status gps_insertion_workspace_size(int32_t width, int32_t height, size_t* o
  * pixel order, those past the capacity are dropped; out_pixel (optional,
  * [capacity]) receives their pixel indices; *out_count (device int32) the
  * number of taken pixels (possibly above the capacity).  ws:
- * gps_insertion_workspace_size bytes, 256-byte aligned.  Four kernels. */
+ * gps_insertion_workspace_size bytes, 256-byte aligned.  Five kernels. */
 gps_status gps_insert_gaussians(const gps_insert_cfg* cfg, const gps_camera* cam, const float* render_rgb,
                                 const float* frame_rgb, const float* weight, const float* sdf_depth, const float* rand,
                                 gps_gaussians* out, int32_t* out_pixel, int32_t* out_count, void* ws, size_t ws_bytes,
@@ -376,6 +394,14 @@ gps_status gps_insert_gaussians(const gps_insert_cfg* cfg, const gps_camera* cam
  * valid (sum and division in binary64, rounded once).  The level's intrinsics
  * are f/2 and (c - 1/2)/2.  width, height >= 2. */
 gps_status gps_depth_downsample(const float* depth, int32_t width, int32_t height, float* out, void* stream);
+
+/* Host call: the camera of level `level` (0 = full resolution) of the depth
+ * hierarchy of `cam`: each level halves the size (integer division), the focal
+ * lengths, and maps the principal point to (c - 1/2) / 2 (the centre of a
+ * coarse pixel is the mean of its 2x2 block's centres); computed in binary64,
+ * rounded once.  R and t are copied.  GPS_ERR_INVALID_ARG for level outside
+ * 0..16 or a level smaller than one pixel. */
+gps_status gps_level_camera(const gps_camera* cam, int32_t level, gps_camera* out);
 
 /* Scratch bytes for gps_icp_reduce on a level of width x height pixels. */
 gps_status gps_icp_workspace_size(int32_t width, int32_t height, size_t* out_bytes);

@@ -41,9 +41,25 @@
  * Readings taken where the paper is silent are documented at each function.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/*
+ * Threads.  Pixels (raycast, render) and lattice points (fusion) are computed
+ * independently of each other, so their loops run on OpenMP threads; every
+ * output is the same whatever the thread count.  The backward computes each
+ * pixel's contributors in parallel and then adds the pixels' adjoints into the
+ * per-Gaussian sums serially, in pixel order, so its sums are the same as
+ * well.  orc_set_threads(n) sets the thread count (n <= 0 keeps the current
+ * one); it returns the count in effect.
+ */
+int32_t orc_set_threads(int32_t n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return (int32_t)omp_get_max_threads();
+}
 
 /* ------------------------------------------------------------------------- */
 /* Plain data passed in from Python (ctypes mirrors these exactly).           */
@@ -173,6 +189,7 @@ void orc_fuse(const orc_grid* g, double* tsdf, double* weight, double* rgb, doub
     const double mu = (double)g->trunc;
     const double wmax = (double)g->max_weight;
 
+#pragma omp parallel for collapse(2) schedule(static)
     for (int z = 0; z < g->nz; ++z)
         for (int y = 0; y < g->ny; ++y)
             for (int x = 0; x < g->nx; ++x) {
@@ -332,6 +349,7 @@ void orc_raycast(const orc_grid* g, const float* tsdf, const float* rgb, const o
         o64[a] = -((double)R[0 * 3 + a] * cam->t[0] + (double)R[1 * 3 + a] * cam->t[1] +
                    (double)R[2 * 3 + a] * cam->t[2]);
 
+#pragma omp parallel for schedule(dynamic, 64)
     for (int32_t k = 0; k < npix; ++k) {
         int32_t p = pix ? pix[k] : k;
         int col = p % cam->width, row = p / cam->width;
@@ -711,26 +729,30 @@ void orc_render(const orc_cfg* cfg, const orc_gauss* G, const orc_cam* cam, cons
     const int W = cam->width, H = cam->height;
     const size_t HW = (size_t)W * H;
     orc_proj* P = project_all(cfg, G, cam);
-    orc_cand* cand = (orc_cand*)malloc(sizeof(orc_cand) * (size_t)(G->count > 0 ? G->count : 1));
-    for (int32_t k = 0; k < npix; ++k) {
-        int32_t p = pix ? pix[k] : k;
-        int col = p % W, row = p / W;
-        float dt32 = base_depth[p];
-        int dvalid = dt32 > 0.0f;
-        float dcull32 = dvalid ? dt32 : INFINITY;
-        double Ct[3] = {base_rgb[p], base_rgb[HW + p], base_rgb[2 * HW + p]};
-        int32_t flag = 0;
-        int n = gather_candidates(cfg, P, G->count, (double)col, (double)row, dcull32, cand, &flag);
-        orc_pix r;
-        composite_pixel(cfg, P, G, cand, n, Ct, (double)dt32, dvalid, &r, &flag);
-        for (int c = 0; c < 3; ++c) out_rgb[(size_t)c * npix + k] = r.C[c];
-        out_depth[k] = r.D;
-        if (out_T) out_T[k] = r.T;
-        if (out_flag) out_flag[k] = flag;
-        if (out_n) out_n[k] = r.n_used;
-        if (out_W) out_W[k] = r.W;
+#pragma omp parallel
+    {
+        orc_cand* cand = (orc_cand*)malloc(sizeof(orc_cand) * (size_t)(G->count > 0 ? G->count : 1));
+#pragma omp for schedule(dynamic, 16)
+        for (int32_t k = 0; k < npix; ++k) {
+            int32_t p = pix ? pix[k] : k;
+            int col = p % W, row = p / W;
+            float dt32 = base_depth[p];
+            int dvalid = dt32 > 0.0f;
+            float dcull32 = dvalid ? dt32 : INFINITY;
+            double Ct[3] = {base_rgb[p], base_rgb[HW + p], base_rgb[2 * HW + p]};
+            int32_t flag = 0;
+            int n = gather_candidates(cfg, P, G->count, (double)col, (double)row, dcull32, cand, &flag);
+            orc_pix r;
+            composite_pixel(cfg, P, G, cand, n, Ct, (double)dt32, dvalid, &r, &flag);
+            for (int c = 0; c < 3; ++c) out_rgb[(size_t)c * npix + k] = r.C[c];
+            out_depth[k] = r.D;
+            if (out_T) out_T[k] = r.T;
+            if (out_flag) out_flag[k] = flag;
+            if (out_n) out_n[k] = r.n_used;
+            if (out_W) out_W[k] = r.W;
+        }
+        free(cand);
     }
-    free(cand);
     free(P);
 }
 
@@ -997,24 +1019,50 @@ void orc_render_bwd(const orc_cfg* cfg, const orc_gauss* G, const orc_cam* cam, 
     const size_t HW = (size_t)W * H;
     const int M = G->count;
     orc_proj* P = project_all(cfg, G, cam);
-    orc_cand* cand = (orc_cand*)malloc(sizeof(orc_cand) * (size_t)(M > 0 ? M : 1));
     double* acc = (double*)calloc((size_t)(M > 0 ? M : 1) * A_N, sizeof(double));
+    /* the pixels' contributors and forward values (in parallel), kept per pixel */
+    orc_cand** lists = (orc_cand**)calloc((size_t)(npix > 0 ? npix : 1), sizeof(orc_cand*));
+    int* counts = (int*)malloc(sizeof(int) * (size_t)(npix > 0 ? npix : 1));
+    orc_pix* fws = (orc_pix*)malloc(sizeof(orc_pix) * (size_t)(npix > 0 ? npix : 1));
+#pragma omp parallel
+    {
+        orc_cand* cand = (orc_cand*)malloc(sizeof(orc_cand) * (size_t)(M > 0 ? M : 1));
+#pragma omp for schedule(dynamic, 16)
+        for (int32_t k = 0; k < npix; ++k) {
+            int32_t p = pix ? pix[k] : k;
+            int col = p % W, row = p / W;
+            float dt32 = base_depth[p];
+            int dvalid = dt32 > 0.0f;
+            float dcull32 = dvalid ? dt32 : INFINITY;
+            double Ct[3] = {base_rgb[p], base_rgb[HW + p], base_rgb[2 * HW + p]};
+            double gD = dvalid ? g_pix_depth[k] : 0.0;
+            counts[k] = -1;
+            if (g_pix_rgb[k] == 0.0 && g_pix_rgb[(size_t)npix + k] == 0.0 && g_pix_rgb[2 * (size_t)npix + k] == 0.0 &&
+                gD == 0.0)
+                continue;
+            int32_t flag = 0;
+            int n = gather_candidates(cfg, P, M, (double)col, (double)row, dcull32, cand, &flag);
+            composite_pixel(cfg, P, G, cand, n, Ct, (double)dt32, dvalid, &fws[k], &flag);
+            lists[k] = (orc_cand*)malloc(sizeof(orc_cand) * (size_t)(n > 0 ? n : 1));
+            memcpy(lists[k], cand, sizeof(orc_cand) * (size_t)n);
+            counts[k] = n;
+        }
+        free(cand);
+    }
+    /* the adjoints, added in pixel order */
     for (int32_t k = 0; k < npix; ++k) {
+        if (counts[k] < 0) continue;
         int32_t p = pix ? pix[k] : k;
         int col = p % W, row = p / W;
-        float dt32 = base_depth[p];
-        int dvalid = dt32 > 0.0f;
-        float dcull32 = dvalid ? dt32 : INFINITY;
-        double Ct[3] = {base_rgb[p], base_rgb[HW + p], base_rgb[2 * HW + p]};
+        int dvalid = base_depth[p] > 0.0f;
         double gC[3] = {g_pix_rgb[k], g_pix_rgb[(size_t)npix + k], g_pix_rgb[2 * (size_t)npix + k]};
         double gD = dvalid ? g_pix_depth[k] : 0.0;
-        if (gC[0] == 0.0 && gC[1] == 0.0 && gC[2] == 0.0 && gD == 0.0) continue;
-        int32_t flag = 0;
-        int n = gather_candidates(cfg, P, M, (double)col, (double)row, dcull32, cand, &flag);
-        orc_pix fw;
-        composite_pixel(cfg, P, G, cand, n, Ct, (double)dt32, dvalid, &fw, &flag);
-        pixel_adjoint(cfg, P, G, cand, n, &fw, (double)col, (double)row, gC, gD, acc);
+        pixel_adjoint(cfg, P, G, lists[k], counts[k], &fws[k], (double)col, (double)row, gC, gD, acc);
+        free(lists[k]);
     }
+    free(lists);
+    free(counts);
+    free(fws);
     for (int i = 0; i < M; ++i) {
         if (!P[i].valid) continue;
         const double* A = acc + (size_t)i * A_N;
@@ -1023,7 +1071,6 @@ void orc_render_bwd(const orc_cfg* cfg, const orc_gauss* G, const orc_cam* cam, 
         projection_adjoint(&P[i], cam, A, M, i, g_mean, g_log_scale, g_quat, g_opacity, g_rgb, g_pose);
     }
     free(acc);
-    free(cand);
     free(P);
 }
 

@@ -21,7 +21,8 @@ _SRC = os.path.join(_HERE, "gps_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # -ffp-contract=off: every binary32 statement of the decision arithmetic rounds once.
-CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math"]
+# -fopenmp: independent pixels and lattice points on threads (results do not depend on the count).
+CFLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math", "-fopenmp"]
 
 
 def build(force: bool = True) -> str:
@@ -87,8 +88,15 @@ def lib():
         L.orc_adam.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, ctypes.c_double, ctypes.c_int32]
         L.orc_adam.restype = None
+        L.orc_set_threads.argtypes = [ctypes.c_int32]
+        L.orc_set_threads.restype = ctypes.c_int32
         _lib = L
     return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    """OpenMP threads of the reference (n <= 0 keeps the current count); returns the count in effect."""
+    return int(lib().orc_set_threads(int(n)))
 
 
 def _ptr(a):
@@ -373,38 +381,52 @@ def remove_gaussians(g, companions=(), **thresholds):
 #  * rotation: the quaternion (w, x, y, z) that turns the local z axis onto the
 #    normal, (1 + n_z, -n_y, n_x, 0) normalised, (0, 1, 0, 0) when n = -z;
 #  * opacity 0.5 (logit 0), colour C_k(u); new Gaussians in row-major pixel order.
-INSERT_DEFAULTS = {"delta_c": 0.05, "delta_w": 4.0, "fraction": 0.25, "radius": 4, "scale_cap": 0.1,
+INSERT_DEFAULTS = {"delta_c": 0.05, "delta_w": 4.0, "fraction": 0.25, "scale_cap": 0.1,
                    "flat_ratio": 0.1, "opacity": 0.5}
 
 
 def insertion_mask(render_rgb, frame_rgb, weight, sdf_depth, delta_c=0.05, delta_w=4.0):
-    """Eq. 6 mask (binary32 decisions), [H][W] bool."""
+    """Eq. 6 mask (binary32 decisions), [H][W] bool: an SDF surface, colour error (the
+    mean of the three absolute channel differences, as (|e0| + |e1|) + |e2| > 3 delta_c)
+    and Gaussian weight below delta_W.  Elementwise binary32 array arithmetic rounds
+    every operation once, as a scalar loop would."""
     C = np.asarray(render_rgb, np.float32)
     K = np.asarray(frame_rgb, np.float32)
-    H, W = C.shape[1], C.shape[2]
     t_c, t_w = np.float32(3.0 * delta_c), np.float32(delta_w)
     Wg = np.asarray(weight, np.float32)
     D = np.asarray(sdf_depth, np.float32)
-    mask = np.zeros((H, W), bool)
-    for j in range(H):
-        for i in range(W):
-            e = (np.float32(abs(C[0, j, i] - K[0, j, i])) + np.float32(abs(C[1, j, i] - K[1, j, i]))) + \
-                np.float32(abs(C[2, j, i] - K[2, j, i]))
-            mask[j, i] = D[j, i] > 0 and e > t_c and Wg[j, i] < t_w
-    return mask
+    e = (np.abs(C[0] - K[0]) + np.abs(C[1] - K[1])) + np.abs(C[2] - K[2])
+    assert e.dtype == np.float32
+    return (D > 0) & (e > t_c) & (Wg < t_w)
 
 
-def _backproject(cam, i, j, d):
+def _vertex_map(cam, D):
+    """World points V*(u) of every pixel with depth D (binary64), [H][W][3]; 0 where D = 0."""
+    H, W = D.shape
     R = np.asarray(cam["R"], np.float64).reshape(3, 3)
     t = np.asarray(cam["t"], np.float64).reshape(3)
-    xc = np.array([(i - cam["cx"]) / cam["fx"] * d, (j - cam["cy"]) / cam["fy"] * d, d])
-    return R.T @ (xc - t)
+    jj, ii = np.mgrid[0:H, 0:W]
+    d = D.astype(np.float64)
+    xc = np.stack([(ii - float(cam["cx"])) / float(cam["fx"]) * d, (jj - float(cam["cy"])) / float(cam["fy"]) * d, d],
+                  axis=-1)
+    V = (xc - t) @ R  # rows of R^T (x - t)
+    V[D <= 0] = 0.0
+    return V
 
 
 def insert_gaussians(cam, render_rgb, frame_rgb, weight, sdf_depth, rand, delta_c=0.05, delta_w=4.0,
-                     fraction=0.25, radius=4, scale_cap=0.1, flat_ratio=0.1, opacity=0.5):
+                     fraction=0.25, scale_cap=0.1, flat_ratio=0.1, opacity=0.5):
     """New Gaussians for the sampled mask pixels (dict of [rows][n] float64 arrays) and
-    their pixel indices (row-major)."""
+    their pixel indices (row-major).
+
+    Appendix A: the scale comes from the three mask vertices V*(u_1..3), u_k in the
+    whole mask M (not only the sample), closest to V*(u); u itself is not its own
+    neighbour.  The formula prints the square root of the mean distance; it is read
+    as the root mean square of the three distances (the 3DGS / RTG-SLAM
+    initialisation it follows): s1 = min(scale_cap, sqrt(mean of d_k^2)), s2 = s1,
+    s3 = flat_ratio * s1.  With fewer than three other mask vertices the mean runs
+    over those there are; with none, s1 = scale_cap.  The neighbours are found by
+    brute force over every mask vertex (binary64 distances)."""
     D = np.asarray(sdf_depth, np.float32)
     H, W = D.shape
     K = np.asarray(frame_rgb, np.float32)
@@ -412,12 +434,10 @@ def insert_gaussians(cam, render_rgb, frame_rgb, weight, sdf_depth, rand, delta_
     take = mask & (np.asarray(rand, np.float32) < np.float32(fraction))
     R = np.asarray(cam["R"], np.float64).reshape(3, 3)
     center = -R.T @ np.asarray(cam["t"], np.float64).reshape(3)
-    V = np.zeros((H, W, 3))
-    for j in range(H):
-        for i in range(W):
-            if D[j, i] > 0:
-                V[j, i] = _backproject(cam, i, j, float(D[j, i]))
+    V = _vertex_map(cam, D)
     valid = D > 0
+    mask_idx = np.nonzero(mask.reshape(-1))[0]
+    mask_V = V.reshape(-1, 3)[mask_idx]
     pix = [(j, i) for j in range(H) for i in range(W) if take[j, i]]
     out = {"mean": [], "log_scale": [], "quat": [], "opacity_logit": [], "rgb": []}
     for (j, i) in pix:
@@ -431,13 +451,11 @@ def insert_gaussians(cam, render_rgb, frame_rgb, weight, sdf_depth, rand, delta_
         n = n / np.linalg.norm(n)
         if np.dot(n, center - p) < 0:
             n = -n
-        cand = []
-        for jj in range(max(0, j - radius), min(H, j + radius + 1)):
-            for ii in range(max(0, i - radius), min(W, i + radius + 1)):
-                if (jj, ii) != (j, i) and mask[jj, ii]:
-                    cand.append((np.linalg.norm(V[jj, ii] - p), jj * W + ii))
-        cand.sort()
-        s1 = scale_cap if not cand else min(scale_cap, np.sqrt(np.mean([c[0] for c in cand[:3]])))
+        # the three nearest other mask vertices: squared distances to every mask vertex
+        d2 = ((mask_V - p) ** 2).sum(axis=1)
+        others = mask_idx != j * W + i
+        d2 = np.sort(d2[others])[:3]
+        s1 = scale_cap if d2.size == 0 else min(scale_cap, float(np.sqrt(d2.mean())))
         q = np.array([1.0 + n[2], -n[1], n[0], 0.0])
         q = q / np.linalg.norm(q) if np.linalg.norm(q) > 1e-12 else np.array([0.0, 1.0, 0.0, 0.0])
         out["mean"].append(p)

@@ -101,9 +101,4 @@ gps_status launch_adam(const gps_adam_group* groups, int n_groups, int step, int
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
 }
 
-void launch_step_incr(int* step_counter, hipStream_t s)
-{
-    GPS_LAUNCH(K_STEP_INCR, s, k_step_incr, dim3(1), dim3(64), 0, s, step_counter);
-}
-
 }  // namespace gps

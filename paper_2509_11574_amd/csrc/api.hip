@@ -161,6 +161,8 @@ static gps_status build_tables(const gps_render_cfg* cfg, const gps_gaussians* g
         d.target_depth = s.target_depth;
         d.out_rgb = s.out_rgb;
         d.out_depth = s.out_depth;
+        d.pose_xi = s.pose_xi;
+        d.out_aux = s.out_aux;
     }
     vt->n_tiles = tb;
     rp->eps = cfg->eps_cull;
@@ -391,7 +393,7 @@ gps_status gps_adam_step(const gps_adam_group* groups, int32_t n_groups, int32_t
 {
     if (!groups || n_groups < 1 || n_groups > 8) return GPS_ERR_INVALID_ARG;
     if (!step_counter && step < 1) return GPS_ERR_INVALID_ARG;
-    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps >= 0.0f))
+    if (!(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f) || !std::isfinite(eps))
         return GPS_ERR_INVALID_ARG;
     for (int k = 0; k < n_groups; ++k) {
         const gps_adam_group& gr = groups[k];
@@ -401,6 +403,26 @@ gps_status gps_adam_step(const gps_adam_group* groups, int32_t n_groups, int32_t
     gps_status st = check_device();
     if (st != GPS_OK) return st;
     return launch_adam(groups, n_groups, step, step_counter, beta1, beta2, eps, (hipStream_t)stream);
+}
+
+static gps_status check_removal_args(const gps_removal_cfg* cfg, const gps_gaussians* sets_in,
+                                     const gps_gaussians* sets_out, int32_t n_sets)
+{
+    if (!cfg || !sets_in || !sets_out || n_sets < 1 || n_sets > 4) return GPS_ERR_INVALID_ARG;
+    if (!(cfg->min_opacity > 0.0f && cfg->min_opacity < 1.0f) || !(cfg->max_scale > 0.0f) ||
+        !(cfg->min_scale > 0.0f) || !(cfg->min_scale <= cfg->max_scale))
+        return GPS_ERR_INVALID_ARG;
+    const int M = sets_in[0].count;
+    if (M < 0) return GPS_ERR_INVALID_ARG;
+    for (int k = 0; k < n_sets; ++k) {
+        const gps_gaussians& gi = sets_in[k];
+        const gps_gaussians& go = sets_out[k];
+        if (gi.count != M) return GPS_ERR_INVALID_ARG;
+        if (M > 0 && (!gi.mean || !gi.log_scale || !gi.quat || !gi.opacity_logit || !gi.rgb || !go.mean ||
+                      !go.log_scale || !go.quat || !go.opacity_logit || !go.rgb))
+            return GPS_ERR_INVALID_ARG;
+    }
+    return GPS_OK;
 }
 
 void gps_removal_cfg_default(gps_removal_cfg* cfg)
@@ -421,20 +443,9 @@ gps_status gps_removal_workspace_size(int32_t n_gaussians, size_t* out_bytes)
 gps_status gps_remove_gaussians(const gps_removal_cfg* cfg, const gps_gaussians* sets_in, gps_gaussians* sets_out,
                                 int32_t n_sets, int32_t* out_count, void* ws, size_t ws_bytes, void* stream)
 {
-    if (!cfg || !sets_in || !sets_out || n_sets < 1 || n_sets > 4) return GPS_ERR_INVALID_ARG;
-    if (!(cfg->min_opacity > 0.0f && cfg->min_opacity < 1.0f) || !(cfg->max_scale > 0.0f) ||
-        !(cfg->min_scale > 0.0f) || !(cfg->min_scale <= cfg->max_scale))
-        return GPS_ERR_INVALID_ARG;
+    gps_status st0 = check_removal_args(cfg, sets_in, sets_out, n_sets);
+    if (st0 != GPS_OK) return st0;
     const int M = sets_in[0].count;
-    if (M < 0) return GPS_ERR_INVALID_ARG;
-    for (int k = 0; k < n_sets; ++k) {
-        const gps_gaussians& gi = sets_in[k];
-        const gps_gaussians& go = sets_out[k];
-        if (gi.count != M) return GPS_ERR_INVALID_ARG;
-        if (M > 0 && (!gi.mean || !gi.log_scale || !gi.quat || !gi.opacity_logit || !gi.rgb || !go.mean ||
-                      !go.log_scale || !go.quat || !go.opacity_logit || !go.rgb))
-            return GPS_ERR_INVALID_ARG;
-    }
     if (!ws || ((uintptr_t)ws & 255)) return GPS_ERR_INVALID_ARG;
     if (ws_bytes < removal_workspace_bytes(M)) return GPS_ERR_WORKSPACE_TOO_SMALL;
     gps_status st = check_device();
@@ -449,7 +460,6 @@ void gps_insert_cfg_default(gps_insert_cfg* cfg)
     cfg->delta_c = 0.05f;
     cfg->delta_w = 4.0f;
     cfg->fraction = 0.25f;
-    cfg->radius = 4;
     cfg->scale_cap = 0.1f;
     cfg->flat_ratio = 0.1f;
     cfg->opacity = 0.5f;
@@ -474,7 +484,7 @@ gps_status gps_insert_gaussians(const gps_insert_cfg* cfg, const gps_camera* cam
 {
     if (!cfg || !cam || !out || !cam_ok(*cam) || !insert_frame_ok(cam->width, cam->height)) return GPS_ERR_INVALID_ARG;
     if (!(cfg->delta_c >= 0.0f) || !std::isfinite(cfg->delta_c) || !(cfg->delta_w > 0.0f) ||
-        !(cfg->fraction >= 0.0f && cfg->fraction <= 1.0f) || cfg->radius < 1 || cfg->radius > 8 ||
+        !(cfg->fraction >= 0.0f && cfg->fraction <= 1.0f) ||
         !(cfg->scale_cap > 0.0f) || !std::isfinite(cfg->scale_cap) || !(cfg->flat_ratio > 0.0f) ||
         !(cfg->flat_ratio <= 1.0f) || !(cfg->opacity > 0.0f && cfg->opacity < 1.0f))
         return GPS_ERR_INVALID_ARG;
@@ -497,6 +507,31 @@ gps_status gps_depth_downsample(const float* depth, int32_t width, int32_t heigh
     gps_status st = check_device();
     if (st != GPS_OK) return st;
     return launch_depth_downsample(depth, width, height, out, (hipStream_t)stream);
+}
+
+gps_status gps_level_camera(const gps_camera* cam, int32_t level, gps_camera* out)
+{
+    if (!cam || !out || level < 0 || level > 16) return GPS_ERR_INVALID_ARG;
+    int32_t W = cam->width, H = cam->height;
+    double fx = cam->fx, fy = cam->fy, cx = cam->cx, cy = cam->cy;
+    for (int k = 0; k < level; ++k) {
+        if (W < 2 || H < 2) return GPS_ERR_INVALID_ARG;
+        W /= 2;  // a level holds the 2x2 blocks that fit
+        H /= 2;
+        fx *= 0.5;
+        fy *= 0.5;
+        cx = (cx - 0.5) * 0.5;  // pixel centres: coarse (i, j) is the mean of 2i, 2i + 1
+        cy = (cy - 0.5) * 0.5;
+    }
+    gps_camera c = *cam;
+    c.width = W;
+    c.height = H;
+    c.fx = (float)fx;
+    c.fy = (float)fy;
+    c.cx = (float)cx;
+    c.cy = (float)cy;
+    *out = c;
+    return GPS_OK;
 }
 
 gps_status gps_icp_workspace_size(int32_t width, int32_t height, size_t* out_bytes)

@@ -189,6 +189,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
         V.out_rgb[2 * HW + p] = Cs[2];
         V.out_depth[p] = Ds;
         w.pix_aux[(size_t)V.pix_base + p] = T[k];
+        if (V.out_aux) V.out_aux[p] = T[k];
         if (V.target_rgb) {
             lc += fabsf(Cs[0] - V.target_rgb[p]) + fabsf(Cs[1] - V.target_rgb[HW + p]) +
                   fabsf(Cs[2] - V.target_rgb[2 * HW + p]);

@@ -139,10 +139,11 @@ gps_status launch_remove_gaussians(const gps_removal_cfg* cfg, const gps_gaussia
 //   k_insert_flags  per pixel: mask (bit 0) and sample (bit 1) flags and the
 //                   mask depth (the depth on mask pixels, 0 elsewhere); per
 //                   block of 256 pixels, the number taken
+//   k_insert_bits   per 8x8 pixel block: a 64-bit word of its mask pixels
 //   k_insert_scan   one block: block offsets, total taken -> out_count
 //   k_insert_place  per taken pixel: its row-major output position
-//   k_insert_init   per new Gaussian: its surface point, normal, scale, rotation
-constexpr int kInsertMaxRadius = 8;  // the window radius the C ABI accepts
+//   k_insert_init   per new Gaussian: its surface point, normal, scale (the
+//                   three nearest mask vertices over the whole mask), rotation
 
 struct InsertArgs {
     DevCam cam;
@@ -154,9 +155,11 @@ struct InsertArgs {
     float* out[5];  // mean, log_scale, quat, opacity_logit, rgb: planar [rows][capacity]
     int* out_pixel;
     int* out_count;
-    int capacity, radius;
+    int capacity;
+    int nbx, nby;  // 8x8 pixel blocks per row and column
     float t_c, t_w, t_frac, scale_cap, flat_ratio, logit_opacity;
     unsigned int* flags;
+    unsigned long long* bits;  // per 8x8 block: bit (8 row + column) set on mask pixels
     unsigned int* blk_cnt;
     unsigned int* blk_off;
     unsigned int* total;
@@ -181,6 +184,18 @@ __global__ void __launch_bounds__(256) k_insert_flags(InsertArgs a)
     unsigned int tot;
     block_excl_scan<256>((f >> 1) & 1u, &tot);
     if (threadIdx.x == 0) a.blk_cnt[blockIdx.x] = tot;
+}
+
+// One wavefront per 8x8 pixel block: lane 8 r + c holds pixel (8 bx + c, 8 by + r).
+__global__ void __launch_bounds__(256) k_insert_bits(InsertArgs a)
+{
+    const int blk = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (blk >= a.nbx * a.nby) return;  // uniform per wavefront
+    const int bx = blk % a.nbx, by = blk / a.nbx;
+    const int px = bx * 8 + (lane & 7), py = by * 8 + (lane >> 3);
+    const bool m = px < a.cam.W && py < a.cam.H && a.mdepth[(size_t)py * a.cam.W + px] > 0.0f;
+    const unsigned long long word = __ballot(m);
+    if (lane == 0) a.bits[blk] = word;
 }
 
 __global__ void __launch_bounds__(1024) k_insert_scan(InsertArgs a, int nblk)
@@ -284,51 +299,88 @@ __global__ void __launch_bounds__(256) k_insert_init(InsertArgs a)
         nv[k] = c.R[k] * nc[0] + c.R[3 + k] * nc[1] + c.R[6 + k] * nc[2];
         V[k] = c.R[k] * xt[0] + c.R[3 + k] * xt[1] + c.R[6 + k] * xt[2];
     }
-    // the three nearest mask vertices of the window
-    float best[3] = {INFINITY, INFINITY, INFINITY};
-    int nb = 0;
-    const int j0 = max(0, j - a.radius), j1 = min(H - 1, j + a.radius);
-    const int i0 = max(0, i - a.radius), i1 = min(W - 1, i + a.radius);
-    // one window row at a time: its (up to 17) mask depths are loaded together,
-    // then searched (the mask depth is > 0 exactly on the mask pixels)
-    for (int jj = j0; jj <= j1; ++jj) {
-        const float* row = a.mdepth + (size_t)jj * W;
-        float dv[2 * kInsertMaxRadius + 1];
-#pragma unroll
-        for (int t = 0; t < 2 * kInsertMaxRadius + 1; ++t) {
-            const int ii = i0 + t;
-            dv[t] = ii <= i1 ? row[ii] : 0.0f;
-        }
-#pragma unroll
-        for (int t = 0; t < 2 * kInsertMaxRadius + 1; ++t) {
-            const int ii = i0 + t;
-            if (!(dv[t] > 0.0f) || (jj == j && ii == i)) continue;
-            float U[3];
-            cam_point(c, ii, jj, dv[t], U);
-            const float d = sqrtf((U[0] - X[0]) * (U[0] - X[0]) + (U[1] - X[1]) * (U[1] - X[1]) +
-                                  (U[2] - X[2]) * (U[2] - X[2]));
-            ++nb;
-            if (d < best[2]) {
-                if (d < best[1]) {
-                    best[2] = best[1];
-                    if (d < best[0]) {
-                        best[1] = best[0];
-                        best[0] = d;
-                    } else {
-                        best[1] = d;
+    // The three nearest other mask vertices over the whole mask (Appendix A), by
+    // rings of 8x8 blocks around the query's block.  A pixel column c beyond the
+    // scanned window holds only points of the half-space fx x - (c - cx) z <= 0
+    // (or >= 0), so no unscanned vertex is nearer than the distance from X to the
+    // nearest such plane: the search stops once the third distance is within it.
+    // A third distance above sqrt(3) scale_cap gives s1 = scale_cap whatever the
+    // exact neighbours are, so the rings stop there as well once three are held.
+    const float r2max = 3.0f * a.scale_cap * a.scale_cap;
+    float b0 = INFINITY, b1 = INFINITY, b2 = INFINITY;  // squared distances, ascending
+    int cnt = 0;
+    const int bi = i >> 3, bj = j >> 3;
+    // Distance from X (on the ray of pixel column i, depth Z) to the plane through the
+    // camera centre holding the rays of column c: |i - c| Z / |(fx, c - cx)| (the
+    // integer difference is exact, so the bound has no cancellation); rows alike.
+    auto plane_dist = [&](int q, int cq, float f, float cc) {
+        const float k = (float)cq - cc;
+        return (float)abs(q - cq) * X[2] / sqrtf(f * f + k * k);
+    };
+    // lower bound of the distance from X to any point of pixel columns [c0, c1], rows [r0, r1]
+    auto box_bound = [&](int c0, int c1, int r0, int r1) {
+        float lx = 0.0f, ly = 0.0f;
+        if (c0 > i) lx = plane_dist(i, c0, c.fx, c.cx);
+        else if (c1 < i) lx = plane_dist(i, c1, c.fx, c.cx);
+        if (r0 > j) ly = plane_dist(j, r0, c.fy, c.cy);
+        else if (r1 < j) ly = plane_dist(j, r1, c.fy, c.cy);
+        return fmaxf(lx, ly) * (1.0f - 1e-4f);  // rounding margin: never above the true bound
+    };
+    for (int r = 0;; ++r) {
+        const int bx0 = bi - r, bx1 = bi + r, by0 = bj - r, by1 = bj + r;
+        for (int by = max(by0, 0); by <= min(by1, a.nby - 1); ++by) {
+            const bool full = by == by0 || by == by1;  // top and bottom rows of the ring: every block
+            for (int bx = bx0; bx <= bx1; bx = full ? bx + 1 : (bx == bx0 ? bx1 : bx1 + 1)) {
+                if (bx < 0 || bx >= a.nbx) continue;
+                const int c0 = bx * 8, r0 = by * 8;
+                if (cnt >= 3) {
+                    const float lb = box_bound(c0, min(c0 + 7, W - 1), r0, min(r0 + 7, H - 1));
+                    if (lb * lb >= b2) continue;
+                }
+                unsigned long long word = a.bits[(size_t)by * a.nbx + bx];
+                while (word) {
+                    const int k = __ffsll((long long)word) - 1;
+                    word &= word - 1ull;
+                    const int ii = c0 + (k & 7), jj = r0 + (k >> 3);
+                    if (ii == i && jj == j) continue;
+                    float U[3];
+                    cam_point(c, ii, jj, a.mdepth[(size_t)jj * W + ii], U);
+                    const float d2 = (U[0] - X[0]) * (U[0] - X[0]) + (U[1] - X[1]) * (U[1] - X[1]) +
+                                     (U[2] - X[2]) * (U[2] - X[2]);
+                    ++cnt;
+                    if (d2 < b2) {
+                        if (d2 < b1) {
+                            b2 = b1;
+                            if (d2 < b0) {
+                                b1 = b0;
+                                b0 = d2;
+                            } else {
+                                b1 = d2;
+                            }
+                        } else {
+                            b2 = d2;
+                        }
                     }
-                } else {
-                    best[2] = d;
                 }
             }
         }
+        // distance bound of everything outside the scanned window
+        const int x0 = max(bx0, 0) * 8, x1 = min(bx1 * 8 + 7, W - 1);
+        const int y0 = max(by0, 0) * 8, y1 = min(by1 * 8 + 7, H - 1);
+        float bound = INFINITY;
+        if (x0 > 0) bound = fminf(bound, box_bound(0, x0 - 1, j, j));
+        if (x1 < W - 1) bound = fminf(bound, box_bound(x1 + 1, W - 1, j, j));
+        if (y0 > 0) bound = fminf(bound, box_bound(i, i, 0, y0 - 1));
+        if (y1 < H - 1) bound = fminf(bound, box_bound(i, i, y1 + 1, H - 1));
+        if (bound == INFINITY) break;                       // the whole image is scanned
+        if (cnt >= 3 && b2 <= bound * bound) break;         // exact: nothing unscanned is nearer
+        if (cnt >= 3 && bound * bound >= r2max) break;      // the third is beyond sqrt(3) cap: capped
     }
     float s1 = a.scale_cap;
-    if (nb > 0) {
-        const int m = nb < 3 ? nb : 3;
-        float sum = 0.0f;
-        for (int k = 0; k < m; ++k) sum += best[k];
-        s1 = fminf(a.scale_cap, sqrtf(sum / (float)m));
+    if (cnt > 0) {
+        const int m = cnt < 3 ? cnt : 3;
+        const float sum = m == 1 ? b0 : (m == 2 ? b0 + b1 : (b0 + b1) + b2);
+        s1 = fminf(a.scale_cap, sqrtf(sum / (float)m));  // root mean square distance
     }
     // shortest-arc rotation taking the local z axis onto the normal; for a normal
     // near -z the scalar part 1 + n_z is formed as (n_x^2 + n_y^2) / (1 - n_z), its
@@ -364,7 +416,8 @@ size_t insertion_workspace_bytes(int W, int H)
 {
     const size_t n = (size_t)W * H, nblk = n > 0 ? (n + 255) / 256 : 1;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    return 3 * al(4 * n) + 2 * al(4 * nblk) + 256;
+    const size_t nbits = (size_t)((W + 7) / 8) * ((H + 7) / 8);
+    return 3 * al(4 * n) + 2 * al(4 * nblk) + 256 + al(8 * nbits);
 }
 
 gps_status launch_insert_gaussians(const gps_insert_cfg* cfg, const DevCam& cam, const float* render_rgb,
@@ -384,7 +437,8 @@ gps_status launch_insert_gaussians(const gps_insert_cfg* cfg, const DevCam& cam,
     a.out_pixel = out_pixel;
     a.out_count = out_count;
     a.capacity = out->count;
-    a.radius = cfg->radius;
+    a.nbx = (cam.W + 7) / 8;
+    a.nby = (cam.H + 7) / 8;
     a.t_c = (float)(3.0 * (double)cfg->delta_c);
     a.t_w = cfg->delta_w;
     a.t_frac = cfg->fraction;
@@ -401,7 +455,10 @@ gps_status launch_insert_gaussians(const gps_insert_cfg* cfg, const DevCam& cam,
     a.total = reinterpret_cast<unsigned int*>(ws + al(4 * n) + 2 * al(4 * nb));
     a.list = reinterpret_cast<int*>(ws + al(4 * n) + 2 * al(4 * nb) + 256);
     a.mdepth = reinterpret_cast<float*>(ws + 2 * al(4 * n) + 2 * al(4 * nb) + 256);
+    a.bits = reinterpret_cast<unsigned long long*>(ws + 3 * al(4 * n) + 2 * al(4 * nb) + 256);
+    const int nbits = a.nbx * a.nby;
     if (nblk > 0) GPS_LAUNCH(K_INSERT, s, k_insert_flags, dim3(nblk), dim3(256), 0, s, a);
+    if (nbits > 0) GPS_LAUNCH(K_INSERT, s, k_insert_bits, dim3((nbits + 3) / 4), dim3(256), 0, s, a);
     GPS_LAUNCH(K_INSERT, s, k_insert_scan, dim3(1), dim3(1024), 0, s, a, nblk);
     const size_t cap = (size_t)a.capacity < n ? (size_t)a.capacity : n;
     if (nblk > 0 && cap > 0) {

@@ -54,6 +54,8 @@ struct DevView {
     float* out_depth;
     const float* g_rgb;    // explicit upstream adjoints (backward), or null
     const float* g_depth;
+    const float* pose_xi;  // [6] left perturbation applied at upload, or null
+    float* out_aux;        // [H][W] T_final / W_G copy for the caller, or null
 };
 
 struct ViewTable {

@@ -19,6 +19,7 @@
 #include "gps_internal.h"
 #include "launch.h"
 #include "prof.h"
+#include "se3.h"
 
 namespace gps {
 
@@ -216,35 +217,6 @@ __global__ void __launch_bounds__(1024) k_icp_total(const float* __restrict__ pa
         sys[k0] = s0;
         if (two) sys[k1] = s1;
     }
-}
-
-// Exp of xi = (rho, phi) in SE(3) (Rodrigues' formula for the rotation, the left
-// Jacobian of SO(3) for the translation).
-__device__ void se3_exp_d(const double xi[6], double R[9], double t[3])
-{
-    const double wx = xi[3], wy = xi[4], wz = xi[5];
-    const double th2 = wx * wx + wy * wy + wz * wz, th = sqrt(th2);
-    const double K[9] = {0.0, -wz, wy, wz, 0.0, -wx, -wy, wx, 0.0};
-    double K2[9];
-    for (int r = 0; r < 3; ++r)
-        for (int c = 0; c < 3; ++c) K2[3 * r + c] = K[3 * r] * K[c] + K[3 * r + 1] * K[3 + c] + K[3 * r + 2] * K[6 + c];
-    double A, B, C;
-    if (th < 1e-6) {  // series of sin(th)/th, (1 - cos th)/th^2, (th - sin th)/th^3
-        A = 1.0 - th2 / 6.0;
-        B = 0.5 - th2 / 24.0;
-        C = 1.0 / 6.0 - th2 / 120.0;
-    } else {
-        A = sin(th) / th;
-        B = (1.0 - cos(th)) / th2;
-        C = (th - sin(th)) / (th2 * th);
-    }
-    double V[9];
-    for (int k = 0; k < 9; ++k) {
-        const double I = (k % 4 == 0) ? 1.0 : 0.0;
-        R[k] = I + A * K[k] + B * K2[k];
-        V[k] = I + B * K[k] + C * K2[k];
-    }
-    for (int r = 0; r < 3; ++r) t[r] = V[3 * r] * xi[0] + V[3 * r + 1] * xi[1] + V[3 * r + 2] * xi[2];
 }
 
 // The Gauss-Newton step: res = (new pose (12), xi (6)); the pose is kept when fewer

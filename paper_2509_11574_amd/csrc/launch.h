@@ -20,7 +20,6 @@ gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const
                              const ViewTable& vt, const WsLayout& L, char* ws, int explicit_upstream,
                              const float* loss_scale, gps_gaussians* grads, float* dpose, const gps_adam_fused* adam,
                              hipStream_t s);
-void launch_step_incr(int* step_counter, hipStream_t s);
 bool dispatch_cfwd(const gps_render_cfg* cfg, const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles,
                    hipStream_t s);
 bool dispatch_cbwd(const gps_render_cfg* cfg, const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles,

@@ -13,6 +13,7 @@
 #include "launch.h"
 #include "prof.h"
 #include "render_common.h"
+#include "se3.h"
 
 namespace gps {
 
@@ -43,6 +44,10 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
     const int g = blockIdx.x * kBlk + threadIdx.x;
     const int lane = threadIdx.x & 63;
     const bool live = g < M;
+    // After a capacity overflow the forward stopped before it wrote the slot offsets
+    // and partials: no slot is read, every gradient is zero and the Adam step of the
+    // epilogue is skipped, so parameters and moments stay as they were.
+    const bool over = w.hdr->n_inst > rp.cap;
     float gmean[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.0f, grgb[3] = {0, 0, 0};
     __shared__ float pred[kBlk / 64][6];
     __shared__ float sbc[2];
@@ -95,7 +100,7 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
     for (int v = 0; v < vt.n; ++v) {
         float pose[6] = {0, 0, 0, 0, 0, 0};
         const size_t vg = (size_t)v * M + g;
-        unsigned int cnt = live ? w.cnt[vg] : 0u;
+        unsigned int cnt = (live && !over) ? w.cnt[vg] : 0u;
         const unsigned int o = cnt ? w.off[vg] : 0u;
         if ((unsigned long long)o + cnt > w.hdr->n_inst) cnt = 0u;  // guard: stay inside the emitted slots
         // Slots of tiles removed by the depth cull were zeroed by the emission, so the
@@ -306,7 +311,7 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
         gg.rgb[M + g] = grgb[1];
         gg.rgb[2 * M + g] = grgb[2];
     }
-    if (live && af.on) {
+    if (live && af.on && !over) {
         // this lane's Gaussian only: its parameters were read above by this lane alone
         const float ibc1 = sbc[0], ibc2 = sbc[1];
         const float* gr[5] = {gmean, gls, gq, &gop, grgb};
@@ -326,11 +331,14 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
     }
 }
 
-__global__ void __launch_bounds__(256) k_pose_reduce(RParams rp, WsPtrs w, int nblk, float* dpose, int* step_ctr)
+__global__ void __launch_bounds__(256) k_pose_reduce(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w, int nblk,
+                                                     float* dpose, int* step_ctr)
 {
     // the Adam step counter of a backward with Adam in its epilogue (one lane,
-    // vector memory path: the address depends on the lane id)
-    if (step_ctr && blockIdx.x == 0 && threadIdx.x == 0) step_ctr[threadIdx.x] += 1;
+    // vector memory path: the address depends on the lane id); not advanced after
+    // a capacity overflow, where the epilogue skipped the update
+    if (step_ctr && blockIdx.x == 0 && threadIdx.x == 0 && w.hdr->n_inst <= rp.cap) step_ctr[threadIdx.x] += 1;
+    if (!dpose) return;  // launched for the counter alone
     // One block per view: the six components summed per lane over the blocks (in
     // strides), per wavefront (DPP), then over the four wavefronts in order.
     const int v = blockIdx.x, lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -343,8 +351,26 @@ __global__ void __launch_bounds__(256) k_pose_reduce(RParams rp, WsPtrs w, int n
         if (lane == 0) red[wid][q] = t;
     }
     __syncthreads();
-    if (threadIdx.x < 6) dpose[v * 6 + threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
-                                                      red[3][threadIdx.x];
+    const float* xi = vtp->v[v].pose_xi;
+    if (!xi) {
+        if (threadIdx.x < 6)
+            dpose[v * 6 + threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) +
+                                         red[3][threadIdx.x];
+    } else if (threadIdx.x == 0) {
+        // the view was rendered from Exp(xi) T: the gradient with respect to xi is
+        // J_l(xi)^T times the gradient of the left perturbation at that pose
+        double gz[6], xd[6], J[36];
+        for (int q = 0; q < 6; ++q) {
+            gz[q] = (double)(((red[0][q] + red[1][q]) + red[2][q]) + red[3][q]);
+            xd[q] = (double)xi[q];
+        }
+        se3_left_jacobian_d(xd, J);
+        for (int c = 0; c < 6; ++c) {
+            double a = 0.0;
+            for (int r = 0; r < 6; ++r) a += J[6 * r + c] * gz[r];
+            dpose[v * 6 + c] = (float)a;
+        }
+    }
 }
 
 // ------------------------------------- per-Gaussian sort-free backward
@@ -548,10 +574,11 @@ gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const
         GPS_LAUNCH(K_GAUSS_BWD, s, k_gauss_bwd, dim3(L.nblk_g), dim3(kBlk), 0, s, dvt, rp, gp, gg, w, af);
     }
     int* ctr = adam ? adam->step_counter : nullptr;
-    if (dpose && L.nblk_g > 0)
-        GPS_LAUNCH(K_POSE_REDUCE, s, k_pose_reduce, dim3(vt.n), dim3(256), 0, s, rp, w, L.nblk_g, dpose, ctr);
-    else if (ctr)
-        launch_step_incr(ctr, s);
+    // one block per view (an empty set sums no block partials: dpose = 0), or one
+    // block for the step counter alone
+    if (dpose || ctr)
+        GPS_LAUNCH(K_POSE_REDUCE, s, k_pose_reduce, dim3(dpose ? vt.n : 1), dim3(256), 0, s, dvt, rp, w, L.nblk_g,
+                   dpose, ctr);
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
 }
 

@@ -25,6 +25,7 @@
 #include "launch.h"
 #include "prof.h"
 #include "render_common.h"
+#include "se3.h"
 
 namespace gps {
 
@@ -586,11 +587,27 @@ __global__ void __launch_bounds__(1024) k_loss_reduce(const ViewTable* __restric
 // ------------------------------------------------------------ view table
 // Copies the by-value view table into the workspace, so that a replayed
 // sequence of kernels reads whatever table was uploaded last.
+// A view with pose_xi is written with the camera Exp(xi) T_cw (binary64
+// composition, rounded once to binary32).
 __global__ void __launch_bounds__(256) k_upload_views(ViewTable vt, ViewTable* dst)
 {
     const unsigned int* src = reinterpret_cast<const unsigned int*>(&vt);
     unsigned int* d = reinterpret_cast<unsigned int*>(dst);
     for (int i = threadIdx.x; i < (int)(sizeof(ViewTable) / 4); i += 256) d[i] = src[i];
+    __syncthreads();
+    const int v = threadIdx.x;
+    if (v < vt.n && vt.v[v].pose_xi) {
+        double xi[6], E[9], e[3];
+        for (int k = 0; k < 6; ++k) xi[k] = (double)vt.v[v].pose_xi[k];
+        se3_exp_d(xi, E, e);
+        const DevCam& c = vt.v[v].cam;
+        DevCam& o = dst->v[v].cam;
+        for (int r = 0; r < 3; ++r) {
+            for (int k = 0; k < 3; ++k)
+                o.R[3 * r + k] = (float)(E[3 * r] * c.R[k] + E[3 * r + 1] * c.R[3 + k] + E[3 * r + 2] * c.R[6 + k]);
+            o.t[r] = (float)(E[3 * r] * c.t[0] + E[3 * r + 1] * c.t[1] + E[3 * r + 2] * c.t[2] + e[r]);
+        }
+    }
 }
 
 // The table upload, then (with_tilemax) the tile depth maxima of its views.

@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(256) k_fuse(FuseArgs a)
         if (!(fu >= 0.0f && fu < (float)c.W && fv >= 0.0f && fv < (float)c.H)) return;
         i = (int)fu;
         j = (int)fv;
-        float d = __ldg(a.depth + (size_t)j * c.W + i);
+        float d = a.depth[(size_t)j * c.W + i];
         if (!(d > 0.0f)) return;
         eta = d - zc;
         if (eta < -a.mu) return;
@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(256) k_fuse(FuseArgs a)
         const size_t p = (size_t)j * c.W + i;
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
-            float obs = __ldg(a.img + ch * HW + p);
+            float obs = a.img[ch * HW + p];
             float* cp = a.col + (size_t)ch * a.N + idx;
             *cp = (wc * *cp + obs) / (wc + 1.0f);
         }
@@ -202,8 +202,8 @@ __device__ __forceinline__ float dec_trilinear(const RayArgs& a, const float g[3
     *inside = 1;
     const size_t sx = 1, sy = (size_t)a.n[0], sz = (size_t)a.n[0] * a.n[1];
     const float* p = a.tsdf + bi[0] + sy * bi[1] + sz * bi[2];
-    float v000 = __ldg(p), v100 = __ldg(p + sx), v010 = __ldg(p + sy), v110 = __ldg(p + sy + sx);
-    float v001 = __ldg(p + sz), v101 = __ldg(p + sz + sx), v011 = __ldg(p + sz + sy), v111 = __ldg(p + sz + sy + sx);
+    float v000 = p[0], v100 = p[sx], v010 = p[sy], v110 = p[sy + sx];
+    float v001 = p[sz], v101 = p[sz + sx], v011 = p[sz + sy], v111 = p[sz + sy + sx];
     float c00 = d32_lerp(v000, v100, fr[0]);
     float c10 = d32_lerp(v010, v110, fr[0]);
     float c01 = d32_lerp(v001, v101, fr[0]);
@@ -344,12 +344,12 @@ __global__ void __launch_bounds__(256) k_raycast(RayArgs a)
                 const int i0 = (int)b0 >> 3, i1 = (int)b1 >> 3, i2 = (int)b2 >> 3;
                 const int j0 = i0 / kSuper, j1 = i1 / kSuper, j2 = i2 / kSuper;
                 int edge = 0, bb[3];
-                if (__ldg(a.smin + j0 + a.sx * (j1 + a.sy * j2)) > kBrickPositive) {
+                if (a.smin[j0 + a.sx * (j1 + a.sy * j2)] > kBrickPositive) {
                     edge = kBrick * kSuper;  // the whole superbrick is positive
                     bb[0] = j0;
                     bb[1] = j1;
                     bb[2] = j2;
-                } else if (__ldg(a.bmin + i0 + a.bx * (i1 + a.by * i2)) > kBrickPositive) {
+                } else if (a.bmin[i0 + a.bx * (i1 + a.by * i2)] > kBrickPositive) {
                     edge = kBrick;
                     bb[0] = i0;
                     bb[1] = i1;

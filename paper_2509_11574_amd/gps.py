@@ -51,7 +51,8 @@ class GaussiansS(ctypes.Structure):
 class ViewS(ctypes.Structure):
     _fields_ = [("cam", Camera), ("base_rgb", ctypes.c_void_p), ("base_depth", ctypes.c_void_p),
                 ("target_rgb", ctypes.c_void_p), ("target_depth", ctypes.c_void_p),
-                ("out_rgb", ctypes.c_void_p), ("out_depth", ctypes.c_void_p)]
+                ("out_rgb", ctypes.c_void_p), ("out_depth", ctypes.c_void_p), ("pose_xi", ctypes.c_void_p),
+                ("out_aux", ctypes.c_void_p)]
 
 
 class RenderCfgS(ctypes.Structure):
@@ -68,7 +69,7 @@ class RemovalCfgS(ctypes.Structure):
 
 class InsertCfgS(ctypes.Structure):
     _fields_ = [("delta_c", ctypes.c_float), ("delta_w", ctypes.c_float), ("fraction", ctypes.c_float),
-                ("radius", ctypes.c_int32), ("scale_cap", ctypes.c_float), ("flat_ratio", ctypes.c_float),
+                ("scale_cap", ctypes.c_float), ("flat_ratio", ctypes.c_float),
                 ("opacity", ctypes.c_float)]
 
 
@@ -94,7 +95,7 @@ EXPORTS = ["gps_abi_version", "gps_status_string", "gps_render_cfg_default", "gp
            "gps_profile_read", "gps_views_upload", "gps_removal_cfg_default", "gps_removal_workspace_size",
            "gps_remove_gaussians", "gps_insert_cfg_default", "gps_insertion_workspace_size",
            "gps_insert_gaussians", "gps_depth_downsample", "gps_icp_workspace_size", "gps_icp_reduce",
-           "gps_icp_solve", "gps_render_bwd_adam"]
+           "gps_icp_solve", "gps_render_bwd_adam", "gps_level_camera"]
 
 _lib = None
 
@@ -139,6 +140,7 @@ def lib():
         L.gps_icp_reduce.argtypes = [P, P, P, P, P, F, P, P, ctypes.c_size_t, P]
         L.gps_icp_solve.argtypes = [P, P, P, P]
         L.gps_render_bwd_adam.argtypes = [P, P, P, I32, P, P, P, P, P, P, P, ctypes.c_size_t, P]
+        L.gps_level_camera.argtypes = [P, I32, P]
         for n in EXPORTS:
             if n not in ("gps_render_cfg_default", "gps_status_string", "gps_abi_version", "gps_removal_cfg_default",
                          "gps_insert_cfg_default"):
@@ -346,6 +348,7 @@ class View:
     target_depth: torch.Tensor | None = None
     out_rgb: torch.Tensor | None = None
     out_depth: torch.Tensor | None = None
+    out_aux: torch.Tensor | None = None  # [H,W]: T_final (sorted) or W_G (sort-free), written by render_fwd
 
     def __post_init__(self):
         c = camera(self.cam)
@@ -355,12 +358,14 @@ class View:
         if self.out_depth is None:
             self.out_depth = torch.empty(c.height, c.width, dtype=torch.float32, device=dev)
 
-    def struct(self) -> ViewS:
+    def struct(self, pose_xi: torch.Tensor | None = None) -> ViewS:
+        """pose_xi: optional [6] device tensor, the left perturbation the view is rendered at."""
         c = camera(self.cam)
         HW = c.width * c.height
         return ViewS(c, _ptr(self.base_rgb, "base_rgb", 3 * HW), _ptr(self.base_depth, "base_depth", HW),
                      _ptr(self.target_rgb, "target_rgb", 3 * HW), _ptr(self.target_depth, "target_depth", HW),
-                     _ptr(self.out_rgb, "out_rgb", 3 * HW), _ptr(self.out_depth, "out_depth", HW))
+                     _ptr(self.out_rgb, "out_rgb", 3 * HW), _ptr(self.out_depth, "out_depth", HW),
+                     _ptr(pose_xi, "pose_xi", 6), _ptr(self.out_aux, "out_aux", HW))
 
 
 def workspace_size(cfg: RenderCfg, n_gaussians: int, cams) -> int:
@@ -402,28 +407,34 @@ class Workspace:
                 "view_omega": list(s.view_omega)[:max(s.n_views, 0)]}
 
 
-def _views_array(views):
+def _views_array(views, pose_xi=None):
     V = len(views)
     if not 1 <= V <= MAX_VIEWS:
         raise ValueError(f"1..{MAX_VIEWS} views per call")
+    if pose_xi is not None:
+        if pose_xi.dtype != torch.float32 or tuple(pose_xi.shape) != (V, 6) or not pose_xi.is_contiguous():
+            raise ValueError("pose_xi must be a contiguous float32 [n_views, 6] tensor")
+        return (ViewS * V)(*[v.struct(pose_xi[i]) for i, v in enumerate(views)])
     return (ViewS * V)(*[v.struct() for v in views])
 
 
 def render_fwd(cfg: RenderCfg, gauss: dict, views, ws: Workspace, out_loss: torch.Tensor | None = None,
-               stream=None):
+               stream=None, pose_xi: torch.Tensor | None = None):
+    """pose_xi: optional [V, 6] device tensor; view v is rendered from Exp(pose_xi[v]) T_cw."""
     cs = cfg.struct()
     gs = gaussians_struct(gauss)
-    va = _views_array(views)
+    va = _views_array(views, pose_xi)
     _check(lib().gps_render_fwd(ctypes.byref(cs), ctypes.byref(gs), va, len(views), ws.ptr(), ws.nbytes,
                                 _ptr(out_loss, "out_loss", 1) if out_loss is not None else None, _stream(stream)),
            "gps_render_fwd")
 
 
-def views_upload(cfg: RenderCfg, gauss: dict, views, ws: Workspace, dL_drgb=None, dL_ddepth=None, stream=None):
+def views_upload(cfg: RenderCfg, gauss: dict, views, ws: Workspace, dL_drgb=None, dL_ddepth=None, stream=None,
+                 pose_xi: torch.Tensor | None = None):
     """Write the view table into the workspace for calls made with cfg.views_preset."""
     cs = cfg.struct()
     gs = gaussians_struct(gauss)
-    va = _views_array(views)
+    va = _views_array(views, pose_xi)
     V = len(views)
     rgb_arr = dep_arr = None
     if dL_drgb is not None:
@@ -436,11 +447,13 @@ def views_upload(cfg: RenderCfg, gauss: dict, views, ws: Workspace, dL_drgb=None
 
 
 def render_bwd(cfg: RenderCfg, gauss: dict, views, ws: Workspace, grads: dict, dpose: torch.Tensor | None = None,
-               dL_drgb=None, dL_ddepth=None, loss_scale: torch.Tensor | None = None, stream=None):
+               dL_drgb=None, dL_ddepth=None, loss_scale: torch.Tensor | None = None, stream=None,
+               pose_xi: torch.Tensor | None = None):
+    """pose_xi must be the tensor the matching render_fwd was given (dpose is then dL/dpose_xi)."""
     cs = cfg.struct()
     gs = gaussians_struct(gauss)
     gg = gaussians_struct(grads)
-    va = _views_array(views)
+    va = _views_array(views, pose_xi)
     V = len(views)
     rgb_arr = dep_arr = None
     if dL_drgb is not None:
@@ -544,41 +557,56 @@ class Session:
         self.loss = torch.zeros(1, dtype=torch.float32, device=device)
 
 
+def _pose_arg(pose_xi, n_views):
+    """The [V, 6] float32 device tensor the library reads, or None."""
+    if pose_xi is None:
+        return None
+    xi = pose_xi.detach()
+    if tuple(xi.shape) != (n_views, 6):
+        raise ValueError(f"pose_xi must have shape ({n_views}, 6)")
+    return xi.to(torch.float32).contiguous()
+
+
 class RenderLoss(torch.autograd.Function):
     """loss = RenderLoss.apply(mean, log_scale, quat, opacity_logit, rgb, pose_xi, session).
-    pose_xi [V,6] is a placeholder at zero (the poses live in the session's cameras); its gradient is
-    dL/dxi of the left perturbation T <- Exp(xi) T, translation first."""
+    pose_xi [V,6] (or None): view v is rendered from Exp(pose_xi[v]) T_cw, the left perturbation of its
+    camera, translation first; its gradient is dL/dpose_xi at the given value."""
 
     @staticmethod
     def forward(ctx, mean, log_scale, quat, opacity_logit, rgb, pose_xi, session: Session):
         g = {"mean": mean, "log_scale": log_scale, "quat": quat, "opacity_logit": opacity_logit, "rgb": rgb}
-        render_fwd(session.cfg, g, session.views, session.ws, out_loss=session.loss)
+        xi = _pose_arg(pose_xi, len(session.views))
+        render_fwd(session.cfg, g, session.views, session.ws, out_loss=session.loss, pose_xi=xi)
         ctx.session = session
-        ctx.save_for_backward(mean, log_scale, quat, opacity_logit, rgb)
+        ctx.pose_given = pose_xi is not None
+        ctx.save_for_backward(mean, log_scale, quat, opacity_logit, rgb, xi)
         return session.loss.clone().reshape(())
 
     @staticmethod
     def backward(ctx, gloss):
         s = ctx.session
-        mean, log_scale, quat, opacity_logit, rgb = ctx.saved_tensors
+        mean, log_scale, quat, opacity_logit, rgb, xi = ctx.saved_tensors
         g = {"mean": mean, "log_scale": log_scale, "quat": quat, "opacity_logit": opacity_logit, "rgb": rgb}
         grads = zeros_like_gaussians(g)
         dpose = torch.zeros(len(s.views), 6, dtype=torch.float32, device=mean.device)
         scale = gloss.detach().to(torch.float32).reshape(1).contiguous()
-        render_bwd(s.cfg, g, s.views, s.ws, grads, dpose, loss_scale=scale)
-        return grads["mean"], grads["log_scale"], grads["quat"], grads["opacity_logit"], grads["rgb"], dpose, None
+        render_bwd(s.cfg, g, s.views, s.ws, grads, dpose, loss_scale=scale, pose_xi=xi)
+        return (grads["mean"], grads["log_scale"], grads["quat"], grads["opacity_logit"], grads["rgb"],
+                dpose if ctx.pose_given else None, None)
 
 
 class Render(torch.autograd.Function):
     """rgb_0, depth_0, rgb_1, depth_1, ... = Render.apply(mean, log_scale, quat, opacity_logit, rgb, pose_xi,
-    session) for arbitrary downstream losses."""
+    session) for arbitrary downstream losses (pose_xi as in RenderLoss)."""
 
     @staticmethod
     def forward(ctx, mean, log_scale, quat, opacity_logit, rgb, pose_xi, session: Session):
         g = {"mean": mean, "log_scale": log_scale, "quat": quat, "opacity_logit": opacity_logit, "rgb": rgb}
-        render_fwd(session.cfg, g, session.views, session.ws)
+        xi = _pose_arg(pose_xi, len(session.views))
+        render_fwd(session.cfg, g, session.views, session.ws, pose_xi=xi)
         ctx.session = session
-        ctx.save_for_backward(mean, log_scale, quat, opacity_logit, rgb)
+        ctx.pose_given = pose_xi is not None
+        ctx.save_for_backward(mean, log_scale, quat, opacity_logit, rgb, xi)
         outs = []
         for v in session.views:
             outs += [v.out_rgb.clone(), v.out_depth.clone()]
@@ -587,7 +615,7 @@ class Render(torch.autograd.Function):
     @staticmethod
     def backward(ctx, *gouts):
         s = ctx.session
-        mean, log_scale, quat, opacity_logit, rgb = ctx.saved_tensors
+        mean, log_scale, quat, opacity_logit, rgb, xi = ctx.saved_tensors
         g = {"mean": mean, "log_scale": log_scale, "quat": quat, "opacity_logit": opacity_logit, "rgb": rgb}
         grads = zeros_like_gaussians(g)
         dpose = torch.zeros(len(s.views), 6, dtype=torch.float32, device=mean.device)
@@ -596,8 +624,9 @@ class Render(torch.autograd.Function):
             gr, gd = gouts[2 * i], gouts[2 * i + 1]
             drgb.append((gr if gr is not None else torch.zeros_like(v.out_rgb)).contiguous())
             ddep.append((gd if gd is not None else torch.zeros_like(v.out_depth)).contiguous())
-        render_bwd(s.cfg, g, s.views, s.ws, grads, dpose, dL_drgb=drgb, dL_ddepth=ddep)
-        return grads["mean"], grads["log_scale"], grads["quat"], grads["opacity_logit"], grads["rgb"], dpose, None
+        render_bwd(s.cfg, g, s.views, s.ws, grads, dpose, dL_drgb=drgb, dL_ddepth=ddep, pose_xi=xi)
+        return (grads["mean"], grads["log_scale"], grads["quat"], grads["opacity_logit"], grads["rgb"],
+                dpose if ctx.pose_given else None, None)
 
 
 def remove_gaussians(params: dict, companions=(), min_opacity=0.005, max_scale=0.1, min_scale=0.003, stream=None):
@@ -630,7 +659,7 @@ def remove_gaussians(params: dict, companions=(), min_opacity=0.005, max_scale=0
 
 
 def insert_gaussians(cam, render_rgb, frame_rgb, weight, sdf_depth, rand, capacity=None, delta_c=0.05, delta_w=4.0,
-                     fraction=0.25, radius=4, scale_cap=0.1, flat_ratio=0.1, opacity=0.5, stream=None):
+                     fraction=0.25, scale_cap=0.1, flat_ratio=0.1, opacity=0.5, stream=None):
     """Gaussian insertion of Eq. 6 and App. A (gps_insert_gaussians): the new Gaussians
     (planar [rows][n] tensors, row-major pixel order), their pixel indices and the
     number of sampled pixels n_taken (the output keeps min(n_taken, capacity));
@@ -649,7 +678,7 @@ def insert_gaussians(cam, render_rgb, frame_rgb, weight, sdf_depth, rand, capaci
     _check(lib().gps_insertion_workspace_size(W, H, ctypes.byref(nbytes)), "gps_insertion_workspace_size")
     ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
     count = torch.zeros(1, dtype=torch.int32, device=dev)
-    cfg = InsertCfgS(delta_c, delta_w, fraction, radius, scale_cap, flat_ratio, opacity)
+    cfg = InsertCfgS(delta_c, delta_w, fraction, scale_cap, flat_ratio, opacity)
     _check(lib().gps_insert_gaussians(ctypes.byref(cfg), ctypes.byref(c), _ptr(render_rgb, "render_rgb", 3 * W * H),
                                       _ptr(frame_rgb, "frame_rgb", 3 * W * H), _ptr(weight, "weight", W * H),
                                       _ptr(sdf_depth, "sdf_depth", W * H), _ptr(rand, "rand", W * H),
@@ -666,12 +695,12 @@ def insert_gaussians(cam, render_rgb, frame_rgb, weight, sdf_depth, rand, capaci
 # Camera tracking (Eq. 5)                                                      #
 # --------------------------------------------------------------------------- #
 def level_camera(cam, level: int) -> dict:
-    """Size and intrinsics of a level of the depth hierarchy (f / 2, (c - 1/2) / 2 per level)."""
+    """Size and intrinsics of a level of the depth hierarchy (gps_level_camera)."""
+    src = camera({**cam, "R": cam.get("R", np.eye(3)), "t": cam.get("t", np.zeros(3))})
+    out = Camera()
+    _check(lib().gps_level_camera(ctypes.byref(src), int(level), ctypes.byref(out)), "gps_level_camera")
     c = dict(cam)
-    for _ in range(level):
-        c["width"], c["height"] = c["width"] // 2, c["height"] // 2
-        c["fx"], c["fy"] = c["fx"] / 2.0, c["fy"] / 2.0
-        c["cx"], c["cy"] = (c["cx"] - 0.5) / 2.0, (c["cy"] - 0.5) / 2.0
+    c.update(width=out.width, height=out.height, fx=out.fx, fy=out.fy, cx=out.cx, cy=out.cy)
     return c
 
 

@@ -40,9 +40,25 @@ def test_every_declared_symbol_is_exported(P):
 
 def test_abi_version_and_status_strings(P):
     L = P.lib()
-    assert L.gps_abi_version() == 2
+    assert L.gps_abi_version() == 3
     assert L.gps_status_string(0) == b"ok"
     assert b"capacity" in L.gps_status_string(-3)
+
+
+def test_level_camera_matches_the_reference(P):
+    """gps_level_camera (a host call) against the reference tracker's own level intrinsics."""
+    from oracle import icp as OI
+    cam = {"width": 1280, "height": 720, "fx": 1200.0, "fy": 1190.0, "cx": 639.7, "cy": 360.2,
+           "R": np.eye(3), "t": np.zeros(3)}
+    for lvl in range(4):
+        got, ref = P.gps.level_camera(cam, lvl), OI.level_camera(cam, lvl)
+        assert (got["width"], got["height"]) == (ref["width"], ref["height"])
+        for k in ("fx", "fy", "cx", "cy"):
+            assert got[k] == np.float32(ref[k]), (lvl, k)
+    with pytest.raises(P.GpsError):
+        P.gps.level_camera(cam, 17)
+    with pytest.raises(P.GpsError):
+        P.gps.level_camera({**cam, "width": 3, "height": 3}, 2)
 
 
 def test_default_cfg(P):
@@ -114,6 +130,12 @@ def test_null_pointers_rejected_before_launch(P):
     assert L.gps_adam_step(grp, 1, 1, None, 0.9, 0.999, 1e-15, None) == -1
     assert L.gps_adam_step(grp, 0, 1, None, 0.9, 0.999, 1e-15, None) == -1
     assert L.gps_adam_step(grp, 9, 1, None, 0.9, 0.999, 1e-15, None) == -1
+    # eps must be positive and finite, as for the backward with Adam in its epilogue
+    # (with eps = 0 an element whose gradients were all zero would become 0/0)
+    empty = (P.gps.AdamGroupS * 1)()
+    empty[0].n = 0
+    for bad_eps in (0.0, -1e-8, float("nan"), float("inf")):
+        assert L.gps_adam_step(empty, 1, 1, None, 0.9, 0.999, bad_eps, None) == -1
     st = ctypes.c_int32(0)
     assert L.gps_device_status(None, 0, ctypes.byref(st), None) == -1
 
@@ -158,8 +180,8 @@ def test_insertion_defaults_and_argument_checks(P):
     L = P.lib()
     c = P.gps.InsertCfgS()
     L.gps_insert_cfg_default(ctypes.byref(c))
-    assert (c.delta_c, c.delta_w, c.fraction, c.radius, c.scale_cap, c.flat_ratio, c.opacity) == pytest.approx(
-        (0.05, 4.0, 0.25, 4, 0.1, 0.1, 0.5))
+    assert (c.delta_c, c.delta_w, c.fraction, c.scale_cap, c.flat_ratio, c.opacity) == pytest.approx(
+        (0.05, 4.0, 0.25, 0.1, 0.1, 0.5))
     n = ctypes.c_size_t(0)
     assert L.gps_insertion_workspace_size(64, 48, ctypes.byref(n)) == 0 and n.value >= 4 * 64 * 48
     assert L.gps_insertion_workspace_size(0, 48, ctypes.byref(n)) == -1
@@ -174,7 +196,7 @@ def test_insertion_defaults_and_argument_checks(P):
         return L.gps_insert_gaussians(ctypes.byref(cfg), ctypes.byref(cam), img, img, img, img, img, ctypes.byref(g),
                                       None, ctypes.byref(cnt), None, ws_bytes, None)
     assert call(c) == -1                                                   # no workspace
-    for field, value in (("radius", 0), ("radius", 9), ("fraction", 1.5), ("opacity", 1.0), ("scale_cap", 0.0),
+    for field, value in (("fraction", 1.5), ("opacity", 1.0), ("scale_cap", 0.0), ("flat_ratio", 1.5),
                          ("delta_w", 0.0), ("delta_c", float("nan"))):
         bad = P.gps.InsertCfgS.from_buffer_copy(c)
         setattr(bad, field, value)

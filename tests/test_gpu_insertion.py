@@ -10,10 +10,14 @@ on (its sign is the camera-facing choice; it is compared exactly away from
 grazing surfaces).  The quaternion itself is compared where the shortest-arc
 rotation is well conditioned (axis not near -z).
 
+The three nearest mask vertices of App. A are searched over the whole mask on
+both sides (the reference by brute force over every mask vertex).
+
 Inputs: the small analytic scene at 160x120 and the room at 320x240, whole
-frames; the room at 1280x720 on sampled pixels, each recomputed by the
-reference on the crop that holds its search window; plus capacity limits,
-empty samples, odd frame sizes and the window radii 1 and 8.
+frames; sparse masks whose nearest vertices lie far away in the image, isolated
+mask pixels (capped scales) and masks of one and two pixels; the room at
+1280x720 on 300 sampled Gaussians (the reference samples only those, over the
+same whole-frame mask); plus capacity limits, empty samples and odd frame sizes.
 """
 import numpy as np
 import pytest
@@ -99,16 +103,52 @@ def test_insertion_parity_whole_frame(P, O, which):
     _compare(got, want, cam.as_dict())
 
 
-@pytest.mark.parametrize("radius", [1, 8])
-def test_insertion_window_radius(P, O, radius):
-    say(f"insertion parity: radius {radius}")
+@pytest.mark.parametrize("density", [0.002, 0.02, 0.2])
+def test_insertion_sparse_masks(P, O, density):
+    """Masks of a given density over the room at 160x120: at low density the three nearest
+    mask vertices are many blocks away in the image or beyond the cap distance."""
+    say(f"insertion parity: sparse mask, density {density}")
     scene, cam = synth.scene_room(), _room_cam(160, 120, frame=7)
-    inputs = synth.insertion_inputs(scene, cam, seed=11, device=DEV)
-    want, wpix = O.insert_gaussians(cam.as_dict(), *inputs, radius=radius)
-    got, pix, n_taken = _gpu(P, cam.as_dict(), inputs, radius=radius)
+    C, K, Wg, D, r = synth.insertion_inputs(scene, cam, seed=11, device=DEV)
+    rng = np.random.default_rng(int(density * 1e4))
+    err = rng.uniform(size=D.shape) < density
+    C = K.copy()
+    C[:, err] += 0.3
+    Wg = np.zeros_like(Wg)
+    r = np.where(rng.uniform(size=D.shape) < 0.5, 0.0, 1.0).astype(np.float32)
+    inputs = (C, K, Wg, D, r)
+    want, wpix = O.insert_gaussians(cam.as_dict(), *inputs)
+    got, pix, n_taken = _gpu(P, cam.as_dict(), inputs)
     assert n_taken == wpix.size > 0
     np.testing.assert_array_equal(pix, wpix)
     _compare(got, want, cam.as_dict())
+    if density < 0.01:
+        assert (np.exp(want["log_scale"][0]) >= 0.1 - 1e-12).any()   # isolated: capped
+    assert (np.exp(want["log_scale"][0]) < 0.1).any()
+
+
+@pytest.mark.parametrize("n_mask", [1, 2, 3, 4])
+def test_insertion_tiny_masks(P, O, n_mask):
+    """One to four mask pixels far apart in the image: the mean runs over the other mask
+    vertices there are (none: the cap), found wherever they are in the frame."""
+    say(f"insertion parity: {n_mask} mask pixels")
+    W, H = 96, 64
+    cam = {"width": W, "height": H, "fx": 300.0, "fy": 300.0, "cx": W / 2, "cy": H / 2,
+           "R": np.eye(3, dtype=np.float32), "t": np.zeros(3, np.float32)}
+    D = np.full((H, W), 1.5, np.float32)
+    K = np.zeros((3, H, W), np.float32)
+    C = K.copy()
+    # the first two are 0.083 m apart (below the cap), the others half a metre away
+    for (j, i) in [(3, 5), (10, 20), (60, 90), (40, 7)][:n_mask]:
+        C[:, j, i] = 0.5
+    z = np.zeros((H, W), np.float32)
+    want, wpix = O.insert_gaussians(cam, C, K, z, D, z)
+    got, pix, n_taken = _gpu(P, cam, (C, K, z, D, z))
+    assert n_taken == wpix.size == n_mask
+    np.testing.assert_array_equal(pix, wpix)
+    _compare(got, want, cam)
+    if n_mask == 2:
+        assert (np.exp(want["log_scale"][0]) < 0.09).all()
 
 
 def test_insertion_capacity_and_empty(P, O):
@@ -150,7 +190,7 @@ def test_insertion_odd_sizes(P, O, W, H):
 
 def test_insertion_plane_closed_form(P):
     """A fronto-parallel plane at depth d: every pixel is sampled, the means are the
-    back-projected pixels, s1 = sqrt(d / f) inside (all three neighbours at d / f), the
+    back-projected pixels, s1 = d / f inside (all three neighbours at d / f), the
     disc axis is -z inside and points to the camera on the border."""
     say("insertion: plane closed form")
     W, H, f, d = 40, 30, 200.0, 0.5
@@ -164,8 +204,8 @@ def test_insertion_plane_closed_form(P):
     np.testing.assert_allclose(got["mean"][0], (ii - cam["cx"]) * d / f, atol=1e-7)
     np.testing.assert_allclose(got["mean"][1], (jj - cam["cy"]) * d / f, atol=1e-7)
     inner = (ii > 0) & (ii < W - 1) & (jj > 0) & (jj < H - 1)
-    np.testing.assert_allclose(got["log_scale"][0, inner], 0.5 * np.log(d / f), atol=5e-6)
-    np.testing.assert_allclose(got["log_scale"][2, inner], 0.5 * np.log(d / f) + np.log(0.1), atol=5e-6)
+    np.testing.assert_allclose(got["log_scale"][0, inner], np.log(d / f), atol=5e-6)
+    np.testing.assert_allclose(got["log_scale"][2, inner], np.log(d / f) + np.log(0.1), atol=5e-6)
     az = _rot_z(got["quat"])
     np.testing.assert_allclose(az[:, inner], np.array([[0.0], [0.0], [-1.0]]) * np.ones((1, inner.sum())), atol=1e-6)
     p = got["mean"][:, ~inner]
@@ -174,7 +214,8 @@ def test_insertion_plane_closed_form(P):
 
 def test_insertion_full_size_sampled(P, O):
     """Room at 1280x720: the sample decisions and order on every pixel (the reference
-    mask), and 300 sampled Gaussians recomputed on the crop holding their window."""
+    mask), and 300 sampled Gaussians recomputed by the reference over the whole-frame
+    mask (its draw takes only those 300 pixels; the mask does not depend on the draw)."""
     say("insertion: room 1280x720, sampled")
     scene, cam = synth.scene_room(), _room_cam(1280, 720)
     inputs = synth.insertion_inputs(scene, cam, device=DEV)
@@ -187,20 +228,8 @@ def test_insertion_full_size_sampled(P, O):
     np.testing.assert_array_equal(pix, wpix)
     rng = np.random.default_rng(5)
     sel = np.sort(rng.choice(wpix.size, 300, replace=False))
-    R4 = 4
-    cd = cam.as_dict()
-    H, W = D.shape
-    want = {k: [] for k in KEYS}
-    for s in sel:
-        j, i = divmod(int(wpix[s]), W)
-        j0, j1, i0, i1 = max(0, j - R4), min(H - 1, j + R4), max(0, i - R4), min(W - 1, i + R4)
-        crop = {**cd, "width": i1 - i0 + 1, "height": j1 - j0 + 1, "cx": cd["cx"] - i0, "cy": cd["cy"] - j0}
-        sl = (slice(j0, j1 + 1), slice(i0, i1 + 1))
-        rc = np.ones_like(r[sl])
-        rc[j - j0, i - i0] = 0.0          # sample only the centre; the mask is unchanged
-        o, opix = O.insert_gaussians(crop, C[(slice(None),) + sl], K[(slice(None),) + sl], Wg[sl], D[sl], rc)
-        assert opix.tolist() == [(j - j0) * crop["width"] + (i - i0)]
-        for k in KEYS:
-            want[k].append(o[k][:, 0])
-    want = {k: np.stack(v, axis=1) for k, v in want.items()}
-    _compare({k: v[:, sel] for k, v in got.items()}, want, cd)
+    r_sel = np.ones_like(r)
+    r_sel.reshape(-1)[wpix[sel]] = 0.0
+    want, opix = O.insert_gaussians(cam.as_dict(), C, K, Wg, D, r_sel)
+    np.testing.assert_array_equal(opix, wpix[sel])
+    _compare({k: v[:, sel] for k, v in got.items()}, want, cam.as_dict())

@@ -323,12 +323,20 @@ def test_adam_parity(P, O):
         rp, rm, rv = p0.astype(np.float64), np.zeros(size), np.zeros(size)
         for step in range(1, 4):
             g = (rng.normal(size=size) * 10 ** rng.uniform(-4, 1, size)).astype(np.float32)
+            p_old, m_old = rp.copy(), rm.copy()
             P.adam_step([(p, t(g), m, v, 1e-3)], step)
-            O.adam(rp, g.astype(np.float64), rm, rv, 1e-3, step)
+            # the C ABI takes lr, beta1, beta2 and eps as binary32: the reference gets those values
+            # (beta2 = 0.999 rounds to 0.99900001287, so 1 - beta2 differs from 0.001 by 1.3e-5)
+            f32 = lambda x: float(np.float32(x))
+            O.adam(rp, g.astype(np.float64), rm, rv, f32(1e-3), step, b1=f32(0.9), b2=f32(0.999), eps=f32(1e-15))
             torch.cuda.synchronize()
-            # compare from identical inputs: reset the reference state to the GPU's
-            ref_p = rp.copy()
-            assert np.abs(h(p) - ref_p).max() <= 1e-6 * np.abs(ref_p).max() + 1e-7
+            # compare from identical inputs (the reference state is reset to the GPU's after each
+            # step), element by element, 1e-6 relative; the only extra allowance is one binary32
+            # rounding of the terms that cancel (p - step, b1 m + (1 - b1) g)
+            ulp = 2.0 ** -23
+            assert (np.abs(h(p) - rp) <= 1e-6 * np.abs(rp) + ulp * np.abs(p_old)).all()
+            assert (np.abs(h(m) - rm) <= 1e-6 * np.abs(rm) + ulp * (0.9 * np.abs(m_old) + 0.1 * np.abs(g))).all()
+            assert (np.abs(h(v) - rv) <= 1e-6 * np.abs(rv)).all()
             rp, rm, rv = h(p).astype(np.float64), h(m).astype(np.float64), h(v).astype(np.float64)
 
 
@@ -399,6 +407,38 @@ def test_capacity_overflow_is_reported_and_recoverable(P, O):
     assert ws2.status() == 0
     r = O.render(oc, case["gauss"], case["cam"], case["base_rgb"], case["base_depth"])
     assert normwise(h(views2[0].out_rgb).reshape(3, -1), r["rgb"], r["flag"] == 0) < 1e-4
+
+
+@pytest.mark.parametrize("with_pose", [True, False])
+def test_overflowed_backward_changes_nothing(P, O, with_pose):
+    """A backward (with Adam in its epilogue) on an overflowed workspace reads no slot: gradients and
+    dpose are zero, parameters, moments and the step counter are unchanged."""
+    say(f"overflowed backward with Adam: pose {with_pose}")
+    case = tiny_case(6, M=60, W=53, H=37, log_scale=-2.0)
+    gc, _ = cfg_pair(P, O, eps=0.03, max_instances=8)
+    views, ws, gd, _ = _render_gpu(P, gc, case["gauss"], [case])
+    opt = P.Adam(gd)
+    for k in KEYS:  # non-trivial moments, so an update would move them
+        opt.m[k].fill_(0.01)
+        opt.v[k].fill_(0.02)
+    opt.counter.fill_(5)
+    before = {k: (gd[k].clone(), opt.m[k].clone(), opt.v[k].clone()) for k in KEYS}
+    grads = {k: torch.full_like(v, 7.0) for k, v in gd.items()}
+    dpose = torch.full((1, 6), 7.0, device=DEV) if with_pose else None
+    P.render_bwd_adam(gc, gd, views, ws, opt, grads=grads, dpose=dpose)
+    torch.cuda.synchronize()
+    assert ws.status() == -3
+    for k in KEYS:
+        assert torch.equal(gd[k], before[k][0]) and torch.equal(opt.m[k], before[k][1]), k
+        assert torch.equal(opt.v[k], before[k][2]), k
+        assert (grads[k] == 0).all(), k
+    if with_pose:
+        assert (dpose == 0).all()
+    assert int(opt.counter.item()) == 5
+    # the plain backward on the overflowed workspace: zero gradients as well
+    got = _grads_gpu(P, gc, gd, views, ws)
+    for k in KEYS + ("pose",):
+        assert (got[k] == 0).all(), k
 
 
 def test_bad_device_pointer_kind_is_refused(P):

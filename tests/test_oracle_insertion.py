@@ -65,10 +65,10 @@ def test_fronto_parallel_plane():
     np.testing.assert_allclose(out["mean"][0], (ii - cam["cx"]) * d / f, rtol=0, atol=1e-12)
     np.testing.assert_allclose(out["mean"][1], (jj - cam["cy"]) * d / f, rtol=0, atol=1e-12)
     np.testing.assert_allclose(out["mean"][2], d, rtol=0, atol=1e-12)
-    # three neighbours at d / f: s1 = sqrt(d / f) (below the cap), the short axis a tenth
-    # of it; a corner has two at d / f and the diagonal one at sqrt(2) d / f
+    # three neighbours at d / f: s1 = d / f (the root mean square, below the cap), the short
+    # axis a tenth of it; a corner has two at d / f and the diagonal one at sqrt(2) d / f
     corner = ((ii == 0) | (ii == W - 1)) & ((jj == 0) | (jj == H - 1))
-    s1 = np.where(corner, np.sqrt(d / f * (2 + np.sqrt(2)) / 3), np.sqrt(d / f))
+    s1 = np.where(corner, d / f * np.sqrt((1 + 1 + 2) / 3), d / f)
     np.testing.assert_allclose(np.exp(out["log_scale"]), np.vstack([s1, s1, 0.1 * s1]), rtol=1e-12)
     # inside the image the normal is the plane's, facing the camera (-z); on the border
     # (a neighbour missing) it is the direction to the camera; the rotation takes z onto it
@@ -82,7 +82,7 @@ def test_fronto_parallel_plane():
 
 
 def test_scale_cap_and_tilted_plane():
-    W, H, f = 14, 12, 50.0
+    W, H, f = 14, 12, 15.0
     cam = _cam(W, H, f)
     a, z0 = 0.4, 2.0  # plane z = z0 + a x in the camera frame
     jj, ii = np.mgrid[0:H, 0:W]
@@ -96,8 +96,64 @@ def test_scale_cap_and_tilted_plane():
         R = _quat_rot(out["quat"][:, k])
         if 0 < i < W - 1 and 0 < j < H - 1:
             np.testing.assert_allclose(R @ [0, 0, 1], n_ref, atol=1e-5)  # D is stored in binary32
-    # neighbours ~ z / f apart: sqrt(z / f) > 0.1, so every s1 is capped
+    # neighbours about z / f >= 0.13 apart: above the 0.1 cap, so every s1 is capped
     np.testing.assert_allclose(np.exp(out["log_scale"][0]), 0.1, rtol=1e-12)
+
+
+def test_nearest_vertices_over_the_whole_mask():
+    """A sparse mask over a rough surface: the three nearest mask vertices of every new
+    Gaussian come from the whole mask, wherever they are in the image, and s1 is their root
+    mean square distance, against a k-d tree over the mask's vertices (scipy)."""
+    from scipy.spatial import cKDTree
+    rng = np.random.default_rng(7)
+    W, H, f = 48, 36, 40.0
+    cam = _cam(W, H, f)
+    D = (1.2 + 0.3 * rng.uniform(size=(H, W))).astype(np.float32)  # rough: neighbours in depth, not pixels
+    D[rng.uniform(size=(H, W)) < 0.05] = 0.0
+    K = rng.uniform(size=(3, H, W)).astype(np.float32)
+    C = K.copy()
+    err = rng.uniform(size=(H, W)) < 0.08  # a sparse mask: about 8 % of the pixels
+    C[:, err] += 0.2
+    u = rng.uniform(size=(H, W)).astype(np.float32)
+    out, pix = O.insert_gaussians(cam, C, K, np.zeros((H, W), np.float32), D, u)
+    mask = O.insertion_mask(C, K, np.zeros((H, W), np.float32), D)
+    jj, ii = np.nonzero(mask)
+    d = D[jj, ii].astype(np.float64)
+    Vm = np.stack([(ii - cam["cx"]) / f * d, (jj - cam["cy"]) / f * d, d], axis=1)
+    tree = cKDTree(Vm)
+    assert pix.size > 10
+    far = 0
+    for k, p in enumerate(pix):
+        q = np.array([(p % W - cam["cx"]) / f * D[p // W, p % W], (p // W - cam["cy"]) / f * D[p // W, p % W],
+                      D[p // W, p % W]], np.float64)
+        dist, idx = tree.query(q, k=4)  # itself first
+        assert dist[0] == 0.0
+        rms = np.sqrt(np.mean(dist[1:] ** 2))
+        np.testing.assert_allclose(np.exp(out["log_scale"][0, k]), min(0.1, rms), rtol=1e-12)
+        # how often a neighbour lies outside a 9 x 9 pixel window (what a window search would miss)
+        pj, pi = jj[idx[1:]], ii[idx[1:]]
+        far += int((np.abs(pj - p // W) > 4).any() or (np.abs(pi - p % W) > 4).any())
+    assert far > 0  # the case the whole-mask search exists for occurs in this input
+
+
+def test_fewer_than_three_other_mask_vertices():
+    """Two mask pixels: each one's only neighbour is the other (mean over one); one mask
+    pixel: no neighbour, s1 = the cap."""
+    W, H, f = 20, 10, 100.0
+    cam = _cam(W, H, f)
+    D = np.full((H, W), 1.0, np.float32)
+    K = np.zeros((3, H, W), np.float32)
+    C = K.copy()
+    C[:, 2, 3] = 0.5
+    C[:, 4, 6] = 0.5
+    out, pix = O.insert_gaussians(cam, C, K, np.zeros((H, W), np.float32), D, np.zeros((H, W), np.float32))
+    assert pix.tolist() == [2 * W + 3, 4 * W + 6]
+    gap = np.hypot(3, 2) / f  # both at depth 1: the pixel offset scaled by d / f (below the cap)
+    np.testing.assert_allclose(np.exp(out["log_scale"][0]), [gap] * 2, rtol=1e-12)
+    C[:, 4, 6] = 0.0
+    out, pix = O.insert_gaussians(cam, C, K, np.zeros((H, W), np.float32), D, np.zeros((H, W), np.float32))
+    assert pix.tolist() == [2 * W + 3]
+    np.testing.assert_allclose(np.exp(out["log_scale"][0]), [0.1], rtol=1e-12)
 
 
 def test_sample_is_the_uniform_draw_below_the_fraction():
