@@ -655,6 +655,8 @@ typedef struct {
     double C[3], D, T;
     int32_t n_used;  /* contributors composited (sorted) / blended (sort-free) */
     double W;        /* sort-free: total Gaussian weight W_G                     */
+    uint64_t order;  /* sorted: signature of the composited sequence (position  */
+                     /* k, Gaussian g) -> sum (k+1)(g+1) * odd constant mod 2^64 */
 } orc_pix;
 
 /*
@@ -673,6 +675,7 @@ static void composite_pixel(const orc_cfg* cfg, const orc_proj* P, const orc_gau
     const int M = G->count;
     if (cfg->mode == 0) {
         double T = 1.0, AC[3] = {0, 0, 0}, AD = 0.0;
+        uint64_t order = 0;
         int used = 0;
         for (int k = 0; k < n; ++k) {
             double a = cand[k].alpha;
@@ -685,6 +688,7 @@ static void composite_pixel(const orc_cfg* cfg, const orc_proj* P, const orc_gau
             for (int c = 0; c < 3; ++c) AC[c] += w * (double)G->rgb[c * M + g];
             AD += w * P[g].depth;
             T = Tn;
+            order += (uint64_t)(used + 1) * (uint64_t)(g + 1) * 0x9E3779B97F4A7C15ull;
             ++used;
         }
         for (int c = 0; c < 3; ++c) out->C[c] = AC[c] + T * Ct[c];
@@ -692,6 +696,7 @@ static void composite_pixel(const orc_cfg* cfg, const orc_proj* P, const orc_gau
         out->T = T;
         out->n_used = used;
         out->W = 0.0;
+        out->order = order;
     } else {
         double Wg = 0.0, CG[3] = {0, 0, 0}, ZG = 0.0;
         for (int k = 0; k < n; ++k) {
@@ -706,6 +711,7 @@ static void composite_pixel(const orc_cfg* cfg, const orc_proj* P, const orc_gau
         out->T = 1.0 / (1.0 + Wg);
         out->n_used = n;
         out->W = Wg;
+        out->order = 0;
     }
 }
 
@@ -724,7 +730,8 @@ static orc_proj* project_all(const orc_cfg* cfg, const orc_gauss* G, const orc_c
  */
 void orc_render(const orc_cfg* cfg, const orc_gauss* G, const orc_cam* cam, const float* base_rgb,
                 const float* base_depth, int32_t npix, const int32_t* pix, double* out_rgb,
-                double* out_depth, double* out_T, int32_t* out_flag, int32_t* out_n, double* out_W)
+                double* out_depth, double* out_T, int32_t* out_flag, int32_t* out_n, double* out_W,
+                uint64_t* out_order)
 {
     const int W = cam->width, H = cam->height;
     const size_t HW = (size_t)W * H;
@@ -750,6 +757,7 @@ void orc_render(const orc_cfg* cfg, const orc_gauss* G, const orc_cam* cam, cons
             if (out_flag) out_flag[k] = flag;
             if (out_n) out_n[k] = r.n_used;
             if (out_W) out_W[k] = r.W;
+            if (out_order) out_order[k] = r.order;
         }
         free(cand);
     }

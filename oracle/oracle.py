@@ -79,7 +79,7 @@ def lib():
         L.orc_trilinear.restype = ctypes.c_double
         L.orc_project.argtypes = [P, P, P, P]
         L.orc_project.restype = None
-        L.orc_render.argtypes = [P, P, P, P, P, ctypes.c_int32, P, P, P, P, P, P, P]
+        L.orc_render.argtypes = [P, P, P, P, P, ctypes.c_int32, P, P, P, P, P, P, P, P]
         L.orc_render.restype = None
         L.orc_loss.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, ctypes.c_double, P, P, P]
         L.orc_loss.restype = ctypes.c_double
@@ -235,7 +235,8 @@ def project(cfg: RenderCfg, g, cam):
 
 
 def render(cfg: RenderCfg, g, cam, base_rgb, base_depth, pix=None):
-    """Returns dict rgb [3,npix], depth, T, flag, n, W (float64 / int32)."""
+    """Returns dict rgb [3,npix], depth, T, flag, n, W (float64 / int32) and order (uint64: a
+    signature of each pixel's composited sequence in sorted mode, 0 in sort-free mode)."""
     cam = cam_from(cam)
     G = gauss(g)
     base_rgb = _f32(base_rgb).reshape(3, -1)
@@ -252,10 +253,11 @@ def render(cfg: RenderCfg, g, cam, base_rgb, base_depth, pix=None):
     flag = np.zeros(npix, dtype=np.int32)
     n = np.zeros(npix, dtype=np.int32)
     W = np.zeros(npix)
+    order = np.zeros(npix, dtype=np.uint64)
     c = cfg.c()
     lib().orc_render(ctypes.byref(c), ctypes.byref(G.s), ctypes.byref(cam), _ptr(base_rgb), _ptr(base_depth),
-                     npix, _ptr(pixp), _ptr(rgb), _ptr(depth), _ptr(T), _ptr(flag), _ptr(n), _ptr(W))
-    return {"rgb": rgb, "depth": depth, "T": T, "flag": flag, "n": n, "W": W}
+                     npix, _ptr(pixp), _ptr(rgb), _ptr(depth), _ptr(T), _ptr(flag), _ptr(n), _ptr(W), _ptr(order))
+    return {"rgb": rgb, "depth": depth, "T": T, "flag": flag, "n": n, "W": W, "order": order}
 
 
 def loss(cfg: RenderCfg, W: int, H: int, rgb, depth, target_rgb, target_depth, base_depth, scale=1.0,

@@ -5,8 +5,9 @@
   reference's analytic gradients (each Gaussian's support box re-rendered by the
   reference, with the loss's adjoint there), and central differences of the FP64
   reference loss (h = 1e-4) on 64 parameters of those Gaussians, re-rendering only the
-  parameter's support box, under the active-set rule (same contributors, flags and
-  residual signs at +h and -h; otherwise the next seeded parameter is drawn), tolerance
+  parameter's support box, under the active-set rule (same contributors in the same depth
+  order, no flags and the same residual signs at +h and -h; otherwise the next seeded
+  parameter is drawn), tolerance
   1e-2 of max(|analytic|, |difference|).  The backward recomputes the per-pixel
   transmittance (nothing per pixel is stored by the forward besides T_final).
 * Large streaming map (512^3 at 5 mm, 1,000,000 Gaussians, 4 keyframes at 1280x720):
@@ -139,6 +140,7 @@ def test_differentiation_640x480_50k(P, O):
             Lp, _, _, rp = box_loss(gp, pix)
             Lm, _, _, rm = box_loss(gm, pix)
             same = np.array_equal(rp["n"], rm["n"]) and (rp["flag"] == 0).all() and (rm["flag"] == 0).all()
+            same = same and np.array_equal(rp["order"], rm["order"])  # no two depths swapped places
             same = same and np.array_equal(np.sign(rp["rgb"] - c.reshape(3, -1)[:, pix]),
                                            np.sign(rm["rgb"] - c.reshape(3, -1)[:, pix]))
             same = same and np.array_equal(np.sign(rp["depth"] - d.reshape(-1)[pix]),
@@ -170,7 +172,10 @@ def test_large_map_iteration_512_1m(P, O):
     np.testing.assert_array_equal(h(vol.weight), ref["weight"].astype(np.float32))
     upd = ref["weight"] > 0
     assert upd.sum() > 5_000_000
-    assert np.abs(h(vol.tsdf)[upd] - ref["tsdf"][upd]).max() < 2e-5
+    # binary32 camera-frame depth of a voxel: a 3-term dot product over coordinates up to ~3 m,
+    # rounded to ~3u * 5 m ~ 1e-6 m, i.e. ~5e-5 of the 2 cm truncation; the running average
+    # keeps it there.  Bound: the 1e-4 relative tolerance of the tsdf's range [-1, 1].
+    assert np.abs(h(vol.tsdf)[upd] - ref["tsdf"][upd]).max() < 1e-4
     t32, c32 = ref["tsdf"].astype(np.float32), ref["rgb"].astype(np.float32)
     del ref
     rng = np.random.Generator(np.random.PCG64(81))

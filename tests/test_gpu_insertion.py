@@ -124,7 +124,8 @@ def test_insertion_sparse_masks(P, O, density):
     _compare(got, want, cam.as_dict())
     if density < 0.01:
         assert (np.exp(want["log_scale"][0]) >= 0.1 - 1e-12).any()   # isolated: capped
-    assert (np.exp(want["log_scale"][0]) < 0.1).any()
+    else:
+        assert (np.exp(want["log_scale"][0]) < 0.1).any()            # neighbours within reach
 
 
 @pytest.mark.parametrize("n_mask", [1, 2, 3, 4])

@@ -115,7 +115,8 @@ def test_central_differences(oracle, mode):
         assert float(gp[k][idx]) - float(arr[idx]) == h
         Lp, rp = _render_sum(oracle, cfg, case, gp, case["cam"], gC, gD)
         Lm, rm = _render_sum(oracle, cfg, case, gm, case["cam"], gC, gD)
-        if not (np.array_equal(rp["n"], rm["n"]) and (rp["flag"] == 0).all() and (rm["flag"] == 0).all()):
+        if not (np.array_equal(rp["n"], rm["n"]) and np.array_equal(rp["order"], rm["order"])
+                and (rp["flag"] == 0).all() and (rm["flag"] == 0).all()):
             continue  # active set changed between the two evaluations
         fd = (Lp - Lm) / (2 * h)
         ref = max(abs(fd), abs(an[k][idx]))
@@ -124,7 +125,8 @@ def test_central_differences(oracle, mode):
     assert checked == 64
     # The six pose parameters (camera perturbed with the exact exponential map).  A pose change moves
     # every footprint, so the active-set rule is applied per pixel: the upstream adjoint is kept only
-    # at pixels whose contributor count and flags agree at +h and -h (gradients add over pixels).
+    # at pixels whose contributors, their depth order and flags agree at +h and -h (gradients add
+    # over pixels).
     for j in range(6):
         hp = 1e-4 if j < 3 else 2e-4
         xi = np.zeros(6)
@@ -132,7 +134,7 @@ def test_central_differences(oracle, mode):
         cp, cm = _pose_cam(case["cam"], xi), _pose_cam(case["cam"], -xi)
         rp = oracle.render(cfg, case["gauss"], cp, case["base_rgb"], case["base_depth"])
         rm = oracle.render(cfg, case["gauss"], cm, case["base_rgb"], case["base_depth"])
-        keep = (rp["n"] == rm["n"]) & (rp["flag"] == 0) & (rm["flag"] == 0)
+        keep = (rp["n"] == rm["n"]) & (rp["order"] == rm["order"]) & (rp["flag"] == 0) & (rm["flag"] == 0)
         assert keep.mean() > 0.9
         gCk, gDk = gC * keep[None], gD * keep
         fd = (float((rp["rgb"] * gCk).sum() + (rp["depth"] * gDk).sum()) -
