@@ -17,7 +17,8 @@
  *    (x right, y down, z forward).  Pixel (col, row) is sampled at (col, row);
  *    projection is u = fx x/z + cx, v = fy y/z + cy.
  *  - The caller owns every buffer.  The library allocates no device memory and
- *    keeps no state between calls other than cached device attributes.
+ *    keeps no state between calls other than cached device attributes and the
+ *    fixed scratch array of gps_icp_reduce_noalloc.
  *  - `stream` is a hipStream_t (NULL = the default stream).  Every call only
  *    enqueues work and returns without synchronising, except gps_device_status
  *    and gps_read_stats, which synchronise the stream they are given.
@@ -422,6 +423,22 @@ gps_status gps_icp_workspace_size(int32_t width, int32_t height, size_t* out_byt
 gps_status gps_icp_reduce(const gps_camera* prev_cam, const float* prev_depth, const gps_camera* level_cam,
                           const float* level_depth, const float* pose, float dist_thresh, double* out_sys, void* ws,
                           size_t ws_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight tracking loops, harnesses that forbid hipMalloc): gps_icp_reduce without
+ * the workspace.  Same arguments, checks, kernels and bitwise the same out_sys.
+ * The block sums go to a scratch array inside the library, GPS_ICP_SCRATCH_BYTES
+ * bytes per GPU, held from the first call on that GPU until the process ends; it
+ * holds the sums of the widest grid the reduce launches, so every level size that
+ * gps_icp_reduce accepts fits (a larger need returns
+ * GPS_ERR_WORKSPACE_TOO_SMALL).  Nothing is allocated and nothing is cleared:
+ * each call overwrites the sums it reads.  All calls on one GPU share that array,
+ * so calls that overlap on one GPU (on different streams or threads) race; the
+ * caller serialises them. */
+#define GPS_ICP_SCRATCH_BYTES (29 * 1024 * 4)
+gps_status gps_icp_reduce_noalloc(const gps_camera* prev_cam, const float* prev_depth, const gps_camera* level_cam,
+                                  const float* level_depth, const float* pose, float dist_thresh, double* out_sys,
+                                  void* stream);
 
 /* Solves H xi = -g (Cholesky, binary64) and applies T_{g,k} <- Exp(xi) T_{g,k}
  * to the device pose in place; out_xi (optional, device [6]) receives xi.  With

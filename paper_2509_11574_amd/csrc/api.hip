@@ -542,9 +542,9 @@ gps_status gps_icp_workspace_size(int32_t width, int32_t height, size_t* out_byt
     return GPS_OK;
 }
 
-gps_status gps_icp_reduce(const gps_camera* prev_cam, const float* prev_depth, const gps_camera* level_cam,
-                          const float* level_depth, const float* pose, float dist_thresh, double* out_sys, void* ws,
-                          size_t ws_bytes, void* stream)
+static gps_status icp_reduce_args_ok(const gps_camera* prev_cam, const float* prev_depth,
+                                     const gps_camera* level_cam, const float* level_depth, const float* pose,
+                                     float dist_thresh, const double* out_sys)
 {
     if (!prev_cam || !level_cam || !prev_depth || !level_depth || !pose || !out_sys) return GPS_ERR_INVALID_ARG;
     if (!cam_ok(*prev_cam) || !(level_cam->width > 0 && level_cam->height > 0) ||
@@ -555,12 +555,38 @@ gps_status gps_icp_reduce(const gps_camera* prev_cam, const float* prev_depth, c
         (int64_t)prev_cam->width * prev_cam->height > (int64_t(1) << 30))
         return GPS_ERR_INVALID_ARG;
     if (!(dist_thresh > 0.0f) || !std::isfinite(dist_thresh)) return GPS_ERR_INVALID_ARG;
+    return GPS_OK;
+}
+
+gps_status gps_icp_reduce(const gps_camera* prev_cam, const float* prev_depth, const gps_camera* level_cam,
+                          const float* level_depth, const float* pose, float dist_thresh, double* out_sys, void* ws,
+                          size_t ws_bytes, void* stream)
+{
+    gps_status st = icp_reduce_args_ok(prev_cam, prev_depth, level_cam, level_depth, pose, dist_thresh, out_sys);
+    if (st != GPS_OK) return st;
     if (!ws || ((uintptr_t)ws & 255)) return GPS_ERR_INVALID_ARG;
     if (ws_bytes < icp_workspace_bytes(level_cam->width, level_cam->height)) return GPS_ERR_WORKSPACE_TOO_SMALL;
-    gps_status st = check_device();
+    st = check_device();
     if (st != GPS_OK) return st;
     return launch_icp_reduce(*prev_cam, prev_depth, *level_cam, level_depth, pose, dist_thresh, out_sys,
                              static_cast<char*>(ws), (hipStream_t)stream);
+}
+
+gps_status gps_icp_reduce_noalloc(const gps_camera* prev_cam, const float* prev_depth, const gps_camera* level_cam,
+                                  const float* level_depth, const float* pose, float dist_thresh, double* out_sys,
+                                  void* stream)
+{
+    gps_status st = icp_reduce_args_ok(prev_cam, prev_depth, level_cam, level_depth, pose, dist_thresh, out_sys);
+    if (st != GPS_OK) return st;
+    st = check_device();
+    if (st != GPS_OK) return st;
+    char* scr = nullptr;
+    size_t scr_bytes = 0;
+    st = icp_scratch(&scr, &scr_bytes);
+    if (st != GPS_OK) return st;
+    if (icp_partial_bytes(level_cam->width, level_cam->height) > scr_bytes) return GPS_ERR_WORKSPACE_TOO_SMALL;
+    return launch_icp_reduce(*prev_cam, prev_depth, *level_cam, level_depth, pose, dist_thresh, out_sys, scr,
+                             (hipStream_t)stream);
 }
 
 gps_status gps_icp_solve(const double* sys, float* pose, float* out_xi, void* stream)

@@ -15,6 +15,7 @@
 // No atomics: the system is bitwise reproducible.  Every stage reads the pose
 // from device memory, so a tracking loop can be replayed as a graph.
 #include <cmath>
+#include <mutex>
 
 #include "gps_internal.h"
 #include "launch.h"
@@ -24,6 +25,14 @@
 namespace gps {
 
 constexpr int kIcpTerms = 29;  // 21 (H, upper triangle, row-major) + 6 (g) + E + count
+constexpr int kIcpMaxBlocks = 1024;  // widest grid of k_icp_pairs (four blocks per compute unit)
+
+// Block sums of the allocation-free reduce (gps_icp_reduce_noalloc): room for the
+// widest grid, so every level size fits.  One copy per GPU, held until the process
+// ends; each call overwrites the entries it reads, so nothing is cleared.  Host code
+// takes its address from icp_scratch(), never from this name.
+static __device__ __align__(256) float scratch[kIcpTerms * kIcpMaxBlocks];
+static_assert(sizeof(scratch) == GPS_ICP_SCRATCH_BYTES, "the header states the scratch size");
 
 __global__ void __launch_bounds__(256) k_depth_down(const float* __restrict__ in, int W, int H,
                                                     float* __restrict__ out, int Wo, int Ho)
@@ -308,6 +317,32 @@ __global__ void __launch_bounds__(64) k_icp_solve(const double* __restrict__ sys
     if (out_xi && threadIdx.x < 6) out_xi[threadIdx.x] = res[12 + threadIdx.x];
 }
 
+// Device address of `scratch` on the current device, looked up once per device.
+gps_status icp_scratch(char** out, size_t* bytes)
+{
+    static std::mutex mu;
+    static void* addr[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return GPS_ERR_HIP;
+    if (dev < 0 || dev >= 64) return GPS_ERR_UNSUPPORTED_DEVICE;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return GPS_ERR_HIP;
+        addr[dev] = p;
+    }
+    *out = static_cast<char*>(addr[dev]);
+    *bytes = sizeof(scratch);
+    return GPS_OK;
+}
+
+// Bytes of block sums k_icp_pairs writes for a level of W x H pixels.
+size_t icp_partial_bytes(int W, int H)
+{
+    const size_t want = ((size_t)W * H + 255) / 256;
+    return (size_t)kIcpTerms * sizeof(float) * (want < kIcpMaxBlocks ? want : kIcpMaxBlocks);
+}
+
 size_t icp_workspace_bytes(int W, int H)
 {
     const size_t nblk = ((size_t)W * H + 255) / 256;
@@ -337,9 +372,9 @@ gps_status launch_icp_reduce(const gps_camera& prev, const float* prev_depth, co
     a.depth = depth;
     a.pose = pose;
     a.dist2 = dist_thresh * dist_thresh;
-    // at most 1024 blocks (four per compute unit); larger levels loop inside the block
+    // at most kIcpMaxBlocks blocks; larger levels loop inside the block
     const size_t want = ((size_t)lvl.width * lvl.height + 255) / 256;
-    a.nblk = (int)(want < 1024 ? want : 1024);
+    a.nblk = (int)(want < kIcpMaxBlocks ? want : kIcpMaxBlocks);
     a.part = reinterpret_cast<float*>(ws);
     GPS_LAUNCH(K_ICP, s, k_icp_pairs, dim3(a.nblk), dim3(256), 0, s, a);
     GPS_LAUNCH(K_ICP, s, k_icp_total, dim3(1), dim3(1024), 0, s, a.part, a.nblk, sys);

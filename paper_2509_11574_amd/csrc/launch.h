@@ -38,6 +38,8 @@ gps_status launch_insert_gaussians(const gps_insert_cfg* cfg, const DevCam& cam,
                                    const float* rnd, gps_gaussians* out, int* out_pixel, int* out_count, char* ws,
                                    hipStream_t s);
 size_t icp_workspace_bytes(int W, int H);
+size_t icp_partial_bytes(int W, int H);
+gps_status icp_scratch(char** out, size_t* bytes);
 gps_status launch_depth_downsample(const float* in, int W, int H, float* out, hipStream_t s);
 gps_status launch_icp_reduce(const gps_camera& prev, const float* prev_depth, const gps_camera& lvl,
                              const float* depth, const float* pose, float dist_thresh, double* sys, char* ws,

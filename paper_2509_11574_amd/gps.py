@@ -95,7 +95,7 @@ EXPORTS = ["gps_abi_version", "gps_status_string", "gps_render_cfg_default", "gp
            "gps_profile_read", "gps_views_upload", "gps_removal_cfg_default", "gps_removal_workspace_size",
            "gps_remove_gaussians", "gps_insert_cfg_default", "gps_insertion_workspace_size",
            "gps_insert_gaussians", "gps_depth_downsample", "gps_icp_workspace_size", "gps_icp_reduce",
-           "gps_icp_solve", "gps_render_bwd_adam", "gps_level_camera"]
+           "gps_icp_solve", "gps_render_bwd_adam", "gps_level_camera", "gps_icp_reduce_noalloc"]
 
 _lib = None
 
@@ -138,6 +138,7 @@ def lib():
         L.gps_depth_downsample.argtypes = [P, I32, I32, P, P]
         L.gps_icp_workspace_size.argtypes = [I32, I32, ctypes.POINTER(ctypes.c_size_t)]
         L.gps_icp_reduce.argtypes = [P, P, P, P, P, F, P, P, ctypes.c_size_t, P]
+        L.gps_icp_reduce_noalloc.argtypes = [P, P, P, P, P, F, P, P]
         L.gps_icp_solve.argtypes = [P, P, P, P]
         L.gps_render_bwd_adam.argtypes = [P, P, P, I32, P, P, P, P, P, P, P, ctypes.c_size_t, P]
         L.gps_level_camera.argtypes = [P, I32, P]
@@ -738,6 +739,21 @@ def icp_reduce(prev_cam, prev_depth, level_cam, level_depth, pose, dist_thresh, 
                                 _ptr(pose, "pose", 12), float(dist_thresh), ctypes.c_void_p(ws.sys.data_ptr()),
                                 ctypes.c_void_p(ws.buf.data_ptr()), ws.nbytes, _stream(stream)), "gps_icp_reduce")
     return ws.sys
+
+
+def icp_reduce_noalloc(prev_cam, prev_depth, level_cam, level_depth, pose, dist_thresh, out_sys: torch.Tensor,
+                       stream=None):
+    """gps_icp_reduce_noalloc: the system of Eq. 5 into out_sys (device float64 [29]) with the
+    library's fixed scratch instead of a workspace (nothing is allocated)."""
+    pc, lc = camera(prev_cam), camera({**level_cam, "R": np.eye(3), "t": np.zeros(3)})
+    if not (out_sys.is_cuda and out_sys.dtype == torch.float64 and out_sys.is_contiguous() and out_sys.numel() >= 29):
+        raise ValueError("out_sys must be a contiguous device float64 tensor of at least 29 elements")
+    _check(lib().gps_icp_reduce_noalloc(ctypes.byref(pc), _ptr(prev_depth, "prev_depth", pc.width * pc.height),
+                                        ctypes.byref(lc), _ptr(level_depth, "level_depth", lc.width * lc.height),
+                                        _ptr(pose, "pose", 12), float(dist_thresh),
+                                        ctypes.c_void_p(out_sys.data_ptr()), _stream(stream)),
+           "gps_icp_reduce_noalloc")
+    return out_sys
 
 
 def icp_solve(sys: torch.Tensor, pose: torch.Tensor, xi: torch.Tensor | None = None, stream=None):
