@@ -88,8 +88,10 @@ def parse():
     ap.add_argument("--tile", type=str, default="auto",
                     help="tile_w x tile_h x batch x pixels_per_lane, or 'auto' (autotuned on the first frame)")
     ap.add_argument("--graph", type=int, default=0,
-                    help="time graph replay of the iteration (default: kernel-by-kernel launches with the view "
-                         "table uploaded once per frame); the other mode is timed on later frames")
+                    help="0: time kernel-by-kernel launches (the default: on the same frames they ran ahead of "
+                         "graph replay); 1: time graph replay of each iteration (the view table is uploaded "
+                         "once per frame either way); the other mode replays the same frames from the same "
+                         "map state")
     ap.add_argument("--mode", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -102,7 +104,7 @@ def parse():
     ap.add_argument("--maintenance", type=int, default=1,
                     help="time Gaussian removal (Eq. 8) and insertion (Eq. 6) once the timed frames are done")
     ap.add_argument("--other-mode", type=int, default=1,
-                    help="also time the other launch mode (graph replay or kernel-by-kernel) on later frames")
+                    help="also time the other launch mode (graph replay or kernel-by-kernel) on the same frames")
     ap.add_argument("--tracking", type=int, default=1,
                     help="time ICP tracking (Eq. 5) of one frame against the previous frame's raycast")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -128,10 +130,11 @@ def main():
     torch.cuda.set_device(0)
     W_img, H_img = (int(x) for x in args.res.split("x"))
     K, Wu, M = args.steps, args.warmup, args.gaussians
-    # warm-up frames, then K frames for each of: the timed pass, the pass with per-kernel
-    # events, the pass in the other launch mode (each frame new to the map, as in mapping),
-    # then one frame that is tracked against the raycast of the last one
-    n_frames = Wu + 3 * K + 1
+    # warm-up frames, then K frames for the timed pass (timed again in the other launch mode
+    # from the same map state), K new frames for the pass with per-kernel events (each frame
+    # new to the map, as in mapping), then one frame that is tracked against the raycast of
+    # the last one
+    n_frames = Wu + 2 * K + 1
 
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 4
@@ -213,20 +216,44 @@ def main():
         for _ in range(ITERS_PER_FRAME):
             graph.replay()
 
-    frame_step = frame_step_eager
     last_view = None
     for k in range(Wu):
-        last_view = frame_step(k)
+        last_view = frame_step_eager(k)
+    from paper_2509_11574_amd.graph import IterationGraph
+    # captured on the last warm-up frame's view (capturing runs nothing on the device)
+    graph = IterationGraph(cfg, params, [last_view], ws, grads, opt, loss, dpose, fused_adam=True)
     if args.graph:
-        from paper_2509_11574_amd.graph import IterationGraph
-        # captured on the last warm-up frame's view (capturing runs nothing on the device)
-        graph = IterationGraph(cfg, params, [last_view], ws, grads, opt, loss, dpose, fused_adam=True)
-        frame_step = frame_step_graph
+        frame_step, mode_name, alt_step, alt_mode = frame_step_graph, "graph", frame_step_eager, "eager"
+    else:
+        frame_step, mode_name, alt_step, alt_mode = frame_step_eager, "eager", frame_step_graph, "graph"
     torch.cuda.synchronize()
     st0 = ws.stats()
     if st0["status"] != 0:
         raise RuntimeError(f"device status {st0['status']} after warm-up: {st0}")
     first_loss = float(loss.item())
+
+    # the map state before the timed frames: the other launch mode replays the same frames from it
+    def snapshot():
+        st = {("p", k): v.clone() for k, v in params.items()}
+        st.update({("m", k): v.clone() for k, v in opt.m.items()})
+        st.update({("v", k): v.clone() for k, v in opt.v.items()})
+        st.update({("vol", n): getattr(vol, n).clone() for n in ("tsdf", "weight", "rgb", "rgb_weight")})
+        st[("ctr", "")] = opt.counter.clone()
+        return st, opt.t
+
+    def restore(snap):
+        st, t = snap
+        for (kind, k), v in st.items():
+            dst = {"p": params, "m": opt.m, "v": opt.v}.get(kind)
+            if dst is not None:
+                dst[k].copy_(v)
+            elif kind == "vol":
+                getattr(vol, k).copy_(v)
+            else:
+                opt.counter.copy_(v)
+        opt.t = t
+
+    snap = snapshot() if args.other_mode else None
 
     # ------------------------------------------------------- timed frames
     torch.cuda.synchronize()
@@ -252,8 +279,32 @@ def main():
     pct = lambda q: per_frame[min(K - 1, int(round(q * (K - 1))))]
     frame_ms_pct = {"p10": round(pct(0.1), 4), "p50": round(pct(0.5), 4), "p90": round(pct(0.9), 4)}
 
-    log(f"timed {K} frames: {ms_per_frame:.3f} ms/frame (events {ms_event / K:.3f}), {iters_per_s:.1f} iters/s, "
-        f"loss {first_loss:.5f} -> {last_loss:.6f}, instances {st1['n_instances']}")
+    log(f"timed {K} frames ({mode_name}): {ms_per_frame:.3f} ms/frame (events {ms_event / K:.3f}), "
+        f"{iters_per_s:.1f} iters/s, loss {first_loss:.5f} -> {last_loss:.6f}, instances {st1['n_instances']}")
+
+    # ------------- the same frames from the same map state in the other launch mode
+    alt = None
+    if snap is not None:
+        end_params = {k: v.clone() for k, v in params.items()}
+        restore(snap)
+        del snap
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for k in range(Wu, Wu + K):
+            alt_step(k)
+        torch.cuda.synchronize()
+        te = time.perf_counter() - t1
+        same = float(loss.item()) == last_loss and all(torch.equal(params[k], end_params[k]) for k in params)
+        del end_params
+        alt = {"launch": alt_mode, "ms_per_frame": round(1000.0 * te / K, 4),
+               "iters_per_s": round(ITERS_PER_FRAME * K / te, 1),
+               "bitwise_same_map": same,
+               "frames": "the same %d frames from the same map state (parameters, moments, step counter and "
+                         "volume restored), each iteration %s" %
+                         (K, "launched kernel by kernel" if alt_mode == "eager"
+                          else "replayed as one captured HIP graph")}
+        log(f"other launch mode ({alt_mode}) on the same frames: {alt['ms_per_frame']:.3f} ms/frame, "
+            f"{alt['iters_per_s']:.1f} iters/s, bitwise the same map: {same}")
 
     # --------------------------------------- per-kernel times (HIP events)
     kernels, pairs = {}, None
@@ -269,28 +320,6 @@ def main():
         n_fwd = kernels.get("composite_fwd", (1, 0))[0]
         pairs = {"eval_per_launch": (stp1["pairs_eval"] - stp0["pairs_eval"]) / n_fwd,
                  "contrib_per_launch": (stp1["pairs_contrib"] - stp0["pairs_contrib"]) / n_fwd}
-    # ------------------ the next frames in the other launch mode (wall clock)
-    alt = None
-    if not args.other_mode:
-        alt_step = None
-    elif args.graph:
-        alt_step, alt_mode = frame_step_eager, "eager"
-    else:
-        from paper_2509_11574_amd.graph import IterationGraph
-        graph = IterationGraph(cfg, params, [last_view], ws, grads, opt, loss, dpose, fused_adam=True)
-        alt_step, alt_mode = frame_step_graph, "graph"
-    if alt_step is not None:
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for k in range(Wu + 2 * K, Wu + 3 * K):
-            alt_step(k)
-        torch.cuda.synchronize()
-        te = time.perf_counter() - t1
-        alt = {"launch": alt_mode, "ms_per_frame": round(1000.0 * te / K, 4),
-               "iters_per_s": round(ITERS_PER_FRAME * K / te, 1),
-               "frames": "the %d frames after the profiled ones, each iteration %s" %
-                         (K, "launched kernel by kernel" if alt_mode == "eager"
-                          else "replayed as one captured HIP graph")}
     roofline = None
     if kernels:
         dom = max(kernels, key=lambda n: kernels[n][1])
@@ -327,19 +356,20 @@ def main():
     hbm_gbs = bytes_iter / (iter_ms / 1e3) / 1e9 if iter_ms else None
 
     # ------------------------ sorted against sort-free passes (Table 7 analogue)
-    modes = bench_modes(P, cfg, params, frame_prep(Wu + K - 1), M, cam0, reps=40) if args.modes else None
+    mview = frame_prep(Wu + K - 1)
+    modes = bench_modes(P, cfg, params, mview, M, cam0, reps=40) if args.modes else None
 
     # ----------------------------------- batched keyframes and the large map
     batched = bench_batched(P, synth, dev, cfg, reps=20) if args.batched else None
     large = bench_large(P, synth, dev, cfg, args.large_frames) if args.large_frames > 0 else None
 
     # -------------------------------- map maintenance: removal and insertion
-    maint = bench_maintenance(P, synth, scene, cams[Wu], params, opt) if args.maintenance else None
+    maint = bench_maintenance(P, cfg, mview, params, opt) if args.maintenance else None
 
     # ------------- camera tracking of the next frame against the last raycast
     tracking = None
     if args.tracking:
-        kl = Wu + 3 * K - 1
+        kl = Wu + 2 * K - 1
         frame_prep(kl)  # base_depth: the SDF raycast of the last frame
         tracking = bench_tracking(P, cams[kl].as_dict(), base_depth, cams[kl + 1].as_dict(), frames[kl + 1][0])
 
@@ -433,40 +463,92 @@ def bench_modes(P, cfg, params, view, M, cam0, reps=40):
     return out
 
 
-def bench_maintenance(P, synth, scene, cam, params, opt, reps=20):
-    """Map maintenance of Sec. 3.2.2, kernel time per call (HIP events around each
-    launch): removal (Eq. 8) over the trained Gaussians with their two Adam moment
-    sets as companions (3 sets, out of place), and insertion (Eq. 6, App. A) on one
-    frame of the room with the seeded insertion inputs.  Algorithmic bytes: removal
-    reads the 16 B that decide each Gaussian, all 56 B rows of every set and writes
-    the kept rows; insertion reads 36 B per pixel and writes 60 B per new Gaussian
-    (its rows and pixel index)."""
-    import numpy as np
+def bench_maintenance(P, cfg, view, params, opt, reps=20):
+    """Map maintenance of Sec. 3.2.2 on the trained map and a room frame.
+    Kernel time per call (HIP events around each launch): removal (Eq. 8) over the
+    Gaussians with their two Adam moment sets as companions (3 sets, out of place);
+    insertion (Eq. 6, App. A) from the map's own sort-free render of the frame (C* and
+    the Gaussian weight W_G of Eq. 2, one forward in mode 1) with a seeded uniform draw.
+    Algorithmic bytes: removal reads the 16 B that decide each Gaussian, all 56 B rows
+    of every set and writes the kept rows; insertion reads 36 B per pixel and writes
+    60 B per new Gaussian (its rows and pixel index).
+    Then one whole keyframe cycle on a copy of the map (wall clock, host reads of the
+    counts included): sort-free render, insertion and append, ten iterations of forward
+    and backward with Adam on the grown map, and removal."""
+    from dataclasses import replace
+
     import torch
+
+    from paper_2509_11574_amd.mapping import GaussianMap, insert_from_render
     dev = params["mean"].device
     M = int(params["opacity_logit"].numel())
-    imgs = [torch.as_tensor(np.ascontiguousarray(a)).to(dev) for a in synth.insertion_inputs(scene, cam, device=dev)]
-    cd = cam.as_dict()
+    c = P.camera(view.cam)
+    W, H = c.width, c.height
+    cfg1 = replace(cfg, mode=1, views_preset=False)
+    v1 = P.View(view.cam, view.base_rgb, view.base_depth, view.target_rgb, view.target_depth,
+                out_aux=torch.empty(H, W, device=dev))
+    ws1 = P.Workspace(cfg1, M, [view.cam], device=dev)
+    rand = torch.rand(H, W, device=dev, generator=torch.Generator(device=dev).manual_seed(5))
+    cd = view.cam
+
+    def once():
+        P.render_fwd(cfg1, params, [v1], ws1)
+        ins = P.insert_gaussians(cd, v1.out_rgb, v1.target_rgb, v1.out_aux, v1.base_depth, rand)
+        rem = P.remove_gaussians(params, [opt.m, opt.v])
+        return ins, rem
+
     for _ in range(2):
-        P.remove_gaussians(params, [opt.m, opt.v])
-        P.insert_gaussians(cd, *imgs)
+        once()
     torch.cuda.synchronize()
     P.gps.profile_start()
     for _ in range(reps):
-        _, _, kept = P.remove_gaussians(params, [opt.m, opt.v])
-        _, new, n_taken = P.insert_gaussians(cd, *imgs)
+        (new, _, n_taken), (_, _, kept) = once()
     torch.cuda.synchronize()
     P.gps.profile_stop()
     kt = P.gps.profile_read()
     rem_ms, ins_ms = kt["remove"][1] / reps, kt["insert"][1] / reps
-    px = cam.width * cam.height
+    render_ms = sum(kt[n][1] for n in kt if n not in ("remove", "insert")) / reps
+    px = W * H
     rem_bytes = 16 * M + 3 * 56 * (M + kept)
-    ins_bytes = 36 * px + 60 * int(new.numel())
-    return {"removal": {"gaussians": M, "kept": kept, "sets": 3, "ms_per_call": round(rem_ms, 4),
-                        "algorithmic_bytes": rem_bytes, "gbs": round(rem_bytes / (rem_ms / 1e3) / 1e9, 1)},
-            "insertion": {"pixels": px, "new": n_taken, "ms_per_call": round(ins_ms, 4),
-                          "algorithmic_bytes": ins_bytes, "gbs": round(ins_bytes / (ins_ms / 1e3) / 1e9, 1)},
-            "launches_per_call": {"removal": 3, "insertion": 4}}
+    ins_bytes = 36 * px + 60 * min(n_taken, px)
+    out = {"removal": {"gaussians": M, "kept": kept, "sets": 3, "ms_per_call": round(rem_ms, 4),
+                       "algorithmic_bytes": rem_bytes, "gbs": round(rem_bytes / (rem_ms / 1e3) / 1e9, 1)},
+           "insertion": {"pixels": px, "new": n_taken, "ms_per_call": round(ins_ms, 4),
+                         "algorithmic_bytes": ins_bytes, "gbs": round(ins_bytes / (ins_ms / 1e3) / 1e9, 1),
+                         "inputs": "C* and W_G of the map's sort-free render of the frame, "
+                                   "uniform draw from a seeded generator",
+                         "render_ms": round(render_ms, 4)},
+           "launches_per_call": {"removal": 3, "insertion": 4}}
+    # one keyframe cycle on a copy of the map
+    gmap = GaussianMap({k: v.clone() for k, v in params.items()})
+    for k in gmap.params:
+        gmap.opt.m[k].copy_(opt.m[k])
+        gmap.opt.v[k].copy_(opt.v[k])
+    gmap.opt.t = opt.t
+    gmap.opt.counter.copy_(opt.counter)
+    loss = torch.zeros(1, device=dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, n_new = insert_from_render(gmap, cfg, v1, rand)
+    ws = P.Workspace(cfg, gmap.count, [view.cam], device=dev)
+    P.gps.views_upload(cfg, gmap.params, [view], ws)
+    cfg_pre = replace(cfg, views_preset=True)
+    first = None
+    for it in range(ITERS_PER_FRAME):
+        P.render_fwd(cfg_pre, gmap.params, [view], ws, out_loss=loss)
+        if it == 0:
+            first = loss.clone()
+        P.render_bwd_adam(cfg_pre, gmap.params, [view], ws, gmap.opt)
+    grown = gmap.count
+    n_kept = gmap.prune()
+    torch.cuda.synchronize()
+    cyc_ms = 1000.0 * (time.perf_counter() - t0)
+    out["keyframe_cycle"] = {"ms": round(cyc_ms, 3), "gaussians_before": M, "inserted": n_new, "grown": grown,
+                             "kept": n_kept, "loss_first_last": [round(float(first.item()), 6),
+                                                                 round(float(loss.item()), 6)],
+                             "steps": "sort-free render + insertion + append, %d iterations (forward, backward "
+                                      "with Adam) on the grown map, removal; one run, wall clock" % ITERS_PER_FRAME}
+    return out
 
 
 def bench_tracking(P, prev_cam, prev_depth, cur_cam, cur_depth, reps=10):
@@ -641,15 +723,22 @@ def bench_large(P, synth, dev, cfg, n_frames, n_gauss=1_000_000, warm=2):
             "instances": st["n_instances"]}
 
 
-def cpu_baseline(scene, cam, frame, gauss_np, cfg):
-    """The reference implementation, as it stands, on this host: one fusion of the
-    full volume, the raycast of every 8th pixel in each direction and one
-    forward + backward of every 16th, scaled to a whole frame of the same
-    workload (fusion + raycast + 10 iterations); Adam over all parameters."""
+def _host_threads():
+    """Threads the host gives this process: the OpenMP setting where it is set, else the
+    CPUs this process may run on."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        n = os.cpu_count() or 1
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    return max(1, min(n, int(env))) if env.isdigit() else n
+
+
+def _oracle_frame(O, scene, cam, frame, gauss_np, cfg):
+    """Seconds of the reference on a bounded sample of one frame of the room workload: one
+    fusion of the full volume, the raycast of every 8th pixel in each direction and one
+    forward + backward of every 16th, Adam over all parameters; scaled to the frame."""
     import numpy as np
-
-    from oracle import oracle as O
-
     depth = frame[0].cpu().numpy()
     rgb = frame[1].cpu().numpy()
     camd = cam.as_dict()
@@ -690,12 +779,57 @@ def cpu_baseline(scene, cam, frame, gauss_np, cfg):
     scale = Pp / pix_f.size
     t_iter = (t_fwd + t_bwd) * scale + t_adam
     t_frame = t_fuse + t_ray + ITERS_PER_FRAME * t_iter
-    return {"value": round(ITERS_PER_FRAME / t_frame, 5), "unit": "iters/s", "cores": 1, "kind": "oracle",
-            "ms_per_frame": round(1e3 * t_frame, 1), "ms_per_iteration": round(1e3 * t_iter, 1),
-            "sample": f"FP64 C reference, 1 thread: full-volume fusion ({t_fuse:.2f} s), raycast of "
-                      f"{pix_r.size} px scaled x{Pp / pix_r.size:.0f}, forward+backward of {pix_f.size} px "
-                      f"({t_fwd + t_bwd:.2f} s) scaled x{scale:.0f}, Adam over all parameters",
-            "cpu": _cpu_model()}
+    return {"t_frame": t_frame, "t_iter": t_iter, "t_fuse": t_fuse, "t_fwd_bwd": t_fwd + t_bwd,
+            "pix_r": pix_r.size, "pix_f": pix_f.size, "ray_scale": Pp / pix_r.size, "fb_scale": scale}
+
+
+def _oracle_tiny(O, synth):
+    """Seconds of the reference on the whole tiny workload, unsampled: 64^3 fusion, raycast
+    of every pixel of the 160x120 frame, forward + backward over 2,000 Gaussians, Adam."""
+    import numpy as np
+    w = synth.workload_small(M=2000)
+    sc, cam = w["scene"], w["cam"]
+    camd = cam.as_dict()
+    t = time.perf_counter()
+    grid = O.make_grid(sc.dims, sc.origin, sc.voxel, sc.trunc, 100.0)
+    vol = O.fuse(grid, O.new_volume(grid), camd, w["depth"], w["rgb"])
+    rd, rc, _ = O.raycast(grid, vol["tsdf"].astype(np.float32), vol["rgb"].astype(np.float32), camd)
+    bd, bc = rd.astype(np.float32), rc.astype(np.float32)
+    ocfg = O.RenderCfg(eps_cull=sc.voxel)
+    r = O.render(ocfg, w["gauss"], camd, bc, bd)
+    L, gC, gD, _ = O.loss(ocfg, cam.width, cam.height, r["rgb"], r["depth"], w["rgb"], w["depth"], bd)
+    g = O.render_bwd(ocfg, w["gauss"], camd, bc, bd, gC, gD)
+    for k, v in w["gauss"].items():
+        a = v.astype(np.float64).reshape(-1).copy()
+        O.adam(a, g[k].reshape(-1), np.zeros_like(a), np.zeros_like(a), O.PAPER_LR[k], 1)
+    return time.perf_counter() - t
+
+
+def cpu_baseline(scene, cam, frame, gauss_np, cfg):
+    """The reference implementation, as it stands, on this host's cores: a bounded sample of
+    one frame of the room workload (see _oracle_frame) at the host's thread count and at
+    one thread, and the whole tiny workload unsampled at the host's thread count."""
+    import synth
+    from oracle import oracle as O
+
+    n = _host_threads()
+    O.set_threads(n)
+    full = _oracle_frame(O, scene, cam, frame, gauss_np, cfg)
+    tiny = _oracle_tiny(O, synth)
+    O.set_threads(1)
+    one = _oracle_frame(O, scene, cam, frame, gauss_np, cfg)
+    O.set_threads(n)
+    return {"value": round(ITERS_PER_FRAME / full["t_frame"], 5), "unit": "iters/s", "cores": n, "kind": "oracle",
+            "ms_per_frame": round(1e3 * full["t_frame"], 1), "ms_per_iteration": round(1e3 * full["t_iter"], 1),
+            "sample": f"FP64 C reference, {n} OpenMP threads: full-volume fusion ({full['t_fuse']:.2f} s), raycast of "
+                      f"{full['pix_r']} px scaled x{full['ray_scale']:.0f}, forward+backward of {full['pix_f']} px "
+                      f"({full['t_fwd_bwd']:.2f} s) scaled x{full['fb_scale']:.0f}, Adam over all parameters",
+            "one_thread": {"value": round(ITERS_PER_FRAME / one["t_frame"], 5), "ms_per_frame": round(1e3 * one["t_frame"], 1),
+                           "ms_per_iteration": round(1e3 * one["t_iter"], 1)},
+            "tiny_workload_unsampled": {"threads": n, "ms": round(1e3 * tiny, 1),
+                                        "steps": "64^3 fusion, raycast of 160x120, forward + backward of 2,000 "
+                                                 "Gaussians, Adam"},
+            "cpu": _cpu_model(), "host_threads": n}
 
 
 def _cpu_model():

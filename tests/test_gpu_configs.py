@@ -233,27 +233,36 @@ def test_large_map_iteration_512_1m(P, O):
         assert normwise(h(grads[k]), refs[k]) < 1e-3, k
     assert normwise(h(dpose), refs["pose"]) < 1e-3
     # Adam (first step) from the reference gradient on the reference side, elementwise where
-    # the update does not hinge on the gradient's last digits.  The first step moves a
-    # parameter by lr g / (|g| + eps): its sensitivity to g is lr eps / (|g| + eps)^2, so for
-    # |g| below ~1e3 eps (1e-12) a gradient inside its own tolerance moves the update by more
-    # than 1e-6 |p|; those elements (Gaussians seen through a transmittance near T_min at
-    # one sampled pixel) and sign flips of near-zero gradients are counted, not compared.
+    # the update does not hinge on the gradient's own error.  The first step moves a
+    # parameter by lr g / (|g| + eps), whose sensitivity to g is lr eps / (|g| + eps)^2: a
+    # gradient element off by up to its own size (tiny elements can be, under the normwise
+    # 1e-3 bound of the gradient) moves the update by up to lr eps / |g|.  Elements where
+    # that exceeds a tenth of the update's tolerance (gradients below ~1e-8; Gaussians seen
+    # through a transmittance near T_min at one sampled pixel) and sign flips of near-zero
+    # gradients are counted, not compared.
     f32 = lambda x: float(np.float32(x))
     eps = f32(1e-15)
     for k in KEYS:
         p = gauss[k].astype(np.float64).reshape(-1).copy()
         gr = refs[k].reshape(-1).astype(np.float64)
-        O.adam(p, gr, np.zeros_like(p), np.zeros_like(p), f32(O.PAPER_LR[k]), 1, b1=f32(0.9), b2=f32(0.999),
-               eps=eps)
+        lr = f32(O.PAPER_LR[k])
+        O.adam(p, gr, np.zeros_like(p), np.zeros_like(p), lr, 1, b1=f32(0.9), b2=f32(0.999), eps=eps)
         got = h(gd[k]).astype(np.float64).reshape(-1)
         p0 = gauss[k].astype(np.float64).reshape(-1)
-        same = np.sign(h(grads[k]).reshape(-1)) == np.sign(gr)
-        firm = same & (np.abs(gr) >= 1e3 * eps)
         # 1e-6 relative on both terms of p = p0 - step (the step carries its own roundings,
         # and p0 - step cancels where p0 ~ lr), plus one rounding of p0
-        assert (np.abs(got - p) <= 1e-6 * (np.abs(p) + np.abs(p0 - p)) + 2.0 ** -23 * np.abs(p0))[firm].all(), k
+        tol = 1e-6 * (np.abs(p) + np.abs(p0 - p)) + 2.0 ** -23 * np.abs(p0)
+        same = np.sign(h(grads[k]).reshape(-1)) == np.sign(gr)
+        with np.errstate(divide="ignore"):
+            firm = same & (lr * eps / np.abs(gr) <= 0.1 * tol)
+        bad = np.flatnonzero(firm & ~(np.abs(got - p) <= tol))
+        for b in bad[:8]:
+            say(f"  adam {k} element {b}: p0 {p0[b]!r} gpu {got[b]!r} ref {p[b]!r} "
+                f"g_ref {gr[b]!r} g_gpu {h(grads[k]).reshape(-1)[b]!r}")
+        assert bad.size == 0, (k, bad.size)
         nz = gr != 0
         assert (~same).sum() <= max(3, 1e-3 * nz.sum()), (k, (~same).sum(), nz.sum())
         soft = same & nz & ~firm
-        say(f"  adam {k}: {firm.sum()} compared, {soft.sum()} with 0 < |g| < 1e3 eps, {(~same).sum()} sign flips")
-        assert soft.sum() <= 1e-2 * nz.sum(), (k, soft.sum(), nz.sum())
+        say(f"  adam {k}: {firm.sum()} compared, {soft.sum()} with the update sensitive to the gradient's "
+            f"error, {(~same).sum()} sign flips")
+        assert soft.sum() <= 0.1 * nz.sum(), (k, soft.sum(), nz.sum())  # most elements are compared
