@@ -24,6 +24,11 @@
  *                    every Gaussian parameter and the 6-DoF pose
  *   orc_adam         Adam update with the per-attribute learning
  *                    rates of Appendix C
+ *   orc_alloc_blocks voxel blocks a frame allocates in the block
+ *                    hash of the SDF (Sec. 3.2.1, "SDF fusion":
+ *                    the SDF lives in a hash table of voxel blocks,
+ *                    following InfiniTAM); orc_fuse with a block
+ *                    mask is fusion into the allocated blocks only
  *
  * Precision.  Every value is computed in binary64.  Where floating point
  * decides an integer -- the nearest pixel a voxel projects to during fusion,
@@ -180,8 +185,11 @@ static size_t grid_index(const orc_grid* g, int x, int y, int z)
 /* and the separate colour weight are readings.                               */
 /* ========================================================================= */
 void orc_fuse(const orc_grid* g, double* tsdf, double* weight, double* rgb, double* rgb_weight,
-              const orc_cam* cam, const float* depth, const float* img)
+              const orc_cam* cam, const float* depth, const float* img, const uint8_t* block_mask,
+              int32_t block)
 {
+    const int nbx = block > 0 ? (g->nx + block - 1) / block : 0;
+    const int nby = block > 0 ? (g->ny + block - 1) / block : 0;
     const size_t N = (size_t)g->nx * g->ny * g->nz;
     const int W = cam->width, H = cam->height;
     const float mu32 = g->trunc;
@@ -193,6 +201,10 @@ void orc_fuse(const orc_grid* g, double* tsdf, double* weight, double* rgb, doub
     for (int z = 0; z < g->nz; ++z)
         for (int y = 0; y < g->ny; ++y)
             for (int x = 0; x < g->nx; ++x) {
+                /* with a block mask, only lattice points of allocated blocks exist */
+                if (block_mask &&
+                    !block_mask[(size_t)(x / block) + (size_t)nbx * ((size_t)(y / block) + (size_t)nby * (z / block))])
+                    continue;
                 /* decision: which pixel, and whether the voxel is updated (binary32) */
                 float p0 = d32_lattice(g->origin[0], g->voxel, x);
                 float p1 = d32_lattice(g->origin[1], g->voxel, y);
@@ -239,6 +251,74 @@ void orc_fuse(const orc_grid* g, double* tsdf, double* weight, double* rgb, doub
                     rgb_weight[idx] = (wc + 1.0 < wmax) ? wc + 1.0 : wmax;
                 }
             }
+}
+
+/* ========================================================================= */
+/* O1b -- voxel-block allocation (Sec. 3.2.1 "SDF fusion": the SDF and colour */
+/* live in a global hash table of voxel blocks, following InfiniTAM).         */
+/*                                                                            */
+/* The lattice is split into blocks of `block`^3 points (block b covers the   */
+/* points [block*b, block*b + block) per axis).  A frame allocates, for every */
+/* pixel (i, j) with depth d > 0, the blocks that contain the points of its   */
+/* ray at camera depths z_k = d + k * voxel, k = -K .. K, K = ceil(mu/voxel)  */
+/* (the truncation band around the measured surface, one sample per voxel     */
+/* length), for z_k > 0 and inside the lattice's blocks.  Fusion then updates */
+/* the allocated blocks only; every other lattice point keeps tsdf 1,         */
+/* weight 0 and colour 0, which is what the raycast reads there.              */
+/* Readings: the paper names the structure, not its constants -- the block    */
+/* edge (8) and the sample spacing are the InfiniTAM conventions, the band is */
+/* the truncation distance.  The block index of a sample is decided in       */
+/* binary32 with the order written below.                                     */
+/* mask: nbx*nby*nbz bytes (x fastest), set to 1 for every block allocated;   */
+/* existing entries are kept (allocation accumulates over frames).            */
+/* ========================================================================= */
+void orc_alloc_blocks(const orc_grid* g, const orc_cam* cam, const float* depth, int32_t block, uint8_t* mask)
+{
+    const int W = cam->width, H = cam->height;
+    const int nb[3] = {(g->nx + block - 1) / block, (g->ny + block - 1) / block, (g->nz + block - 1) / block};
+    const int K = (int)ceil((double)g->trunc / (double)g->voxel);
+    const float bsz = g->voxel * (float)block;
+    const float* R = cam->R;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int j = 0; j < H; ++j)
+        for (int i = 0; i < W; ++i) {
+            float d = depth[(size_t)j * W + i];
+            if (!(d > 0.0f)) continue;
+            float xn = (float)i - cam->cx;
+            xn = xn / cam->fx;
+            float yn = (float)j - cam->cy;
+            yn = yn / cam->fy;
+            for (int k = -K; k <= K; ++k) {
+                float dz = (float)k * g->voxel;
+                float z = d + dz;
+                if (!(z > 0.0f)) continue;
+                float xc = xn * z;
+                float yc = yn * z;
+                float q0 = xc - cam->t[0];
+                float q1 = yc - cam->t[1];
+                float q2 = z - cam->t[2];
+                int b[3], ok = 1;
+                for (int a = 0; a < 3; ++a) {
+                    float s = R[0 * 3 + a] * q0;
+                    float u = R[1 * 3 + a] * q1;
+                    s = s + u;
+                    float w = R[2 * 3 + a] * q2;
+                    s = s + w;
+                    float r = s - g->origin[a];
+                    r = r / bsz;
+                    float f = floorf(r);
+                    if (!(f >= 0.0f && f < (float)nb[a])) {
+                        ok = 0;
+                        break;
+                    }
+                    b[a] = (int)f;
+                }
+                if (!ok) continue;
+                size_t idx = (size_t)b[0] + (size_t)nb[0] * ((size_t)b[1] + (size_t)nb[1] * (size_t)b[2]);
+#pragma omp atomic write
+                mask[idx] = 1;
+            }
+        }
 }
 
 /* ========================================================================= */

@@ -71,7 +71,9 @@ def lib():
             build(force=True)
         L = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
-        L.orc_fuse.argtypes = [P, P, P, P, P, P, P, P]
+        L.orc_fuse.argtypes = [P, P, P, P, P, P, P, P, P, ctypes.c_int32]
+        L.orc_alloc_blocks.argtypes = [P, P, P, ctypes.c_int32, P]
+        L.orc_alloc_blocks.restype = None
         L.orc_fuse.restype = None
         L.orc_raycast.argtypes = [P, P, P, P, ctypes.c_float, ctypes.c_float, ctypes.c_int32, P, P, P, P]
         L.orc_raycast.restype = None
@@ -186,17 +188,42 @@ def new_volume(grid: Grid):
     return {"tsdf": np.ones(N), "weight": np.zeros(N), "rgb": np.zeros((3, N)), "rgb_weight": np.zeros(N)}
 
 
-def fuse(grid: Grid, vol: dict, cam, depth, rgb):
-    """In-place FP64 fusion of one frame into ``vol`` (dict of float64 arrays)."""
+def fuse(grid: Grid, vol: dict, cam, depth, rgb, block_mask=None, block=8):
+    """In-place FP64 fusion of one frame into ``vol`` (dict of float64 arrays).  With
+    ``block_mask`` (uint8 [nbz][nby][nbx], blocks of ``block``^3 lattice points) only the
+    points of allocated blocks are updated: fusion into a voxel-block hash."""
     cam = cam_from(cam)
     depth = _f32(depth)
     rgb = _f32(rgb)
     assert depth.shape == (cam.height, cam.width) and rgb.shape == (3, cam.height, cam.width)
     for k in ("tsdf", "weight", "rgb", "rgb_weight"):
         assert vol[k].dtype == np.float64 and vol[k].flags.c_contiguous
+    if block_mask is not None:
+        assert block_mask.dtype == np.uint8 and block_mask.size == np.prod(block_grid(grid, block))
+        block_mask = np.ascontiguousarray(block_mask)
     lib().orc_fuse(ctypes.byref(grid), _ptr(vol["tsdf"]), _ptr(vol["weight"]), _ptr(vol["rgb"]),
-                   _ptr(vol["rgb_weight"]), ctypes.byref(cam), _ptr(depth), _ptr(rgb))
+                   _ptr(vol["rgb_weight"]), ctypes.byref(cam), _ptr(depth), _ptr(rgb), _ptr(block_mask),
+                   int(block))
     return vol
+
+
+def block_grid(grid: Grid, block=8):
+    """Blocks per axis (x, y, z) of the lattice split into ``block``^3 blocks."""
+    return tuple((n + block - 1) // block for n in (grid.nx, grid.ny, grid.nz))
+
+
+def alloc_blocks(grid: Grid, cam, depth, mask=None, block=8):
+    """Voxel blocks a frame allocates (orc_alloc_blocks): uint8 mask [nbz][nby][nbx], updated
+    in place when given (allocation accumulates over frames)."""
+    cam = cam_from(cam)
+    depth = _f32(depth)
+    assert depth.shape == (cam.height, cam.width)
+    nbx, nby, nbz = block_grid(grid, block)
+    if mask is None:
+        mask = np.zeros((nbz, nby, nbx), np.uint8)
+    assert mask.dtype == np.uint8 and mask.shape == (nbz, nby, nbx) and mask.flags.c_contiguous
+    lib().orc_alloc_blocks(ctypes.byref(grid), ctypes.byref(cam), _ptr(depth), int(block), _ptr(mask))
+    return mask
 
 
 def raycast(grid: Grid, tsdf32, rgb32, cam, z_near=0.2, step=0.0, pix=None):
