@@ -91,7 +91,9 @@ typedef struct {
     const float* log_scale;  /* [3][M] */
     const float* quat;       /* [4][M]  (w, x, y, z), not necessarily unit */
     const float* opacity_logit; /* [M] */
-    const float* rgb;        /* [3][M] */
+    const float* rgb;        /* [3][M]  degree-0 colour */
+    int32_t sh_degree;       /* 0..3: view-dependent bands 1..sh_degree */
+    const float* sh;         /* [3][K][M], K = (sh_degree+1)^2 - 1; NULL when sh_degree = 0 */
 } orc_gauss;
 
 typedef struct {
@@ -116,6 +118,9 @@ typedef struct {
     double depth;     /* d_i = camera z of the centre              */
     float depth32;    /* the same depth in binary32, the sort key  */
     double box[4];    /* support bounding box: xmin, xmax, ymin, ymax */
+    double col[3];    /* colour seen from this camera (degree 0 plus the SH bands) */
+    double dir[3];    /* unit direction from the camera centre to the centre       */
+    double dist;      /* distance from the camera centre to the centre             */
     /* intermediates reused by the adjoint */
     double qn[4], qnorm, s[3], Rq[9], S3[9], J[6], W[6];
 } orc_proj;
@@ -564,6 +569,64 @@ static void quat_to_rot(const double q[4], double Rm[9])
     Rm[8] = 1.0 - 2.0 * (x * x + y * y);
 }
 
+/* ------------------------------------------------------------------------- */
+/* View-dependent colour (Sec. 3.1: SH coefficients per Gaussian, following   */
+/* 3DGS).  c(d) = rgb + sum_{l=1..L} sum_m sh_{l,m} Y_{l,m}(d) for the unit   */
+/* direction d from the camera centre to the Gaussian, with the real          */
+/* spherical harmonics in the basis and order 3DGS uses (the degree-0 term is */
+/* stored directly as the colour, so its constant and offset are absorbed;    */
+/* the colour is not clamped).  Y[k] for k = 0 .. K-1 (bands 1..L in order)   */
+/* and, when dY is given, dY[3k + a] = dY_k / dd_a with d's components taken  */
+/* as independent (the normalisation is applied by the caller).               */
+/* ------------------------------------------------------------------------- */
+static void sh_basis(int L, const double d[3], double* Y, double* dY)
+{
+    const double x = d[0], y = d[1], z = d[2];
+    const double c1 = 0.4886025119029199;
+    const double c2[5] = {1.0925484305920792, -1.0925484305920792, 0.31539156525252005, -1.0925484305920792,
+                          0.5462742152960396};
+    const double c3[7] = {-0.5900435899266435, 2.890611442640554, -0.4570457994644658, 0.3731763325901154,
+                          -0.4570457994644658, 1.445305721320277, -0.5900435899266435};
+    double v[15], g[45];
+    memset(g, 0, sizeof(g));
+    /* band 1 */
+    v[0] = -c1 * y;  g[0 * 3 + 1] = -c1;
+    v[1] = c1 * z;   g[1 * 3 + 2] = c1;
+    v[2] = -c1 * x;  g[2 * 3 + 0] = -c1;
+    /* band 2 */
+    v[3] = c2[0] * x * y;                    g[3 * 3 + 0] = c2[0] * y; g[3 * 3 + 1] = c2[0] * x;
+    v[4] = c2[1] * y * z;                    g[4 * 3 + 1] = c2[1] * z; g[4 * 3 + 2] = c2[1] * y;
+    v[5] = c2[2] * (2 * z * z - x * x - y * y);
+    g[5 * 3 + 0] = -2 * c2[2] * x; g[5 * 3 + 1] = -2 * c2[2] * y; g[5 * 3 + 2] = 4 * c2[2] * z;
+    v[6] = c2[3] * x * z;                    g[6 * 3 + 0] = c2[3] * z; g[6 * 3 + 2] = c2[3] * x;
+    v[7] = c2[4] * (x * x - y * y);          g[7 * 3 + 0] = 2 * c2[4] * x; g[7 * 3 + 1] = -2 * c2[4] * y;
+    /* band 3 */
+    v[8] = c3[0] * y * (3 * x * x - y * y);
+    g[8 * 3 + 0] = 6 * c3[0] * x * y; g[8 * 3 + 1] = c3[0] * (3 * x * x - 3 * y * y);
+    v[9] = c3[1] * x * y * z;
+    g[9 * 3 + 0] = c3[1] * y * z; g[9 * 3 + 1] = c3[1] * x * z; g[9 * 3 + 2] = c3[1] * x * y;
+    v[10] = c3[2] * y * (4 * z * z - x * x - y * y);
+    g[10 * 3 + 0] = -2 * c3[2] * x * y; g[10 * 3 + 1] = c3[2] * (4 * z * z - x * x - 3 * y * y);
+    g[10 * 3 + 2] = 8 * c3[2] * y * z;
+    v[11] = c3[3] * z * (2 * z * z - 3 * x * x - 3 * y * y);
+    g[11 * 3 + 0] = -6 * c3[3] * x * z; g[11 * 3 + 1] = -6 * c3[3] * y * z;
+    g[11 * 3 + 2] = c3[3] * (6 * z * z - 3 * x * x - 3 * y * y);
+    v[12] = c3[4] * x * (4 * z * z - x * x - y * y);
+    g[12 * 3 + 0] = c3[4] * (4 * z * z - 3 * x * x - y * y); g[12 * 3 + 1] = -2 * c3[4] * x * y;
+    g[12 * 3 + 2] = 8 * c3[4] * x * z;
+    v[13] = c3[5] * z * (x * x - y * y);
+    g[13 * 3 + 0] = 2 * c3[5] * x * z; g[13 * 3 + 1] = -2 * c3[5] * y * z; g[13 * 3 + 2] = c3[5] * (x * x - y * y);
+    v[14] = c3[6] * x * (x * x - 3 * y * y);
+    g[14 * 3 + 0] = c3[6] * (3 * x * x - 3 * y * y); g[14 * 3 + 1] = -6 * c3[6] * x * y;
+    const int K = (L + 1) * (L + 1) - 1;
+    for (int k = 0; k < K; ++k) Y[k] = v[k];
+    if (dY)
+        for (int k = 0; k < 3 * K; ++k) dY[k] = g[k];
+}
+
+/* Exposed for the library pin (scipy's spherical harmonics). */
+void orc_sh_basis(int32_t L, const double* d, double* Y, double* dY) { sh_basis(L, d, Y, dY); }
+
 static void project_one(const orc_cfg* cfg, const orc_gauss* G, const orc_cam* cam, int i, orc_proj* P)
 {
     const int M = G->count;
@@ -577,6 +640,26 @@ static void project_one(const orc_cfg* cfg, const orc_gauss* G, const orc_cam* c
     double mu[3] = {mu0, mu1, mu2};
     cam_apply64(cam, mu, P->pc);
     double x = P->pc[0], y = P->pc[1], z = P->pc[2];
+    /* colour from this camera: d = (mu - o) / |mu - o|, camera centre o = -R^T t */
+    {
+        double v[3], r2 = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            const double o = -((double)cam->R[0 * 3 + a] * cam->t[0] + (double)cam->R[1 * 3 + a] * cam->t[1] +
+                               (double)cam->R[2 * 3 + a] * cam->t[2]);
+            v[a] = mu[a] - o;
+            r2 += v[a] * v[a];
+        }
+        P->dist = sqrt(r2);
+        for (int a = 0; a < 3; ++a) P->dir[a] = v[a] / P->dist;
+        for (int c = 0; c < 3; ++c) P->col[c] = (double)G->rgb[c * M + i];
+        if (G->sh_degree > 0) {
+            const int K = (G->sh_degree + 1) * (G->sh_degree + 1) - 1;
+            double Y[15];
+            sh_basis(G->sh_degree, P->dir, Y, NULL);
+            for (int c = 0; c < 3; ++c)
+                for (int k = 0; k < K; ++k) P->col[c] += (double)G->sh[((size_t)c * K + k) * M + i] * Y[k];
+        }
+    }
     double q[4] = {G->quat[i], G->quat[M + i], G->quat[2 * M + i], G->quat[3 * M + i]};
     double qn = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
     P->qnorm = qn;
@@ -765,7 +848,7 @@ static void composite_pixel(const orc_cfg* cfg, const orc_proj* P, const orc_gau
             if (Tn < (double)cfg->T_min) break;
             double w = a * T;
             int g = cand[k].g;
-            for (int c = 0; c < 3; ++c) AC[c] += w * (double)G->rgb[c * M + g];
+            for (int c = 0; c < 3; ++c) AC[c] += w * P[g].col[c];
             AD += w * P[g].depth;
             T = Tn;
             order += (uint64_t)(used + 1) * (uint64_t)(g + 1) * 0x9E3779B97F4A7C15ull;
@@ -783,7 +866,7 @@ static void composite_pixel(const orc_cfg* cfg, const orc_proj* P, const orc_gau
             double a = cand[k].alpha;
             int g = cand[k].g;
             Wg += a;
-            for (int c = 0; c < 3; ++c) CG[c] += a * (double)G->rgb[c * M + g];
+            for (int c = 0; c < 3; ++c) CG[c] += a * P[g].col[c];
             ZG += a * P[g].depth;
         }
         for (int c = 0; c < 3; ++c) out->C[c] = (Ct[c] + CG[c]) / (1.0 + Wg);
@@ -913,7 +996,7 @@ static void pixel_adjoint(const orc_cfg* cfg, const orc_proj* P, const orc_gauss
             int g = cd->g;
             const orc_proj* p = &P[g];
             double a = cd->alpha, w = a * T;
-            double c[3] = {G->rgb[g], G->rgb[M + g], G->rgb[2 * M + g]};
+            double c[3] = {p->col[0], p->col[1], p->col[2]};
             double d = p->depth;
             for (int ch = 0; ch < 3; ++ch) PC[ch] += w * c[ch];
             PD += w * d;
@@ -945,7 +1028,7 @@ static void pixel_adjoint(const orc_cfg* cfg, const orc_proj* P, const orc_gauss
             int g = cd->g;
             const orc_proj* p = &P[g];
             double a = cd->alpha;
-            double c[3] = {G->rgb[g], G->rgb[M + g], G->rgb[2 * M + g]};
+            double c[3] = {p->col[0], p->col[1], p->col[2]};
             double d = p->depth;
             double* A = acc + (size_t)g * A_N;
             A[A_R] += a * inv * gC[0];
@@ -967,9 +1050,9 @@ static void pixel_adjoint(const orc_cfg* cfg, const orc_proj* P, const orc_gauss
 }
 
 /* EWA chain rule for one Gaussian: screen-space adjoints -> parameters + pose. */
-static void projection_adjoint(const orc_proj* p, const orc_cam* cam, const double* A, int M, int i,
-                               double* g_mean, double* g_log_scale, double* g_quat, double* g_opacity,
-                               double* g_rgb, double* g_pose)
+static void projection_adjoint(const orc_proj* p, const orc_cam* cam, const orc_gauss* G, const double* A, int M,
+                               int i, double* g_mean, double* g_log_scale, double* g_quat, double* g_opacity,
+                               double* g_rgb, double* g_sh, double* g_pose)
 {
     const double x = p->pc[0], y = p->pc[1], z = p->pc[2];
     const double fx = cam->fx, fy = cam->fy;
@@ -979,6 +1062,27 @@ static void projection_adjoint(const orc_proj* p, const orc_cam* cam, const doub
     g_rgb[i] += A[A_R];
     g_rgb[M + i] += A[A_G];
     g_rgb[2 * M + i] += A[A_B];
+    /* SH bands: the coefficients, then the view direction d = (mu - o) / |mu - o|.
+       Its adjoint moves the centre by (I - d d^T) / |mu - o| times it; the camera
+       centre moves by -R^T rho under the left perturbation (not with phi), so rho
+       takes R times the same vector. */
+    if (G->sh_degree > 0) {
+        const int K = (G->sh_degree + 1) * (G->sh_degree + 1) - 1;
+        double Y[15], dY[45], gd[3] = {0, 0, 0};
+        sh_basis(G->sh_degree, p->dir, Y, dY);
+        for (int c = 0; c < 3; ++c)
+            for (int k = 0; k < K; ++k) {
+                const double coef = (double)G->sh[((size_t)c * K + k) * M + i];
+                if (g_sh) g_sh[((size_t)c * K + k) * M + i] += A[A_R + c] * Y[k];
+                for (int a = 0; a < 3; ++a) gd[a] += A[A_R + c] * coef * dY[3 * k + a];
+            }
+        const double dd = p->dir[0] * gd[0] + p->dir[1] * gd[1] + p->dir[2] * gd[2];
+        double u[3];
+        for (int a = 0; a < 3; ++a) u[a] = (gd[a] - p->dir[a] * dd) / p->dist;
+        for (int a = 0; a < 3; ++a) g_mean[a * M + i] += u[a];
+        if (g_pose)
+            for (int r = 0; r < 3; ++r) g_pose[r] += R[3 * r + 0] * u[0] + R[3 * r + 1] * u[1] + R[3 * r + 2] * u[2];
+    }
     g_opacity[i] += A[A_SIG] * p->sigma * (1.0 - p->sigma);
 
     /* conic -> Sigma_2D:  G2 = -Q Gq Q, Gq the symmetric full-matrix adjoint */
@@ -1101,7 +1205,7 @@ static void projection_adjoint(const orc_proj* p, const orc_cam* cam, const doub
 void orc_render_bwd(const orc_cfg* cfg, const orc_gauss* G, const orc_cam* cam, const float* base_rgb,
                     const float* base_depth, int32_t npix, const int32_t* pix, const double* g_pix_rgb,
                     const double* g_pix_depth, double* g_mean, double* g_log_scale, double* g_quat,
-                    double* g_opacity, double* g_rgb, double* g_pose, double* g_screen)
+                    double* g_opacity, double* g_rgb, double* g_sh, double* g_pose, double* g_screen)
 {
     const int W = cam->width, H = cam->height;
     const size_t HW = (size_t)W * H;
@@ -1156,7 +1260,7 @@ void orc_render_bwd(const orc_cfg* cfg, const orc_gauss* G, const orc_cam* cam, 
         const double* A = acc + (size_t)i * A_N;
         if (g_screen)
             for (int a = 0; a < A_N; ++a) g_screen[(size_t)i * A_N + a] += A[a];
-        projection_adjoint(&P[i], cam, A, M, i, g_mean, g_log_scale, g_quat, g_opacity, g_rgb, g_pose);
+        projection_adjoint(&P[i], cam, G, A, M, i, g_mean, g_log_scale, g_quat, g_opacity, g_rgb, g_sh, g_pose);
     }
     free(acc);
     free(P);

@@ -51,7 +51,7 @@ class Gauss(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32),
                 ("mean", ctypes.c_void_p), ("log_scale", ctypes.c_void_p),
                 ("quat", ctypes.c_void_p), ("opacity_logit", ctypes.c_void_p),
-                ("rgb", ctypes.c_void_p)]
+                ("rgb", ctypes.c_void_p), ("sh_degree", ctypes.c_int32), ("sh", ctypes.c_void_p)]
 
 
 class Cfg(ctypes.Structure):
@@ -85,7 +85,9 @@ def lib():
         L.orc_render.restype = None
         L.orc_loss.argtypes = [P, ctypes.c_int32, ctypes.c_int32, P, P, P, P, P, ctypes.c_double, P, P, P]
         L.orc_loss.restype = ctypes.c_double
-        L.orc_render_bwd.argtypes = [P, P, P, P, P, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P]
+        L.orc_render_bwd.argtypes = [P, P, P, P, P, ctypes.c_int32, P, P, P, P, P, P, P, P, P, P, P]
+        L.orc_sh_basis.argtypes = [ctypes.c_int32, P, P, P]
+        L.orc_sh_basis.restype = None
         L.orc_render_bwd.restype = None
         L.orc_adam.argtypes = [ctypes.c_int64, P, P, P, P, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, ctypes.c_double, ctypes.c_int32]
@@ -166,18 +168,42 @@ def make_grid(dims, origin, voxel, trunc, max_weight=100.0) -> Grid:
 class _GaussKeep:
     """Keeps the float32 copies alive for as long as the ctypes struct is used."""
 
-    def __init__(self, mean, log_scale, quat, opacity_logit, rgb):
+    def __init__(self, mean, log_scale, quat, opacity_logit, rgb, sh=None):
         self.arrs = [_f32(mean), _f32(log_scale), _f32(quat), _f32(opacity_logit).reshape(-1), _f32(rgb)]
         M = self.arrs[3].shape[0]
         assert self.arrs[0].shape == (3, M) and self.arrs[1].shape == (3, M)
         assert self.arrs[2].shape == (4, M) and self.arrs[4].shape == (3, M)
-        self.s = Gauss(M, *[_ptr(a) for a in self.arrs])
+        self.L = 0
+        self.sh = None
+        if sh is not None:
+            self.sh = _f32(sh)
+            K = self.sh.shape[1]
+            self.L = SH_DEGREE_OF[K]
+            assert self.sh.shape == (3, K, M)
+        self.s = Gauss(M, *[_ptr(a) for a in self.arrs], self.L, _ptr(self.sh))
         self.M = M
 
 
+# coefficients per channel of the view-dependent bands for each SH degree, and back
+SH_COEFFS = {0: 0, 1: 3, 2: 8, 3: 15}
+SH_DEGREE_OF = {v: k for k, v in SH_COEFFS.items()}
+
+
 def gauss(g) -> _GaussKeep:
-    """g: dict with mean [3,M], log_scale [3,M], quat [4,M], opacity_logit [M], rgb [3,M]."""
-    return _GaussKeep(g["mean"], g["log_scale"], g["quat"], g["opacity_logit"], g["rgb"])
+    """g: dict with mean [3,M], log_scale [3,M], quat [4,M], opacity_logit [M], rgb [3,M] and
+    optionally sh [3,K,M] (K = 3, 8 or 15: the bands 1..L of degree L = 1, 2, 3)."""
+    return _GaussKeep(g["mean"], g["log_scale"], g["quat"], g["opacity_logit"], g["rgb"], g.get("sh"))
+
+
+def sh_basis(L: int, d):
+    """The real SH of bands 1..L at unit direction d (Y [K]) and their partial
+    derivatives with respect to d's components taken as independent (dY [K,3])."""
+    K = SH_COEFFS[L]
+    d = np.ascontiguousarray(d, np.float64)
+    Y = np.zeros(max(K, 1))
+    dY = np.zeros((max(K, 1), 3))
+    lib().orc_sh_basis(int(L), _ptr(d), _ptr(Y), _ptr(dY))
+    return Y[:K], dY[:K]
 
 
 # --------------------------------------------------------------------------- #
@@ -321,12 +347,14 @@ def render_bwd(cfg: RenderCfg, g, cam, base_rgb, base_depth, g_pix_rgb, g_pix_de
     gpd = _f64(g_pix_depth).reshape(npix)
     out = {"mean": np.zeros((3, M)), "log_scale": np.zeros((3, M)), "quat": np.zeros((4, M)),
            "opacity_logit": np.zeros(M), "rgb": np.zeros((3, M)), "pose": np.zeros(6)}
+    if G.L > 0:
+        out["sh"] = np.zeros((3, SH_COEFFS[G.L], M))
     scr = np.zeros((M, 10)) if want_screen else None
     c = cfg.c()
     lib().orc_render_bwd(ctypes.byref(c), ctypes.byref(G.s), ctypes.byref(cam), _ptr(base_rgb),
                          _ptr(base_depth), npix, _ptr(pixp), _ptr(gpr), _ptr(gpd), _ptr(out["mean"]),
                          _ptr(out["log_scale"]), _ptr(out["quat"]), _ptr(out["opacity_logit"]),
-                         _ptr(out["rgb"]), _ptr(out["pose"]), _ptr(scr))
+                         _ptr(out["rgb"]), _ptr(out.get("sh")), _ptr(out["pose"]), _ptr(scr))
     if want_screen:
         out["screen"] = scr
     return out
@@ -341,7 +369,7 @@ def adam(param, grad, m, v, lr, t, b1=0.9, b2=0.999, eps=1e-15):
 
 # Learning rates per attribute, Appendix C (position, SH0 -> rgb, alpha -> opacity
 # logit, scale -> log-scale, rotation -> quaternion).
-PAPER_LR = {"mean": 1.6e-4, "rgb": 2.5e-3, "opacity_logit": 0.05, "log_scale": 5e-3, "quat": 1e-3}
+PAPER_LR = {"mean": 1.6e-4, "rgb": 2.5e-3, "opacity_logit": 0.05, "log_scale": 5e-3, "quat": 1e-3, "sh": 5e-4}
 
 
 # --------------------------------------------------------------------------- #

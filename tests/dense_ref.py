@@ -45,6 +45,37 @@ def quat_rot(q):
     ], -2)  # [M,3,3]
 
 
+def sh_real(L, d):
+    """Real spherical harmonics of bands 1..L at the unit directions d [3,M] (torch), built
+    from the associated Legendre functions: Y_l^m = N_lm P_l^|m|(z) times the real or
+    imaginary part of (x + i y)^|m| (which is sin^|m| theta e^{i |m| phi}), with the
+    Condon-Shortley phase, sqrt(2) for m != 0, sine terms for m < 0, and m = -l .. l within
+    each band.  Returns [K,M]."""
+    import math
+    from numpy.polynomial import legendre as leg
+    from numpy.polynomial import polynomial as poly
+    x, y, z = d
+    out = []
+    for l in range(1, L + 1):
+        for m in range(-l, l + 1):
+            a = abs(m)
+            # d^a/dz^a P_l(z) in the power basis
+            c = leg.leg2poly(leg.legder([0] * l + [1], a))
+            q = sum(float(ck) * z ** k for k, ck in enumerate(c))
+            re, im = torch.ones_like(x), torch.zeros_like(x)
+            for _ in range(a):  # (x + i y)^a
+                re, im = re * x - im * y, re * y + im * x
+            N = math.sqrt((2 * l + 1) / (4 * math.pi) * math.factorial(l - a) / math.factorial(l + a))
+            cs = (-1) ** a
+            if m < 0:
+                out.append(math.sqrt(2) * N * cs * q * im)
+            elif m == 0:
+                out.append(N * q)
+            else:
+                out.append(math.sqrt(2) * N * cs * q * re)
+    return torch.stack(out)
+
+
 def render(params, cam, base_rgb, base_depth, cfg, xi=None):
     """params: dict of float64 tensors (mean [3,M], log_scale [3,M], quat [4,M], opacity_logit [M],
     rgb [3,M]) holding float32-representable values; cam: dict; base_rgb [3,H,W], base_depth [H,W]
@@ -102,6 +133,15 @@ def render(params, cam, base_rgb, base_depth, cfg, xi=None):
     Ct = torch.as_tensor(np.asarray(base_rgb, np.float32).reshape(3, -1).astype(np.float64))  # [3,P]
     Dt = torch.as_tensor(bd.astype(np.float64))
     rgb = params["rgb"]  # [3,M]
+    if params.get("sh") is not None:
+        # view-dependent bands (3DGS): the unit direction from the perturbed camera's centre
+        # o = -Rp^T tp (tp its translation, to first order in xi) to the centre
+        tp = (torch.eye(3, dtype=torch.float64) + hat(phi)) @ t + rho
+        v = mu + (Rp.T @ tp)[:, None]
+        dirs = v / v.norm(dim=0, keepdim=True)
+        K = params["sh"].shape[1]
+        L = {3: 1, 8: 2, 15: 3}[K]
+        rgb = rgb + (params["sh"] * sh_real(L, dirs)[None]).sum(dim=1)
 
     if cfg.mode == 0:
         alpha = torch.where(raw > cfg.alpha_max, torch.full_like(raw, cfg.alpha_max), raw)
@@ -130,6 +170,7 @@ def render(params, cam, base_rgb, base_depth, cfg, xi=None):
 
 def to_params(g, requires_grad=False):
     out = {}
-    for k in ("mean", "log_scale", "quat", "opacity_logit", "rgb"):
-        out[k] = torch.tensor(np.asarray(g[k], np.float32).astype(np.float64), requires_grad=requires_grad)
+    for k in ("mean", "log_scale", "quat", "opacity_logit", "rgb", "sh"):
+        if k in g:
+            out[k] = torch.tensor(np.asarray(g[k], np.float32).astype(np.float64), requires_grad=requires_grad)
     return out

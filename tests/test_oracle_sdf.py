@@ -189,5 +189,5 @@ def test_paper_learning_rates(oracle):
     gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_constants.json")))
     lr = gold["learning_rates"]["values"]
     assert oracle.PAPER_LR == {"mean": lr["position"], "rgb": lr["SH0"], "opacity_logit": lr["alpha"],
-                               "log_scale": lr["scale"], "quat": lr["rotation"]}
+                               "log_scale": lr["scale"], "quat": lr["rotation"], "sh": lr["SH_rest"]}
     assert oracle.RenderCfg().alpha_min == gold["alpha_threshold"]["value"]
