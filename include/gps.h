@@ -43,7 +43,7 @@
 extern "C" {
 #endif
 
-#define GPS_ABI_VERSION 3
+#define GPS_ABI_VERSION 4
 
 /* Size in floats of gps_volume.brick_min for an nx x ny x nz lattice. */
 #define GPS_BRICKS_(n) (((n) + 7) / 8)
@@ -88,15 +88,24 @@ typedef struct gps_volume {
                           NULL disables */
 } gps_volume;
 
-/* The Gaussian set G = {p_i, sigma_i, r_i, s_i, SH_i} (Sec. 3.1), with
- * degree-0 colour stored as linear RGB.  The same struct carries gradients. */
+/* The Gaussian set G = {p_i, sigma_i, r_i, s_i, SH_i} (Sec. 3.1; SH following
+ * 3DGS).  The colour seen from a camera whose centre is o is
+ *   c_i(d) = rgb_i + sum_{l=1..L} sum_{m=-l..l} sh_i[l,m] Y_lm(d),
+ *   d = (p_i - o) / |p_i - o|,
+ * with the real spherical harmonics of 3DGS (Condon-Shortley phase, sine terms
+ * for m < 0); the degree-0 coefficient is stored directly as the linear colour
+ * rgb_i (its constant and offset absorbed) and the colour is not clamped.  The
+ * same struct carries gradients and Adam moments. */
 typedef struct gps_gaussians {
     int32_t count;        /* M                                              */
     float* mean;          /* [3][M] centre p_i (world, m)                   */
     float* log_scale;     /* [3][M] log of the axis scales s_i              */
     float* quat;          /* [4][M] rotation r_i as (w, x, y, z), any norm  */
     float* opacity_logit; /* [M]    sigma_i = 1/(1+exp(-logit))             */
-    float* rgb;           /* [3][M] colour c_i                              */
+    float* rgb;           /* [3][M] degree-0 colour rgb_i                   */
+    int32_t sh_degree;    /* L in 0..3 (0: view-independent colour)         */
+    float* sh;            /* [3][K][M], K = (L+1)^2 - 1 coefficients per
+                             channel (bands 1..L, m = -l..l); NULL when L = 0 */
 } gps_gaussians;
 
 /* One view of a render call. */
@@ -223,6 +232,66 @@ gps_status gps_fuse(const gps_volume* vol, const gps_camera* cam, const float* d
 gps_status gps_raycast(const gps_volume* vol, const gps_camera* cams, int32_t n_views, float* const* out_depth,
                        float* const* out_rgb, float z_near, float step, void* stream);
 
+/* ---- Voxel-block hash of the colourised TSDF (Sec. 3.2.1, "SDF fusion": the SDF
+ * and colour live in a global hash table of voxel blocks, following InfiniTAM).
+ * The lattice of a region (points origin + voxel * (x, y, z), 0 <= x < nx, ...) is
+ * split into blocks of 8^3 points; only allocated blocks hold values, in planar
+ * pools (24 B per point; point (lx, ly, lz) of pool block b at b*512 + lx + 8 (ly +
+ * 8 lz)); every other point reads tsdf 1, weight 0, colour 0.  Memory grows with
+ * the allocated blocks, not with nx*ny*nz.  Block (bx, by, bz) has the key
+ * bx | by << 21 | bz << 42 (at most 2^21 blocks per axis); the table is open-
+ * addressing with linear probing.  All arrays are caller-owned device memory. */
+#define GPS_HASH_BLOCK 8
+#define GPS_HASH_EMPTY 0xffffffffffffffffull
+typedef struct gps_hash_volume {
+    int32_t nx, ny, nz;     /* region, lattice points per axis (the raycast's box)    */
+    float origin[3];
+    float voxel, trunc, max_weight;
+    int32_t n_buckets;      /* power of two; at least twice the capacity is advised   */
+    int32_t capacity;       /* pool blocks                                            */
+    uint64_t* keys;         /* [n_buckets] block keys, GPS_HASH_EMPTY = free          */
+    int32_t* slots;         /* [n_buckets] pool block of each key (-1: no room)       */
+    uint64_t* block_key;    /* [capacity] key of each pool block, allocation order    */
+    int32_t* state;         /* [4]: blocks allocated (may exceed capacity after an
+                               overflow), allocated before the last fusion, blocks
+                               visible in the last fusion, status bits (1: the pool
+                               overflowed, 2: the table filled up)                     */
+    int32_t* visible;       /* [capacity] scratch: pool blocks seen by the last fusion */
+    float* block_min;       /* [capacity] scratch for the raycast's skipping of
+                               positive blocks, or NULL                                */
+    float* tsdf;            /* [capacity * 512]                                       */
+    float* weight;          /* [capacity * 512]                                       */
+    float* rgb;             /* [3][capacity * 512]                                    */
+    float* rgb_weight;      /* [capacity * 512]                                       */
+} gps_hash_volume;
+
+/* Empties the table and the counters (fills keys with GPS_HASH_EMPTY; pools are
+ * initialised block by block as blocks are allocated).  Two kernels. */
+gps_status gps_hash_reset(const gps_hash_volume* vol, void* stream);
+
+/* Fuses one RGB-D frame: (1) allocation -- for every pixel with depth d > 0 the
+ * blocks holding its ray's points at camera depths d + k voxel, |k| <=
+ * ceil(trunc / voxel), inside the region, decided in binary32 (the block
+ * coordinate of a point is floor(((R^T (x - t))_a - origin_a) / (8 voxel)) with
+ * the camera-frame point x = (z (i - cx) / fx, z (j - cy) / fy, z)); new blocks
+ * start at tsdf 1, weights 0, colour 0; (2) the visible list -- allocated blocks
+ * whose lattice box projects into the image (conservative); (3) the update of
+ * gps_fuse applied to every point of the visible blocks.  The result equals
+ * gps_fuse on a dense lattice whose points outside the allocated blocks are left
+ * alone.  A full pool or table sets a status bit in state[3] (sticky until
+ * gps_hash_reset); blocks without room are then read as unallocated.
+ * depth [H][W], rgb [3][H][W].  Five kernels, nothing read back. */
+gps_status gps_hash_fuse(const gps_hash_volume* vol, const gps_camera* cam, const float* depth, const float* rgb,
+                         void* stream);
+
+/* The raycast of gps_raycast over the hashed volume (same march, decisions and
+ * values; the march runs inside the region's box): samples whose 2x2x2 stencil
+ * lies in one block that is unallocated, or whose points are all positive
+ * (vol->block_min), are skipped, which does not change the crossing found.
+ * cams, out_depth, out_rgb as in gps_raycast.  Two kernels. */
+gps_status gps_hash_raycast(const gps_hash_volume* vol, const gps_camera* cams, int32_t n_views,
+                            float* const* out_depth, float* const* out_rgb, float z_near, float step, void* stream);
+
 /* Forward render of n_views (<= GPS_MAX_VIEWS) views (views: host array) and,
  * when every view has target_rgb, the loss
  *   L = (1/V) sum_v [ mean_{pixels,channels} |C* - C_k| (Eq. 7)
@@ -291,13 +360,14 @@ gps_status gps_adam_step(const gps_adam_group* groups, int32_t n_groups, int32_t
 
 /* ---- Backward with the Adam step in its epilogue (one optimisation iteration's
  * backward + Adam without the separate Adam launch).  The same as gps_render_bwd
- * followed by gps_adam_step over the five attribute groups with the learning
+ * followed by gps_adam_step over the attribute groups (five, six with SH) with the learning
  * rates below, and bitwise the same parameters, moments and counter; `g` is
  * updated in place after its gradient is formed.  grads may be NULL (the
  * gradients are then not stored). */
 typedef struct gps_adam_fused {
     gps_gaussians m, v;   /* first and second moments (device), same layout and count as g */
     float lr_mean, lr_log_scale, lr_quat, lr_opacity, lr_rgb;
+    float lr_sh;          /* the SH bands above 0 (0.0005 in Appendix C)    */
     float beta1, beta2, eps;
     int32_t step;         /* 1-based step, used when step_counter is NULL */
     int32_t* step_counter;/* device int32 or NULL: t = *step_counter + 1, incremented afterwards */

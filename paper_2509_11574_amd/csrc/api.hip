@@ -122,6 +122,14 @@ static gps_status compute_layout(const gps_render_cfg* cfg, int M, const gps_cam
     return GPS_OK;
 }
 
+// The SH bands of a Gaussian set (or of its gradients or moments): degree 0..3 equal
+// to `degree`, coefficients present when there are any.
+static bool sh_ok(const gps_gaussians* x, int degree, int count)
+{
+    if (x->sh_degree < 0 || x->sh_degree > 3 || x->sh_degree != degree) return false;
+    return degree == 0 || count == 0 || x->sh != nullptr;
+}
+
 static gps_status build_tables(const gps_render_cfg* cfg, const gps_gaussians* g, const gps_view* views, int V,
                                ViewTable* vt, RParams* rp, WsLayout* L)
 {
@@ -129,6 +137,7 @@ static gps_status build_tables(const gps_render_cfg* cfg, const gps_gaussians* g
     if (g->count < 0) return GPS_ERR_INVALID_ARG;
     if (g->count > 0 && (!g->mean || !g->log_scale || !g->quat || !g->opacity_logit || !g->rgb))
         return GPS_ERR_INVALID_ARG;
+    if (!sh_ok(g, g->sh_degree, g->count)) return GPS_ERR_INVALID_ARG;
     gps_camera cams[GPS_MAX_VIEWS];
     if (V < 1 || V > GPS_MAX_VIEWS) return GPS_ERR_INVALID_ARG;
     for (int v = 0; v < V; ++v) cams[v] = views[v].cam;
@@ -285,6 +294,63 @@ gps_status gps_raycast(const gps_volume* vol, const gps_camera* cams, int32_t n_
     return launch_raycast(vol, cams, n_views, out_depth, out_rgb, z_near, step, (hipStream_t)stream);
 }
 
+static gps_status hash_vol_ok(const gps_hash_volume* v)
+{
+    if (!v) return GPS_ERR_INVALID_ARG;
+    if (v->nx < 2 || v->ny < 2 || v->nz < 2) return GPS_ERR_INVALID_ARG;
+    const int lim = (1 << 21) * GPS_HASH_BLOCK;  // block coordinates take 21 bits
+    if (v->nx > lim || v->ny > lim || v->nz > lim) return GPS_ERR_INVALID_ARG;
+    if (!(v->voxel > 0.0f) || !std::isfinite(v->voxel) || !(v->trunc > 0.0f) || !std::isfinite(v->trunc) ||
+        !(v->max_weight >= 1.0f))
+        return GPS_ERR_INVALID_ARG;
+    for (int k = 0; k < 3; ++k)
+        if (!std::isfinite(v->origin[k])) return GPS_ERR_INVALID_ARG;
+    if (v->n_buckets < 2 || v->n_buckets > (1 << 30) || (v->n_buckets & (v->n_buckets - 1))) return GPS_ERR_INVALID_ARG;
+    if (v->capacity < 1 || (int64_t)v->capacity * GPS_HASH_BLOCK * GPS_HASH_BLOCK * GPS_HASH_BLOCK > (int64_t(1) << 40))
+        return GPS_ERR_INVALID_ARG;
+    if (!v->keys || !v->slots || !v->block_key || !v->state || !v->visible || !v->tsdf || !v->weight || !v->rgb ||
+        !v->rgb_weight)
+        return GPS_ERR_INVALID_ARG;
+    if ((double)v->trunc / (double)v->voxel > 1024.0) return GPS_ERR_INVALID_ARG;  // band points per ray
+    return GPS_OK;
+}
+
+gps_status gps_hash_reset(const gps_hash_volume* vol, void* stream)
+{
+    gps_status st = hash_vol_ok(vol);
+    if (st != GPS_OK) return st;
+    st = check_device();
+    if (st != GPS_OK) return st;
+    return launch_hash_reset(vol, (hipStream_t)stream);
+}
+
+gps_status gps_hash_fuse(const gps_hash_volume* vol, const gps_camera* cam, const float* depth, const float* rgb,
+                         void* stream)
+{
+    gps_status st = hash_vol_ok(vol);
+    if (st != GPS_OK) return st;
+    if (!cam || !depth || !rgb || !cam_ok(*cam)) return GPS_ERR_INVALID_ARG;
+    st = check_device();
+    if (st != GPS_OK) return st;
+    return launch_hash_fuse(vol, cam, depth, rgb, (hipStream_t)stream);
+}
+
+gps_status gps_hash_raycast(const gps_hash_volume* vol, const gps_camera* cams, int32_t n_views,
+                            float* const* out_depth, float* const* out_rgb, float z_near, float step, void* stream)
+{
+    gps_status st = hash_vol_ok(vol);
+    if (st != GPS_OK) return st;
+    if (!cams || !out_depth || !out_rgb || n_views < 1 || n_views > GPS_MAX_VIEWS) return GPS_ERR_INVALID_ARG;
+    if (!(z_near >= 0.0f) || !std::isfinite(z_near) || !(step >= 0.0f) || !std::isfinite(step))
+        return GPS_ERR_INVALID_ARG;
+    if (step != 0.0f && step < 1e-3f * vol->voxel) return GPS_ERR_INVALID_ARG;
+    for (int v = 0; v < n_views; ++v)
+        if (!cam_ok(cams[v]) || !out_depth[v] || !out_rgb[v]) return GPS_ERR_INVALID_ARG;
+    st = check_device();
+    if (st != GPS_OK) return st;
+    return launch_hash_raycast(vol, cams, n_views, out_depth, out_rgb, z_near, step, (hipStream_t)stream);
+}
+
 gps_status gps_render_fwd(const gps_render_cfg* cfg, const gps_gaussians* g, const gps_view* views, int32_t n_views,
                           void* ws, size_t ws_bytes, float* out_loss, void* stream)
 {
@@ -315,15 +381,18 @@ static gps_status render_bwd_common(const gps_render_cfg* cfg, const gps_gaussia
     if (!grads && !adam) return GPS_ERR_INVALID_ARG;
     if (grads && (grads->count != g->count ||
                   (g->count > 0 && (!grads->mean || !grads->log_scale || !grads->quat || !grads->opacity_logit ||
-                                    !grads->rgb))))
+                                    !grads->rgb)) ||
+                  !sh_ok(grads, g->sh_degree, g->count)))
         return GPS_ERR_INVALID_ARG;
     if (adam) {
         const gps_gaussians* mv[2] = {&adam->m, &adam->v};
         for (const gps_gaussians* x : mv)
             if (x->count != g->count ||
-                (g->count > 0 && (!x->mean || !x->log_scale || !x->quat || !x->opacity_logit || !x->rgb)))
+                (g->count > 0 && (!x->mean || !x->log_scale || !x->quat || !x->opacity_logit || !x->rgb)) ||
+                !sh_ok(x, g->sh_degree, g->count))
                 return GPS_ERR_INVALID_ARG;
-        const float lr[5] = {adam->lr_mean, adam->lr_log_scale, adam->lr_quat, adam->lr_opacity, adam->lr_rgb};
+        const float lr[6] = {adam->lr_mean, adam->lr_log_scale, adam->lr_quat, adam->lr_opacity, adam->lr_rgb,
+                             adam->lr_sh};
         for (float x : lr)
             if (!std::isfinite(x)) return GPS_ERR_INVALID_ARG;
         if (!(adam->beta1 >= 0.0f && adam->beta1 < 1.0f) || !(adam->beta2 >= 0.0f && adam->beta2 < 1.0f) ||
@@ -421,6 +490,8 @@ static gps_status check_removal_args(const gps_removal_cfg* cfg, const gps_gauss
         if (M > 0 && (!gi.mean || !gi.log_scale || !gi.quat || !gi.opacity_logit || !gi.rgb || !go.mean ||
                       !go.log_scale || !go.quat || !go.opacity_logit || !go.rgb))
             return GPS_ERR_INVALID_ARG;
+        // every set carries the SH bands of the first (and its output too)
+        if (!sh_ok(&gi, sets_in[0].sh_degree, M) || !sh_ok(&go, sets_in[0].sh_degree, M)) return GPS_ERR_INVALID_ARG;
     }
     return GPS_OK;
 }
@@ -492,6 +563,7 @@ gps_status gps_insert_gaussians(const gps_insert_cfg* cfg, const gps_camera* cam
     if (out->count < 0) return GPS_ERR_INVALID_ARG;
     if (out->count > 0 && (!out->mean || !out->log_scale || !out->quat || !out->opacity_logit || !out->rgb))
         return GPS_ERR_INVALID_ARG;
+    if (!sh_ok(out, out->sh_degree, out->count)) return GPS_ERR_INVALID_ARG;
     if (!ws || ((uintptr_t)ws & 255)) return GPS_ERR_INVALID_ARG;
     if (ws_bytes < insertion_workspace_bytes(cam->width, cam->height)) return GPS_ERR_WORKSPACE_TOO_SMALL;
     gps_status st = check_device();

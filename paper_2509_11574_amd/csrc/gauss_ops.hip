@@ -18,8 +18,9 @@ namespace gps {
 constexpr int kRemoveSets = 4;
 
 struct RemovalArgs {
-    const float* in[kRemoveSets][5];  // per set: mean, log_scale, quat, opacity_logit, rgb
-    float* out[kRemoveSets][5];
+    const float* in[kRemoveSets][6];  // per set: mean, log_scale, quat, opacity_logit, rgb, SH bands
+    float* out[kRemoveSets][6];
+    int sh_rows;                      // rows of the SH bands (3 K; 0 without)
     int n_sets, M;
     float t_logit, t_hi, t_lo;        // logit(min_opacity), ln(max_scale), ln(min_scale)
     unsigned int* blk_cnt;
@@ -90,11 +91,13 @@ __global__ void __launch_bounds__(256) k_remove_scatter(RemovalArgs a)
     if (!k) return;
     const size_t pos = a.blk_off[blockIdx.x] + excl;
     const size_t nk = *a.total;  // row stride of the outputs
-    for (int s = 0; s < a.n_sets; ++s)
+    for (int s = 0; s < a.n_sets; ++s) {
 #pragma unroll
         for (int f = 0; f < 5; ++f)
             for (int r = 0; r < kRows[f]; ++r)
                 a.out[s][f][(size_t)r * nk + pos] = a.in[s][f][(size_t)r * a.M + g];
+        for (int r = 0; r < a.sh_rows; ++r) a.out[s][5][(size_t)r * nk + pos] = a.in[s][5][(size_t)r * a.M + g];
+    }
 }
 
 size_t removal_workspace_bytes(int M)
@@ -120,7 +123,10 @@ gps_status launch_remove_gaussians(const gps_removal_cfg* cfg, const gps_gaussia
         a.in[k][4] = gi.rgb;
         a.out[k][0] = go.mean, a.out[k][1] = go.log_scale, a.out[k][2] = go.quat, a.out[k][3] = go.opacity_logit,
         a.out[k][4] = go.rgb;
+        a.in[k][5] = gi.sh;
+        a.out[k][5] = go.sh;
     }
+    a.sh_rows = 3 * sh_count(sets_in[0].sh_degree);
     const int nblk = a.M > 0 ? (a.M + 255) / 256 : 0;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t nb = nblk > 0 ? (size_t)nblk : 1;
@@ -152,7 +158,8 @@ struct InsertArgs {
     const float* weight;
     const float* depth;
     const float* rnd;
-    float* out[5];  // mean, log_scale, quat, opacity_logit, rgb: planar [rows][capacity]
+    float* out[6];  // mean, log_scale, quat, opacity_logit, rgb, SH bands: planar [rows][capacity]
+    int sh_rows;    // rows of the SH bands (3 K; 0 without): new Gaussians start with zeros there
     int* out_pixel;
     int* out_count;
     int capacity;
@@ -409,6 +416,7 @@ __global__ void __launch_bounds__(256) k_insert_init(InsertArgs a)
     a.out[3][pos] = a.logit_opacity;
 #pragma unroll
     for (int k = 0; k < 3; ++k) a.out[4][k * C + pos] = a.frame_rgb[k * HW + p];
+    for (int r = 0; r < a.sh_rows; ++r) a.out[5][r * C + pos] = 0.0f;
     if (a.out_pixel) a.out_pixel[pos] = p;
 }
 
@@ -434,6 +442,8 @@ gps_status launch_insert_gaussians(const gps_insert_cfg* cfg, const DevCam& cam,
     a.rnd = rnd;
     a.out[0] = out->mean, a.out[1] = out->log_scale, a.out[2] = out->quat, a.out[3] = out->opacity_logit,
     a.out[4] = out->rgb;
+    a.out[5] = out->sh;
+    a.sh_rows = 3 * sh_count(out->sh_degree);
     a.out_pixel = out_pixel;
     a.out_count = out_count;
     a.capacity = out->count;

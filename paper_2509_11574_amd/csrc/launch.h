@@ -45,5 +45,10 @@ gps_status launch_icp_reduce(const gps_camera& prev, const float* prev_depth, co
                              const float* depth, const float* pose, float dist_thresh, double* sys, char* ws,
                              hipStream_t s);
 gps_status launch_icp_solve(const double* sys, float* pose, float* out_xi, hipStream_t s);
+gps_status launch_hash_reset(const gps_hash_volume* v, hipStream_t s);
+gps_status launch_hash_fuse(const gps_hash_volume* v, const gps_camera* cam, const float* depth, const float* rgb,
+                            hipStream_t s);
+gps_status launch_hash_raycast(const gps_hash_volume* v, const gps_camera* cams, int n_views, float* const* out_depth,
+                               float* const* out_rgb, float z_near, float step, hipStream_t s);
 
 }  // namespace gps

@@ -31,6 +31,7 @@ enum KernelId {
     K_REMOVE,
     K_INSERT,
     K_ICP,
+    K_HASH,
     K_COUNT
 };
 

@@ -11,7 +11,7 @@ namespace gps {
 static const char* kNames[K_COUNT] = {"fuse", "brick_min", "raycast", "tilemax", "project", "scan", "count",
                                       "scan_tiles", "emit", "tile_sort", "tile_sort_large", "composite_fwd", "loss_reduce", "composite_bwd", "gauss_bwd",
                                       "pose_reduce", "adam", "step_incr", "ws_reset",
-                                      "upload_views", "remove", "insert", "icp"};
+                                      "upload_views", "remove", "insert", "icp", "hash"};
 
 const char* kernel_name(int id) { return (id >= 0 && id < K_COUNT) ? kNames[id] : "?"; }
 

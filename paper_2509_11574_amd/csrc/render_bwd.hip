@@ -23,19 +23,27 @@ constexpr unsigned int kCoopSlots = 32;  // more slots than this: summed by the 
 // EWA chain rule of one Gaussian in one view.  The summed instance partials are
 // first turned into A[10] = dL/d(mx, my, a, b, c), sigma dL/dsigma, dL/d(r, g, b, d),
 // where (a, b, c) is the conic and b multiplies 2 dx dy.
-// Adam applied in the epilogue of k_gauss_bwd: the five attribute groups (mean,
-// log-scale, quaternion, opacity logit, rgb), each with its learning rate.
+// Adam applied in the epilogue of k_gauss_bwd: the attribute groups (mean,
+// log-scale, quaternion, opacity logit, rgb, and the SH bands when there are
+// any), each with its learning rate.
 struct AdamFuse {
-    float* p[5];
-    float* m[5];
-    float* v[5];
-    float lr[5];
+    float* p[6];
+    float* m[6];
+    float* v[6];
+    float lr[6];
     const int* step_ctr;
     int step;
     float b1, b2, eps;
     int on;
 };
 
+// SHK: SH coefficients per channel (0, 3, 8 or 15).  The colour adjoint of each
+// view (A[6..8]) goes to rgb and, times the basis at that view's direction, to the
+// coefficients; through the direction d = (mu - o) / |mu - o| it moves the centre by
+// (I - d d^T) / |mu - o| times the basis gradient weighted by the coefficients, and
+// the camera centre moves by -R^T rho under the left perturbation, so rho takes R
+// times the same vector.
+template <int SHK>
 __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict__ vtp, RParams rp, GParams gp, GGrads gg,
                                                     WsPtrs w, AdamFuse af)
 {
@@ -49,6 +57,10 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
     // epilogue is skipped, so parameters and moments stay as they were.
     const bool over = w.hdr->n_inst > rp.cap;
     float gmean[3] = {0, 0, 0}, gls[3] = {0, 0, 0}, gq[4] = {0, 0, 0, 0}, gop = 0.0f, grgb[3] = {0, 0, 0};
+    constexpr int NSH = SHK > 0 ? 3 * SHK : 1;
+    float gsh[NSH];
+#pragma unroll
+    for (int k = 0; k < NSH; ++k) gsh[k] = 0.0f;
     __shared__ float pred[kBlk / 64][6];
     __shared__ float sbc[2];
     if (af.on) {
@@ -182,6 +194,34 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
             grgb[0] += A[6];
             grgb[1] += A[7];
             grgb[2] += A[8];
+            float rho_sh[3] = {0.0f, 0.0f, 0.0f};
+            if constexpr (SHK > 0) {
+                const float v0 = m0 + (R[0] * c.t[0] + R[3] * c.t[1] + R[6] * c.t[2]);
+                const float v1 = m1 + (R[1] * c.t[0] + R[4] * c.t[1] + R[7] * c.t[2]);
+                const float v2 = m2 + (R[2] * c.t[0] + R[5] * c.t[1] + R[8] * c.t[2]);
+                const float ir = 1.0f / sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+                const float d0 = v0 * ir, d1 = v1 * ir, d2 = v2 * ir;
+                float Y[SHK], wk[SHK];
+                sh_basis<SHK>(d0, d1, d2, Y);
+#pragma unroll
+                for (int k = 0; k < SHK; ++k) {
+                    gsh[k] += A[6] * Y[k];
+                    gsh[SHK + k] += A[7] * Y[k];
+                    gsh[2 * SHK + k] += A[8] * Y[k];
+                    wk[k] = A[6] * gp.sh[(size_t)k * M + g] + A[7] * gp.sh[(size_t)(SHK + k) * M + g] +
+                            A[8] * gp.sh[(size_t)(2 * SHK + k) * M + g];
+                }
+                float gd[3];
+                sh_weighted_grad<SHK>(d0, d1, d2, wk, gd);
+                const float dd = d0 * gd[0] + d1 * gd[1] + d2 * gd[2];
+                const float u0 = (gd[0] - d0 * dd) * ir, u1 = (gd[1] - d1 * dd) * ir, u2 = (gd[2] - d2 * dd) * ir;
+                gmean[0] += u0;
+                gmean[1] += u1;
+                gmean[2] += u2;
+                rho_sh[0] = R[0] * u0 + R[1] * u1 + R[2] * u2;
+                rho_sh[1] = R[3] * u0 + R[4] * u1 + R[5] * u2;
+                rho_sh[2] = R[6] * u0 + R[7] * u1 + R[8] * u2;
+            }
             gop += A[5] * (1.0f - sig);  // dL/dsigma * sigma (1 - sigma)
             // G2 = -Q Gq Q with Gq = [[A2, A3/2], [A3/2, A4]]
             const float h = 0.5f * A[3];
@@ -273,9 +313,9 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
                 for (int k = 0; k < 3; ++k)
                     K[3 * r + k] = (Gc[3 * r] * Sc[k] + Gc[3 * r + 1] * Sc[3 + k] + Gc[3 * r + 2] * Sc[6 + k]) -
                                    (Sc[3 * r] * Gc[k] + Sc[3 * r + 1] * Gc[3 + k] + Sc[3 * r + 2] * Gc[6 + k]);
-            pose[0] = gpx;
-            pose[1] = gpy;
-            pose[2] = gpz;
+            pose[0] = gpx + rho_sh[0];
+            pose[1] = gpy + rho_sh[1];
+            pose[2] = gpz + rho_sh[2];
             pose[3] = y * gpz - z * gpy + 2.0f * K[7];
             pose[4] = z * gpx - x * gpz + 2.0f * K[2];
             pose[5] = x * gpy - y * gpx + 2.0f * K[3];
@@ -310,6 +350,10 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
         gg.rgb[g] = grgb[0];
         gg.rgb[M + g] = grgb[1];
         gg.rgb[2 * M + g] = grgb[2];
+        if constexpr (SHK > 0) {
+#pragma unroll
+            for (int k = 0; k < 3 * SHK; ++k) gg.sh[(size_t)k * M + g] = gsh[k];
+        }
     }
     if (live && af.on && !over) {
         // this lane's Gaussian only: its parameters were read above by this lane alone
@@ -328,6 +372,17 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
                     af.m[a][i] = m;
                     af.v[a][i] = v;
                 }
+        if constexpr (SHK > 0) {
+#pragma unroll
+            for (int r = 0; r < 3 * SHK; ++r) {
+                const size_t i = (size_t)r * M + g;
+                float p = af.p[5][i], m = af.m[5][i], v = af.v[5][i];
+                adam_one(p, gsh[r], m, v, af.lr[5], af.b1, af.b2, af.eps, ibc1, ibc2);
+                af.p[5][i] = p;
+                af.m[5][i] = m;
+                af.v[5][i] = v;
+            }
+        }
     }
 }
 
@@ -530,9 +585,12 @@ gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const
                              hipStream_t s)
 {
     WsPtrs w = ws_ptrs(ws, L);
-    GParams gp{g->mean, g->log_scale, g->quat, g->opacity_logit, g->rgb};
-    GGrads gg{nullptr, nullptr, nullptr, nullptr, nullptr};
-    if (grads) gg = GGrads{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->rgb};
+    const int shk = sh_count(g->sh_degree);
+    GParams gp{g->mean, g->log_scale, g->quat, g->opacity_logit, g->rgb, shk ? g->sh : nullptr, shk};
+    GGrads gg{nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+    if (grads)
+        gg = GGrads{grads->mean, grads->log_scale, grads->quat, grads->opacity_logit, grads->rgb,
+                    shk ? grads->sh : nullptr};
     AdamFuse af{};
     af.on = adam != nullptr;
     if (adam) {
@@ -546,6 +604,10 @@ gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const
             af.v[k] = vv[k];
             af.lr[k] = lr[k];
         }
+        af.p[5] = shk ? g->sh : nullptr;
+        af.m[5] = shk ? adam->m.sh : nullptr;
+        af.v[5] = shk ? adam->v.sh : nullptr;
+        af.lr[5] = adam->lr_sh;
         af.step_ctr = adam->step_counter;
         af.step = adam->step;
         af.b1 = adam->beta1;
@@ -571,7 +633,14 @@ gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const
         return GPS_ERR_UNSUPPORTED_CONFIG;
     }
     if (L.nblk_g > 0) {
-        GPS_LAUNCH(K_GAUSS_BWD, s, k_gauss_bwd, dim3(L.nblk_g), dim3(kBlk), 0, s, dvt, rp, gp, gg, w, af);
+        if (shk == 15)
+            GPS_LAUNCH(K_GAUSS_BWD, s, k_gauss_bwd<15>, dim3(L.nblk_g), dim3(kBlk), 0, s, dvt, rp, gp, gg, w, af);
+        else if (shk == 8)
+            GPS_LAUNCH(K_GAUSS_BWD, s, k_gauss_bwd<8>, dim3(L.nblk_g), dim3(kBlk), 0, s, dvt, rp, gp, gg, w, af);
+        else if (shk == 3)
+            GPS_LAUNCH(K_GAUSS_BWD, s, k_gauss_bwd<3>, dim3(L.nblk_g), dim3(kBlk), 0, s, dvt, rp, gp, gg, w, af);
+        else
+            GPS_LAUNCH(K_GAUSS_BWD, s, k_gauss_bwd<0>, dim3(L.nblk_g), dim3(kBlk), 0, s, dvt, rp, gp, gg, w, af);
     }
     int* ctr = adam ? adam->step_counter : nullptr;
     // one block per view (an empty set sums no block partials: dpose = 0), or one

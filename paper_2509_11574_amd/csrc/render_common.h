@@ -2,6 +2,7 @@
 #pragma once
 
 #include "gps_internal.h"
+#include "sh.h"
 
 namespace gps {
 
@@ -11,6 +12,8 @@ struct GParams {
     const float* quat;
     const float* opacity_logit;
     const float* rgb;
+    const float* sh;  // [3][sh_k][M] or null
+    int sh_k;         // SH coefficients per channel: 0, 3, 8 or 15
 };
 
 struct GGrads {
@@ -19,7 +22,33 @@ struct GGrads {
     float* quat;
     float* opacity_logit;
     float* rgb;
+    float* sh;
 };
+
+// The colour of Gaussian g seen from camera c: rgb plus the SH bands at the unit
+// direction from the camera centre o = -R^T t to the centre mu.
+__device__ __forceinline__ void view_colour(const GParams& gp, int M, int g, const DevCam& c, float m0, float m1,
+                                            float m2, float col[3])
+{
+    col[0] = gp.rgb[g];
+    col[1] = gp.rgb[M + g];
+    col[2] = gp.rgb[2 * M + g];
+    if (gp.sh_k == 0) return;
+    const float v0 = m0 + (c.R[0] * c.t[0] + c.R[3] * c.t[1] + c.R[6] * c.t[2]);
+    const float v1 = m1 + (c.R[1] * c.t[0] + c.R[4] * c.t[1] + c.R[7] * c.t[2]);
+    const float v2 = m2 + (c.R[2] * c.t[0] + c.R[5] * c.t[1] + c.R[8] * c.t[2]);
+    const float ir = 1.0f / sqrtf(v0 * v0 + v1 * v1 + v2 * v2);
+    float Y[kShMaxK];
+    if (gp.sh_k == 15) sh_basis<15>(v0 * ir, v1 * ir, v2 * ir, Y);
+    else if (gp.sh_k == 8) sh_basis<8>(v0 * ir, v1 * ir, v2 * ir, Y);
+    else sh_basis<3>(v0 * ir, v1 * ir, v2 * ir, Y);
+    const int K = gp.sh_k;
+    for (int ch = 0; ch < 3; ++ch) {
+        float acc = col[ch];
+        for (int k = 0; k < K; ++k) acc += gp.sh[((size_t)ch * K + k) * M + g] * Y[k];
+        col[ch] = acc;
+    }
+}
 
 // Block-wide exclusive scan of one unsigned per thread (NT a multiple of 64).
 template <int NT>

@@ -73,7 +73,8 @@ __device__ __forceinline__ void forward_resets(const ViewTable& vt, const RParam
 //   p_c = R mu + t, Sigma_3D = R_q diag(s^2) R_q^T, J the pinhole Jacobian,
 //   Sigma_2D = (J R) Sigma_3D (J R)^T + dilation I, conic = Sigma_2D^-1.
 // Record of 12 floats: r0 = (m_x, m_y, A', B'), r1 = (C', log2 sigma, z, red),
-// r2 = (green, blue, half-width, half-height of the support box), where
+// r2 = (green, blue, half-width, half-height of the support box), the colour
+// being the one seen from this view (rgb plus the SH bands), where
 // (A', B', C') = (-0.5 a, -b, -0.5 c) log2(e) for the conic (a, b, c), the
 // opacity then being exp2(A' dx^2 + B' dx dy + C' dy^2 + log2 sigma).
 // The support ellipse where sigma exp(-q/2) >= alpha_min has the bounding box
@@ -154,8 +155,10 @@ __device__ __forceinline__ ProjOut project_one(const DevView& V, const RParams& 
     // conic (a, b, c) = (C, -B, A) / det, pre-scaled for the base-2 exponential
     constexpr float kL2E = 1.4426950408889634f;
     o.r0 = make_float4(mx, my, (-0.5f * kL2E) * (C * idet), kL2E * (B * idet));
-    o.r1 = make_float4((-0.5f * kL2E) * (A * idet), __log2f(sig), z, gp.rgb[g]);
-    o.r2 = make_float4(gp.rgb[M + g], gp.rgb[2 * M + g], rxp, ryp);
+    float col[3];
+    view_colour(gp, M, g, c, m0, m1, m2, col);
+    o.r1 = make_float4((-0.5f * kL2E) * (A * idet), __log2f(sig), z, col[0]);
+    o.r2 = make_float4(col[1], col[2], rxp, ryp);
     o.valid = true;
     return o;
 }
@@ -626,7 +629,8 @@ gps_status launch_render_fwd(const gps_render_cfg* cfg, const RParams& rp, const
                              const ViewTable& vt, const WsLayout& L, char* ws, float* out_loss, hipStream_t s)
 {
     WsPtrs w = ws_ptrs(ws, L);
-    GParams gp{g->mean, g->log_scale, g->quat, g->opacity_logit, g->rgb};
+    GParams gp{g->mean, g->log_scale, g->quat, g->opacity_logit, g->rgb, g->sh_degree > 0 ? g->sh : nullptr,
+               sh_count(g->sh_degree)};
     int has_loss = 1;
     for (int v = 0; v < vt.n; ++v)
         if (!vt.v[v].target_rgb) has_loss = 0;

@@ -43,9 +43,20 @@ class VolumeS(ctypes.Structure):
                 ("rgb", ctypes.c_void_p), ("rgb_weight", ctypes.c_void_p), ("brick_min", ctypes.c_void_p)]
 
 
+class HashVolumeS(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("origin", ctypes.c_float * 3), ("voxel", ctypes.c_float), ("trunc", ctypes.c_float),
+                ("max_weight", ctypes.c_float), ("n_buckets", ctypes.c_int32), ("capacity", ctypes.c_int32),
+                ("keys", ctypes.c_void_p), ("slots", ctypes.c_void_p), ("block_key", ctypes.c_void_p),
+                ("state", ctypes.c_void_p), ("visible", ctypes.c_void_p), ("block_min", ctypes.c_void_p),
+                ("tsdf", ctypes.c_void_p), ("weight", ctypes.c_void_p), ("rgb", ctypes.c_void_p),
+                ("rgb_weight", ctypes.c_void_p)]
+
+
 class GaussiansS(ctypes.Structure):
     _fields_ = [("count", ctypes.c_int32), ("mean", ctypes.c_void_p), ("log_scale", ctypes.c_void_p),
-                ("quat", ctypes.c_void_p), ("opacity_logit", ctypes.c_void_p), ("rgb", ctypes.c_void_p)]
+                ("quat", ctypes.c_void_p), ("opacity_logit", ctypes.c_void_p), ("rgb", ctypes.c_void_p),
+                ("sh_degree", ctypes.c_int32), ("sh", ctypes.c_void_p)]
 
 
 class ViewS(ctypes.Structure):
@@ -89,13 +100,16 @@ class KernelTimeS(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
+ABI_VERSION = 4  # include/gps.h GPS_ABI_VERSION
+
 EXPORTS = ["gps_abi_version", "gps_status_string", "gps_render_cfg_default", "gps_workspace_size",
            "gps_workspace_reset", "gps_fuse", "gps_raycast", "gps_render_fwd", "gps_render_bwd",
            "gps_adam_step", "gps_device_status", "gps_read_stats", "gps_profile_start", "gps_profile_stop",
            "gps_profile_read", "gps_views_upload", "gps_removal_cfg_default", "gps_removal_workspace_size",
            "gps_remove_gaussians", "gps_insert_cfg_default", "gps_insertion_workspace_size",
            "gps_insert_gaussians", "gps_depth_downsample", "gps_icp_workspace_size", "gps_icp_reduce",
-           "gps_icp_solve", "gps_render_bwd_adam", "gps_level_camera", "gps_icp_reduce_noalloc"]
+           "gps_icp_solve", "gps_render_bwd_adam", "gps_level_camera", "gps_icp_reduce_noalloc",
+           "gps_hash_reset", "gps_hash_fuse", "gps_hash_raycast"]
 
 _lib = None
 
@@ -108,6 +122,9 @@ def lib():
             raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2509_11574_amd.build` "
                               "(or __graft_entry__.build()); there is no fallback implementation")
         L = ctypes.CDLL(LIB_PATH)
+        L.gps_abi_version.restype = ctypes.c_int32
+        if L.gps_abi_version() != ABI_VERSION:
+            raise ImportError(f"{LIB_PATH} has ABI {L.gps_abi_version()}, this binding needs {ABI_VERSION}: rebuild it")
         P, I32, I64, F = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
         L.gps_abi_version.restype = I32
         L.gps_status_string.argtypes = [I32]
@@ -139,6 +156,9 @@ def lib():
         L.gps_icp_workspace_size.argtypes = [I32, I32, ctypes.POINTER(ctypes.c_size_t)]
         L.gps_icp_reduce.argtypes = [P, P, P, P, P, F, P, P, ctypes.c_size_t, P]
         L.gps_icp_reduce_noalloc.argtypes = [P, P, P, P, P, F, P, P]
+        L.gps_hash_reset.argtypes = [P, P]
+        L.gps_hash_fuse.argtypes = [P, P, P, P, P]
+        L.gps_hash_raycast.argtypes = [P, P, I32, P, P, F, F, P]
         L.gps_icp_solve.argtypes = [P, P, P, P]
         L.gps_render_bwd_adam.argtypes = [P, P, P, I32, P, P, P, P, P, P, P, ctypes.c_size_t, P]
         L.gps_level_camera.argtypes = [P, I32, P]
@@ -168,7 +188,7 @@ def _ptr(t, name="tensor", numel=None):
         raise TypeError(f"{name} must be a torch tensor")
     if not t.is_cuda:
         raise ValueError(f"{name} must be on the GPU")
-    if t.dtype not in (torch.float32, torch.int32, torch.uint8):
+    if t.dtype not in (torch.float32, torch.int32, torch.int64, torch.uint8):
         raise TypeError(f"{name} must be float32 (got {t.dtype})")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
@@ -243,21 +263,45 @@ GAUSS_KEYS = ("mean", "log_scale", "quat", "opacity_logit", "rgb")
 GAUSS_ROWS = {"mean": 3, "log_scale": 3, "quat": 4, "opacity_logit": 1, "rgb": 3}
 
 
+# SH bands above degree 0 (optional key "sh", [3][K][M]): coefficients per channel for
+# degree 1, 2, 3, and back
+SH_COEFFS = {0: 0, 1: 3, 2: 8, 3: 15}
+SH_DEGREE_OF = {v: k for k, v in SH_COEFFS.items()}
+
+
+def gauss_keys(g: dict) -> tuple:
+    """The attribute keys of a Gaussian dict: the five, plus "sh" when it carries SH bands."""
+    return GAUSS_KEYS + (("sh",) if g.get("sh") is not None else ())
+
+
+def sh_degree(g: dict) -> int:
+    sh = g.get("sh")
+    if sh is None:
+        return 0
+    if sh.dim() != 3 or sh.shape[0] != 3 or sh.shape[1] not in SH_DEGREE_OF:
+        raise ValueError("sh must have shape [3, K, M] with K = 3, 8 or 15")
+    return SH_DEGREE_OF[int(sh.shape[1])]
+
+
 def gaussians_struct(g: dict) -> GaussiansS:
     M = int(g["opacity_logit"].numel())
     s = GaussiansS()
     s.count = M
     for k in GAUSS_KEYS:
         setattr(s, k, _ptr(g[k], k, GAUSS_ROWS[k] * M))
+    L = sh_degree(g)
+    s.sh_degree = L
+    s.sh = _ptr(g["sh"], "sh", 3 * SH_COEFFS[L] * M) if L > 0 else None
     return s
 
 
 def gaussians_to_device(g: dict, device="cuda") -> dict:
-    return {k: torch.as_tensor(np.ascontiguousarray(g[k], np.float32)).to(device) for k in GAUSS_KEYS}
+    keys = GAUSS_KEYS + (("sh",) if g.get("sh") is not None else ())
+    return {k: torch.as_tensor(np.ascontiguousarray(g[k], np.float32)).to(device) for k in keys}
 
 
 def zeros_like_gaussians(g: dict) -> dict:
-    return {k: torch.zeros_like(g[k]) for k in GAUSS_KEYS}
+    return {k: torch.zeros_like(g[k]) for k in gauss_keys(g)}
 
 
 @dataclass
@@ -315,6 +359,91 @@ def raycast(vol: Volume, cams, z_near=0.2, step=0.0, out=None, stream=None):
     s = vol.struct()
     _check(lib().gps_raycast(ctypes.byref(s), carr, V, dptr, cptr, float(z_near), float(step), _stream(stream)),
            "gps_raycast")
+    return out
+
+
+# --------------------------------------------------------------------------- #
+# Voxel-block hash of the TSDF (Sec. 3.2.1)                                    #
+# --------------------------------------------------------------------------- #
+HASH_BLOCK = 8
+
+
+@dataclass
+class HashVolume:
+    """Colourised TSDF in a voxel-block hash (gps_hash_volume): a region of dims lattice
+    points, blocks of 8^3 points allocated from the depth frames, `capacity` pool
+    blocks, `n_buckets` table buckets (default: the power of two >= 2 * capacity)."""
+    dims: tuple
+    origin: tuple
+    voxel: float
+    trunc: float
+    capacity: int
+    n_buckets: int = 0
+    max_weight: float = 100.0
+    device: str = "cuda"
+    skip_blocks: bool = True
+
+    def __post_init__(self):
+        cap = int(self.capacity)
+        if self.n_buckets <= 0:
+            self.n_buckets = 1 << max(1, (2 * cap - 1).bit_length())
+        nb, dev = int(self.n_buckets), self.device
+        self.keys = torch.empty(nb, dtype=torch.int64, device=dev)
+        self.slots = torch.empty(nb, dtype=torch.int32, device=dev)
+        self.block_key = torch.empty(cap, dtype=torch.int64, device=dev)
+        self.state_t = torch.zeros(4, dtype=torch.int32, device=dev)
+        self.visible = torch.empty(cap, dtype=torch.int32, device=dev)
+        self.block_min = torch.empty(cap, dtype=torch.float32, device=dev) if self.skip_blocks else None
+        n = cap * HASH_BLOCK ** 3
+        self.tsdf = torch.empty(n, dtype=torch.float32, device=dev)
+        self.weight = torch.empty(n, dtype=torch.float32, device=dev)
+        self.rgb = torch.empty(3, n, dtype=torch.float32, device=dev)
+        self.rgb_weight = torch.empty(n, dtype=torch.float32, device=dev)
+        self.reset()
+
+    def struct(self) -> HashVolumeS:
+        s = HashVolumeS()
+        s.nx, s.ny, s.nz = (int(d) for d in self.dims)
+        for k in range(3):
+            s.origin[k] = float(self.origin[k])
+        s.voxel, s.trunc, s.max_weight = float(self.voxel), float(self.trunc), float(self.max_weight)
+        s.n_buckets, s.capacity = int(self.n_buckets), int(self.capacity)
+        for name in ("keys", "slots", "block_key", "visible", "tsdf", "weight", "rgb", "rgb_weight"):
+            setattr(s, name, _ptr(getattr(self, name), name))
+        s.state = _ptr(self.state_t, "state", 4)
+        s.block_min = _ptr(self.block_min, "block_min") if self.block_min is not None else None
+        return s
+
+    def reset(self, stream=None):
+        s = self.struct()
+        _check(lib().gps_hash_reset(ctypes.byref(s), _stream(stream)), "gps_hash_reset")
+
+    def state(self) -> dict:
+        """Counters (reads them back: synchronises)."""
+        a = self.state_t.cpu().tolist()
+        return {"allocated": a[0], "allocated_before": a[1], "visible": a[2], "status": a[3]}
+
+
+def hash_fuse(vol: HashVolume, cam, depth: torch.Tensor, rgb: torch.Tensor, stream=None):
+    c = camera(cam)
+    s = vol.struct()
+    _check(lib().gps_hash_fuse(ctypes.byref(s), ctypes.byref(c), _ptr(depth, "depth", c.width * c.height),
+                               _ptr(rgb, "rgb", 3 * c.width * c.height), _stream(stream)), "gps_hash_fuse")
+
+
+def hash_raycast(vol: HashVolume, cams, z_near=0.2, step=0.0, out=None, stream=None):
+    """As raycast, over the hashed volume."""
+    cams = [camera(c) for c in cams]
+    V = len(cams)
+    if out is None:
+        out = [(torch.empty(c.height, c.width, dtype=torch.float32, device=vol.tsdf.device),
+                torch.empty(3, c.height, c.width, dtype=torch.float32, device=vol.tsdf.device)) for c in cams]
+    carr = (Camera * V)(*cams)
+    dptr = (ctypes.c_void_p * V)(*[_ptr(d, "out_depth", c.width * c.height).value for (d, _), c in zip(out, cams)])
+    cptr = (ctypes.c_void_p * V)(*[_ptr(r, "out_rgb", 3 * c.width * c.height).value for (_, r), c in zip(out, cams)])
+    s = vol.struct()
+    _check(lib().gps_hash_raycast(ctypes.byref(s), carr, V, dptr, cptr, float(z_near), float(step), _stream(stream)),
+           "gps_hash_raycast")
     return out
 
 
@@ -471,7 +600,7 @@ def render_bwd(cfg: RenderCfg, gauss: dict, views, ws: Workspace, grads: dict, d
 class AdamFusedS(ctypes.Structure):
     _fields_ = [("m", GaussiansS), ("v", GaussiansS), ("lr_mean", ctypes.c_float), ("lr_log_scale", ctypes.c_float),
                 ("lr_quat", ctypes.c_float), ("lr_opacity", ctypes.c_float), ("lr_rgb", ctypes.c_float),
-                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("lr_sh", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
                 ("step", ctypes.c_int32), ("step_counter", ctypes.c_void_p)]
 
 
@@ -494,7 +623,7 @@ def render_bwd_adam(cfg: RenderCfg, gauss: dict, views, ws: Workspace, opt: "Ada
     opt.t += 1
     af = AdamFusedS(gaussians_struct(opt.m), gaussians_struct(opt.v), float(opt.lr["mean"]),
                     float(opt.lr["log_scale"]), float(opt.lr["quat"]), float(opt.lr["opacity_logit"]),
-                    float(opt.lr["rgb"]), opt.b1, opt.b2, opt.eps, opt.t,
+                    float(opt.lr["rgb"]), float(opt.lr["sh"]), opt.b1, opt.b2, opt.eps, opt.t,
                     ctypes.c_void_p(opt.counter.data_ptr()) if opt.counter is not None else None)
     _check(lib().gps_render_bwd_adam(ctypes.byref(cs), ctypes.byref(gs), va, V, rgb_arr, dep_arr,
                                      _ptr(loss_scale, "loss_scale", 1) if loss_scale is not None else None,
@@ -504,8 +633,9 @@ def render_bwd_adam(cfg: RenderCfg, gauss: dict, views, ws: Workspace, opt: "Ada
 
 
 # Learning rates per attribute (Appendix C): position, SH0 (applied to rgb),
-# alpha (applied to the opacity logit), scale (log-scale), rotation (quaternion).
-PAPER_LR = {"mean": 1.6e-4, "rgb": 2.5e-3, "opacity_logit": 0.05, "log_scale": 5e-3, "quat": 1e-3}
+# alpha (applied to the opacity logit), scale (log-scale), rotation (quaternion),
+# the SH bands above 0.
+PAPER_LR = {"mean": 1.6e-4, "rgb": 2.5e-3, "opacity_logit": 0.05, "log_scale": 5e-3, "quat": 1e-3, "sh": 5e-4}
 
 
 class Adam:
@@ -517,20 +647,21 @@ class Adam:
         self.lr = dict(PAPER_LR if lr is None else lr)
         self.b1, self.b2 = betas
         self.eps = eps
-        self.m = {k: torch.zeros_like(params[k]) for k in GAUSS_KEYS}
-        self.v = {k: torch.zeros_like(params[k]) for k in GAUSS_KEYS}
+        self.m = {k: torch.zeros_like(params[k]) for k in gauss_keys(params)}
+        self.v = {k: torch.zeros_like(params[k]) for k in gauss_keys(params)}
         self.t = 0
         self.counter = torch.zeros(1, dtype=torch.int32, device=params["mean"].device) if device_counter else None
 
     def step(self, grads: dict, stream=None):
-        groups = (AdamGroupS * len(GAUSS_KEYS))()
-        for i, k in enumerate(GAUSS_KEYS):
+        keys = gauss_keys(self.params)
+        groups = (AdamGroupS * len(keys))()
+        for i, k in enumerate(keys):
             p = self.params[k]
             groups[i] = AdamGroupS(_ptr(p, k), _ptr(grads[k], "grad " + k, p.numel()), _ptr(self.m[k]),
                                    _ptr(self.v[k]), p.numel(), float(self.lr[k]))
         self.t += 1
         ctr = ctypes.c_void_p(self.counter.data_ptr()) if self.counter is not None else None
-        _check(lib().gps_adam_step(groups, len(GAUSS_KEYS), self.t, ctr, self.b1, self.b2, self.eps,
+        _check(lib().gps_adam_step(groups, len(keys), self.t, ctr, self.b1, self.b2, self.eps,
                                    _stream(stream)), "gps_adam_step")
 
 
@@ -569,45 +700,48 @@ def _pose_arg(pose_xi, n_views):
 
 
 class RenderLoss(torch.autograd.Function):
-    """loss = RenderLoss.apply(mean, log_scale, quat, opacity_logit, rgb, pose_xi, session).
+    """loss = RenderLoss.apply(mean, log_scale, quat, opacity_logit, rgb, pose_xi, session[, sh]).
     pose_xi [V,6] (or None): view v is rendered from Exp(pose_xi[v]) T_cw, the left perturbation of its
-    camera, translation first; its gradient is dL/dpose_xi at the given value."""
+    camera, translation first; its gradient is dL/dpose_xi at the given value.  sh (optional,
+    [3,K,M]): the SH bands above degree 0 (view-dependent colour)."""
 
     @staticmethod
-    def forward(ctx, mean, log_scale, quat, opacity_logit, rgb, pose_xi, session: Session):
-        g = {"mean": mean, "log_scale": log_scale, "quat": quat, "opacity_logit": opacity_logit, "rgb": rgb}
+    def forward(ctx, mean, log_scale, quat, opacity_logit, rgb, pose_xi, session: Session, sh=None):
+        g = {"mean": mean, "log_scale": log_scale, "quat": quat, "opacity_logit": opacity_logit, "rgb": rgb, "sh": sh}
         xi = _pose_arg(pose_xi, len(session.views))
         render_fwd(session.cfg, g, session.views, session.ws, out_loss=session.loss, pose_xi=xi)
         ctx.session = session
         ctx.pose_given = pose_xi is not None
-        ctx.save_for_backward(mean, log_scale, quat, opacity_logit, rgb, xi)
+        ctx.has_sh = sh is not None
+        ctx.save_for_backward(mean, log_scale, quat, opacity_logit, rgb, xi, sh)
         return session.loss.clone().reshape(())
 
     @staticmethod
     def backward(ctx, gloss):
         s = ctx.session
-        mean, log_scale, quat, opacity_logit, rgb, xi = ctx.saved_tensors
-        g = {"mean": mean, "log_scale": log_scale, "quat": quat, "opacity_logit": opacity_logit, "rgb": rgb}
+        mean, log_scale, quat, opacity_logit, rgb, xi, sh = ctx.saved_tensors
+        g = {"mean": mean, "log_scale": log_scale, "quat": quat, "opacity_logit": opacity_logit, "rgb": rgb, "sh": sh}
         grads = zeros_like_gaussians(g)
         dpose = torch.zeros(len(s.views), 6, dtype=torch.float32, device=mean.device)
         scale = gloss.detach().to(torch.float32).reshape(1).contiguous()
         render_bwd(s.cfg, g, s.views, s.ws, grads, dpose, loss_scale=scale, pose_xi=xi)
         return (grads["mean"], grads["log_scale"], grads["quat"], grads["opacity_logit"], grads["rgb"],
-                dpose if ctx.pose_given else None, None)
+                dpose if ctx.pose_given else None, None, grads["sh"] if ctx.has_sh else None)
 
 
 class Render(torch.autograd.Function):
     """rgb_0, depth_0, rgb_1, depth_1, ... = Render.apply(mean, log_scale, quat, opacity_logit, rgb, pose_xi,
-    session) for arbitrary downstream losses (pose_xi as in RenderLoss)."""
+    session[, sh]) for arbitrary downstream losses (pose_xi and sh as in RenderLoss)."""
 
     @staticmethod
-    def forward(ctx, mean, log_scale, quat, opacity_logit, rgb, pose_xi, session: Session):
-        g = {"mean": mean, "log_scale": log_scale, "quat": quat, "opacity_logit": opacity_logit, "rgb": rgb}
+    def forward(ctx, mean, log_scale, quat, opacity_logit, rgb, pose_xi, session: Session, sh=None):
+        g = {"mean": mean, "log_scale": log_scale, "quat": quat, "opacity_logit": opacity_logit, "rgb": rgb, "sh": sh}
         xi = _pose_arg(pose_xi, len(session.views))
         render_fwd(session.cfg, g, session.views, session.ws, pose_xi=xi)
         ctx.session = session
         ctx.pose_given = pose_xi is not None
-        ctx.save_for_backward(mean, log_scale, quat, opacity_logit, rgb, xi)
+        ctx.has_sh = sh is not None
+        ctx.save_for_backward(mean, log_scale, quat, opacity_logit, rgb, xi, sh)
         outs = []
         for v in session.views:
             outs += [v.out_rgb.clone(), v.out_depth.clone()]
@@ -616,8 +750,8 @@ class Render(torch.autograd.Function):
     @staticmethod
     def backward(ctx, *gouts):
         s = ctx.session
-        mean, log_scale, quat, opacity_logit, rgb, xi = ctx.saved_tensors
-        g = {"mean": mean, "log_scale": log_scale, "quat": quat, "opacity_logit": opacity_logit, "rgb": rgb}
+        mean, log_scale, quat, opacity_logit, rgb, xi, sh = ctx.saved_tensors
+        g = {"mean": mean, "log_scale": log_scale, "quat": quat, "opacity_logit": opacity_logit, "rgb": rgb, "sh": sh}
         grads = zeros_like_gaussians(g)
         dpose = torch.zeros(len(s.views), 6, dtype=torch.float32, device=mean.device)
         drgb, ddep = [], []
@@ -627,7 +761,7 @@ class Render(torch.autograd.Function):
             ddep.append((gd if gd is not None else torch.zeros_like(v.out_depth)).contiguous())
         render_bwd(s.cfg, g, s.views, s.ws, grads, dpose, dL_drgb=drgb, dL_ddepth=ddep, pose_xi=xi)
         return (grads["mean"], grads["log_scale"], grads["quat"], grads["opacity_logit"], grads["rgb"],
-                dpose if ctx.pose_given else None, None)
+                dpose if ctx.pose_given else None, None, grads["sh"] if ctx.has_sh else None)
 
 
 def remove_gaussians(params: dict, companions=(), min_opacity=0.005, max_scale=0.1, min_scale=0.003, stream=None):
@@ -637,14 +771,21 @@ def remove_gaussians(params: dict, companions=(), min_opacity=0.005, max_scale=0
     M = int(params["opacity_logit"].numel())
     dev = params["opacity_logit"].device
     sets = [params] + list(companions)
+    L = sh_degree(params)
+    K = SH_COEFFS[L]
     outs = [{k: torch.empty(GAUSS_ROWS[k], max(M, 1), dtype=torch.float32, device=dev) for k in GAUSS_KEYS}
             for _ in sets]
+    if L > 0:
+        for o in outs:
+            o["sh"] = torch.empty(3 * K, max(M, 1), dtype=torch.float32, device=dev)
     arr_in = (GaussiansS * len(sets))(*[gaussians_struct(s) for s in sets])
     arr_out = (GaussiansS * len(sets))()
     for i, o in enumerate(outs):
         arr_out[i].count = M
         for k in GAUSS_KEYS:
             setattr(arr_out[i], k, ctypes.c_void_p(o[k].data_ptr()))
+        arr_out[i].sh_degree = L
+        arr_out[i].sh = ctypes.c_void_p(o["sh"].data_ptr()) if L > 0 else None
     nbytes = ctypes.c_size_t(0)
     _check(lib().gps_removal_workspace_size(M, ctypes.byref(nbytes)), "gps_removal_workspace_size")
     ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
@@ -656,11 +797,14 @@ def remove_gaussians(params: dict, companions=(), min_opacity=0.005, max_scale=0
     n = int(count.item())
     shaped = [{k: o[k].reshape(-1)[:GAUSS_ROWS[k] * n].view(GAUSS_ROWS[k], n) if GAUSS_ROWS[k] > 1
                else o[k].reshape(-1)[:n] for k in GAUSS_KEYS} for o in outs]
+    if L > 0:
+        for sh_, o in zip(shaped, outs):
+            sh_["sh"] = o["sh"].reshape(-1)[:3 * K * n].view(3, K, n)
     return shaped[0], shaped[1:], n
 
 
 def insert_gaussians(cam, render_rgb, frame_rgb, weight, sdf_depth, rand, capacity=None, delta_c=0.05, delta_w=4.0,
-                     fraction=0.25, scale_cap=0.1, flat_ratio=0.1, opacity=0.5, stream=None):
+                     fraction=0.25, scale_cap=0.1, flat_ratio=0.1, opacity=0.5, sh_degree=0, stream=None):
     """Gaussian insertion of Eq. 6 and App. A (gps_insert_gaussians): the new Gaussians
     (planar [rows][n] tensors, row-major pixel order), their pixel indices and the
     number of sampled pixels n_taken (the output keeps min(n_taken, capacity));
@@ -670,11 +814,16 @@ def insert_gaussians(cam, render_rgb, frame_rgb, weight, sdf_depth, rand, capaci
     dev = frame_rgb.device
     cap = W * H if capacity is None else int(capacity)
     out = {k: torch.empty(GAUSS_ROWS[k], max(cap, 1), dtype=torch.float32, device=dev) for k in GAUSS_KEYS}
+    K = SH_COEFFS[int(sh_degree)]
+    if K:
+        out["sh"] = torch.empty(3 * K, max(cap, 1), dtype=torch.float32, device=dev)
     pix = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
     g = GaussiansS()
     g.count = cap
     for k in GAUSS_KEYS:
         setattr(g, k, ctypes.c_void_p(out[k].data_ptr()))
+    g.sh_degree = int(sh_degree)
+    g.sh = ctypes.c_void_p(out["sh"].data_ptr()) if K else None
     nbytes = ctypes.c_size_t(0)
     _check(lib().gps_insertion_workspace_size(W, H, ctypes.byref(nbytes)), "gps_insertion_workspace_size")
     ws = torch.empty(nbytes.value, dtype=torch.uint8, device=dev)
@@ -689,6 +838,8 @@ def insert_gaussians(cam, render_rgb, frame_rgb, weight, sdf_depth, rand, capaci
     n_taken = int(count.item())
     n = min(n_taken, cap)
     res = {k: out[k][:, :n] if GAUSS_ROWS[k] > 1 else out[k].reshape(-1)[:n] for k in GAUSS_KEYS}
+    if K:
+        res["sh"] = out["sh"][:, :n].reshape(3, K, n).contiguous()
     return res, pix[:n], n_taken
 
 

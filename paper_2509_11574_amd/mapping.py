@@ -11,12 +11,10 @@ import torch
 
 from . import gps
 
-KEYS = gps.GAUSS_KEYS
-
 
 class GaussianMap:
-    """Planar device tensors of the map's Gaussians and an Adam state over them.
-    New Gaussians start with zero moments; the step counter is shared."""
+    """Planar device tensors of the map's Gaussians (and SH bands, if any) and an Adam state
+    over them.  New Gaussians start with zero moments; the step counter is shared."""
 
     def __init__(self, params: dict, opt: gps.Adam | None = None):
         self.params = {k: v.contiguous() for k, v in params.items()}
@@ -28,24 +26,29 @@ class GaussianMap:
         return int(self.params["opacity_logit"].numel())
 
     def _set(self, params: dict, m: dict, v: dict):
-        for k in KEYS:
+        for k in gps.gauss_keys(self.params):
             self.params[k] = params[k].contiguous()
             self.opt.m[k] = m[k].contiguous()
             self.opt.v[k] = v[k].contiguous()
 
     def append(self, new: dict) -> int:
-        """Appends the Gaussians of `new` (planar [rows][n] tensors) after the existing ones."""
+        """Appends the Gaussians of `new` (planar tensors, the Gaussians along the last axis)
+        after the existing ones; the SH bands of new Gaussians start at zero when `new` has
+        none."""
         n = int(new["opacity_logit"].numel())
         if n == 0:
             return 0
-        cat = lambda a, b: torch.cat([a.reshape(gps.GAUSS_ROWS[k], -1), b.reshape(gps.GAUSS_ROWS[k], -1)], 1)
         p, m, v = {}, {}, {}
-        for k in KEYS:
-            shape = (-1,) if gps.GAUSS_ROWS[k] == 1 else (gps.GAUSS_ROWS[k], -1)
-            p[k] = cat(self.params[k], new[k].to(torch.float32)).reshape(shape)
-            z = torch.zeros_like(new[k], dtype=torch.float32)
-            m[k] = cat(self.opt.m[k], z).reshape(shape)
-            v[k] = cat(self.opt.v[k], z).reshape(shape)
+        for k in gps.gauss_keys(self.params):
+            old = self.params[k]
+            add = new.get(k)
+            if add is None:
+                add = torch.zeros(*old.shape[:-1], n, dtype=old.dtype, device=old.device)
+            add = add.to(torch.float32).reshape(*old.shape[:-1], n)
+            p[k] = torch.cat([old, add], dim=-1)
+            z = torch.zeros_like(add)
+            m[k] = torch.cat([self.opt.m[k], z], dim=-1)
+            v[k] = torch.cat([self.opt.v[k], z], dim=-1)
         self._set(p, m, v)
         return n
 
@@ -71,6 +74,7 @@ def insert_from_render(gmap: GaussianMap, cfg: gps.RenderCfg, view: gps.View, ra
         ws = gps.Workspace(cfg1, max(gmap.count, 1), [view.cam], device=dev)
     gps.render_fwd(cfg1, gmap.params, [view], ws)
     new, pix, n_taken = gps.insert_gaussians(view.cam, view.out_rgb, view.target_rgb, view.out_aux,
-                                             view.base_depth, rand, capacity=capacity)
+                                             view.base_depth, rand, capacity=capacity,
+                                             sh_degree=gps.sh_degree(gmap.params))
     gmap.append(new)
     return new, pix, n_taken

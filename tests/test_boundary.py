@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(P):
 
 def test_abi_version_and_status_strings(P):
     L = P.lib()
-    assert L.gps_abi_version() == 3
+    assert L.gps_abi_version() == 4
     assert L.gps_status_string(0) == b"ok"
     assert b"capacity" in L.gps_status_string(-3)
 
@@ -264,3 +264,39 @@ def test_fused_adam_argument_checks(P):
     bad = P.gps.AdamFusedS.from_buffer_copy(good)
     bad.m.count = 5                                        # moments of another size
     assert call(bad) == -1
+
+
+def test_hash_argument_checks(P):
+    """Voxel-block hash (Sec. 3.2.1): bad volumes and arguments are refused before any launch."""
+    L = P.lib()
+    from paper_2509_11574_amd.gps import HashVolumeS
+    buf = (ctypes.c_float * 64)()
+    p = ctypes.cast(buf, ctypes.c_void_p)
+
+    def vol(**kw):
+        s = HashVolumeS()
+        s.nx = s.ny = s.nz = 64
+        s.voxel, s.trunc, s.max_weight = 0.02, 0.08, 100.0
+        s.n_buckets, s.capacity = 1024, 256
+        for name in ("keys", "slots", "block_key", "state", "visible", "block_min", "tsdf", "weight", "rgb",
+                     "rgb_weight"):
+            setattr(s, name, p)
+        for k, v in kw.items():
+            setattr(s, k, v)
+        return s
+
+    cam = P.camera(_cam())
+    cams = (P.gps.Camera * 1)(cam)
+    ptrs = (ctypes.c_void_p * 1)(p.value)
+    for bad in (dict(n_buckets=1000), dict(n_buckets=1), dict(capacity=0), dict(voxel=0.0), dict(trunc=-1.0),
+                dict(nx=1), dict(keys=None), dict(tsdf=None), dict(state=None), dict(max_weight=0.5)):
+        v = vol(**bad)
+        assert L.gps_hash_reset(ctypes.byref(v), None) == -1, bad
+        assert L.gps_hash_fuse(ctypes.byref(v), ctypes.byref(cam), p, p, None) == -1, bad
+        assert L.gps_hash_raycast(ctypes.byref(v), cams, 1, ptrs, ptrs, 0.2, 0.0, None) == -1, bad
+    v = vol()
+    assert L.gps_hash_fuse(ctypes.byref(v), ctypes.byref(cam), None, p, None) == -1
+    assert L.gps_hash_fuse(ctypes.byref(v), None, p, p, None) == -1
+    assert L.gps_hash_raycast(ctypes.byref(v), cams, 0, ptrs, ptrs, 0.2, 0.0, None) == -1
+    assert L.gps_hash_raycast(ctypes.byref(v), cams, 1, ptrs, ptrs, -0.1, 0.0, None) == -1
+    assert L.gps_hash_raycast(ctypes.byref(v), cams, 1, None, ptrs, 0.2, 0.0, None) == -1
