@@ -41,3 +41,15 @@ def cfg_pair(P, O, mode=0, eps=0.02, tile=(16, 16, 256, 1), **kw):
 
 def gauss_dev(g):
     return {k: t(v) for k, v in g.items()}
+
+
+def report_flags(tag, keep, got, want, tol=1e-3):
+    """Prints how many pixels the reference flagged (a 1/255, cap or transmittance decision
+    within rounding reach) and, of those, how many the GPU decided the other way (its value
+    differs from the reference's beyond tol): the flip count of the comparison."""
+    got = np.asarray(got, np.float64).reshape(-1, keep.size)
+    want = np.asarray(want, np.float64).reshape(-1, keep.size)
+    differ = np.abs(got - want).max(axis=0) > tol * max(1.0, float(np.abs(want).max()))
+    flips = int((differ & ~keep).sum())
+    say(f"  {tag}: {int((~keep).sum())} of {keep.size} pixels flagged, {flips} flipped")
+    return flips

@@ -21,7 +21,7 @@ import pytest
 import torch
 
 import synth
-from tests.gpu_util import DEV, cfg_pair, gauss_dev, h, normwise, say, t
+from tests.gpu_util import DEV, cfg_pair, gauss_dev, h, normwise, report_flags, say, t
 
 pytestmark = pytest.mark.gpu
 KEYS = ("mean", "log_scale", "quat", "opacity_logit", "rgb")
@@ -213,6 +213,7 @@ def test_large_map_iteration_512_1m(P, O):
         D = h(v.out_depth).reshape(-1)
         assert normwise(C[:, pix], r["rgb"], keep) < 1e-4
         assert normwise(D[pix], r["depth"], keep) < 1e-4
+        report_flags("large map view", keep, C[:, pix], r["rgb"])
         gC = np.zeros((3, 1280 * 720), np.float32)
         gD = np.zeros(1280 * 720, np.float32)
         ps = pix[keep]

@@ -13,7 +13,7 @@ import pytest
 import torch
 
 import synth
-from tests.gpu_util import DEV, cfg_pair, gauss_dev, h, normwise, say, t
+from tests.gpu_util import DEV, cfg_pair, gauss_dev, h, normwise, report_flags, say, t
 
 pytestmark = pytest.mark.gpu
 KEYS = ("mean", "log_scale", "quat", "opacity_logit", "rgb")
@@ -107,6 +107,7 @@ def test_room_render_sampled(P, O, room, tile):
     D = h(view.out_depth).reshape(-1)
     assert normwise(C[:, pix], r["rgb"], keep) < 1e-4
     assert normwise(D[pix], r["depth"], keep) < 1e-4
+    report_flags("room 1280x720 sampled pixels", keep, C[:, pix], r["rgb"])
     # the fused loss equals the L1 of the output images (a property at any size)
     om = (d1.reshape(-1) > 0) & (base_depth.reshape(-1) > 0)
     L = np.abs(C.astype(np.float64) - c1.reshape(3, -1)).mean() + \

@@ -14,7 +14,7 @@ import pytest
 import torch
 
 import synth
-from tests.gpu_util import DEV, cfg_pair, gauss_dev, h, normwise, say, t
+from tests.gpu_util import DEV, cfg_pair, gauss_dev, h, normwise, report_flags, say, t
 from tests.tiny_cases import tiny_case
 
 pytestmark = pytest.mark.gpu
@@ -192,6 +192,7 @@ def test_render_fwd_parity_small_scene(P, O, small, mode):
     keep = r["flag"] == 0
     C, D = h(views[0].out_rgb).reshape(3, -1), h(views[0].out_depth).reshape(-1)
     assert normwise(C, r["rgb"], keep) < 1e-4 and normwise(D, r["depth"], keep) < 1e-4
+    report_flags(f"small scene mode {mode}", keep, C, r["rgb"])
     L, _, _, om = O.loss(oc, 160, 120, r["rgb"], r["depth"], small["rgb"], small["depth"],
                          vn["base_depth"].astype(np.float32), want_grad=False)
     assert abs(loss.item() - L) <= 1e-4 * abs(L)
