@@ -422,17 +422,20 @@ def _window_views(P, synth, scene, vol, cams, frames, dev, cfg):
 
 def bench_modes(P, cfg, params, view, M, cam0, reps=40):
     """Forward pass (binning, sort, compositing, fused loss) and backward pass (compositing
-    backward, per-Gaussian reduce, pose) of one room view, timed with HIP events, in the
-    sorted mode and in the sort-free blend of Eq. 1-4 (mode 1).  Mode 1 runs the same
-    binning and tile sort: the sort fixes the summation order, which keeps its results
-    bitwise reproducible.  The third line is the sort-free mode with the per-Gaussian
-    backward over pixel chunks.  Median of `reps` calls each."""
+    backward, per-Gaussian reduce, pose) of one room view, timed with HIP events: the
+    sorted over-compositing (mode 0); the sort-free blend of Eq. 1-4 without any depth
+    sort (mode 1 with no_sort: the paper's renderer, its lists in emission order), with
+    the tile backward and with the per-Gaussian backward over pixel chunks (App. B); and
+    the sort-free blend with the lists sorted (bitwise reproducible).  Median of `reps`
+    calls each."""
     import statistics
     from dataclasses import replace
     import torch
     out = {}
-    for mode, name, pg in ((0, "sorted", False), (1, "sort_free", False), (1, "sort_free_per_gaussian_bwd", True)):
-        c = replace(cfg, mode=mode, bwd_per_gaussian=pg)
+    for mode, name, pg, ns in ((0, "sorted", False, False), (1, "sort_free", False, True),
+                               (1, "sort_free_per_gaussian_bwd", True, True),
+                               (1, "sort_free_sorted_lists", False, False)):
+        c = replace(cfg, mode=mode, bwd_per_gaussian=pg, no_sort=ns)
         ws = P.Workspace(c, M, [cam0], device=view.base_depth.device)
         grads = P.zeros_like_gaussians(params)
         dpose = torch.zeros(1, 6, device=view.base_depth.device)

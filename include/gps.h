@@ -30,7 +30,8 @@
  *    sequence of kernels with identical arguments and never reads device data
  *    on the host, so it may be captured in a HIP graph and replayed.
  *  - Every entry point is deterministic: the same inputs give bitwise the same
- *    outputs (no floating-point atomics anywhere).
+ *    outputs (no floating-point atomics anywhere), except a render with
+ *    GPS_RENDER_NO_SORT, whose summation order follows the binning's atomics.
  *  - Calls that share a workspace must not run concurrently.
  */
 #ifndef GPS_H_
@@ -143,7 +144,8 @@ typedef struct gps_render_cfg {
     float z_near;            /* centres nearer than this are culled (0.2 m)        */
     int64_t max_instances;   /* capacity for (view, tile, Gaussian) slots;
                                 0 = 32 per view-Gaussian, at least 2^20            */
-    int32_t flags;           /* GPS_RENDER_VIEWS_PRESET or 0                       */
+    int32_t flags;           /* GPS_RENDER_VIEWS_PRESET, GPS_RENDER_BWD_PER_GAUSSIAN,
+                                GPS_RENDER_NO_SORT (or-ed), or 0                   */
 } gps_render_cfg;
 
 /* The render kernels read the view table (cameras and image pointers) from the
@@ -164,6 +166,17 @@ typedef struct gps_render_cfg {
  * per-Gaussian backward of Sec. 3.1 and Appendix B), instead of reducing per
  * tile.  Same results up to rounding; GPS_ERR_UNSUPPORTED_CONFIG in mode 0. */
 #define GPS_RENDER_BWD_PER_GAUSSIAN 2
+
+/* Sort-free mode (mode 1) only: no per-tile depth sort at all (Sec. 3.1: the
+ * blend of Eq. 1, 2, 4 is independent of order).  Each tile's list is taken in
+ * the order the binning emitted it, every record of the list is visited (no list
+ * is cut short by the depth order), and the long-list sort is not launched.  The
+ * emission order comes from atomic counters, so the order of the floating-point
+ * sums -- and the last bits of C*, D* and W_G -- may differ between calls (the
+ * only exception to the determinism of the other entry points); the gradients
+ * differ from call to call only through those bits.  GPS_ERR_UNSUPPORTED_CONFIG
+ * in mode 0. */
+#define GPS_RENDER_NO_SORT 4
 
 /* One Adam parameter group. */
 typedef struct gps_adam_group {

@@ -51,7 +51,9 @@ static gps_status compute_layout(const gps_render_cfg* cfg, int M, const gps_cam
     if (cfg->mode != 0 && cfg->mode != 1) return GPS_ERR_INVALID_ARG;
     if (!tile_config_supported(cfg)) return GPS_ERR_UNSUPPORTED_CONFIG;
     if (cfg->max_instances < 0) return GPS_ERR_INVALID_ARG;
-    if (cfg->flags & ~(GPS_RENDER_VIEWS_PRESET | GPS_RENDER_BWD_PER_GAUSSIAN)) return GPS_ERR_INVALID_ARG;
+    if (cfg->flags & ~(GPS_RENDER_VIEWS_PRESET | GPS_RENDER_BWD_PER_GAUSSIAN | GPS_RENDER_NO_SORT))
+        return GPS_ERR_INVALID_ARG;
+    if ((cfg->flags & GPS_RENDER_NO_SORT) && cfg->mode != 1) return GPS_ERR_UNSUPPORTED_CONFIG;
     const float consts[7] = {cfg->eps_cull, cfg->lambda_depth, cfg->dilation, cfg->alpha_min,
                              cfg->alpha_max, cfg->T_min, cfg->z_near};
     for (float c : consts)
@@ -181,7 +183,7 @@ static gps_status build_tables(const gps_render_cfg* cfg, const gps_gaussians* g
     rp->amax = cfg->alpha_max;
     rp->Tmin = cfg->T_min;
     rp->znear = cfg->z_near;
-    rp->mode = cfg->mode;
+    rp->mode = (cfg->mode == 1 && (cfg->flags & GPS_RENDER_NO_SORT)) ? 2 : cfg->mode;  // 2: sort-free, unsorted
     rp->M = g->count;
     rp->V = V;
     rp->nvg = L->nvg;

@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
             cs1 = V.out_rgb[HW + p];
             cs2 = V.out_rgb[2 * HW + p];
             ds = V.out_depth[p];
-            if (MODE == 1) invW[k] = 1.0f / (1.0f + w.pix_aux[(size_t)V.pix_base + p]);
+            if (MODE != 0) invW[k] = 1.0f / (1.0f + w.pix_aux[(size_t)V.pix_base + p]);
             if (explicit_up) {
                 G0[k] = V.g_rgb[p];
                 G1[k] = V.g_rgb[HW + p];
@@ -222,7 +222,8 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                     wave_rows_sum10_store(g, slab + jw * kRecStride + wid * 4 * kAdj, lane);
                     written |= 1ull << jw;
                 }
-                if (!any_live) {  // this record and all deeper ones fail every pixel
+                if (MODE != 2 && !any_live) {  // this record and all deeper ones fail every pixel
+                                               // (an unsorted list, MODE 2, goes on)
                     wave_alive = false;
                     break;
                 }
@@ -262,7 +263,8 @@ static void launch_cbwd(const ViewTable* vt, const RParams& rp, const WsPtrs& w,
                         const float* loss_scale, hipStream_t s)
 {
     if (rp.mode == 0) launch_cbwd_mode<TW, TH, B, PPT, 0>(vt, rp, w, n_tiles, explicit_up, loss_scale, s);
-    else launch_cbwd_mode<TW, TH, B, PPT, 1>(vt, rp, w, n_tiles, explicit_up, loss_scale, s);
+    else if (rp.mode == 1) launch_cbwd_mode<TW, TH, B, PPT, 1>(vt, rp, w, n_tiles, explicit_up, loss_scale, s);
+    else launch_cbwd_mode<TW, TH, B, PPT, 2>(vt, rp, w, n_tiles, explicit_up, loss_scale, s);
 }
 
 bool dispatch_cbwd(const gps_render_cfg* cfg, const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles,

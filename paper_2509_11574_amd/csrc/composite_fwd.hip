@@ -93,8 +93,9 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
     const unsigned int s = w.tile_start[tile], e = w.tile_start[tile + 1];
     // Depth order: lists shorter than kLongTile are sorted here, in registers of
     // the first wavefront (the longer ones by k_tile_sort_large before this
-    // kernel); the barrier publishes the sorted keys to the block.
-    if (e - s > 1u && e - s < kLongTile) {
+    // kernel); the barrier publishes the sorted keys to the block.  MODE 2 (the
+    // sort-free blend without the sort) takes the list in emission order.
+    if (MODE != 2 && e - s > 1u && e - s < kLongTile) {
         if (wid == 0) wave_sort_tile(w.keys + s, (int)(e - s), lane);
         __syncthreads();
     }
@@ -152,8 +153,8 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
                                          n_eval, n_contrib, live_b);
                 }
                 // A record that no lane passes ends the wavefront's list: every later
-                // record is deeper.
-                if (!live_a || (hb && !live_b)) {
+                // record is deeper (not so in an unsorted list, MODE 2).
+                if (MODE != 2 && (!live_a || (hb && !live_b))) {
                     wave_alive = false;
                     break;
                 }
@@ -246,7 +247,8 @@ template <int TW, int TH, int B, int PPT>
 static void launch_cfwd(const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles, hipStream_t s)
 {
     if (rp.mode == 0) launch_cfwd_mode<TW, TH, B, PPT, 0>(vt, rp, w, n_tiles, s);
-    else launch_cfwd_mode<TW, TH, B, PPT, 1>(vt, rp, w, n_tiles, s);
+    else if (rp.mode == 1) launch_cfwd_mode<TW, TH, B, PPT, 1>(vt, rp, w, n_tiles, s);
+    else launch_cfwd_mode<TW, TH, B, PPT, 2>(vt, rp, w, n_tiles, s);
 }
 
 bool dispatch_cfwd(const gps_render_cfg* cfg, const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles,

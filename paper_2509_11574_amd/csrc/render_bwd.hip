@@ -620,7 +620,7 @@ gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const
         if (st != GPS_OK) return st;
     }
     if (cfg->flags & GPS_RENDER_BWD_PER_GAUSSIAN) {
-        if (rp.mode != 1) return GPS_ERR_UNSUPPORTED_CONFIG;
+        if (rp.mode == 0) return GPS_ERR_UNSUPPORTED_CONFIG;
         int npix = 0;
         for (int v = 0; v < vt.n; ++v) npix += vt.v[v].cam.W * vt.v[v].cam.H;
         if (npix > 0)

@@ -648,8 +648,9 @@ gps_status launch_render_fwd(const gps_render_cfg* cfg, const RParams& rp, const
     GPS_LAUNCH(K_SCAN_TILES, s, k_scan_tiles, dim3(1), dim3(1024), 0, s, rp, w, L.n_tiles);
     if (L.nblk_vg > 0)
         GPS_LAUNCH(K_EMIT, s, k_expand<true>, dim3(L.nblk_vg * (kBlk / kExpG)), dim3(kBlk), 0, s, dvt, rp, w);
-    GPS_LAUNCH(K_TILE_SORT_LARGE, s, k_tile_sort_large, dim3(L.n_tiles), dim3(256), kSortCap * sizeof(unsigned long long),
-               s, rp, w);
+    if (rp.mode != 2)  // the unsorted sort-free blend keeps the emission order
+        GPS_LAUNCH(K_TILE_SORT_LARGE, s, k_tile_sort_large, dim3(L.n_tiles), dim3(256),
+                   kSortCap * sizeof(unsigned long long), s, rp, w);
     if (!dispatch_cfwd(cfg, dvt, rp, w, L.n_tiles, s)) return GPS_ERR_UNSUPPORTED_CONFIG;
     GPS_LAUNCH(K_LOSS_REDUCE, s, k_loss_reduce, dim3(1), dim3(1024), 0, s, dvt, rp, w, out_loss, has_loss);
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;

@@ -321,12 +321,14 @@ class RenderCfg:
     max_instances: int = 0
     views_preset: bool = False  # read the view table uploaded by views_upload (for graph replay)
     bwd_per_gaussian: bool = False  # sort-free mode: per-Gaussian backward over pixel chunks (Appendix B)
+    no_sort: bool = False  # sort-free mode: no per-tile depth sort (lists in emission order)
 
     def struct(self) -> RenderCfgS:
         return RenderCfgS(self.tile_w, self.tile_h, self.batch, self.pix_per_thread, self.mode, self.eps_cull,
                           self.lambda_depth, self.dilation, self.alpha_min, self.alpha_max, self.T_min,
                           self.z_near, int(self.max_instances),
-                          (1 if self.views_preset else 0) | (2 if self.bwd_per_gaussian else 0))
+                          (1 if self.views_preset else 0) | (2 if self.bwd_per_gaussian else 0) |
+                          (4 if self.no_sort else 0))
 
 
 # Tile / batch / pixels-per-lane combinations compiled into libgps.

@@ -32,7 +32,7 @@ def normwise(a, b, mask=None):
 
 
 def cfg_pair(P, O, mode=0, eps=0.02, tile=(16, 16, 256, 1), **kw):
-    gpu_only = {k: kw.pop(k) for k in ("max_instances",) if k in kw}
+    gpu_only = {k: kw.pop(k) for k in ("max_instances", "no_sort", "bwd_per_gaussian", "views_preset") if k in kw}
     gc = P.RenderCfg(tile_w=tile[0], tile_h=tile[1], batch=tile[2], pix_per_thread=tile[3], mode=mode,
                      eps_cull=eps, **kw, **gpu_only)
     oc = O.RenderCfg(mode=mode, eps_cull=eps, **kw)
