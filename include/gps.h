@@ -161,10 +161,15 @@ typedef struct gps_render_cfg {
 #define GPS_RENDER_VIEWS_PRESET 1
 
 /* Sort-free mode (mode 1) only: gps_render_bwd forms each view-Gaussian's
- * screen-space adjoints by walking the pixels of its support box itself, in
- * chunks of a fixed number of pixels spread over the lanes of a block (the
- * per-Gaussian backward of Sec. 3.1 and Appendix B), instead of reducing per
- * tile.  Same results up to rounding; GPS_ERR_UNSUPPORTED_CONFIG in mode 0. */
+ * screen-space adjoints the way Sec. 3.1 and Appendix B organise the backward of
+ * the sort-free blend: per Gaussian, summed in-thread over the pixels of its
+ * support box (one block per screen tile holds the tile's per-pixel adjoint state
+ * in LDS; its wavefronts take the tile's Gaussians one at a time, their lanes
+ * sweeping the Gaussian's box 64 pixels at a time; one wave reduction per
+ * Gaussian and tile), with no ordering and no atomics; instead of the tile
+ * backward's per-pixel-group reductions.  Same results up to rounding;
+ * GPS_ERR_UNSUPPORTED_CONFIG in mode 0 or for tiles other than 8x8, 16x16 and
+ * 16x32. */
 #define GPS_RENDER_BWD_PER_GAUSSIAN 2
 
 /* Sort-free mode (mode 1) only: no per-tile depth sort at all (Sec. 3.1: the

@@ -99,8 +99,6 @@ static gps_status compute_layout(const gps_render_cfg* cfg, int M, const gps_cam
     o = align_up(o + 8 * (size_t)n_tiles);
     L->pix_aux = o;
     o = align_up(o + 4 * (size_t)npix);
-    L->pix_grad = o;
-    o = align_up(o + 32 * (size_t)npix);
     L->rec = o;
     o = align_up(o + 4 * kRecFloats * (size_t)nvg);
     L->cnt = o;

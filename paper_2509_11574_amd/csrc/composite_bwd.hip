@@ -249,6 +249,170 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     }
 }
 
+// ------------------------------------------- per-Gaussian backward (sort-free)
+// The backward of the sort-free blend (Eq. 1, 2, 4) as Appendix B organises it:
+// each Gaussian accumulates its own adjoints in-thread over the pixels it covers,
+// with no atomics.  The blend's adjoints are independent per (pixel, Gaussian)
+// (they need only the pixel's C*, D*, W_G and upstream adjoint), so the pixels are
+// grouped by screen tile: one block per tile stages the tile's per-pixel state in
+// LDS once, then each wavefront takes the tile's Gaussians one at a time and its
+// lanes sweep the Gaussian's support rectangle inside the tile 64 pixels at a
+// time, summing in registers; one wave reduction per (Gaussian, tile) gives the
+// instance partial, written into its slot.  Nothing per pixel is re-read from
+// memory for every Gaussian.
+template <int TW, int TH>
+__global__ void __launch_bounds__(256) k_composite_bwd_pg(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w,
+                                                         int explicit_up, const float* loss_scale)
+{
+    constexpr int NP = TW * TH;
+    const ViewTable& vt = *vtp;
+    static_assert(TW <= 64, "a step of 64 lanes covers at least one box row");
+    __shared__ float4 s_g[NP];  // (dL/dC*, dL/dD*) / (1 + W_G)
+    __shared__ float2 s_x[NP];  // G.(C*, D*) / (1 + W_G), D_t + eps (-inf outside the image)
+    __shared__ float s_red[4][4 * kAdj];  // per wavefront: the ten row totals of its four rows
+    if (w.hdr->n_inst > rp.cap) return;
+    const int tile = (int)w.tile_queue[blockIdx.x];
+    const int v = find_view(vt, tile);
+    const DevView& V = vt.v[v];
+    const int lt = tile - V.tile_base;
+    const int tx = lt % V.tiles_x, ty = lt / V.tiles_x;
+    const int Wd = V.cam.W, Ht = V.cam.H;
+    const size_t HW = (size_t)Wd * Ht;
+    const int tx0 = tx * TW, ty0 = ty * TH;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    {
+        float sc = 1.0f;
+        if (!explicit_up && loss_scale) sc = *loss_scale;
+        const float invV = 1.0f / (float)rp.V;
+        const float om = w.hdr->view_stats[v][2];
+        for (int i = threadIdx.x; i < NP; i += 256) {
+            const int px = tx0 + i % TW, py = ty0 + i / TW;
+            float4 g = make_float4(0.f, 0.f, 0.f, 0.f);
+            float2 x = make_float2(0.f, -INFINITY);
+            if (px < Wd && py < Ht) {
+                const size_t p = (size_t)py * Wd + px;
+                const float dt = V.base_depth[p];
+                const bool dvalid = dt > 0.0f;
+                const float cs0 = V.out_rgb[p], cs1 = V.out_rgb[HW + p], cs2 = V.out_rgb[2 * HW + p];
+                const float ds = V.out_depth[p];
+                float G0, G1, G2, GD = 0.0f;
+                if (explicit_up) {
+                    G0 = V.g_rgb[p];
+                    G1 = V.g_rgb[HW + p];
+                    G2 = V.g_rgb[2 * HW + p];
+                    GD = (V.g_depth && dvalid) ? V.g_depth[p] : 0.0f;
+                } else {
+                    const float cn = sc * invV / (3.0f * (float)HW);
+                    G0 = cn * sgnf(cs0 - V.target_rgb[p]);
+                    G1 = cn * sgnf(cs1 - V.target_rgb[HW + p]);
+                    G2 = cn * sgnf(cs2 - V.target_rgb[2 * HW + p]);
+                    if (V.target_depth && dvalid && om > 0.0f) {
+                        const float dobs = V.target_depth[p];
+                        if (dobs > 0.0f) GD = sc * invV * rp.lambda / om * sgnf(ds - dobs);
+                    }
+                }
+                const float invW = 1.0f / (1.0f + w.pix_aux[(size_t)V.pix_base + p]);
+                const float CG = G0 * cs0 + G1 * cs1 + G2 * cs2 + GD * ds;
+                g = make_float4(G0 * invW, G1 * invW, G2 * invW, GD * invW);
+                x = make_float2(CG * invW, (dvalid ? dt : INFINITY) + rp.eps);
+            }
+            s_g[i] = g;
+            s_x[i] = x;
+        }
+    }
+    __syncthreads();
+    const unsigned int s = w.tile_start[tile], e = w.tile_start[tile + 1];
+    for (unsigned int j = s + (unsigned int)wid; j < e; j += 4u) {
+        unsigned int vg = (unsigned int)w.keys[j];
+        if (vg >= (unsigned int)rp.nvg) vg = 0u;  // guard: never read outside the records
+        const float4* r = w.rec + 3 * (size_t)vg;
+        const float4 r0 = r[0], r1 = r[1], r2 = r[2];
+        const float zi = r1.z, c0 = r1.w, c1 = r2.x, c2 = r2.y;
+        // the record's support box (padded, it holds every pixel with alpha >= alpha_min)
+        // inside this tile and the image
+        const int x0 = max(max((int)ceilf(r0.x - r2.z), tx0), 0);
+        const int x1 = min(min((int)floorf(r0.x + r2.z), tx0 + TW - 1), Wd - 1);
+        const int y0 = max(max((int)ceilf(r0.y - r2.w), ty0), 0);
+        const int y1 = min(min((int)floorf(r0.y + r2.w), ty0 + TH - 1), Ht - 1);
+        float g[kAdj];
+#pragma unroll
+        for (int q = 0; q < kAdj; ++q) g[q] = 0.0f;
+        if (x0 <= x1 && y0 <= y1) {
+            const int bw = x1 - x0 + 1, bh = y1 - y0 + 1;
+            const int dr = 64 / bw, dc = 64 - dr * bw;  // a step of 64 pixels in rows and columns
+            int row = lane / bw, col = lane - (lane / bw) * bw;
+            while (row < bh) {
+                const int px = x0 + col, py = y0 + row;
+                const int li = (py - ty0) * TW + (px - tx0);
+                const float4 G = s_g[li];
+                const float2 X = s_x[li];
+                const AlphaEval ae = eval_alpha((float)px, (float)py, r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
+                const bool use = zi < X.y && ae.raw >= rp.amin;  // depth test (Eq. 1-2), alpha_min
+                const float a = use ? ae.raw : 0.0f;
+                const float direct = G.x * c0 + G.y * c1 + G.z * c2 + G.w * zi;
+                const float u = a * (direct - X.x);  // alpha dL/dalpha
+                g[0] = __builtin_fmaf(u, ae.dx, g[0]);
+                g[1] = __builtin_fmaf(u, ae.dy, g[1]);
+                g[2] = __builtin_fmaf(u, ae.dxx, g[2]);
+                g[3] = __builtin_fmaf(u, ae.dxy, g[3]);
+                g[4] = __builtin_fmaf(u, ae.dyy, g[4]);
+                g[5] += u;
+                g[6] = __builtin_fmaf(a, G.x, g[6]);  // dC*/dc_i = alpha / (1 + W_G)
+                g[7] = __builtin_fmaf(a, G.y, g[7]);
+                g[8] = __builtin_fmaf(a, G.z, g[8]);
+                g[9] = __builtin_fmaf(a, G.w, g[9]);
+                row += dr;
+                col += dc;
+                if (col >= bw) {
+                    col -= bw;
+                    ++row;
+                }
+            }
+        }
+        // The ten sums over the wavefront: a DPP transpose-reduction within each 16-lane row,
+        // then lane q adds the four row totals of component q in a fixed order.  The LDS
+        // words are this wavefront's own; the fences order its stores and loads.
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        wave_rows_sum10_store(g, s_red[wid], lane);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        float mine = 0.0f;  // lane q keeps component q
+        if (lane < kAdj)
+            mine = (s_red[wid][lane] + s_red[wid][kAdj + lane]) + (s_red[wid][2 * kAdj + lane] + s_red[wid][3 * kAdj + lane]);
+        // the instance's slot: its view-Gaussian's first slot plus this tile's place in
+        // the tile rectangle (the rectangle the expansion walked)
+        TileRect rr;
+        if (lane < kAdj && rect_of(r0.x, r0.y, r2.z, r2.w, Wd, Ht, rp.tile_w, rp.tile_h, &rr)) {
+            const unsigned int slot =
+                w.off[vg] + (unsigned int)((ty - rr.ty0) * (rr.tx1 - rr.tx0 + 1) + (tx - rr.tx0));
+            if (slot < rp.cap) w.partial[(size_t)slot * kAdj + lane] = mine;
+        }
+    }
+}
+
+template <int TW, int TH>
+static void launch_cbwd_pg(const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles, int explicit_up,
+                           const float* loss_scale, hipStream_t s)
+{
+    GPS_LAUNCH(K_COMPOSITE_BWD, s, (k_composite_bwd_pg<TW, TH>), dim3(n_tiles), dim3(256), 0, s, vt, rp, w,
+               explicit_up, loss_scale);
+}
+
+// The per-Gaussian backward of the sort-free blend (GPS_RENDER_BWD_PER_GAUSSIAN).
+bool dispatch_cbwd_pg(const gps_render_cfg* cfg, const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles,
+                      int explicit_up, const float* loss_scale, hipStream_t s)
+{
+    if (cfg->tile_w == 8 && cfg->tile_h == 8) launch_cbwd_pg<8, 8>(vt, rp, w, n_tiles, explicit_up, loss_scale, s);
+    else if (cfg->tile_w == 16 && cfg->tile_h == 16)
+        launch_cbwd_pg<16, 16>(vt, rp, w, n_tiles, explicit_up, loss_scale, s);
+    else if (cfg->tile_w == 16 && cfg->tile_h == 32)
+        launch_cbwd_pg<16, 32>(vt, rp, w, n_tiles, explicit_up, loss_scale, s);
+    else return false;
+    return true;
+}
+
 // ----------------------------------------------------------------- launch
 template <int TW, int TH, int B, int PPT, int MODE>
 static void launch_cbwd_mode(const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles, int explicit_up,

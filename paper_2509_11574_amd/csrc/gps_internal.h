@@ -95,7 +95,7 @@ struct WsHeader {
 
 struct WsLayout {
     size_t total;
-    size_t hdr, vtab, tilemax, tile_cnt, tile_start, tile_queue, tile_loss, tile_pairs, pix_aux, pix_grad, rec, cnt, off,
+    size_t hdr, vtab, tilemax, tile_cnt, tile_start, tile_queue, tile_loss, tile_pairs, pix_aux, rec, cnt, off,
         blk_sum, blk_off,
         keys, inst_vg, partial, pose_part;
     int n_tiles, nvg, nblk_vg, nblk_g;
@@ -112,7 +112,6 @@ struct WsPtrs {
     float4* tile_loss;          // per tile: colour L1 sum, depth L1 sum, |Omega| count, 0
     uint2* tile_pairs;          // per tile: evaluated and composited (pixel, instance) pairs
     float* pix_aux;             // per pixel: T_final (sorted) or W_G (sort-free)
-    float4* pix_grad;           // per pixel, two float4 (per-Gaussian sort-free backward): (dL/dC*, dL/dD*), (G.(C*,D*), 1/(1+W_G), D_t + eps, 0)
     float4* rec;                // 3 float4 per view-Gaussian
     unsigned int* cnt;
     unsigned int* off;
@@ -135,7 +134,6 @@ inline WsPtrs ws_ptrs(char* ws, const WsLayout& L)
     p.tile_loss = reinterpret_cast<float4*>(ws + L.tile_loss);
     p.tile_pairs = reinterpret_cast<uint2*>(ws + L.tile_pairs);
     p.pix_aux = reinterpret_cast<float*>(ws + L.pix_aux);
-    p.pix_grad = reinterpret_cast<float4*>(ws + L.pix_grad);
     p.rec = reinterpret_cast<float4*>(ws + L.rec);
     p.cnt = reinterpret_cast<unsigned int*>(ws + L.cnt);
     p.off = reinterpret_cast<unsigned int*>(ws + L.off);

@@ -24,6 +24,8 @@ bool dispatch_cfwd(const gps_render_cfg* cfg, const ViewTable* vt, const RParams
                    hipStream_t s);
 bool dispatch_cbwd(const gps_render_cfg* cfg, const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles,
                    int explicit_up, const float* loss_scale, hipStream_t s);
+bool dispatch_cbwd_pg(const gps_render_cfg* cfg, const ViewTable* vt, const RParams& rp, const WsPtrs& w, int n_tiles,
+                      int explicit_up, const float* loss_scale, hipStream_t s);
 gps_status launch_views_upload(const ViewTable& vt, const RParams& rp, const WsLayout& L, char* ws, int with_tilemax,
                                hipStream_t s);
 gps_status launch_adam(const gps_adam_group* groups, int n_groups, int step, int* step_counter, float b1, float b2,

@@ -6,6 +6,8 @@
 //       range per view, summed in order), apply the EWA chain rule to the
 //       parameters and form the per-Gaussian pose terms, reduced per block.
 //   k_pose_reduce per view: sum the block pose partials in order.
+//   The per-Gaussian backward of the sort-free blend (GPS_RENDER_BWD_PER_GAUSSIAN)
+//   replaces k_composite_bwd by k_composite_bwd_pg (composite_bwd.hip).
 //   With Adam in the epilogue (gps_render_bwd_adam), k_gauss_bwd also applies
 //   the Adam step to its Gaussian and k_pose_reduce advances the step counter.
 // No floating-point atomics: results are bitwise reproducible.
@@ -428,156 +430,6 @@ __global__ void __launch_bounds__(256) k_pose_reduce(const ViewTable* __restrict
     }
 }
 
-// ------------------------------------- per-Gaussian sort-free backward
-// The sort-free blend (Eq. 4) gives each pixel C* = (C_t + sum_i alpha_i c_i) /
-// (1 + W_G), W_G = sum_i alpha_i, and likewise D*; its adjoints are independent
-// per (pixel, Gaussian): dL/dc_i = alpha_i G / (1 + W_G) and dL/dalpha_i =
-// (G.(c_i, d_i) - G.(C*, D*)) / (1 + W_G), with G = (dL/dC*, dL/dD*).  So each
-// Gaussian can sum its own gradients over the pixels of its support box, with
-// no ordering and no atomics (Sec. 3.1 and Appendix B: the work is cut into
-// chunks of a fixed number of pixels so that large and small Gaussians load
-// the lanes evenly).
-
-__device__ __forceinline__ float sign_of(float x) { return (float)((x > 0.0f) - (x < 0.0f)); }
-
-// Per pixel of every view: G, G.(C*, D*), 1/(1 + W_G) and the depth-test
-// threshold, the same values the tile backward forms in its prologue.
-__global__ void __launch_bounds__(256) k_pixgrad(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w, int npix,
-                                                 int explicit_up, const float* loss_scale)
-{
-    const ViewTable& vt = *vtp;
-    const int q = blockIdx.x * 256 + threadIdx.x;
-    if (q >= npix) return;
-    int v = 0;
-#pragma unroll 1
-    for (int k = 1; k < vt.n; ++k)
-        if (q >= vt.v[k].pix_base) v = k;
-    const DevView& V = vt.v[v];
-    const size_t HW = (size_t)V.cam.W * V.cam.H;
-    const size_t p = (size_t)(q - V.pix_base);
-    float sc = 1.0f;
-    if (!explicit_up && loss_scale) sc = *loss_scale;
-    const float invV = 1.0f / (float)rp.V;
-    const float om = w.hdr->view_stats[v][2];
-    const float dt = V.base_depth[p];
-    const bool dvalid = dt > 0.0f;
-    const float cs0 = V.out_rgb[p], cs1 = V.out_rgb[HW + p], cs2 = V.out_rgb[2 * HW + p], ds = V.out_depth[p];
-    float G0, G1, G2, GD = 0.0f;
-    if (explicit_up) {
-        G0 = V.g_rgb[p];
-        G1 = V.g_rgb[HW + p];
-        G2 = V.g_rgb[2 * HW + p];
-        GD = (V.g_depth && dvalid) ? V.g_depth[p] : 0.0f;
-    } else {
-        const float cn = sc * invV / (3.0f * (float)HW);
-        G0 = cn * sign_of(cs0 - V.target_rgb[p]);
-        G1 = cn * sign_of(cs1 - V.target_rgb[HW + p]);
-        G2 = cn * sign_of(cs2 - V.target_rgb[2 * HW + p]);
-        if (V.target_depth && dvalid && om > 0.0f) {
-            const float dobs = V.target_depth[p];
-            if (dobs > 0.0f) GD = sc * invV * rp.lambda / om * sign_of(ds - dobs);
-        }
-    }
-    const float CG = G0 * cs0 + G1 * cs1 + G2 * cs2 + GD * ds;
-    const float invW = 1.0f / (1.0f + w.pix_aux[q]);
-    w.pix_grad[2 * (size_t)q] = make_float4(G0, G1, G2, GD);
-    w.pix_grad[2 * (size_t)q + 1] = make_float4(CG, invW, (dvalid ? dt : INFINITY) + rp.eps, 0.0f);
-}
-
-// Blocks of kPgG view-Gaussians (a share of a projection block), one
-// wavefront per Gaussian at a time: the pixels of its support box are taken 64
-// at a time, a lane each (consecutive pixels of a box row are consecutive
-// lanes, so the per-pixel loads coalesce), so every Gaussian costs a number of
-// wavefront steps proportional to its pixel count (the fixed-size work groups
-// of Appendix B).  Each lane sums its pixels in order, then ten wave sums in a
-// fixed order give the Gaussian's adjoints, written into its first instance
-// slot; its other slots are cleared (they may hold a tile backward's partials
-// of the same forward), so the per-Gaussian reduce takes the whole sum.
-constexpr int kPgG = 16;
-
-__global__ void __launch_bounds__(kBlk) k_gauss_pixel_bwd(const ViewTable* __restrict__ vtp, RParams rp, WsPtrs w)
-{
-    constexpr int kSplit = kBlk / kPgG;
-    const ViewTable& vt = *vtp;
-    if (w.hdr->n_inst > rp.cap) return;
-    __shared__ float4 sr0[kPgG];
-    __shared__ float4 sr1[kPgG];  // C', depth, red, green
-    __shared__ float4 sr2[kPgG];  // blue, log2 sigma, -, pixel count (bits)
-    __shared__ int4 sbox[kPgG];   // first pixel column, first row, box width, view
-    const int pb = blockIdx.x / kSplit;
-    const int g0 = (blockIdx.x % kSplit) * kPgG;
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    if (tid < kPgG) {
-        unsigned int npx = 0u;
-        const int vg = pb * kBlk + g0 + tid;
-        if (vg < rp.nvg && w.cnt[vg] > 0u) {
-            const float4 r0 = w.rec[3 * (size_t)vg], r1 = w.rec[3 * (size_t)vg + 1], r2 = w.rec[3 * (size_t)vg + 2];
-            const int v = vg / rp.M;
-            const DevCam& c = vt.v[v].cam;
-            // the pixel box of the support, as the tile rectangle is formed
-            const float xlo = fmaxf(r0.x - r2.z, 0.0f), xhi = fminf(r0.x + r2.z, (float)(c.W - 1));
-            const float ylo = fmaxf(r0.y - r2.w, 0.0f), yhi = fminf(r0.y + r2.w, (float)(c.H - 1));
-            if (xlo <= xhi && ylo <= yhi) {
-                const int px0 = (int)ceilf(xlo), px1 = (int)floorf(xhi), py0 = (int)ceilf(ylo), py1 = (int)floorf(yhi);
-                if (px0 <= px1 && py0 <= py1) {
-                    npx = (unsigned int)(px1 - px0 + 1) * (unsigned int)(py1 - py0 + 1);
-                    sbox[tid] = make_int4(px0, py0, px1 - px0 + 1, v);
-                    sr0[tid] = r0;
-                    sr1[tid] = make_float4(r1.x, r1.z, r1.w, r2.x);
-                    sr2[tid] = make_float4(r2.y, r1.y, 0.0f, 0.0f);
-                }
-            }
-        }
-        sr2[tid].w = __int_as_float((int)npx);
-    }
-    __syncthreads();
-    for (int k = wid; k < kPgG; k += kBlk / 64) {
-        const unsigned int npx = (unsigned int)__float_as_int(sr2[k].w);
-        if (npx == 0u) continue;  // uniform over the wavefront
-        const float4 r0 = sr0[k], r1 = sr1[k], r2 = sr2[k];
-        const int4 bx = sbox[k];
-        const DevView& V = vt.v[bx.w];
-        const float zi = r1.y, c0 = r1.z, c1 = r1.w, c2 = r2.x;
-        float g[kAdj];
-#pragma unroll
-        for (int q = 0; q < kAdj; ++q) g[q] = 0.0f;
-        for (unsigned int i = (unsigned int)lane; i < npx; i += 64) {
-            const int px = bx.x + (int)(i % (unsigned int)bx.z), py = bx.y + (int)(i / (unsigned int)bx.z);
-            const size_t q = (size_t)V.pix_base + (size_t)py * V.cam.W + px;
-            const float4 G = w.pix_grad[2 * q], X = w.pix_grad[2 * q + 1];
-            const AlphaEval ae = eval_alpha((float)px, (float)py, r0.x, r0.y, r0.z, r0.w, r1.x, r2.y);
-            const bool use = zi < X.z && ae.raw >= rp.amin;  // depth test (Eq. 1-2), alpha_min
-            const float a = use ? ae.raw : 0.0f;
-            const float direct = G.x * c0 + G.y * c1 + G.z * c2 + G.w * zi;
-            const float u = a * (X.y * (direct - X.x));  // alpha dL/dalpha
-            const float wgt = a * X.y;                  // dC*/dc_i
-            g[0] = __builtin_fmaf(u, ae.dx, g[0]);
-            g[1] = __builtin_fmaf(u, ae.dy, g[1]);
-            g[2] = __builtin_fmaf(u, ae.dxx, g[2]);
-            g[3] = __builtin_fmaf(u, ae.dxy, g[3]);
-            g[4] = __builtin_fmaf(u, ae.dyy, g[4]);
-            g[5] += u;
-            g[6] = __builtin_fmaf(wgt, G.x, g[6]);
-            g[7] = __builtin_fmaf(wgt, G.y, g[7]);
-            g[8] = __builtin_fmaf(wgt, G.z, g[8]);
-            g[9] = __builtin_fmaf(wgt, G.w, g[9]);
-        }
-        float mine = 0.0f;  // lane q keeps component q
-#pragma unroll
-        for (int q = 0; q < kAdj; ++q) {
-            const float tq = wave_sum(g[q]);
-            if (lane == q) mine = tq;
-        }
-        const int vg = pb * kBlk + g0 + k;
-        const unsigned int slot = w.off[vg], n = w.cnt[vg];
-        if ((unsigned long long)slot + n <= w.hdr->n_inst) {
-            if (lane < kAdj) w.partial[(size_t)slot * kAdj + lane] = mine;
-            for (unsigned int e = (unsigned int)lane; e < (n - 1u) * kAdj; e += 64)
-                w.partial[(size_t)(slot + 1u) * kAdj + e] = 0.0f;
-        }
-    }
-}
-
 // ----------------------------------------------------------------- launch
 gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const gps_gaussians* g,
                              const ViewTable& vt, const WsLayout& L, char* ws, int explicit_upstream,
@@ -621,14 +473,8 @@ gps_status launch_render_bwd(const gps_render_cfg* cfg, const RParams& rp, const
     }
     if (cfg->flags & GPS_RENDER_BWD_PER_GAUSSIAN) {
         if (rp.mode == 0) return GPS_ERR_UNSUPPORTED_CONFIG;
-        int npix = 0;
-        for (int v = 0; v < vt.n; ++v) npix += vt.v[v].cam.W * vt.v[v].cam.H;
-        if (npix > 0)
-            GPS_LAUNCH(K_COMPOSITE_BWD, s, k_pixgrad, dim3((npix + 255) / 256), dim3(256), 0, s, dvt, rp, w, npix,
-                       explicit_upstream, loss_scale);
-        if (L.nblk_vg > 0)
-            GPS_LAUNCH(K_COMPOSITE_BWD, s, k_gauss_pixel_bwd, dim3(L.nblk_vg * (kBlk / kPgG)), dim3(kBlk), 0, s, dvt,
-                       rp, w);
+        if (!dispatch_cbwd_pg(cfg, dvt, rp, w, L.n_tiles, explicit_upstream, loss_scale, s))
+            return GPS_ERR_UNSUPPORTED_CONFIG;
     } else if (!dispatch_cbwd(cfg, dvt, rp, w, L.n_tiles, explicit_upstream, loss_scale, s)) {
         return GPS_ERR_UNSUPPORTED_CONFIG;
     }
