@@ -52,6 +52,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     const int px = wx0 + Lay::lane_x(lane);
     const int py0 = wy0 + Lay::lane_y(lane);
     const float fpx = (float)px;
+    const float l2amin = __log2f(rp.amin);  // the support test of the staged records
 
     float sc = 1.0f;
     if (!explicit_up && loss_scale) sc = *loss_scale;
@@ -119,7 +120,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                 srec[3 * j + 0] = r0;
                 srec[3 * j + 1] = r1;
                 srec[3 * j + 2] = r2;
-                mk = wave_box_mask<Lay>(r0.x, r0.y, r2.z, r2.w, tx0, ty0);
+                mk = wave_support_mask<Lay>(r0, r1, l2amin, tx0, ty0);
                 // the instance's slot: its view-Gaussian's first slot plus this tile's
                 // place in the tile rectangle (the rectangle the expansion walked)
                 TileRect rr;
@@ -146,14 +147,14 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                 const float4 r0 = srec[3 * j], r1 = srec[3 * j + 1], r2 = srec[3 * j + 2];
                 const float c0 = r1.w, c1 = r2.x, c2 = r2.y, zi = r1.z;
                 // the forward's decisions, in the same order and arithmetic
-                unsigned long long any_live = 0ull, any_use = 0ull;
+                bool lane_live = false, lane_use = false;  // over the lane's pixels
                 AlphaEval ae[PPT];
                 float av[PPT], Tn[PPT];
                 bool use[PPT];
 #pragma unroll
                 for (int k = 0; k < PPT; ++k) {
                     const bool live = zi < thr[k];
-                    any_live |= __builtin_amdgcn_ballot_w64(live);
+                    lane_live = lane_live || live;
                     ae[k] = eval_alpha(fpx, (float)(py0 + k * Lay::LROWS), r0.x, r0.y, r0.z, r0.w, r1.x, r1.y);
                     if (MODE == 0) {
                         av[k] = fminf(ae[k].raw, rp.amax);
@@ -167,9 +168,10 @@ __global__ void __launch_bounds__(TW * TH / PPT)
                         Tn[k] = 0.0f;
                         use[k] = live && av[k] >= rp.amin;
                     }
-                    any_use |= __builtin_amdgcn_ballot_w64(use[k]);
+                    lane_use = lane_use || use[k];
                 }
-                if (any_use) {
+                const unsigned long long any_live = __builtin_amdgcn_ballot_w64(lane_live);
+                if (__builtin_amdgcn_ballot_w64(lane_use)) {
                     // Adjoints of the contributing lanes; the others carry zero
                     // weight, so no accumulator needs clearing.
                     float g[kAdj];

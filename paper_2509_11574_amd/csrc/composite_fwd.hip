@@ -46,7 +46,7 @@ __device__ __forceinline__ void composite_step(bool live, float raw, const float
     const unsigned long long lm = __builtin_amdgcn_ballot_w64(live);
     live_mask |= lm;
     n_eval += (unsigned int)__builtin_popcountll(lm);
-    n_contrib += (unsigned int)__builtin_popcountll(__builtin_amdgcn_ballot_w64(use));
+    n_contrib += use ? 1u : 0u;  // per lane, summed over the wavefront in the epilogue
 }
 
 template <int TW, int TH, int B, int PPT, int MODE>
@@ -73,13 +73,14 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
     const int px = wx0 + Lay::lane_x(lane);
     const int py0 = wy0 + Lay::lane_y(lane);
     const float fpx = (float)px;
+    const float l2amin = __log2f(rp.amin);  // the support test of the staged records
 
     // thr: the depth test of Eq. 1-2 passes while d_i < D_t + eps.  The list is
     // depth-ordered, so once a record fails it every later record fails too; a
     // pixel that stops for another reason (outside the image, transmittance
     // below T_min) gets thr = -inf, so the one comparison carries every stop.
     float thr[PPT], T[PPT], ac0[PPT], ac1[PPT], ac2[PPT], ad[PPT];
-    unsigned int n_eval = 0, n_contrib = 0;  // per wavefront (uniform)
+    unsigned int n_eval = 0, n_contrib = 0;  // per wavefront (uniform) / per lane
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int py = py0 + k * Lay::LROWS;
@@ -116,7 +117,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
                 srec[3 * j + 0] = r0;
                 srec[3 * j + 1] = r1;
                 srec[3 * j + 2] = r2;
-                mk = wave_box_mask<Lay>(r0.x, r0.y, r2.z, r2.w, tx0, ty0);
+                mk = wave_support_mask<Lay>(r0, r1, l2amin, tx0, ty0);
             }
             smask[j] = mk;
         }
@@ -211,6 +212,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
     lc = wave_sum(lc);
     ld = wave_sum(ld);
     lo = wave_sum(lo);
+    for (int o = 32; o > 0; o >>= 1) n_contrib += __shfl_xor(n_contrib, o, 64);
     if (lane == 0) {
         sred[wid][0] = lc;
         sred[wid][1] = ld;

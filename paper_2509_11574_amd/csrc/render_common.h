@@ -132,22 +132,54 @@ struct TileLayout {
     __device__ static int lane_y(int lane) { return lane / WW; }
 };
 
-// Wavefronts of a tile (origin tx0, ty0) whose pixel rectangle meets the
-// support box [mx - rx, mx + rx] x [my - ry, my + ry]: bit w for wavefront w.
-// A record outside a wavefront's rectangle has opacity below alpha_min at every
-// one of its pixels, so the wavefront may skip it.
+// Whether a record's opacity can reach alpha_min at some pixel of a rectangle
+// of pixels [x0, x0 + w - 1] x [y0, y0 + h - 1] (the support ellipse of Eq. 3
+// against the rectangle, not its bounding box).  The per-pixel test is
+// l2s + A dx^2 + B dx dy + C dy^2 >= log2(alpha_min) with the record's
+// binary32 coefficients (A, C < 0, B^2 < 4AC: a concave quadratic).  Its largest
+// value over a box is 0 when the box holds the centre, else on an edge, where
+// it is the one-variable maximum clamped to the edge: dy = -B dx / (2C) on the
+// edges of fixed dx, dx = -B dy / (2A) on those of fixed dy.  The box is the
+// rectangle grown by one pixel on every side and the threshold is lowered by a
+// small slack, so that every pixel passing the rounded per-pixel test (which
+// lies within one pixel of the exact ellipse) is in a rectangle that passes.
+struct SupportTest {
+    float mx, my, A, B, C, kx, ky, need;
+    __device__ SupportTest(const float4& r0, const float4& r1, float l2amin)
+        : mx(r0.x), my(r0.y), A(r0.z), B(r0.w), C(r1.x)
+    {
+        kx = -0.5f * B * __builtin_amdgcn_rcpf(A);
+        ky = -0.5f * B * __builtin_amdgcn_rcpf(C);
+        need = (l2amin - r1.y) * 1.0001f - 1e-4f;  // log2(alpha_min / sigma), with slack
+    }
+    __device__ float at(float dx, float dy) const { return dx * (A * dx + B * dy) + C * dy * dy; }
+    __device__ bool meets(float x0, float y0, float w, float h) const
+    {
+        const float X0 = (x0 - 1.0f) - mx, X1 = (x0 + w) - mx;
+        const float Y0 = (y0 - 1.0f) - my, Y1 = (y0 + h) - my;
+        if (X0 <= 0.0f && X1 >= 0.0f && Y0 <= 0.0f && Y1 >= 0.0f) return true;
+        const float e0 = at(X0, fminf(fmaxf(ky * X0, Y0), Y1));
+        const float e1 = at(X1, fminf(fmaxf(ky * X1, Y0), Y1));
+        const float e2 = at(fminf(fmaxf(kx * Y0, X0), X1), Y0);
+        const float e3 = at(fminf(fmaxf(kx * Y1, X0), X1), Y1);
+        return !(fmaxf(fmaxf(e0, e1), fmaxf(e2, e3)) < need);  // a NaN keeps the record
+    }
+};
+
+// Wavefronts of a tile (origin tx0, ty0) whose pixel rectangle the record's
+// support meets: bit w for wavefront w.  A wavefront outside the support has
+// opacity below alpha_min at every one of its pixels, so it may skip the record.
 template <class Lay>
-__device__ __forceinline__ unsigned int wave_box_mask(float mx, float my, float rx, float ry, int tx0, int ty0)
+__device__ __forceinline__ unsigned int wave_support_mask(const float4& r0, const float4& r1, float l2amin, int tx0,
+                                                          int ty0)
 {
     static_assert(Lay::NW <= 32, "wavefront mask fits 32 bits");
+    const SupportTest st(r0, r1, l2amin);
     unsigned int mk = 0u;
 #pragma unroll
     for (int wv = 0; wv < Lay::NW; ++wv) {
-        const int x0 = tx0 + Lay::wave_x0(wv), y0 = ty0 + Lay::wave_y0(wv);
-        const float fx0 = (float)x0, fx1 = (float)(x0 + Lay::WW - 1);
-        const float fy0 = (float)y0, fy1 = (float)(y0 + Lay::WH - 1);
-        const bool miss = mx + rx < fx0 || mx - rx > fx1 || my + ry < fy0 || my - ry > fy1;
-        if (!miss) mk |= 1u << wv;
+        const float x0 = (float)(tx0 + Lay::wave_x0(wv)), y0 = (float)(ty0 + Lay::wave_y0(wv));
+        if (st.meets(x0, y0, (float)Lay::WW, (float)Lay::WH)) mk |= 1u << wv;
     }
     return mk;
 }

@@ -342,12 +342,13 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(RParams rp, WsPtrs w, int n
 // lanes per Gaussian instead of serialising one lane.  Slots are numbered per
 // projection block: instance i of projection block b has slot blk_off[b] + i,
 // whichever expansion block handles it.
-//   COUNT:  tiles that pass the exact depth cull get one of their kCntSplit
-//           sub-counters (chosen by block index) incremented; the count before
-//           the increment (the instance's rank in that sub-counter) is parked in
-//           inst_vg[slot]; the per-view-Gaussian slot offsets are written.
-//   EMIT:   the same instances (the cull is the same binary32 test on the same
-//           values, the block index the same) write the key
+//   COUNT:  tiles that the support ellipse meets (SupportTest) and that pass
+//           the exact depth cull get one of their kCntSplit sub-counters
+//           (chosen by block index) incremented; the count before the increment
+//           (the instance's rank in that sub-counter) is parked in inst_vg[slot];
+//           the per-view-Gaussian slot offsets are written.
+//   EMIT:   the same instances (the culls are the same binary32 tests on the
+//           same values, the block index the same) write the key
 //           (depth bits << 32) | view-Gaussian at the sub-counter's start + rank,
 //           with no atomics, and zero the instance partials of every slot.  A
 //           tile holds at most one instance of a view-Gaussian, and slots grow
@@ -362,6 +363,7 @@ __global__ void __launch_bounds__(kBlk) k_expand(const ViewTable* __restrict__ v
     if (w.hdr->n_inst > rp.cap) return;
     __shared__ unsigned int pre[kExpG + 1];
     __shared__ float4 sbox[kExpG];  // mx, my, rxp, ryp
+    __shared__ float4 scon[kExpG];  // the exponent's coefficients A, B, C and log2 sigma
     __shared__ float sz[kExpG];
     __shared__ int4 sview[kExpG];   // tile_base, tiles_x, W, H
     const int pb = blockIdx.x / kSplit;
@@ -377,6 +379,7 @@ __global__ void __launch_bounds__(kBlk) k_expand(const ViewTable* __restrict__ v
         if (c > 0) {
             const float4 r0 = w.rec[3 * (size_t)vg], r1 = w.rec[3 * (size_t)vg + 1], r2 = w.rec[3 * (size_t)vg + 2];
             sbox[k] = make_float4(r0.x, r0.y, r2.z, r2.w);
+            scon[k] = make_float4(r0.z, r0.w, r1.x, r1.y);
             sz[k] = r1.z;
             const DevView& V = vt.v[vg / rp.M];
             sview[k] = make_int4(V.tile_base, V.tiles_x, V.cam.W, V.cam.H);
@@ -388,6 +391,7 @@ __global__ void __launch_bounds__(kBlk) k_expand(const ViewTable* __restrict__ v
     const size_t sub = (size_t)(blockIdx.x % kCntSplit) * vt.n_tiles;
     __syncthreads();
     const unsigned int first = pre[0], last = pre[kExpG];
+    const float l2amin = __log2f(rp.amin);
     for (unsigned int i = first + threadIdx.x; i < last; i += kBlk) {
         int lo = 0, hi = kExpG;  // pre[lo] <= i < pre[hi]
 #pragma unroll
@@ -402,7 +406,8 @@ __global__ void __launch_bounds__(kBlk) k_expand(const ViewTable* __restrict__ v
         TileRect r;
         if (!rect_of(bx.x, bx.y, bx.z, bx.w, vw.z, vw.w, rp.tile_w, rp.tile_h, &r)) continue;
         const unsigned int wdt = (unsigned int)(r.tx1 - r.tx0 + 1);
-        const int tile = vw.x + (r.ty0 + (int)(j / wdt)) * vw.y + r.tx0 + (int)(j % wdt);
+        const int tix = r.tx0 + (int)(j % wdt), tiy = r.ty0 + (int)(j / wdt);
+        const int tile = vw.x + tiy * vw.y + tix;
         const float z = sz[lo];
         const unsigned int slot = base + i;
         if (EMIT) {
@@ -412,6 +417,10 @@ __global__ void __launch_bounds__(kBlk) k_expand(const ViewTable* __restrict__ v
 #pragma unroll
             for (int q = 0; q < kAdj; ++q) pz[q] = 0.0f;
         }
+        // the support ellipse must meet the tile (its box may only overlap it)
+        const float4 cn = scon[lo];
+        const SupportTest st(make_float4(bx.x, bx.y, cn.x, cn.y), make_float4(cn.z, cn.w, 0.0f, 0.0f), l2amin);
+        if (!st.meets((float)(tix * rp.tile_w), (float)(tiy * rp.tile_h), (float)rp.tile_w, (float)rp.tile_h)) continue;
         if (!(z < w.tilemax[tile] + rp.eps)) continue;  // exact tile-level depth cull
         if (!EMIT) {
             w.inst_vg[slot] = atomicAdd(w.tile_cnt + sub + tile, 1u);
