@@ -74,7 +74,7 @@ def measured_traffic(kernel: str, tile: str, mode: int):
     e = table.get(f"{kernel} {tile} mode{mode}")
     if not e or e.get("sources_sha256") != sources_sha256(kernel):
         return None
-    return e.get("hbm_bytes_per_launch")
+    return e.get("hbm_bytes_per_launch"), e.get("hbm_bytes_by_request_size")
 
 
 def parse():
@@ -107,14 +107,155 @@ def parse():
                     help="also time the other launch mode (graph replay or kernel-by-kernel) on the same frames")
     ap.add_argument("--tracking", type=int, default=1,
                     help="time ICP tracking (Eq. 5) of one frame against the previous frame's raycast")
-    ap.add_argument("--copy-calibration", type=int, default=0,
-                    help="MiB copied (device to device, 3 times) before the workload, so that a counter run can "
-                         "scale FETCH_SIZE / WRITE_SIZE by a copy of known size")
+    ap.add_argument("--hash-frames", type=int, default=30,
+                    help="frames fused and raycast over the voxel-block hash and over the dense lattice (0 skips)")
+    ap.add_argument("--sh-frames", type=int, default=10,
+                    help="frames of the mapping loop with SH bands 1-3 and without, from the same map (0 skips)")
+    ap.add_argument("--calibrate-counters", type=int, default=0,
+                    help="MiB written 3 times by a write-only kernel, then read 3 times by a read-only kernel, "
+                         "before the workload, so that a counter run can scale WRITE_SIZE / FETCH_SIZE to bytes")
+    ap.add_argument("--summarize-counters", nargs="+", default=None, metavar="DIR",
+                    help="no GPU run: read the rocprofv3 counter CSVs under the given directories (made with "
+                         "--calibrate-counters) and print per-dispatch means for the compositing kernels at --tile "
+                         "and the calibration kernels; with FETCH_SIZE and WRITE_SIZE present, also the scaled "
+                         "HBM bytes per launch (--write-traffic records them in profiles/traffic.json)")
+    ap.add_argument("--summarize-trace", nargs="+", default=None, metavar="DIR",
+                    help="no GPU run: the gps kernels of the rocprofv3 kernel-trace run under DIR (stats table, "
+                         "and the mean of the last --last dispatches of the compositing kernels at --tile)")
+    ap.add_argument("--last", type=int, default=300, help="dispatches averaged by --summarize-counters / -trace")
+    ap.add_argument("--write-traffic", action="store_true")
     return ap.parse_args()
+
+
+def _kname(name: str) -> str:
+    """A rocprofv3 kernel name without its return type and argument list."""
+    name = name.split("(")[0].strip()
+    return name[5:] if name.startswith("void ") else name
+
+
+def _counter_rows(dirs):
+    """(dispatch id, kernel name, counter, value) of every rocprofv3 counter CSV under dirs."""
+    import csv
+    import glob
+    rows = []
+    for d in dirs:
+        for path in sorted(glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)):
+            with open(path) as fh:
+                for r in csv.DictReader(fh):
+                    rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], r["Counter_Name"],
+                                 float(r["Counter_Value"])))
+    rows.sort()
+    return rows
+
+
+def summarize_trace(args):
+    """The gps kernels of a rocprofv3 --kernel-trace --stats run (its stats table), and the
+    mean duration of the last --last dispatches of the compositing kernels at --tile."""
+    import csv
+    import glob
+    for d in args.summarize_trace:
+        for path in sorted(glob.glob(os.path.join(d, "**", "*kernel_stats.csv"), recursive=True)):
+            print("| kernel | calls | avg µs | min µs | max µs | total µs |")
+            print("|---|---|---|---|---|---|")
+            with open(path) as fh:
+                for r in csv.DictReader(fh):
+                    if "gps::" not in r["Name"]:
+                        continue
+                    print(f"| `{_kname(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                          f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | "
+                          f"{float(r['TotalDurationNs']) / 1e3:.0f} |")
+        tw, th, b, ppt = args.tile.split("x")
+        for path in sorted(glob.glob(os.path.join(d, "**", "*kernel_trace.csv"), recursive=True)):
+            per = {}
+            with open(path) as fh:
+                for r in csv.DictReader(fh):
+                    name = _kname(r["Kernel_Name"])
+                    per.setdefault(name, []).append((int(r["Start_Timestamp"]),
+                                                     int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+            for k in ("fwd", "bwd"):
+                name = f"gps::k_composite_{k}<{tw}, {th}, {b}, {ppt}, {args.mode}>"
+                v = [dt for _, dt in sorted(per.get(name, []))][-args.last:]
+                if v:
+                    print(f"{name}: mean of the last {len(v)} of {len(per[name])} dispatches "
+                          f"{sum(v) / len(v) / 1e3:.2f} µs")
+
+
+def summarize_counters(args):
+    """Per-dispatch means of the counters of the compositing kernels at --tile (the last
+    --last dispatches) and of the calibration kernels; FETCH_SIZE and WRITE_SIZE scaled to
+    bytes by what they read for the calibration kernels of known traffic."""
+    rows = _counter_rows(args.summarize_counters)
+    tw, th, b, ppt = args.tile.split("x")
+    want = {f"gps::k_composite_{k}<{tw}, {th}, {b}, {ppt}, {args.mode}>": f"composite_{k}" for k in ("fwd", "bwd")}
+    want.update({"gps::k_stream_read": "stream_read", "gps::k_stream_write": "stream_write"})
+    vals = {}
+    for _, name, ctr, v in rows:
+        base = _kname(name)
+        if base in want:
+            vals.setdefault((want[base], ctr), []).append(v)
+    out = {}
+    for (k, ctr), v in sorted(vals.items()):
+        last = v if k.startswith("stream") else v[-args.last:]
+        out.setdefault(k, {})[ctr] = (sum(last) / len(last), len(last), len(v))
+    for k, c in out.items():
+        print(f"{k}: " + ", ".join(f"{n}={m:.6g} (mean of {u} of {t})" for n, (m, u, t) in sorted(c.items())))
+    kib = args.calibrate_counters * 1024.0
+    rd, wr = out.get("stream_read", {}), out.get("stream_write", {})
+    if kib > 0 and "FETCH_SIZE" in rd and "WRITE_SIZE" in wr:
+        fs, ws_ = kib / rd["FETCH_SIZE"][0], kib / wr["WRITE_SIZE"][0]
+        print(f"scale: FETCH_SIZE x {fs:.4f} (read-only kernel: {rd['FETCH_SIZE'][0]:.1f} KiB for {kib:.0f} KiB), "
+              f"WRITE_SIZE x {ws_:.4f} (write-only kernel: {wr['WRITE_SIZE'][0]:.1f} KiB for {kib:.0f} KiB)")
+        table = {}
+        path = os.path.join(ROOT, "profiles", "traffic.json")
+        if os.path.exists(path):
+            with open(path) as fh:
+                table = json.load(fh)
+        rq = ("TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum", "TCC_EA0_RDREQ_128B_sum")
+
+        def read_bytes(c):  # read requests counted by size: 32, 64 and 128 bytes
+            if not all(n in c for n in rq):
+                return None
+            return 32.0 * c[rq[0]][0] + 64.0 * c[rq[1]][0] + 128.0 * c[rq[2]][0]
+
+        if read_bytes(rd) is not None:
+            print(f"read requests by size, read-only kernel: {read_bytes(rd) / 1024:.1f} KiB for {kib:.0f} KiB")
+        for k in ("composite_fwd", "composite_bwd"):
+            c = out.get(k, {})
+            if "FETCH_SIZE" not in c or "WRITE_SIZE" not in c:
+                continue
+            hbm = (c["FETCH_SIZE"][0] * fs + c["WRITE_SIZE"][0] * ws_) * 1024.0
+            rb = read_bytes(c)
+            by_size = None if rb is None else int(rb + c["WRITE_SIZE"][0] * ws_ * 1024.0)
+            print(f"{k} {args.tile} mode{args.mode}: {hbm / 1e6:.2f} MB of HBM traffic per launch (scaled FETCH_SIZE "
+                  f"+ WRITE_SIZE)" + ("" if rb is None else
+                                      f", {by_size / 1e6:.2f} MB with reads counted by request size "
+                                      f"({c[rq[0]][0]:.0f} x 32 B, {c[rq[1]][0]:.0f} x 64 B, {c[rq[2]][0]:.0f} x 128 B)"))
+            table[f"{k} {args.tile} mode{args.mode}"] = {
+                "hbm_bytes_by_request_size": by_size,
+                "kernel": next(n for n, v in want.items() if v == k).replace("gps::", ""),
+                "fetch_kib_per_launch": round(c["FETCH_SIZE"][0], 1),
+                "write_kib_per_launch": round(c["WRITE_SIZE"][0], 1),
+                "fetch_scale": round(fs, 4), "write_scale": round(ws_, 4),
+                "hbm_bytes_per_launch": int(hbm), "sources_sha256": sources_sha256(k),
+                "dispatches": f"mean of the last {c['FETCH_SIZE'][1]} of {c['FETCH_SIZE'][2]}",
+                "calibration": f"read-only and write-only kernels of {args.calibrate_counters} MiB "
+                               f"(FETCH_SIZE {rd['FETCH_SIZE'][0]:.1f} KiB, WRITE_SIZE {wr['WRITE_SIZE'][0]:.1f} KiB; "
+                               f"cross terms: the read kernel writes {rd.get('WRITE_SIZE', (0.0,))[0]:.1f} KiB, "
+                               f"the write kernel fetches {wr.get('FETCH_SIZE', (0.0,))[0]:.1f} KiB)"}
+        if args.write_traffic:
+            with open(path, "w") as fh:
+                json.dump(table, fh, indent=1)
+                fh.write("\n")
 
 
 def main():
     args = parse()
+    if args.summarize_counters or args.summarize_trace:
+        if args.summarize_trace:
+            summarize_trace(args)
+        if args.summarize_counters:
+            summarize_counters(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the path shards by view across GPUs by design, but no multi-GPU run is made).", file=sys.stderr)
@@ -136,14 +277,17 @@ def main():
     # the last one
     n_frames = Wu + 2 * K + 1
 
-    if args.copy_calibration > 0:
-        n = args.copy_calibration * (1 << 20) // 4
-        src = torch.ones(n, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
+    if args.calibrate_counters > 0:
+        n = args.calibrate_counters * (1 << 20) // 4
+        buf = torch.empty(n, dtype=torch.float32, device=dev)
+        part = torch.empty(P.gps.stream_blocks(), dtype=torch.float32, device=dev)
+        for k in range(3):
+            P.gps.stream_write(buf, 1.0 + k)
         for _ in range(3):
-            dst.copy_(src)
+            P.gps.stream_read(buf, part)
         torch.cuda.synchronize()
-        del src, dst
+        assert float(part.sum()) == 3.0 * n  # the reads saw the last write
+        del buf, part
 
     # ---------------------------------------------------------------- inputs
     t0 = time.time()
@@ -330,9 +474,10 @@ def main():
             flops = FLOPS_EVAL * pairs["eval_per_launch"] + per * pairs["contrib_per_launch"]
             ach = flops / avg_s / 1e12
             tile_s = f"{cfg.tile_w}x{cfg.tile_h}x{cfg.batch}x{cfg.pix_per_thread}"
+            tr = measured_traffic(dom, tile_s, args.mode) or (None, None)
             roofline = {"bound": "alu", "kernel": dom, "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4),
-                        "traffic": measured_traffic(dom, tile_s, args.mode),
+                        "traffic": tr[0], "traffic_by_request_size": tr[1],
                         "avg_launch_ms": round(avg_s * 1e3, 4), "flops_per_launch": flops}
         else:
             roofline = {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -365,6 +510,11 @@ def main():
 
     # -------------------------------- map maintenance: removal and insertion
     maint = bench_maintenance(P, cfg, mview, params, opt) if args.maintenance else None
+
+    # ------------- the voxel-block hash, and view-dependent colour (SH bands 1-3)
+    n_hash, n_sh = min(args.hash_frames, len(frames)), min(args.sh_frames, len(frames) - Wu)
+    hashed = bench_hash(P, scene, cams, frames, cfg.z_near, n_hash) if n_hash > 0 else None
+    sh = bench_sh(P, scene, cams, frames, gauss_np, cfg, Wu, n_sh) if n_sh > 0 else None
 
     # ------------- camera tracking of the next frame against the last raycast
     tracking = None
@@ -399,6 +549,8 @@ def main():
            "batched_keyframes": batched,
            "large_map": large,
            "map_maintenance": maint,
+           "voxel_block_hash": hashed,
+           "sh_degree_3": sh,
            "tracking": tracking,
            "kernels_ms_per_frame": {n: round(v[1] / K, 4) for n, v in sorted(kernels.items(), key=lambda x: -x[1][1])},
            "cpu_baseline": cpu}
@@ -628,6 +780,7 @@ def bench_batched(P, synth, dev, cfg, reps=20, n_gauss=300_000):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / n
 
+    init = {k: v.clone() for k, v in params.items()}
     opt_b = P.Adam(params)
     ws_b = P.Workspace(cfg, n_gauss, [v.cam for v in views], device=dev)
     loss_b = torch.zeros(1, device=dev)
@@ -637,7 +790,6 @@ def bench_batched(P, synth, dev, cfg, reps=20, n_gauss=300_000):
     if st["status"] != 0:
         raise RuntimeError(f"batched keyframes: device status {st}")
     inst_b = st["n_instances"]
-    del g_b, ws_b
     opt_s = P.Adam(params)
     graphs = []
     for v in views:
@@ -655,13 +807,177 @@ def bench_batched(P, synth, dev, cfg, reps=20, n_gauss=300_000):
     nv = len(views)
     log(f"keyframe batch: batched {1e3 * t_b:.3f} ms per 8-view iteration, sequential {1e3 * t_s:.3f} ms "
         f"for 8 single-view iterations")
+
+    # Time to the same accuracy: both forms start from the same map and fresh Adam state;
+    # the batched form runs n_acc iterations, then the single-view form runs rounds of 8
+    # (one per keyframe) until the mean loss over the 8 keyframes, measured by a separate
+    # forward, is at most the batched form's.  Only the optimisation launches are timed.
+    ws_e = P.Workspace(cfg, n_gauss, [v.cam for v in views], device=dev)
+    le = torch.zeros(1, device=dev)
+
+    def window_loss():
+        P.render_fwd(cfg, params, views, ws_e, out_loss=le)
+        torch.cuda.synchronize()
+        return float(le.item())
+
+    def reset(opt):
+        for k in params:
+            params[k].copy_(init[k])
+        for k in opt.m:
+            opt.m[k].zero_()
+            opt.v[k].zero_()
+        opt.counter.zero_()
+        torch.cuda.synchronize()
+
+    n_acc = 40
+    reset(opt_b)
+    l0 = window_loss()
+    t0 = time.perf_counter()
+    for _ in range(n_acc):
+        g_b.replay()
+    torch.cuda.synchronize()
+    tb_acc = time.perf_counter() - t0
+    target = window_loss()
+    reset(opt_s)
+    ts_acc, rounds, ls = 0.0, 0, l0
+    while ls > target and rounds < 4 * n_acc:
+        t0 = time.perf_counter()
+        seq()
+        torch.cuda.synchronize()
+        ts_acc += time.perf_counter() - t0
+        rounds += 1
+        ls = window_loss()
+    accuracy = {"start_loss": round(l0, 6), "target_loss": round(target, 6),
+                "batched": {"iterations": n_acc, "view_iterations": n_acc * nv, "ms": round(1e3 * tb_acc, 3)},
+                "single_view": {"rounds_of_8": rounds, "view_iterations": rounds * nv, "ms": round(1e3 * ts_acc, 3),
+                                "final_loss": round(ls, 6), "reached": bool(ls <= target)},
+                "time_to_accuracy_speedup": round(ts_acc / tb_acc, 3) if ls <= target else None,
+                "note": "mean fused loss over the 8 keyframes; both forms from the same map and fresh Adam state"}
+    log(f"keyframe batch, same accuracy: batched {n_acc} iterations {1e3 * tb_acc:.1f} ms to loss {target:.6f}; "
+        f"single-view {rounds} rounds of 8 {1e3 * ts_acc:.1f} ms to loss {ls:.6f}")
+    del g_b, ws_b, ws_e
     return {"workload": "8 keyframes (3x1280x720, 3x640x480, 2x320x240), 300000 Gaussians, 256^3 room",
             "instances": inst_b,
             "batched_ms_per_iteration": round(1e3 * t_b, 4),
             "sequential_ms_per_8_iterations": round(1e3 * t_s, 4),
             "batched_view_iters_per_s": round(nv / t_b, 1),
             "sequential_view_iters_per_s": round(nv / t_s, 1),
-            "speedup": round(t_s / t_b, 3)}
+            "speedup": round(t_s / t_b, 3),
+            "same_accuracy": accuracy}
+
+
+def bench_hash(P, scene, cams, frames, z_near, n_frames, capacity=32768):
+    """Per-frame map update over the voxel-block hash against the dense lattice, on the
+    same frames from an empty map: fusion (with block allocation) and the raycast of the
+    frame's view, eager launches.  Reports the time per frame, the pool in use and the
+    largest depth difference of the last raycast where both hit (the hash reads points
+    of unallocated blocks as unobserved, so the two may differ at the band's edges)."""
+    import numpy as np
+    import torch
+    dev = frames[0][0].device
+    H, W = frames[0][0].shape
+    out_d = [(torch.empty(H, W, device=dev), torch.empty(3, H, W, device=dev)) for _ in range(2)]
+
+    def run(fuse, raycast, vol, out):
+        for k in range(2):  # warm-up on the first two frames, then the map starts afresh
+            fuse(vol, cams[k].as_dict(), *frames[k])
+            raycast(vol, [cams[k].as_dict()], z_near=z_near, out=[out])
+        return vol
+
+    res = {}
+    for name in ("dense", "hash"):
+        if name == "dense":
+            make = lambda: P.Volume(scene.dims, scene.origin, scene.voxel, scene.trunc, device=dev)
+            fuse, raycast, out = P.fuse, P.raycast, out_d[0]
+        else:
+            make = lambda: P.HashVolume(scene.dims, scene.origin, scene.voxel, scene.trunc, capacity=capacity,
+                                        device=dev)
+            fuse, raycast, out = P.hash_fuse, P.hash_raycast, out_d[1]
+        run(fuse, raycast, make(), out)
+        vol = make()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(n_frames):
+            cam = cams[k].as_dict()
+            fuse(vol, cam, *frames[k])
+            raycast(vol, [cam], z_near=z_near, out=[out])
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / n_frames
+        if name == "dense":
+            mem = 24 * int(np.prod(scene.dims))
+            res[name] = {"ms_per_frame": round(ms, 4), "volume_mb": round(mem / 1e6, 1)}
+        else:
+            st = vol.state()
+            if st["status"] != 0:
+                raise RuntimeError(f"hash volume status {st}")
+            blocks = st["allocated"]
+            mem = 24 * blocks * P.gps.HASH_BLOCK ** 3
+            res[name] = {"ms_per_frame": round(ms, 4), "blocks": blocks, "capacity": capacity,
+                         "pool_in_use_mb": round(mem / 1e6, 1),
+                         "table_mb": round(12 * vol.n_buckets / 1e6, 2)}
+    dd, dh = out_d[0][0], out_d[1][0]
+    both = (dd > 0) & (dh > 0)
+    res["last_raycast"] = {"hit_agree": round(float(((dd > 0) == (dh > 0)).float().mean()), 6),
+                           "max_depth_diff_m": round(float((dd - dh).abs()[both].max()), 6)}
+    res["frames"] = n_frames
+    log(f"hash: {res['hash']['ms_per_frame']:.3f} ms per frame ({res['hash']['blocks']} blocks, "
+        f"{res['hash']['pool_in_use_mb']} MB), dense {res['dense']['ms_per_frame']:.3f} ms "
+        f"({res['dense']['volume_mb']} MB)")
+    return res
+
+
+def bench_sh(P, scene, cams, frames, gauss_np, cfg, first, n_frames, degree=3):
+    """The per-frame mapping loop with view-dependent colour (SH bands 1..degree, 3
+    channels) against the same loop without, on the same frames from the same map:
+    fusion, raycast and 10 iterations of forward + backward with Adam per frame."""
+    import numpy as np
+    import torch
+    dev = frames[0][0].device
+    H, W = frames[0][0].shape
+    K = {1: 3, 2: 8, 3: 15}[degree]
+    M = int(gauss_np["opacity_logit"].size)
+    rng = np.random.Generator(np.random.PCG64(11))
+    res = {}
+    for L in (0, degree):
+        g = dict(gauss_np)
+        if L:
+            g["sh"] = (0.05 * rng.standard_normal((3, K, M))).astype(np.float32)
+        params = P.gaussians_to_device(g, dev)
+        opt = P.Adam(params)
+        vol = P.Volume(scene.dims, scene.origin, scene.voxel, scene.trunc, device=dev)
+        ws = P.Workspace(cfg, M, [cams[first].as_dict()], device=dev)
+        bd, br = torch.empty(H, W, device=dev), torch.empty(3, H, W, device=dev)
+        orgb, od = torch.empty(3, H, W, device=dev), torch.empty(H, W, device=dev)
+        loss, dpose = torch.zeros(1, device=dev), torch.zeros(1, 6, device=dev)
+        from dataclasses import replace
+        cfg_pre = replace(cfg, views_preset=True)
+
+        def frame(k):
+            cam = cams[k].as_dict()
+            P.fuse(vol, cam, *frames[k])
+            P.raycast(vol, [cam], z_near=cfg.z_near, out=[(bd, br)])
+            view = P.View(cam, br, bd, frames[k][1], frames[k][0], out_rgb=orgb, out_depth=od)
+            P.gps.views_upload(cfg, params, [view], ws)
+            for _ in range(ITERS_PER_FRAME):
+                P.render_fwd(cfg_pre, params, [view], ws, out_loss=loss)
+                P.render_bwd_adam(cfg_pre, params, [view], ws, opt, dpose=dpose)
+
+        for k in range(first):
+            frame(k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(first, first + n_frames):
+            frame(k)
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / n_frames
+        if ws.status() != 0:
+            raise RuntimeError("SH leg: device status")
+        res[f"degree_{L}"] = {"ms_per_frame": round(ms, 4), "iters_per_s": round(1e3 * ITERS_PER_FRAME / ms, 1),
+                              "loss_last": round(float(loss.item()), 6)}
+    res["frames"] = n_frames
+    log(f"SH degree {degree}: {res[f'degree_{degree}']['ms_per_frame']:.3f} ms per frame against "
+        f"{res['degree_0']['ms_per_frame']:.3f} without")
+    return res
 
 
 def bench_large(P, synth, dev, cfg, n_frames, n_gauss=1_000_000, warm=2):

@@ -130,7 +130,7 @@ typedef struct gps_view {
 
 /* Renderer constants (each is a reading of the paper where it is silent). */
 typedef struct gps_render_cfg {
-    int32_t tile_w, tile_h;  /* screen tile: 8x8, 16x16 or 16x32                   */
+    int32_t tile_w, tile_h;  /* screen tile: 8x8, 16x16, 16x32 or 32x16            */
     int32_t batch;           /* Gaussians staged in LDS per step: 128, 256 or 512  */
     int32_t pix_per_thread;  /* pixels per lane: 1, 2 or 4                         */
     int32_t mode;            /* 0 sorted over-compositing (the default); 1 the
@@ -168,8 +168,8 @@ typedef struct gps_render_cfg {
  * sweeping the Gaussian's box 64 pixels at a time; one wave reduction per
  * Gaussian and tile), with no ordering and no atomics; instead of the tile
  * backward's per-pixel-group reductions.  Same results up to rounding;
- * GPS_ERR_UNSUPPORTED_CONFIG in mode 0 or for tiles other than 8x8, 16x16 and
- * 16x32. */
+ * GPS_ERR_UNSUPPORTED_CONFIG in mode 0 or for tiles other than 8x8, 16x16, 16x32
+ * and 32x16. */
 #define GPS_RENDER_BWD_PER_GAUSSIAN 2
 
 /* Sort-free mode (mode 1) only: no per-tile depth sort at all (Sec. 3.1: the
@@ -555,6 +555,17 @@ typedef struct gps_kernel_time {
 gps_status gps_profile_start(void);
 gps_status gps_profile_stop(void);
 gps_status gps_profile_read(gps_kernel_time* out, int32_t max_kernels, int32_t* n_out);
+
+/* ---- Streaming kernels of known traffic (not part of the mapping path) ----
+ * For scaling the hardware's memory counters (FETCH_SIZE, WRITE_SIZE) to bytes:
+ * gps_stream_read reads the n floats of device array x once and writes one
+ * float per block (gps_stream_blocks() floats) to device array out;
+ * gps_stream_write writes v to the n floats of device array y once and reads
+ * nothing.  16-byte accesses when the array is 16-byte aligned.  Null pointers
+ * or n = 0 return GPS_ERR_INVALID_ARG; nothing is launched then. */
+int32_t gps_stream_blocks(void);
+gps_status gps_stream_read(const float* x, size_t n, float* out, void* stream);
+gps_status gps_stream_write(float* y, size_t n, float v, void* stream);
 
 #ifdef __cplusplus
 }

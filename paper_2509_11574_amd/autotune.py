@@ -1,4 +1,4 @@
-"""Autotuner for the compositing kernels: screen tile (8x8, 16x16, 16x32) x
+"""Autotuner for the compositing kernels: screen tile (8x8, 16x16, 16x32, 32x16) x
 Gaussians staged per LDS batch (128, 256, 512) x pixels per lane (1, 2, 4).
 
 Every combination compiled into libgps is timed on the caller's real workload

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libgps.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 SOURCES = ["api.hip", "sdf.hip", "render_fwd.hip", "composite_fwd.hip", "render_bwd.hip", "composite_bwd.hip", "adam.hip",
-           "gauss_ops.hip", "icp.hip", "hash.hip", "prof.hip"]
+           "gauss_ops.hip", "icp.hip", "hash.hip", "prof.hip", "calib.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # -ffp-contract=on: only a*b+c written as one expression may become an FMA, so

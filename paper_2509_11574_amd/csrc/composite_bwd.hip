@@ -411,6 +411,8 @@ bool dispatch_cbwd_pg(const gps_render_cfg* cfg, const ViewTable* vt, const RPar
         launch_cbwd_pg<16, 16>(vt, rp, w, n_tiles, explicit_up, loss_scale, s);
     else if (cfg->tile_w == 16 && cfg->tile_h == 32)
         launch_cbwd_pg<16, 32>(vt, rp, w, n_tiles, explicit_up, loss_scale, s);
+    else if (cfg->tile_w == 32 && cfg->tile_h == 16)
+        launch_cbwd_pg<32, 16>(vt, rp, w, n_tiles, explicit_up, loss_scale, s);
     else return false;
     return true;
 }

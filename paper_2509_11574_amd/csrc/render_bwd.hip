@@ -70,6 +70,23 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
         __syncthreads();
     }
 
+    // The Adam state of the five parameter groups (14 scalars) is loaded first, with
+    // the parameters, so that its loads overlap the slot sums instead of following them.
+    constexpr int kAdamRows[5] = {3, 3, 4, 1, 3};
+    float ap[14], am[14], av[14];
+    const bool adam_here = live && af.on && !over;
+    if (adam_here) {
+        int j = 0;
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+#pragma unroll
+            for (int r = 0; r < kAdamRows[a]; ++r, ++j) {
+                const size_t i = (size_t)r * M + g;
+                ap[j] = af.p[a][i];
+                am[j] = af.m[a][i];
+                av[j] = af.v[a][i];
+            }
+    }
     float m0 = 0, m1 = 0, m2 = 0, qw = 1, qx = 0, qy = 0, qz = 0, qn = 1, s[3] = {1, 1, 1}, sig = 0.5f;
     float Rq[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
     if (live) {
@@ -357,23 +374,22 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
             for (int k = 0; k < 3 * SHK; ++k) gg.sh[(size_t)k * M + g] = gsh[k];
         }
     }
-    if (live && af.on && !over) {
-        // this lane's Gaussian only: its parameters were read above by this lane alone
+    if (adam_here) {
+        // this lane's Gaussian only: its parameters and moments were read above by this
+        // lane alone
         const float ibc1 = sbc[0], ibc2 = sbc[1];
         const float* gr[5] = {gmean, gls, gq, &gop, grgb};
-        const int rows[5] = {3, 3, 4, 1, 3};
+        int j = 0;
 #pragma unroll
         for (int a = 0; a < 5; ++a)
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-                if (r < rows[a]) {
-                    const size_t i = (size_t)r * M + g;
-                    float p = af.p[a][i], m = af.m[a][i], v = af.v[a][i];
-                    adam_one(p, gr[a][r], m, v, af.lr[a], af.b1, af.b2, af.eps, ibc1, ibc2);
-                    af.p[a][i] = p;
-                    af.m[a][i] = m;
-                    af.v[a][i] = v;
-                }
+            for (int r = 0; r < kAdamRows[a]; ++r, ++j) {
+                const size_t i = (size_t)r * M + g;
+                adam_one(ap[j], gr[a][r], am[j], av[j], af.lr[a], af.b1, af.b2, af.eps, ibc1, ibc2);
+                af.p[a][i] = ap[j];
+                af.m[a][i] = am[j];
+                af.v[a][i] = av[j];
+            }
         if constexpr (SHK > 0) {
 #pragma unroll
             for (int r = 0; r < 3 * SHK; ++r) {

@@ -185,7 +185,8 @@ __device__ __forceinline__ unsigned int wave_support_mask(const float4& r0, cons
 }
 
 // Tile configurations (tile width, height, staged batch, pixels per lane) for
-// which both compositing kernels are instantiated.
+// which both compositing kernels are instantiated.  A 32-pixel-wide tile reads
+// each row of a float image plane as one whole 128-byte line.
 #define GPS_TILE_CONFIGS(X) \
     X(8, 8, 128, 1)         \
     X(8, 8, 256, 1)         \
@@ -203,6 +204,8 @@ __device__ __forceinline__ unsigned int wave_support_mask(const float4& r0, cons
     X(16, 32, 256, 2)       \
     X(16, 32, 128, 4)       \
     X(16, 32, 256, 4)       \
-    X(16, 32, 512, 4)
+    X(16, 32, 512, 4)       \
+    X(32, 16, 128, 2)       \
+    X(32, 16, 256, 2)
 
 }  // namespace gps

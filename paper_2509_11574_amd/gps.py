@@ -109,7 +109,8 @@ EXPORTS = ["gps_abi_version", "gps_status_string", "gps_render_cfg_default", "gp
            "gps_remove_gaussians", "gps_insert_cfg_default", "gps_insertion_workspace_size",
            "gps_insert_gaussians", "gps_depth_downsample", "gps_icp_workspace_size", "gps_icp_reduce",
            "gps_icp_solve", "gps_render_bwd_adam", "gps_level_camera", "gps_icp_reduce_noalloc",
-           "gps_hash_reset", "gps_hash_fuse", "gps_hash_raycast"]
+           "gps_hash_reset", "gps_hash_fuse", "gps_hash_raycast", "gps_stream_blocks", "gps_stream_read",
+           "gps_stream_write"]
 
 _lib = None
 
@@ -157,6 +158,9 @@ def lib():
         L.gps_icp_reduce.argtypes = [P, P, P, P, P, F, P, P, ctypes.c_size_t, P]
         L.gps_icp_reduce_noalloc.argtypes = [P, P, P, P, P, F, P, P]
         L.gps_hash_reset.argtypes = [P, P]
+        L.gps_stream_blocks.restype = I32
+        L.gps_stream_read.argtypes = [P, ctypes.c_size_t, P, P]
+        L.gps_stream_write.argtypes = [P, ctypes.c_size_t, F, P]
         L.gps_hash_fuse.argtypes = [P, P, P, P, P]
         L.gps_hash_raycast.argtypes = [P, P, I32, P, P, F, F, P]
         L.gps_icp_solve.argtypes = [P, P, P, P]
@@ -335,7 +339,7 @@ class RenderCfg:
 TILE_CONFIGS = [(8, 8, 128, 1), (8, 8, 256, 1), (8, 8, 512, 1), (16, 16, 128, 1), (16, 16, 256, 1),
                 (16, 16, 128, 2), (16, 16, 256, 2), (16, 16, 512, 2), (16, 16, 128, 4), (16, 16, 256, 4),
                 (16, 16, 512, 4), (16, 32, 128, 1), (16, 32, 128, 2), (16, 32, 256, 2), (16, 32, 128, 4),
-                (16, 32, 256, 4), (16, 32, 512, 4)]
+                (16, 32, 256, 4), (16, 32, 512, 4), (32, 16, 128, 2), (32, 16, 256, 2)]
 
 
 # --------------------------------------------------------------------------- #
@@ -452,6 +456,28 @@ def hash_raycast(vol: HashVolume, cams, z_near=0.2, step=0.0, out=None, stream=N
 # --------------------------------------------------------------------------- #
 # Per-kernel timing (HIP events on the launch stream, thread-local)            #
 # --------------------------------------------------------------------------- #
+def stream_read(x, out):
+    """Reads every element of the float32 device tensor x once (measurement support: a
+    kernel of known read traffic); out receives one float per block (stream_blocks())."""
+    if x.dtype != torch.float32 or out.dtype != torch.float32:
+        raise TypeError("x and out must be float32")
+    if out.numel() < stream_blocks():
+        raise ValueError(f"out holds {out.numel()} floats, the read writes {stream_blocks()}")
+    _check(lib().gps_stream_read(_ptr(x, "x"), x.numel(), _ptr(out, "out"), _stream()), "gps_stream_read")
+
+
+def stream_write(y, v: float):
+    """Writes v to every element of the float32 device tensor y once (measurement support:
+    a kernel of known write traffic)."""
+    if y.dtype != torch.float32:
+        raise TypeError("y must be float32")
+    _check(lib().gps_stream_write(_ptr(y, "y"), y.numel(), float(v), _stream()), "gps_stream_write")
+
+
+def stream_blocks() -> int:
+    return int(lib().gps_stream_blocks())
+
+
 def profile_start():
     _check(lib().gps_profile_start(), "gps_profile_start")
 

@@ -84,7 +84,8 @@ def test_room_raycast_every_pixel(P, O, room):
     assert normwise(gc, room["rc"]) < 1e-4
 
 
-@pytest.mark.parametrize("tile", [(16, 16, 256, 1), (16, 32, 128, 2), (16, 32, 256, 2), (16, 16, 128, 4)])
+@pytest.mark.parametrize("tile", [(16, 16, 256, 1), (16, 32, 128, 2), (16, 32, 256, 2), (16, 16, 128, 4),
+                                  (32, 16, 256, 2)])
 def test_room_render_sampled(P, O, room, tile):
     say(f"full-size render: 1280x720, 100k Gaussians, tile {tile}")
     cam = room["frames"][1][0].as_dict()

@@ -19,7 +19,7 @@ from tests.tiny_cases import tiny_case
 
 pytestmark = pytest.mark.gpu
 KEYS = ("mean", "log_scale", "quat", "opacity_logit", "rgb")
-TILES = [(16, 16, 256, 1), (8, 8, 128, 1), (16, 32, 256, 2), (16, 16, 512, 4)]
+TILES = [(16, 16, 256, 1), (8, 8, 128, 1), (16, 32, 256, 2), (16, 16, 512, 4), (32, 16, 128, 2)]
 
 
 @pytest.fixture(scope="module")

@@ -137,7 +137,8 @@ def test_raycast_bricks_do_not_change_result(P, O, small):
 
 
 # ------------------------------------------------------------ render fwd
-TILES = [(16, 16, 256, 1), (8, 8, 128, 1), (16, 16, 128, 2), (16, 16, 512, 4), (16, 32, 256, 2), (16, 32, 128, 1)]
+TILES = [(16, 16, 256, 1), (8, 8, 128, 1), (16, 16, 128, 2), (16, 16, 512, 4), (16, 32, 256, 2), (16, 32, 128, 1),
+         (32, 16, 128, 2)]
 
 
 def _render_gpu(P, gc, g, views_np, targets=True):

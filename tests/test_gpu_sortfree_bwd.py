@@ -42,7 +42,7 @@ def small():
     return synth.workload_small()
 
 
-@pytest.mark.parametrize("tile", [(16, 16, 256, 1), (16, 32, 128, 2)])
+@pytest.mark.parametrize("tile", [(16, 16, 256, 1), (16, 32, 128, 2), (32, 16, 128, 2)])
 def test_per_gaussian_bwd_explicit(P, O, tile):
     say(f"per-Gaussian sort-free bwd (explicit upstream): tile={tile}")
     for seed in (0, 1):
