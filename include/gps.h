@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define GPS_ABI_VERSION 4
+#define GPS_ABI_VERSION 5
 
 /* Size in floats of gps_volume.brick_min for an nx x ny x nz lattice. */
 #define GPS_BRICKS_(n) (((n) + 7) / 8)
@@ -306,9 +306,21 @@ gps_status gps_hash_fuse(const gps_hash_volume* vol, const gps_camera* cam, cons
  * values; the march runs inside the region's box): samples whose 2x2x2 stencil
  * lies in one block that is unallocated, or whose points are all positive
  * (vol->block_min), are skipped, which does not change the crossing found.
- * cams, out_depth, out_rgb as in gps_raycast.  Two kernels. */
+ * cams, out_depth, out_rgb as in gps_raycast.
+ * range (optional, device scratch of range_floats floats, at least
+ * GPS_HASH_RANGE_FLOATS summed over the views): the camera-depth interval that
+ * the allocated blocks, grown by one voxel, cover in each 16x16-pixel tile of each
+ * view is formed first, and the rays of a tile march only over their samples in
+ * that interval (every sample outside it has a stencil of unallocated points, so
+ * it reads positive and the crossing is the same); the free space in front of the
+ * first block costs nothing.  NULL: the rays march the whole region.  Two kernels,
+ * four with range.  GPS_ERR_INVALID_ARG for a range shorter than needed. */
+#define GPS_HASH_TILE 16
+#define GPS_HASH_RANGE_FLOATS(width, height) \
+    (2 * (((width) + GPS_HASH_TILE - 1) / GPS_HASH_TILE) * (((height) + GPS_HASH_TILE - 1) / GPS_HASH_TILE))
 gps_status gps_hash_raycast(const gps_hash_volume* vol, const gps_camera* cams, int32_t n_views,
-                            float* const* out_depth, float* const* out_rgb, float z_near, float step, void* stream);
+                            float* const* out_depth, float* const* out_rgb, float z_near, float step, float* range,
+                            size_t range_floats, void* stream);
 
 /* Forward render of n_views (<= GPS_MAX_VIEWS) views (views: host array) and,
  * when every view has target_rgb, the loss

@@ -336,7 +336,8 @@ gps_status gps_hash_fuse(const gps_hash_volume* vol, const gps_camera* cam, cons
 }
 
 gps_status gps_hash_raycast(const gps_hash_volume* vol, const gps_camera* cams, int32_t n_views,
-                            float* const* out_depth, float* const* out_rgb, float z_near, float step, void* stream)
+                            float* const* out_depth, float* const* out_rgb, float z_near, float step, float* range,
+                            size_t range_floats, void* stream)
 {
     gps_status st = hash_vol_ok(vol);
     if (st != GPS_OK) return st;
@@ -346,9 +347,11 @@ gps_status gps_hash_raycast(const gps_hash_volume* vol, const gps_camera* cams, 
     if (step != 0.0f && step < 1e-3f * vol->voxel) return GPS_ERR_INVALID_ARG;
     for (int v = 0; v < n_views; ++v)
         if (!cam_ok(cams[v]) || !out_depth[v] || !out_rgb[v]) return GPS_ERR_INVALID_ARG;
+    if (range && (((uintptr_t)range & 7) || range_floats < hash_range_floats(cams, n_views)))
+        return GPS_ERR_INVALID_ARG;
     st = check_device();
     if (st != GPS_OK) return st;
-    return launch_hash_raycast(vol, cams, n_views, out_depth, out_rgb, z_near, step, (hipStream_t)stream);
+    return launch_hash_raycast(vol, cams, n_views, out_depth, out_rgb, z_near, step, range, (hipStream_t)stream);
 }
 
 gps_status gps_render_fwd(const gps_render_cfg* cfg, const gps_gaussians* g, const gps_view* views, int32_t n_views,

@@ -137,14 +137,19 @@ __global__ void __launch_bounds__(64) k_hash_begin(int* __restrict__ state)
 }
 
 // Allocation: lane per pixel, the 2K+1 band points of its ray (the reference's
-// orc_alloc_blocks takes the same binary32 steps).
+// orc_alloc_blocks takes the same binary32 steps).  Neighbouring pixels mostly
+// reach the same blocks at the same band point, so a lane leaves a key to the lane
+// before it in the wavefront when that lane has the same key at the same point (the
+// first lane of such a run inserts it); every lane stays in the loop for the
+// exchange, with an empty key where it has none.
 __global__ void __launch_bounds__(256) k_hash_alloc(HashDev h, DevCam c, const float* __restrict__ depth, int K)
 {
     const int p = blockIdx.x * 256 + threadIdx.x;
-    if (p >= c.W * c.H) return;
-    const float d = depth[p];
-    if (!(d > 0.0f)) return;
-    const int i = p % c.W, j = p / c.W;
+    const bool in = p < c.W * c.H;
+    const float d = in ? depth[p] : 0.0f;
+    const bool valid = in && d > 0.0f;
+    const int i = in ? p % c.W : 0, j = in ? p / c.W : 0;
+    const int lane = threadIdx.x & 63;
     float xn, yn, bsz;
     {
 #pragma clang fp contract(off)
@@ -157,12 +162,12 @@ __global__ void __launch_bounds__(256) k_hash_alloc(HashDev h, DevCam c, const f
     unsigned long long last = kHashEmpty;
     for (int k = -K; k <= K; ++k) {
         int b[3];
-        bool ok = true;
+        bool ok = valid;
         {
 #pragma clang fp contract(off)
             float dz = (float)k * h.voxel;
             float z = d + dz;
-            if (!(z > 0.0f)) continue;
+            if (!(z > 0.0f)) ok = false;
             float xc = xn * z;
             float yc = yn * z;
             float q0 = xc - c.t[0];
@@ -182,9 +187,9 @@ __global__ void __launch_bounds__(256) k_hash_alloc(HashDev h, DevCam c, const f
                 b[a] = ok ? (int)f : 0;
             }
         }
-        if (!ok) continue;
-        const unsigned long long key = hash_key(b[0], b[1], b[2]);
-        if (key == last) continue;  // consecutive points in one block: one lookup
+        const unsigned long long key = ok ? hash_key(b[0], b[1], b[2]) : kHashEmpty;
+        const unsigned long long left = __shfl_up(key, 1, 64);
+        if (key == kHashEmpty || key == last || (lane > 0 && left == key)) continue;
         last = key;
         hash_insert(h, key);
     }
@@ -277,9 +282,45 @@ __global__ void __launch_bounds__(256) k_hash_block_min(HashDev h)
     }
 }
 
-// The hashed volume as a Field of the march.
+// The hashed volume as a Field of the march.  Successive samples of a ray mostly
+// stay in one block, so the last lookup (key and pool block) is kept per lane; the
+// table does not change during a raycast, so the kept answer is the table's.
+// Per view and 16x16-pixel tile: the camera depths (lo, hi) outside which the
+// view's rays read positive; tile t of view v at tile_base[v] + t.
+struct HashRange {
+    float2* range;  // null: no ranges
+    int tile_base[GPS_MAX_VIEWS];
+    int tiles_x[GPS_MAX_VIEWS];
+};
+
 struct HashField {
     HashDev h;
+    const float2* range = nullptr;  // this view's tiles, or null
+    int tiles_x = 0;
+    mutable unsigned long long ckey = kHashEmpty, ckey2 = kHashEmpty;  // the last two lookups
+    mutable int cblk = -1, cblk2 = -1;
+
+    __device__ __forceinline__ bool depth_range(int, int col, int row, float* zlo, float* zhi) const
+    {
+        if (!range) return false;
+        const float2 r = range[(row / GPS_HASH_TILE) * tiles_x + col / GPS_HASH_TILE];
+        *zlo = r.x;
+        *zhi = r.y;
+        return true;
+    }
+
+    __device__ __forceinline__ int block_of(int bx, int by, int bz) const
+    {
+        const unsigned long long key = hash_key(bx, by, bz);
+        if (key == ckey) return cblk;
+        const unsigned long long k2 = ckey;
+        const int b2 = cblk;
+        ckey = key;
+        cblk = key == ckey2 ? cblk2 : hash_find(h, key);
+        ckey2 = k2;
+        cblk2 = b2;
+        return cblk;
+    }
 
     __device__ __forceinline__ void fetch8(int plane, const int b[3], float q[8]) const
     {
@@ -287,7 +328,7 @@ struct HashField {
         const float dflt = plane == 0 ? 1.0f : 0.0f;
         const int l0 = b[0] & 7, l1 = b[1] & 7, l2 = b[2] & 7;
         if (l0 < 7 && l1 < 7 && l2 < 7) {  // the stencil lies in one block
-            const int blk = hash_find(h, hash_key(b[0] >> 3, b[1] >> 3, b[2] >> 3));
+            const int blk = block_of(b[0] >> 3, b[1] >> 3, b[2] >> 3);
             if (blk < 0) {
 #pragma unroll
                 for (int k = 0; k < 8; ++k) q[k] = dflt;
@@ -304,10 +345,21 @@ struct HashField {
             q[7] = p[kHB * kHB + kHB + 1];
             return;
         }
+        // The stencil crosses into the next block along the axes where its base sits at
+        // local position 7: each block it touches is looked up once (through the kept
+        // lookups: the next samples of the ray mostly read the same two blocks).
+        const int B0 = b[0] >> 3, B1 = b[1] >> 3, B2 = b[2] >> 3;
+        const bool cx = l0 == 7, cy = l1 == 7, cz = l2 == 7;
+        auto find = [&](bool use, int dx, int dy, int dz) { return use ? block_of(B0 + dx, B1 + dy, B2 + dz) : -1; };
+        const int bl0 = block_of(B0, B1, B2);
+        const int bl1 = find(cx, 1, 0, 0), bl2 = find(cy, 0, 1, 0), bl3 = find(cx && cy, 1, 1, 0);
+        const int bl4 = find(cz, 0, 0, 1), bl5 = find(cx && cz, 1, 0, 1), bl6 = find(cy && cz, 0, 1, 1);
+        const int bl7 = find(cx && cy && cz, 1, 1, 1);
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
             const int x = b[0] + (k & 1), y = b[1] + ((k >> 1) & 1), z = b[2] + (k >> 2);
-            const int blk = hash_find(h, hash_key(x >> 3, y >> 3, z >> 3));
+            const bool sx = (k & 1) && cx, sy = (k & 2) && cy, sz = (k & 4) && cz;
+            const int blk = sz ? (sy ? (sx ? bl7 : bl6) : (sx ? bl5 : bl4)) : (sy ? (sx ? bl3 : bl2) : (sx ? bl1 : bl0));
             q[k] = blk < 0 ? dflt : f[(size_t)blk * kHB3 + (x & 7) + kHB * ((y & 7) + kHB * (z & 7))];
         }
     }
@@ -317,7 +369,7 @@ struct HashField {
     __device__ __forceinline__ bool skip_box(const int b[3], float lo[3], float hi[3]) const
     {
         if ((b[0] & 7) == 7 || (b[1] & 7) == 7 || (b[2] & 7) == 7) return false;
-        const int blk = hash_find(h, hash_key(b[0] >> 3, b[1] >> 3, b[2] >> 3));
+        const int blk = block_of(b[0] >> 3, b[1] >> 3, b[2] >> 3);
         if (blk >= 0 && !(h.bmin && h.bmin[blk] > kBrickPositive)) return false;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -328,14 +380,115 @@ struct HashField {
     }
 };
 
-__global__ void __launch_bounds__(256) k_hash_raycast(MarchArgs a, HashField fld)
+// Depth ranges of the raycast: per view and tile, (lo, hi) start empty (+inf, 0).
+__global__ void __launch_bounds__(256) k_hash_range_clear(float2* __restrict__ range, int n)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i < n) range[i] = make_float2(INFINITY, 0.0f);
+}
+
+// One lane per (allocated block, view): the block's lattice box grown by one voxel
+// on every side (it holds every sample whose stencil touches the block), clipped to
+// the half-space of camera depths at least z_near (no sample lies nearer), is
+// projected: the clipped box is the hull of its corners in the half-space and of the
+// points where its edges cross the plane, so every tile that the bounding rectangle
+// of their projections, grown by a pixel, meets takes the clipped box's depth range
+// (depth is linear, so its extremes lie at those points).  With z_near below 1 mm a
+// box reaching the camera plane covers every tile from depth 0.  Depths are
+// positive, so their bit patterns order as the values do and integer atomics take
+// the min and max.
+__global__ void __launch_bounds__(256) k_hash_range(HashDev h, MarchArgs a, HashRange hr)
+{
+    const int n = min(h.state[0], h.cap);
+    const int view = blockIdx.y;
+    const DevCam& c = a.cams[view];
+    const int tx = hr.tiles_x[view], ty = (c.H + GPS_HASH_TILE - 1) / GPS_HASH_TILE;
+    unsigned int* rg = reinterpret_cast<unsigned int*>(hr.range + hr.tile_base[view]);
+    const float zc = a.z_near * (1.0f - 1e-4f) - 1e-6f;  // the clipping plane, a little nearer than z_near
+    for (int b = blockIdx.x * 256 + threadIdx.x; b < n; b += gridDim.x * 256) {
+        int bc[3];
+        hash_unkey(h.bkey[b], bc);
+        float lo[3], hi[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = h.origin[k] + h.voxel * (float)(bc[k] * kHB - 1);
+            hi[k] = h.origin[k] + h.voxel * (float)(min(bc[k] * kHB + kHB - 1, h.n[k] - 1) + 1);
+        }
+        float X[8], Y[8], Z[8];
+        float zmin = INFINITY, zmax = -INFINITY;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float p0 = (q & 1) ? hi[0] : lo[0], p1 = (q & 2) ? hi[1] : lo[1], p2 = (q & 4) ? hi[2] : lo[2];
+            X[q] = c.R[0] * p0 + c.R[1] * p1 + c.R[2] * p2 + c.t[0];
+            Y[q] = c.R[3] * p0 + c.R[4] * p1 + c.R[5] * p2 + c.t[1];
+            Z[q] = c.R[6] * p0 + c.R[7] * p1 + c.R[8] * p2 + c.t[2];
+            zmin = fminf(zmin, Z[q]);
+            zmax = fmaxf(zmax, Z[q]);
+        }
+        if (!(zmax >= zc)) continue;  // wholly nearer than any sample
+        int t0x, t1x, t0y, t1y;
+        if (zmin < zc && zc < 1e-3f) {
+            zmin = 0.0f;
+            t0x = 0;
+            t1x = tx - 1;
+            t0y = 0;
+            t1y = ty - 1;
+        } else {
+            float umin = INFINITY, umax = -INFINITY, vmin = INFINITY, vmax = -INFINITY;
+            auto take = [&](float x, float y, float z) {
+                const float u = c.fx * x / z + c.cx, v = c.fy * y / z + c.cy;
+                umin = fminf(umin, u);
+                umax = fmaxf(umax, u);
+                vmin = fminf(vmin, v);
+                vmax = fmaxf(vmax, v);
+            };
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (Z[q] >= zc) take(X[q], Y[q], Z[q]);
+#pragma unroll
+                for (int bit = 1; bit < 8; bit <<= 1) {
+                    if (q & bit) continue;
+                    const int r = q | bit;  // the edge (q, r)
+                    if ((Z[q] < zc) != (Z[r] < zc)) {
+                        const float t = (zc - Z[q]) / (Z[r] - Z[q]);
+                        take(X[q] + t * (X[r] - X[q]), Y[q] + t * (Y[r] - Y[q]), zc);
+                    }
+                }
+            }
+            zmin = fmaxf(zmin, zc);
+            if (!(umax >= -1.0f && umin <= (float)c.W && vmax >= -1.0f && vmin <= (float)c.H)) continue;
+            // clamped to the view's tiles before the conversion (an empty range stays empty)
+            const float T = (float)GPS_HASH_TILE;
+            t0x = (int)fminf(fmaxf(floorf((umin - 1.0f) / T), 0.0f), (float)tx);
+            t1x = (int)fmaxf(fminf(floorf((umax + 1.0f) / T), (float)(tx - 1)), -1.0f);
+            t0y = (int)fminf(fmaxf(floorf((vmin - 1.0f) / T), 0.0f), (float)ty);
+            t1y = (int)fmaxf(fminf(floorf((vmax + 1.0f) / T), (float)(ty - 1)), -1.0f);
+        }
+        // a little wider than the exact range: the rounding of the projection
+        const unsigned int blo = __float_as_uint(fmaxf(zmin - 1e-4f * fabsf(zmin) - 1e-6f, 0.0f));
+        const unsigned int bhi = __float_as_uint(zmax + 1e-4f * zmax + 1e-6f);
+        for (int yy = t0y; yy <= t1y; ++yy)
+            for (int xx = t0x; xx <= t1x; ++xx) {
+                atomicMin(rg + 2 * (yy * tx + xx), blo);
+                atomicMax(rg + 2 * (yy * tx + xx) + 1, bhi);
+            }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_hash_raycast(MarchArgs a, HashDev h, HashRange hr)
 {
     const int view = blockIdx.z;
     const DevCam& c = a.cams[view];
     const int col = blockIdx.x * 16 + (threadIdx.x & 15);
     const int row = blockIdx.y * 16 + (threadIdx.x >> 4);
     if (col >= c.W || row >= c.H) return;
-    march_pixel(a, fld, view, col, row);
+    HashField f;  // this lane's field: it carries the lane's last lookup
+    f.h = h;
+    if (hr.range) {
+        f.range = hr.range + hr.tile_base[view];
+        f.tiles_x = hr.tiles_x[view];
+    }
+    march_pixel(a, f, view, col, row);
 }
 
 // ------------------------------------------------------------------ launches
@@ -402,22 +555,40 @@ gps_status launch_hash_fuse(const gps_hash_volume* v, const gps_camera* cam, con
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
 }
 
+size_t hash_range_floats(const gps_camera* cams, int n_views)
+{
+    size_t n = 0;
+    for (int v = 0; v < n_views; ++v) n += GPS_HASH_RANGE_FLOATS((size_t)cams[v].width, (size_t)cams[v].height);
+    return n;
+}
+
 gps_status launch_hash_raycast(const gps_hash_volume* v, const gps_camera* cams, int n_views,
-                               float* const* out_depth, float* const* out_rgb, float z_near, float step,
+                               float* const* out_depth, float* const* out_rgb, float z_near, float step, float* range,
                                hipStream_t s)
 {
     MarchArgs a;
     int maxW, maxH;
     march_setup(&a, v->nx, v->ny, v->nz, v->origin, v->voxel, z_near, step, cams, n_views, out_depth, out_rgb, &maxW,
                 &maxH);
-    HashField f;
-    f.h = hash_dev(*v);
-    if (v->block_min) {
-        const int grid = v->capacity < kHashGrid ? v->capacity : kHashGrid;
-        GPS_LAUNCH(K_BRICK_MIN, s, k_hash_block_min, dim3((grid + 3) / 4), dim3(256), 0, s, f.h);
+    const HashDev h = hash_dev(*v);
+    const int bgrid = v->capacity < kHashGrid ? v->capacity : kHashGrid;
+    if (v->block_min) GPS_LAUNCH(K_BRICK_MIN, s, k_hash_block_min, dim3((bgrid + 3) / 4), dim3(256), 0, s, h);
+    HashRange hr;
+    hr.range = nullptr;
+    if (range) {
+        int tiles = 0;
+        for (int k = 0; k < n_views; ++k) {
+            hr.tile_base[k] = tiles;
+            hr.tiles_x[k] = (cams[k].width + GPS_HASH_TILE - 1) / GPS_HASH_TILE;
+            tiles += hr.tiles_x[k] * ((cams[k].height + GPS_HASH_TILE - 1) / GPS_HASH_TILE);
+        }
+        hr.range = reinterpret_cast<float2*>(range);
+        GPS_LAUNCH(K_RAYCAST, s, k_hash_range_clear, dim3((tiles + 255) / 256), dim3(256), 0, s, hr.range, tiles);
+        const int lanes = v->capacity < (1 << 16) ? v->capacity : (1 << 16);
+        GPS_LAUNCH(K_RAYCAST, s, k_hash_range, dim3((lanes + 255) / 256, n_views), dim3(256), 0, s, h, a, hr);
     }
     dim3 grid((maxW + 15) / 16, (maxH + 15) / 16, n_views);
-    GPS_LAUNCH(K_RAYCAST, s, k_hash_raycast, grid, dim3(256), 0, s, a, f);
+    GPS_LAUNCH(K_RAYCAST, s, k_hash_raycast, grid, dim3(256), 0, s, a, h, hr);
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
 }
 

@@ -50,7 +50,8 @@ gps_status launch_icp_solve(const double* sys, float* pose, float* out_xi, hipSt
 gps_status launch_hash_reset(const gps_hash_volume* v, hipStream_t s);
 gps_status launch_hash_fuse(const gps_hash_volume* v, const gps_camera* cam, const float* depth, const float* rgb,
                             hipStream_t s);
+size_t hash_range_floats(const gps_camera* cams, int n_views);
 gps_status launch_hash_raycast(const gps_hash_volume* v, const gps_camera* cams, int n_views, float* const* out_depth,
-                               float* const* out_rgb, float z_near, float step, hipStream_t s);
+                               float* const* out_rgb, float z_near, float step, float* range, hipStream_t s);
 
 }  // namespace gps

@@ -141,6 +141,8 @@ struct DenseField {
         q[7] = p[sz_ + sy_ + 1];
     }
 
+    __device__ __forceinline__ bool depth_range(int, int, int, float*, float*) const { return false; }
+
     __device__ __forceinline__ bool skip_box(const int b[3], float lo[3], float hi[3]) const
     {
         if (!bmin) return false;

@@ -95,7 +95,10 @@ struct MarchArgs {
 //       at lattice point b (q[dx + 2 dy + 4 dz]; b and b + 1 inside the lattice);
 //   bool skip_box(const int b[3], float lo[3], float hi[3]) const
 //       true when every sample whose stencil base lies in the box [lo, hi) (lattice
-//       coordinates, containing b) reads positive; the box is then skipped.
+//       coordinates, containing b) reads positive; the box is then skipped;
+//   bool depth_range(int view, int col, int row, float* zlo, float* zhi) const
+//       true when every sample of the pixel's ray outside the camera depths
+//       [zlo, zhi] reads positive (zlo > zhi: all of them); false: no such bound.
 
 // binary32 trilinear of the tsdf (decision arithmetic); +1 where the stencil
 // leaves the lattice.
@@ -228,6 +231,25 @@ __device__ __forceinline__ void march_pixel(const MarchArgs& a, const Fld& fld, 
         nsteps = ns < (float)a.max_steps ? (int)ns : a.max_steps;
     }
 
+    // A depth interval outside which every sample reads positive: the march covers
+    // its samples only (two steps of margin on each side cover the rounding of the
+    // bounds, which are values only).  The sample before the first one marched is
+    // then known positive, as after a skipped box.
+    int s_first = 0;
+    {
+        float zlo, zhi;
+        if (fld.depth_range(view, col, row, &zlo, &zhi)) {
+            if (!(zlo <= zhi)) {
+                nsteps = -1;
+            } else {
+                const float shi = ceilf((zhi * rn - lam0) * a.inv_h) + 2.0f;
+                const float slo = floorf((zlo * rn - lam0) * a.inv_h) - 2.0f;
+                if (shi < (float)nsteps) nsteps = shi < 0.0f ? -1 : (int)shi;
+                if (slo > 0.0f) s_first = slo < (float)(nsteps + 1) ? (int)slo : nsteps + 1;
+            }
+        }
+    }
+
     // Lattice-space ray for box exits (values only, never decides a crossing).
     float g0[3], gd[3], igd[3];
 #pragma unroll
@@ -239,9 +261,14 @@ __device__ __forceinline__ void march_pixel(const MarchArgs& a, const Fld& fld, 
 
     float Fprev = 0.0f;
     int prev_inside = 0, prev_skipped = 0;
+    if (s_first > 0) {
+        Fprev = 1.0f;
+        prev_inside = 1;
+        prev_skipped = 1;
+    }
     int hit = -1;
     float Fhit = 0.0f;
-    for (int s = 0; s <= nsteps; ++s) {
+    for (int s = s_first; s <= nsteps; ++s) {
         float g[3];
         {
 #pragma clang fp contract(off)

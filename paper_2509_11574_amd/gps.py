@@ -100,7 +100,7 @@ class KernelTimeS(ctypes.Structure):
     _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 
-ABI_VERSION = 4  # include/gps.h GPS_ABI_VERSION
+ABI_VERSION = 5  # include/gps.h GPS_ABI_VERSION
 
 EXPORTS = ["gps_abi_version", "gps_status_string", "gps_render_cfg_default", "gps_workspace_size",
            "gps_workspace_reset", "gps_fuse", "gps_raycast", "gps_render_fwd", "gps_render_bwd",
@@ -162,7 +162,7 @@ def lib():
         L.gps_stream_read.argtypes = [P, ctypes.c_size_t, P, P]
         L.gps_stream_write.argtypes = [P, ctypes.c_size_t, F, P]
         L.gps_hash_fuse.argtypes = [P, P, P, P, P]
-        L.gps_hash_raycast.argtypes = [P, P, I32, P, P, F, F, P]
+        L.gps_hash_raycast.argtypes = [P, P, I32, P, P, F, F, P, ctypes.c_size_t, P]
         L.gps_icp_solve.argtypes = [P, P, P, P]
         L.gps_render_bwd_adam.argtypes = [P, P, P, I32, P, P, P, P, P, P, P, ctypes.c_size_t, P]
         L.gps_level_camera.argtypes = [P, I32, P]
@@ -372,6 +372,7 @@ def raycast(vol: Volume, cams, z_near=0.2, step=0.0, out=None, stream=None):
 # Voxel-block hash of the TSDF (Sec. 3.2.1)                                    #
 # --------------------------------------------------------------------------- #
 HASH_BLOCK = 8
+HASH_TILE = 16  # include/gps.h GPS_HASH_TILE
 
 
 @dataclass
@@ -437,8 +438,16 @@ def hash_fuse(vol: HashVolume, cam, depth: torch.Tensor, rgb: torch.Tensor, stre
                                _ptr(rgb, "rgb", 3 * c.width * c.height), _stream(stream)), "gps_hash_fuse")
 
 
-def hash_raycast(vol: HashVolume, cams, z_near=0.2, step=0.0, out=None, stream=None):
-    """As raycast, over the hashed volume."""
+def hash_range_floats(cams) -> int:
+    """Floats of the depth-range scratch of hash_raycast for these cameras."""
+    t = HASH_TILE
+    return sum(2 * ((c.width + t - 1) // t) * ((c.height + t - 1) // t) for c in (camera(c) for c in cams))
+
+
+def hash_raycast(vol: HashVolume, cams, z_near=0.2, step=0.0, out=None, stream=None, range_scratch=True):
+    """As raycast, over the hashed volume.  range_scratch: True (a scratch tensor is
+    allocated here), a float32 device tensor of at least hash_range_floats(cams)
+    elements, or None/False (the rays march the whole region)."""
     cams = [camera(c) for c in cams]
     V = len(cams)
     if out is None:
@@ -448,8 +457,14 @@ def hash_raycast(vol: HashVolume, cams, z_near=0.2, step=0.0, out=None, stream=N
     dptr = (ctypes.c_void_p * V)(*[_ptr(d, "out_depth", c.width * c.height).value for (d, _), c in zip(out, cams)])
     cptr = (ctypes.c_void_p * V)(*[_ptr(r, "out_rgb", 3 * c.width * c.height).value for (_, r), c in zip(out, cams)])
     s = vol.struct()
-    _check(lib().gps_hash_raycast(ctypes.byref(s), carr, V, dptr, cptr, float(z_near), float(step), _stream(stream)),
-           "gps_hash_raycast")
+    rng = None
+    if range_scratch is True:
+        rng = torch.empty(hash_range_floats(cams), dtype=torch.float32, device=vol.tsdf.device)
+    elif range_scratch is not None and range_scratch is not False:
+        rng = range_scratch
+    _check(lib().gps_hash_raycast(ctypes.byref(s), carr, V, dptr, cptr, float(z_near), float(step),
+                                  _ptr(rng, "range_scratch"), rng.numel() if rng is not None else 0,
+                                  _stream(stream)), "gps_hash_raycast")
     return out
 
 

@@ -40,7 +40,7 @@ def test_every_declared_symbol_is_exported(P):
 
 def test_abi_version_and_status_strings(P):
     L = P.lib()
-    assert L.gps_abi_version() == 4
+    assert L.gps_abi_version() == 5
     assert L.gps_status_string(0) == b"ok"
     assert b"capacity" in L.gps_status_string(-3)
 
@@ -293,10 +293,13 @@ def test_hash_argument_checks(P):
         v = vol(**bad)
         assert L.gps_hash_reset(ctypes.byref(v), None) == -1, bad
         assert L.gps_hash_fuse(ctypes.byref(v), ctypes.byref(cam), p, p, None) == -1, bad
-        assert L.gps_hash_raycast(ctypes.byref(v), cams, 1, ptrs, ptrs, 0.2, 0.0, None) == -1, bad
+        assert L.gps_hash_raycast(ctypes.byref(v), cams, 1, ptrs, ptrs, 0.2, 0.0, None, 0, None) == -1, bad
     v = vol()
     assert L.gps_hash_fuse(ctypes.byref(v), ctypes.byref(cam), None, p, None) == -1
     assert L.gps_hash_fuse(ctypes.byref(v), None, p, p, None) == -1
-    assert L.gps_hash_raycast(ctypes.byref(v), cams, 0, ptrs, ptrs, 0.2, 0.0, None) == -1
-    assert L.gps_hash_raycast(ctypes.byref(v), cams, 1, ptrs, ptrs, -0.1, 0.0, None) == -1
-    assert L.gps_hash_raycast(ctypes.byref(v), cams, 1, None, ptrs, 0.2, 0.0, None) == -1
+    assert L.gps_hash_raycast(ctypes.byref(v), cams, 0, ptrs, ptrs, 0.2, 0.0, None, 0, None) == -1
+    assert L.gps_hash_raycast(ctypes.byref(v), cams, 1, ptrs, ptrs, -0.1, 0.0, None, 0, None) == -1
+    assert L.gps_hash_raycast(ctypes.byref(v), cams, 1, None, ptrs, 0.2, 0.0, None, 0, None) == -1
+    # a depth-range scratch shorter than 2 floats per 16x16 tile of the views
+    need = 2 * ((cam.width + 15) // 16) * ((cam.height + 15) // 16)
+    assert L.gps_hash_raycast(ctypes.byref(v), cams, 1, ptrs, ptrs, 0.2, 0.0, p, need - 1, None) == -1

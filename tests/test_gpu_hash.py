@@ -10,7 +10,8 @@ mask, orc_raycast of the masked lattice).
 * Raycast: with the reference's binary32 lattice values loaded into the pool, the hit
   set equals the reference's and the depth is within 1e-4 of the largest depth; and the
   hashed raycast is bitwise the dense GPU raycast of the same lattice values, with and
-  without the skipping of positive blocks.
+  without the skipping of positive blocks and with and without the per-tile depth
+  ranges that limit each ray's march.
 * A pool that overflows sets its status bit, keeps every stored block consistent and is
   cleared by the reset; fusing the same frame again allocates nothing new.
 """
@@ -109,17 +110,19 @@ def _raycast_checks(P, O, vol, grid, dims, cams, t32, c32, n_sample=None, z_near
     flat.tsdf.copy_(dense.tsdf)
     flat.rgb.copy_(dense.rgb)
     rng = np.random.Generator(np.random.PCG64(5))
-    for skip in (True, False):
+    for skip, ranged in ((True, True), (True, False), (False, True), (False, False)):
         vol_b = vol.block_min
         if not skip:
             vol.block_min = None
-        outs = P.hash_raycast(vol, cams, z_near=z_near)
+        outs = P.hash_raycast(vol, cams, z_near=z_near, range_scratch=ranged)
         vol.block_min = vol_b
         dref = P.raycast(dense if skip else flat, cams, z_near=z_near)
         torch.cuda.synchronize()
         for cam, (hd, hc), (dd, dc) in zip(cams, outs, dref):
             np.testing.assert_array_equal(h(hd), h(dd))
             np.testing.assert_array_equal(h(hc), h(dc))
+            if not ranged:
+                continue
             HW = cam["width"] * cam["height"]
             pix = None if n_sample is None else np.sort(rng.choice(HW, n_sample, replace=False)).astype(np.int32)
             rd, rc, rk = O.raycast(grid, t32, c32, cam, z_near=z_near, pix=pix)
