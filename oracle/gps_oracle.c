@@ -189,6 +189,63 @@ static size_t grid_index(const orc_grid* g, int x, int y, int z)
 /* Readings: the paper names the method but not its constants; the weight cap */
 /* and the separate colour weight are readings.                               */
 /* ========================================================================= */
+/* The update of one lattice point (x, y, z) by one frame: tsdf, weight, the    */
+/* three colour values and the colour weight are read and written through the  */
+/* given pointers (the point's entries, wherever they are stored).             */
+static void fuse_point(const orc_grid* g, const orc_cam* cam, const float* depth, const float* img, int x, int y,
+                       int z, double* tsdf, double* weight, double* r, double* gr, double* b, double* rgb_weight)
+{
+    const int W = cam->width, H = cam->height;
+    const float mu32 = g->trunc;
+    const float negmu32 = -mu32;
+    const double mu = (double)g->trunc;
+    const double wmax = (double)g->max_weight;
+    /* decision: which pixel, and whether the voxel is updated (binary32) */
+    float p0 = d32_lattice(g->origin[0], g->voxel, x);
+    float p1 = d32_lattice(g->origin[1], g->voxel, y);
+    float p2 = d32_lattice(g->origin[2], g->voxel, z);
+    float xc = d32_row(cam->R, cam->t, 0, p0, p1, p2);
+    float yc = d32_row(cam->R, cam->t, 1, p0, p1, p2);
+    float zc = d32_row(cam->R, cam->t, 2, p0, p1, p2);
+    if (!(zc > 0.0f)) return;
+    float u = cam->fx * xc;
+    u = u / zc;
+    u = u + cam->cx;
+    float v = cam->fy * yc;
+    v = v / zc;
+    v = v + cam->cy;
+    float fu = floorf(u + 0.5f);
+    float fv = floorf(v + 0.5f);
+    if (!(fu >= 0.0f && fu < (float)W && fv >= 0.0f && fv < (float)H)) return;
+    int i = (int)fu, j = (int)fv;
+    float d = depth[(size_t)j * W + i];
+    if (!(d > 0.0f)) return;
+    float eta32 = d - zc;
+    if (eta32 < negmu32) return;
+    int in_band = fabsf(eta32) <= mu32;
+
+    /* values (binary64) */
+    double p[3] = {(double)g->origin[0] + (double)g->voxel * x, (double)g->origin[1] + (double)g->voxel * y,
+                   (double)g->origin[2] + (double)g->voxel * z};
+    double pc[3];
+    cam_apply64(cam, p, pc);
+    double eta = (double)d - pc[2];
+    double f = eta / mu;
+    if (f > 1.0) f = 1.0;
+    double w = *weight;
+    *tsdf = (w * *tsdf + f) / (w + 1.0);
+    *weight = (w + 1.0 < wmax) ? w + 1.0 : wmax;
+    if (in_band) {
+        double wc = *rgb_weight;
+        double* col[3] = {r, gr, b};
+        for (int c = 0; c < 3; ++c) {
+            double obs = (double)img[(size_t)c * W * H + (size_t)j * W + i];
+            *col[c] = (wc * *col[c] + obs) / (wc + 1.0);
+        }
+        *rgb_weight = (wc + 1.0 < wmax) ? wc + 1.0 : wmax;
+    }
+}
+
 void orc_fuse(const orc_grid* g, double* tsdf, double* weight, double* rgb, double* rgb_weight,
               const orc_cam* cam, const float* depth, const float* img, const uint8_t* block_mask,
               int32_t block)
@@ -196,11 +253,6 @@ void orc_fuse(const orc_grid* g, double* tsdf, double* weight, double* rgb, doub
     const int nbx = block > 0 ? (g->nx + block - 1) / block : 0;
     const int nby = block > 0 ? (g->ny + block - 1) / block : 0;
     const size_t N = (size_t)g->nx * g->ny * g->nz;
-    const int W = cam->width, H = cam->height;
-    const float mu32 = g->trunc;
-    const float negmu32 = -mu32;
-    const double mu = (double)g->trunc;
-    const double wmax = (double)g->max_weight;
 
 #pragma omp parallel for collapse(2) schedule(static)
     for (int z = 0; z < g->nz; ++z)
@@ -210,52 +262,26 @@ void orc_fuse(const orc_grid* g, double* tsdf, double* weight, double* rgb, doub
                 if (block_mask &&
                     !block_mask[(size_t)(x / block) + (size_t)nbx * ((size_t)(y / block) + (size_t)nby * (z / block))])
                     continue;
-                /* decision: which pixel, and whether the voxel is updated (binary32) */
-                float p0 = d32_lattice(g->origin[0], g->voxel, x);
-                float p1 = d32_lattice(g->origin[1], g->voxel, y);
-                float p2 = d32_lattice(g->origin[2], g->voxel, z);
-                float xc = d32_row(cam->R, cam->t, 0, p0, p1, p2);
-                float yc = d32_row(cam->R, cam->t, 1, p0, p1, p2);
-                float zc = d32_row(cam->R, cam->t, 2, p0, p1, p2);
-                if (!(zc > 0.0f)) continue;
-                float u = cam->fx * xc;
-                u = u / zc;
-                u = u + cam->cx;
-                float v = cam->fy * yc;
-                v = v / zc;
-                v = v + cam->cy;
-                float fu = floorf(u + 0.5f);
-                float fv = floorf(v + 0.5f);
-                if (!(fu >= 0.0f && fu < (float)W && fv >= 0.0f && fv < (float)H)) continue;
-                int i = (int)fu, j = (int)fv;
-                float d = depth[(size_t)j * W + i];
-                if (!(d > 0.0f)) continue;
-                float eta32 = d - zc;
-                if (eta32 < negmu32) continue;
-                int in_band = fabsf(eta32) <= mu32;
-
-                /* values (binary64) */
-                double p[3] = {(double)g->origin[0] + (double)g->voxel * x,
-                               (double)g->origin[1] + (double)g->voxel * y,
-                               (double)g->origin[2] + (double)g->voxel * z};
-                double pc[3];
-                cam_apply64(cam, p, pc);
-                double eta = (double)d - pc[2];
-                double f = eta / mu;
-                if (f > 1.0) f = 1.0;
                 size_t idx = grid_index(g, x, y, z);
-                double w = weight[idx];
-                tsdf[idx] = (w * tsdf[idx] + f) / (w + 1.0);
-                weight[idx] = (w + 1.0 < wmax) ? w + 1.0 : wmax;
-                if (in_band) {
-                    double wc = rgb_weight[idx];
-                    for (int c = 0; c < 3; ++c) {
-                        double obs = (double)img[(size_t)c * W * H + (size_t)j * W + i];
-                        rgb[(size_t)c * N + idx] = (wc * rgb[(size_t)c * N + idx] + obs) / (wc + 1.0);
-                    }
-                    rgb_weight[idx] = (wc + 1.0 < wmax) ? wc + 1.0 : wmax;
-                }
+                fuse_point(g, cam, depth, img, x, y, z, tsdf + idx, weight + idx, rgb + idx, rgb + N + idx,
+                           rgb + 2 * N + idx, rgb_weight + idx);
             }
+}
+
+/* The same update for a list of n lattice points only (lattice indices idx[k] =  */
+/* x + nx (y + ny z)); their values are stored compactly: tsdf[k], weight[k],    */
+/* rgb[c * n + k], rgb_weight[k].  For checking a long sequence of frames at     */
+/* sampled points without the whole lattice.                                     */
+void orc_fuse_points(const orc_grid* g, const int64_t* idx, int64_t n, double* tsdf, double* weight, double* rgb,
+                     double* rgb_weight, const orc_cam* cam, const float* depth, const float* img)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < n; ++k) {
+        const int64_t q = idx[k];
+        const int x = (int)(q % g->nx), y = (int)((q / g->nx) % g->ny), z = (int)(q / ((int64_t)g->nx * g->ny));
+        fuse_point(g, cam, depth, img, x, y, z, tsdf + k, weight + k, rgb + k, rgb + n + k, rgb + 2 * n + k,
+                   rgb_weight + k);
+    }
 }
 
 /* ========================================================================= */

@@ -72,6 +72,8 @@ def lib():
         L = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         L.orc_fuse.argtypes = [P, P, P, P, P, P, P, P, P, ctypes.c_int32]
+        L.orc_fuse_points.argtypes = [P, P, ctypes.c_int64, P, P, P, P, P, P, P]
+        L.orc_fuse_points.restype = None
         L.orc_alloc_blocks.argtypes = [P, P, P, ctypes.c_int32, P]
         L.orc_alloc_blocks.restype = None
         L.orc_fuse.restype = None
@@ -231,6 +233,27 @@ def fuse(grid: Grid, vol: dict, cam, depth, rgb, block_mask=None, block=8):
                    _ptr(vol["rgb_weight"]), ctypes.byref(cam), _ptr(depth), _ptr(rgb), _ptr(block_mask),
                    int(block))
     return vol
+
+
+def new_points(n: int) -> dict:
+    """Initial values of n lattice points (tsdf 1, weights 0, colour 0), stored compactly."""
+    return {"tsdf": np.ones(n), "weight": np.zeros(n), "rgb": np.zeros((3, n)), "rgb_weight": np.zeros(n)}
+
+
+def fuse_points(grid: Grid, idx, pts: dict, cam, depth, rgb):
+    """The fusion of one frame at the lattice points idx (x + nx (y + ny z)) only, their
+    values in ``pts`` (from new_points), updated in place: the same update as ``fuse``."""
+    cam = cam_from(cam)
+    depth = _f32(depth)
+    rgb = _f32(rgb)
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    n = idx.size
+    assert depth.shape == (cam.height, cam.width) and rgb.shape == (3, cam.height, cam.width)
+    for k in ("tsdf", "weight", "rgb", "rgb_weight"):
+        assert pts[k].dtype == np.float64 and pts[k].flags.c_contiguous and pts[k].size == (3 if k == "rgb" else 1) * n
+    lib().orc_fuse_points(ctypes.byref(grid), _ptr(idx), n, _ptr(pts["tsdf"]), _ptr(pts["weight"]), _ptr(pts["rgb"]),
+                          _ptr(pts["rgb_weight"]), ctypes.byref(cam), _ptr(depth), _ptr(rgb))
+    return pts
 
 
 def block_grid(grid: Grid, block=8):
