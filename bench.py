@@ -95,7 +95,9 @@ def parse():
                          "graph replay); 1: time graph replay of each iteration (the view table is uploaded "
                          "once per frame either way); the other mode replays the same frames from the same "
                          "map state")
-    ap.add_argument("--mode", type=int, default=0)
+    ap.add_argument("--mode", type=int, default=0, help="0 sorted over-compositing, 1 the sort-free blend")
+    ap.add_argument("--no-sort", action="store_true",
+                    help="with --mode 1: no per-tile depth sort at all (the lists in emission order)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--modes", type=int, default=1,
@@ -253,6 +255,9 @@ def summarize_counters(args):
 
 def main():
     args = parse()
+    if args.no_sort and args.mode != 1:
+        print("bench.py: --no-sort needs --mode 1 (the sorted mode composites in depth order)", file=sys.stderr)
+        sys.exit(2)
     if args.summarize_counters or args.summarize_trace:
         if args.summarize_trace:
             summarize_trace(args)
@@ -307,7 +312,7 @@ def main():
         f"{args.volume}^3 volume")
 
     vol = P.Volume(scene.dims, scene.origin, scene.voxel, scene.trunc, device=dev)
-    cfg = P.RenderCfg(mode=args.mode, eps_cull=scene.voxel)
+    cfg = P.RenderCfg(mode=args.mode, eps_cull=scene.voxel, no_sort=args.no_sort)
     cam0 = cams[0].as_dict()
     base_depth = torch.empty(H_img, W_img, device=dev)
     base_rgb = torch.empty(3, H_img, W_img, device=dev)
@@ -339,7 +344,7 @@ def main():
     else:
         tw, th, tb, ppt = (int(x) for x in args.tile.split("x"))
         cfg = P.RenderCfg(tile_w=tw, tile_h=th, batch=tb, pix_per_thread=ppt, mode=args.mode,
-                          eps_cull=scene.voxel)
+                          eps_cull=scene.voxel, no_sort=args.no_sort)
     ws = P.Workspace(cfg, M, [cam0], device=dev)
 
     from dataclasses import replace
@@ -538,7 +543,8 @@ def main():
                                   f"{W_img}x{H_img} orbit frames, {M} Gaussians, {ITERS_PER_FRAME} iterations/frame",
                       "tile": f"{cfg.tile_w}x{cfg.tile_h}x{cfg.batch}x{cfg.pix_per_thread}",
                       "autotuned": args.tile == "auto",
-                      "mode": "sorted" if args.mode == 0 else "sort-free", "graph": bool(args.graph)},
+                      "mode": "sorted" if args.mode == 0 else ("sort-free, no sort" if args.no_sort else "sort-free"),
+                      "graph": bool(args.graph)},
            "autotune_ms_fwd_bwd": tune_ms,
            "ms_per_frame": round(ms_per_frame, 4),
            "ms_per_iteration_kernels": round(iter_ms, 4) if iter_ms else None,

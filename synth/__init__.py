@@ -11,9 +11,9 @@ Seeds (NumPy PCG64): 0 geometry, 1 albedo, 2 trajectory, 3 depth noise,
 4 Gaussians.
 """
 from .scene import (Camera, Scene, look_at, intrinsics_for, scene_small, scene_room, orbit_cameras,
-                    render_frame, seed_gaussians, workload_small, workload_room_frames, insertion_inputs,
-                    STANDARD_VIEWS)
+                    render_frame, seed_gaussians, surface_points, workload_small, workload_room_frames,
+                    insertion_inputs, STANDARD_VIEWS)
 
 __all__ = ["Camera", "Scene", "look_at", "intrinsics_for", "scene_small", "scene_room", "orbit_cameras",
-           "render_frame", "seed_gaussians", "workload_small", "workload_room_frames", "insertion_inputs",
-           "STANDARD_VIEWS"]
+           "render_frame", "seed_gaussians", "surface_points", "workload_small", "workload_room_frames",
+           "insertion_inputs", "STANDARD_VIEWS"]
