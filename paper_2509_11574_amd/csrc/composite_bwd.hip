@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(TW * TH / PPT)
         int alive_now = 1;
         for (int j0 = 0; j0 < n && alive_now; j0 += S) {
             const int j1 = min(j0 + S, n);
-            // Records of this window whose box touches this wavefront (as in the forward).
+            // Records of this window whose support meets this wavefront (as in the forward).
             const int jl = j0 + lane;
             unsigned long long m =
                 __builtin_amdgcn_ballot_w64(wave_alive && lane < S && jl < j1 && ((smask[jl] >> wid) & 1u));

@@ -1,6 +1,6 @@
 // Forward compositing (Sec. 3.1 second pass, Eq. 1-4, Eq. 7): per screen
 // tile, LDS-staged batches of B depth-sorted records; each wavefront skips the
-// records whose support box misses its pixels and composites the rest front to
+// records whose support ellipse misses its pixels and composites the rest front to
 // back over the SDF base colour and depth, with the loss partial of the tile
 // written in the epilogue.
 #include "binning.h"
@@ -105,8 +105,8 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
     for (unsigned int b = s; b < e; b += B) {
         if (__syncthreads_count(wave_alive && lane == 0) == 0) break;
         // Stage B records; each also gets the set of wavefronts whose pixels its
-        // support box touches (the box test runs once per record, not once per
-        // record and wavefront).
+        // support ellipse meets (the test runs once per record, not once per record
+        // and wavefront).
         for (int j = threadIdx.x; j < B; j += NT) {
             unsigned int mk = 0u;
             if (b + j < e) {
@@ -124,7 +124,7 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
         __syncthreads();
         const int n = (int)min((unsigned int)B, e - b);
         for (int c0 = 0; c0 < n && wave_alive; c0 += 64) {
-            // The records of this chunk whose box touches this wavefront; the
+            // The records of this chunk whose support meets this wavefront; the
             // others have opacity below alpha_min at all its pixels.
             const int jl = c0 + lane;
             unsigned long long m = __builtin_amdgcn_ballot_w64(jl < n && ((smask[jl] >> wid) & 1u));

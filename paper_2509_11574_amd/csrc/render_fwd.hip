@@ -17,7 +17,7 @@
 //   k_tile_sort_*  per tile: bitonic sort of its keys in LDS (one wavefront
 //                  for tiles of <= 512 instances, a 256-lane block above)
 //   k_composite_fwd<TW,TH,B,PPT>  (composite_fwd.hip) per tile: LDS-staged
-//                  batches of B records, wavefronts skip records whose box
+//                  batches of B records, wavefronts skip records whose support
 //                  misses their pixels, front-to-back compositing, loss
 //                  partial per tile
 //   k_loss_reduce  one block: per-view and total loss
