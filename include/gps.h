@@ -540,6 +540,15 @@ gps_status gps_icp_reduce_noalloc(const gps_camera* prev_cam, const float* prev_
                                   const float* level_depth, const float* pose, float dist_thresh, double* out_sys,
                                   void* stream);
 
+/* One Gauss-Newton step of Eq. 5: gps_icp_reduce followed by gps_icp_solve on its
+ * system, with the system's sum and the solve in one launch (two kernels instead of
+ * three).  out_sys receives the system as gps_icp_reduce writes it, pose is updated
+ * in place and out_xi (optional) receives xi, bitwise as the two calls give them.
+ * Arguments and checks as gps_icp_reduce; pose is read and written. */
+gps_status gps_icp_step(const gps_camera* prev_cam, const float* prev_depth, const gps_camera* level_cam,
+                        const float* level_depth, float* pose, float dist_thresh, double* out_sys, float* out_xi,
+                        void* ws, size_t ws_bytes, void* stream);
+
 /* Solves H xi = -g (Cholesky, binary64) and applies T_{g,k} <- Exp(xi) T_{g,k}
  * to the device pose in place; out_xi (optional, device [6]) receives xi.  With
  * fewer than 6 pairs or H not positive definite the pose is kept and xi = 0. */

@@ -664,6 +664,20 @@ gps_status gps_icp_reduce_noalloc(const gps_camera* prev_cam, const float* prev_
                              (hipStream_t)stream);
 }
 
+gps_status gps_icp_step(const gps_camera* prev_cam, const float* prev_depth, const gps_camera* level_cam,
+                        const float* level_depth, float* pose, float dist_thresh, double* out_sys, float* out_xi,
+                        void* ws, size_t ws_bytes, void* stream)
+{
+    gps_status st = icp_reduce_args_ok(prev_cam, prev_depth, level_cam, level_depth, pose, dist_thresh, out_sys);
+    if (st != GPS_OK) return st;
+    if (!ws || ((uintptr_t)ws & 255)) return GPS_ERR_INVALID_ARG;
+    if (ws_bytes < icp_workspace_bytes(level_cam->width, level_cam->height)) return GPS_ERR_WORKSPACE_TOO_SMALL;
+    st = check_device();
+    if (st != GPS_OK) return st;
+    return launch_icp_reduce(*prev_cam, prev_depth, *level_cam, level_depth, pose, dist_thresh, out_sys,
+                             static_cast<char*>(ws), (hipStream_t)stream, pose, out_xi);
+}
+
 gps_status gps_icp_solve(const double* sys, float* pose, float* out_xi, void* stream)
 {
     if (!sys || !pose) return GPS_ERR_INVALID_ARG;

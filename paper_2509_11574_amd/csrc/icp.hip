@@ -228,6 +228,49 @@ __global__ void __launch_bounds__(1024) k_icp_total(const float* __restrict__ pa
     }
 }
 
+// The same sums (each wavefront's two terms, the same order), kept in LDS as well,
+// then the Gauss-Newton step of k_icp_solve by the block's first lane: one launch
+// for the system and the step instead of two.
+__device__ void icp_solve_one(const double* sys, const float* pose, float* res);
+
+__global__ void __launch_bounds__(1024) k_icp_total_solve(const float* __restrict__ part, int nblk,
+                                                          double* __restrict__ sys, float* __restrict__ pose,
+                                                          float* __restrict__ out_xi)
+{
+    __shared__ double ssys[kIcpTerms];
+    __shared__ float res[18];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int k0 = wid, k1 = wid + 16;
+    const bool two = k1 < kIcpTerms;
+    const float* p0 = part + (size_t)k0 * nblk;
+    const float* p1 = part + (size_t)(two ? k1 : k0) * nblk;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll 4
+    for (int b = lane; b < nblk; b += 64) {
+        s0 += (double)p0[b];
+        s1 += (double)p1[b];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        s0 += __shfl_xor(s0, o, 64);
+        s1 += __shfl_xor(s1, o, 64);
+    }
+    if (lane == 0) {
+        sys[k0] = s0;
+        ssys[k0] = s0;
+        if (two) {
+            sys[k1] = s1;
+            ssys[k1] = s1;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) icp_solve_one(ssys, pose, res);
+    __syncthreads();
+    // one value per lane (vector stores)
+    if (threadIdx.x < 12) pose[threadIdx.x] = res[threadIdx.x];
+    if (out_xi && threadIdx.x < 6) out_xi[threadIdx.x] = res[12 + threadIdx.x];
+}
+
 // The Gauss-Newton step: res = (new pose (12), xi (6)); the pose is kept when fewer
 // than 6 pairs remain or H is not positive definite (xi = 0 then).
 __device__ void icp_solve_one(const double* sys, const float* pose, float* res)
@@ -359,7 +402,7 @@ gps_status launch_depth_downsample(const float* in, int W, int H, float* out, hi
 
 gps_status launch_icp_reduce(const gps_camera& prev, const float* prev_depth, const gps_camera& lvl,
                              const float* depth, const float* pose, float dist_thresh, double* sys, char* ws,
-                             hipStream_t s)
+                             hipStream_t s, float* step_pose, float* step_xi)
 {
     IcpArgs a;
     a.pfx = prev.fx, a.pfy = prev.fy, a.pcx = prev.cx, a.pcy = prev.cy;
@@ -377,7 +420,10 @@ gps_status launch_icp_reduce(const gps_camera& prev, const float* prev_depth, co
     a.nblk = (int)(want < kIcpMaxBlocks ? want : kIcpMaxBlocks);
     a.part = reinterpret_cast<float*>(ws);
     GPS_LAUNCH(K_ICP, s, k_icp_pairs, dim3(a.nblk), dim3(256), 0, s, a);
-    GPS_LAUNCH(K_ICP, s, k_icp_total, dim3(1), dim3(1024), 0, s, a.part, a.nblk, sys);
+    if (step_pose)  // the step in the same launch as the system's sum (gps_icp_step)
+        GPS_LAUNCH(K_ICP, s, k_icp_total_solve, dim3(1), dim3(1024), 0, s, a.part, a.nblk, sys, step_pose, step_xi);
+    else
+        GPS_LAUNCH(K_ICP, s, k_icp_total, dim3(1), dim3(1024), 0, s, a.part, a.nblk, sys);
     return hipGetLastError() == hipSuccess ? GPS_OK : GPS_ERR_HIP;
 }
 

@@ -45,7 +45,7 @@ gps_status icp_scratch(char** out, size_t* bytes);
 gps_status launch_depth_downsample(const float* in, int W, int H, float* out, hipStream_t s);
 gps_status launch_icp_reduce(const gps_camera& prev, const float* prev_depth, const gps_camera& lvl,
                              const float* depth, const float* pose, float dist_thresh, double* sys, char* ws,
-                             hipStream_t s);
+                             hipStream_t s, float* step_pose = nullptr, float* step_xi = nullptr);
 gps_status launch_icp_solve(const double* sys, float* pose, float* out_xi, hipStream_t s);
 gps_status launch_hash_reset(const gps_hash_volume* v, hipStream_t s);
 gps_status launch_hash_fuse(const gps_hash_volume* v, const gps_camera* cam, const float* depth, const float* rgb,

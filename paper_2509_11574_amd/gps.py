@@ -110,7 +110,7 @@ EXPORTS = ["gps_abi_version", "gps_status_string", "gps_render_cfg_default", "gp
            "gps_insert_gaussians", "gps_depth_downsample", "gps_icp_workspace_size", "gps_icp_reduce",
            "gps_icp_solve", "gps_render_bwd_adam", "gps_level_camera", "gps_icp_reduce_noalloc",
            "gps_hash_reset", "gps_hash_fuse", "gps_hash_raycast", "gps_stream_blocks", "gps_stream_read",
-           "gps_stream_write"]
+           "gps_stream_write", "gps_icp_step"]
 
 _lib = None
 
@@ -157,6 +157,7 @@ def lib():
         L.gps_icp_workspace_size.argtypes = [I32, I32, ctypes.POINTER(ctypes.c_size_t)]
         L.gps_icp_reduce.argtypes = [P, P, P, P, P, F, P, P, ctypes.c_size_t, P]
         L.gps_icp_reduce_noalloc.argtypes = [P, P, P, P, P, F, P, P]
+        L.gps_icp_step.argtypes = [P, P, P, P, P, F, P, P, P, ctypes.c_size_t, P]
         L.gps_hash_reset.argtypes = [P, P]
         L.gps_stream_blocks.restype = I32
         L.gps_stream_read.argtypes = [P, ctypes.c_size_t, P, P]
@@ -950,6 +951,18 @@ def icp_reduce_noalloc(prev_cam, prev_depth, level_cam, level_depth, pose, dist_
     return out_sys
 
 
+def icp_step(prev_cam, prev_depth, level_cam, level_depth, pose, dist_thresh, ws: IcpWorkspace, stream=None):
+    """One Gauss-Newton step (gps_icp_step): the system into ws.sys, the pose updated in
+    place, xi into ws.xi -- icp_reduce then icp_solve with one launch fewer."""
+    pc, lc = camera(prev_cam), camera({**level_cam, "R": np.eye(3), "t": np.zeros(3)})
+    _check(lib().gps_icp_step(ctypes.byref(pc), _ptr(prev_depth, "prev_depth", pc.width * pc.height),
+                              ctypes.byref(lc), _ptr(level_depth, "level_depth", lc.width * lc.height),
+                              _ptr(pose, "pose", 12), float(dist_thresh), ctypes.c_void_p(ws.sys.data_ptr()),
+                              ctypes.c_void_p(ws.xi.data_ptr()), ctypes.c_void_p(ws.buf.data_ptr()), ws.nbytes,
+                              _stream(stream)), "gps_icp_step")
+    return ws.sys
+
+
 def icp_solve(sys: torch.Tensor, pose: torch.Tensor, xi: torch.Tensor | None = None, stream=None):
     """Solve and apply one Gauss-Newton step to the device pose (gps_icp_solve)."""
     _check(lib().gps_icp_solve(ctypes.c_void_p(sys.data_ptr()), _ptr(pose, "pose", 12),
@@ -974,6 +987,5 @@ def icp_track(prev_cam, prev_depth, cur_cam, cur_depth, pose: torch.Tensor, iter
         lvl = L - 1 - k
         lc = level_camera(cur_cam, lvl)
         for _ in range(iters[k]):
-            icp_reduce(prev_cam, prev_depth, lc, pyramid[lvl], pose, dist_thresh[k], ws, stream)
-            icp_solve(ws.sys, pose, ws.xi, stream)
+            icp_step(prev_cam, prev_depth, lc, pyramid[lvl], pose, dist_thresh[k], ws, stream)
     return pose

@@ -226,6 +226,11 @@ def test_icp_argument_checks(P):
     bad = P.camera({**_cam(), "fx": 0.0})
     assert L.gps_icp_reduce(ctypes.byref(cam), p, ctypes.byref(bad), p, p, 0.1, sp, p, 1 << 20, None) == -1
     assert L.gps_icp_solve(None, p, None, None) == -1 and L.gps_icp_solve(sp, None, None, None) == -1
+    # the fused step: the reduce's checks (pose, depth, threshold, workspace)
+    assert L.gps_icp_step(ctypes.byref(cam), p, ctypes.byref(cam), p, None, 0.1, sp, None, sp, 1 << 20, None) == -1
+    assert L.gps_icp_step(ctypes.byref(cam), None, ctypes.byref(cam), p, p, 0.1, sp, None, sp, 1 << 20, None) == -1
+    assert L.gps_icp_step(ctypes.byref(cam), p, ctypes.byref(cam), p, p, 0.0, sp, None, sp, 1 << 20, None) == -1
+    assert L.gps_icp_step(ctypes.byref(cam), p, ctypes.byref(cam), p, p, 0.1, sp, None, None, 1 << 20, None) == -1
     # the variant without a workspace checks the same arguments
     assert L.gps_icp_reduce_noalloc(ctypes.byref(cam), p, ctypes.byref(cam), p, p, 0.0, sp, None) == -1
     assert L.gps_icp_reduce_noalloc(ctypes.byref(cam), None, ctypes.byref(cam), p, p, 0.1, sp, None) == -1

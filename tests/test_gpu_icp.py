@@ -133,6 +133,26 @@ def test_icp_solve_parity(P):
         assert np.array_equal(xi2.cpu().numpy(), np.zeros(6, np.float32))
 
 
+def test_icp_step_is_reduce_then_solve(P):
+    """gps_icp_step (the system's sum and the solve in one launch) against gps_icp_reduce
+    followed by gps_icp_solve: system, pose and xi bitwise equal over four steps on two
+    levels."""
+    say("icp: fused step against reduce + solve")
+    camA, DA, camB, DB = _room_pair(320, 240)
+    ws1, ws2 = P.gps.IcpWorkspace(320, 240), P.gps.IcpWorkspace(320, 240)
+    pose1, pose2 = P.pose_tensor(camA), P.pose_tensor(camA)
+    D1 = t(DB)
+    D2 = P.depth_downsample(D1)
+    for lvl, D in ((1, D2), (1, D2), (0, D1), (0, D1)):
+        lc = P.gps.level_camera(camB, lvl)
+        P.icp_reduce(camA, t(DA), lc, D, pose1, 0.1, ws1)
+        P.icp_solve(ws1.sys, pose1, ws1.xi)
+        P.icp_step(camA, t(DA), lc, D, pose2, 0.1, ws2)
+        torch.cuda.synchronize()
+        assert torch.equal(ws1.sys, ws2.sys) and torch.equal(pose1, pose2) and torch.equal(ws1.xi, ws2.xi)
+    assert not torch.equal(pose1, P.pose_tensor(camA))  # the steps moved the pose
+
+
 def _angle(R, RB):
     """Rotation angle of R RB^T from both its symmetric and skew parts (arccos of the
     trace alone loses half the digits near 0)."""
