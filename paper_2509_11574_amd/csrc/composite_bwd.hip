@@ -38,9 +38,13 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     // wavefronts never share an LDS dword (sub-dword stores from different
     // wavefronts into one dword are not used anywhere).
     __shared__ unsigned long long swritten[NW];
-    if (w.hdr->n_inst > rp.cap) return;
-    // One block per tile, in queue order (longest tile lists first).
-    const int tile = (int)w.tile_queue[blockIdx.x];
+    // One block per tile, in queue order (longest tile lists first).  The queue entry is
+    // read together with the capacity check (one round trip) and checked against the
+    // tile count.
+    const unsigned long long n_inst = w.hdr->n_inst;
+    const unsigned int queued = w.tile_queue[blockIdx.x];
+    if ((n_inst > rp.cap) | (queued >= (unsigned int)vt.n_tiles)) return;
+    const int tile = (int)queued;
     const int v = find_view(vt, tile);
     const DevView& V = vt.v[v];
     const int lt = tile - V.tile_base;
@@ -66,42 +70,66 @@ __global__ void __launch_bounds__(TW * TH / PPT)
     // thr as in the forward: -inf once a pixel has stopped for a reason other
     // than the depth test (which every deeper record fails as well).
     float thr[PPT], T[PPT], G0[PPT], G1[PPT], G2[PPT], GD[PPT], CG[PPT], PG[PPT], invW[PPT];
+    // Every per-pixel load is issued before any is used, so the prologue waits for one
+    // round trip: addresses outside the image are clamped to pixel 0 and an absent
+    // depth plane is read from the base depth, the values then being dropped.
+    bool inb[PPT];
+    float ldt[PPT], lc0[PPT], lc1[PPT], lc2[PPT], lds[PPT], lx0[PPT], lx1[PPT], lx2[PPT], lxd[PPT], laux[PPT];
+    {
+        const float* xrgb = explicit_up ? V.g_rgb : V.target_rgb;
+        const float* xdep = explicit_up ? V.g_depth : V.target_depth;
+        const float* xdl = xdep ? xdep : V.base_depth;
 #pragma unroll
-    for (int k = 0; k < PPT; ++k) {
-        const int py = py0 + k * Lay::LROWS;
-        const bool inb = px < Wd && py < Ht;
-        const size_t p = inb ? (size_t)py * Wd + px : 0;
-        const float dt = inb ? V.base_depth[p] : 0.0f;
-        const bool dvalid = dt > 0.0f;
-        thr[k] = inb ? (dvalid ? dt : INFINITY) + rp.eps : -INFINITY;
-        T[k] = 1.0f;
-        PG[k] = 0.0f;
-        G0[k] = G1[k] = G2[k] = GD[k] = 0.0f;
-        float cs0 = 0.0f, cs1 = 0.0f, cs2 = 0.0f, ds = 0.0f;
-        invW[k] = 1.0f;
-        if (inb) {
-            cs0 = V.out_rgb[p];
-            cs1 = V.out_rgb[HW + p];
-            cs2 = V.out_rgb[2 * HW + p];
-            ds = V.out_depth[p];
-            if (MODE != 0) invW[k] = 1.0f / (1.0f + w.pix_aux[(size_t)V.pix_base + p]);
-            if (explicit_up) {
-                G0[k] = V.g_rgb[p];
-                G1[k] = V.g_rgb[HW + p];
-                G2[k] = V.g_rgb[2 * HW + p];
-                GD[k] = (V.g_depth && dvalid) ? V.g_depth[p] : 0.0f;
-            } else {
-                const float cn = sc * invV / (3.0f * (float)HW);
-                G0[k] = cn * sgnf(cs0 - V.target_rgb[p]);
-                G1[k] = cn * sgnf(cs1 - V.target_rgb[HW + p]);
-                G2[k] = cn * sgnf(cs2 - V.target_rgb[2 * HW + p]);
-                if (V.target_depth && dvalid && om > 0.0f) {
-                    const float dobs = V.target_depth[p];
-                    if (dobs > 0.0f) GD[k] = sc * invV * rp.lambda / om * sgnf(ds - dobs);
+        for (int k = 0; k < PPT; ++k) {
+            const int py = py0 + k * Lay::LROWS;
+            inb[k] = px < Wd && py < Ht;
+            const size_t p = inb[k] ? (size_t)py * Wd + px : 0;
+            ldt[k] = V.base_depth[p];
+            lc0[k] = V.out_rgb[p];
+            lc1[k] = V.out_rgb[HW + p];
+            lc2[k] = V.out_rgb[2 * HW + p];
+            lds[k] = V.out_depth[p];
+            laux[k] = MODE != 0 ? w.pix_aux[(size_t)V.pix_base + p] : 0.0f;
+            lx0[k] = xrgb[p];
+            lx1[k] = xrgb[HW + p];
+            lx2[k] = xrgb[2 * HW + p];
+            lxd[k] = xdl[p];
+        }
+        const bool has_xdep = xdep != nullptr;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const float dt = inb[k] ? ldt[k] : 0.0f;
+            const bool dvalid = dt > 0.0f;
+            thr[k] = inb[k] ? (dvalid ? dt : INFINITY) + rp.eps : -INFINITY;
+            T[k] = 1.0f;
+            PG[k] = 0.0f;
+            G0[k] = G1[k] = G2[k] = GD[k] = 0.0f;
+            float cs0 = 0.0f, cs1 = 0.0f, cs2 = 0.0f, ds = 0.0f;
+            invW[k] = 1.0f;
+            if (inb[k]) {
+                cs0 = lc0[k];
+                cs1 = lc1[k];
+                cs2 = lc2[k];
+                ds = lds[k];
+                if (MODE != 0) invW[k] = 1.0f / (1.0f + laux[k]);
+                if (explicit_up) {
+                    G0[k] = lx0[k];
+                    G1[k] = lx1[k];
+                    G2[k] = lx2[k];
+                    GD[k] = (has_xdep && dvalid) ? lxd[k] : 0.0f;
+                } else {
+                    const float cn = sc * invV / (3.0f * (float)HW);
+                    G0[k] = cn * sgnf(cs0 - lx0[k]);
+                    G1[k] = cn * sgnf(cs1 - lx1[k]);
+                    G2[k] = cn * sgnf(cs2 - lx2[k]);
+                    if (has_xdep && dvalid && om > 0.0f) {
+                        const float dobs = lxd[k];
+                        if (dobs > 0.0f) GD[k] = sc * invV * rp.lambda / om * sgnf(ds - dobs);
+                    }
                 }
             }
+            CG[k] = G0[k] * cs0 + G1[k] * cs1 + G2[k] * cs2 + GD[k] * ds;
         }
-        CG[k] = G0[k] * cs0 + G1[k] * cs1 + G2[k] * cs2 + GD[k] * ds;
     }
 
     const unsigned int s = w.tile_start[tile], e = w.tile_start[tile + 1];
@@ -272,8 +300,10 @@ __global__ void __launch_bounds__(256) k_composite_bwd_pg(const ViewTable* __res
     __shared__ float4 s_g[NP];  // (dL/dC*, dL/dD*) / (1 + W_G)
     __shared__ float2 s_x[NP];  // G.(C*, D*) / (1 + W_G), D_t + eps (-inf outside the image)
     __shared__ float s_red[4][4 * kAdj];  // per wavefront: the ten row totals of its four rows
-    if (w.hdr->n_inst > rp.cap) return;
-    const int tile = (int)w.tile_queue[blockIdx.x];
+    const unsigned long long n_inst = w.hdr->n_inst;
+    const unsigned int queued = w.tile_queue[blockIdx.x];
+    if ((n_inst > rp.cap) | (queued >= (unsigned int)vt.n_tiles)) return;
+    const int tile = (int)queued;
     const int v = find_view(vt, tile);
     const DevView& V = vt.v[v];
     const int lt = tile - V.tile_base;

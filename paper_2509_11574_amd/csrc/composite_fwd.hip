@@ -57,11 +57,15 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
     constexpr int NT = Lay::NT;
     __shared__ float4 srec[3 * B];
     __shared__ unsigned int smask[B];  // wavefront mask per staged record (32-bit: no byte stores in LDS)
-    if (w.hdr->n_inst > rp.cap) return;
     // One block per tile, in queue order (longest tile lists first): the
     // hardware dispatches blocks in index order as resources free up, which
-    // balances tiles of very different lengths without any global counter.
-    const int tile = (int)w.tile_queue[blockIdx.x];
+    // balances tiles of very different lengths without any global counter.  The
+    // queue entry is read together with the capacity check (one round trip) and
+    // checked against the tile count.
+    const unsigned long long n_inst = w.hdr->n_inst;
+    const unsigned int queued = w.tile_queue[blockIdx.x];
+    if ((n_inst > rp.cap) | (queued >= (unsigned int)vt.n_tiles)) return;
+    const int tile = (int)queued;
     const int v = find_view(vt, tile);
     const DevView& V = vt.v[v];
     const int lt = tile - V.tile_base;
@@ -163,17 +167,38 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
         }
     }
 
-    // epilogue: outputs and the fused loss partial of this tile
+    // epilogue: outputs and the fused loss partial of this tile.  The inputs of every
+    // pixel of the lane are loaded before the first store (addresses outside the image
+    // clamped to pixel 0, absent target planes read from the base images, the values
+    // then dropped), so the epilogue waits for one round trip.
     float lc = 0.0f, ld = 0.0f, lo = 0.0f;
+    float edt[PPT], ec0[PPT], ec1[PPT], ec2[PPT], et0[PPT], et1[PPT], et2[PPT], etd[PPT];
+    {
+        const float* trgb = V.target_rgb ? V.target_rgb : V.base_rgb;
+        const float* tdep = V.target_depth ? V.target_depth : V.base_depth;
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const int py = py0 + k * Lay::LROWS;
+            const size_t p = (px < Wd && py < Ht) ? (size_t)py * Wd + px : 0;
+            edt[k] = V.base_depth[p];
+            ec0[k] = V.base_rgb[p];
+            ec1[k] = V.base_rgb[HW + p];
+            ec2[k] = V.base_rgb[2 * HW + p];
+            et0[k] = trgb[p];
+            et1[k] = trgb[HW + p];
+            et2[k] = trgb[2 * HW + p];
+            etd[k] = tdep[p];
+        }
+    }
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         const int py = py0 + k * Lay::LROWS;
         if (!(px < Wd && py < Ht)) continue;
         const size_t p = (size_t)py * Wd + px;
-        const float dt = V.base_depth[p];
+        const float dt = edt[k];
         const bool dvalid = dt > 0.0f;
         float Cs[3], Ds;
-        const float ct0 = V.base_rgb[p], ct1 = V.base_rgb[HW + p], ct2 = V.base_rgb[2 * HW + p];
+        const float ct0 = ec0[k], ct1 = ec1[k], ct2 = ec2[k];
         if (MODE == 0) {
             Cs[0] = __builtin_fmaf(T[k], ct0, ac0[k]);
             Cs[1] = __builtin_fmaf(T[k], ct1, ac1[k]);
@@ -193,10 +218,9 @@ __global__ void __launch_bounds__(TW * TH / PPT) k_composite_fwd(const ViewTable
         w.pix_aux[(size_t)V.pix_base + p] = T[k];
         if (V.out_aux) V.out_aux[p] = T[k];
         if (V.target_rgb) {
-            lc += fabsf(Cs[0] - V.target_rgb[p]) + fabsf(Cs[1] - V.target_rgb[HW + p]) +
-                  fabsf(Cs[2] - V.target_rgb[2 * HW + p]);
+            lc += fabsf(Cs[0] - et0[k]) + fabsf(Cs[1] - et1[k]) + fabsf(Cs[2] - et2[k]);
             if (V.target_depth) {
-                const float dobs = V.target_depth[p];
+                const float dobs = etd[k];
                 if (dobs > 0.0f && dvalid) {
                     ld += fabsf(Ds - dobs);
                     lo += 1.0f;

@@ -64,18 +64,16 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
 #pragma unroll
     for (int k = 0; k < NSH; ++k) gsh[k] = 0.0f;
     __shared__ float pred[kBlk / 64][6];
-    __shared__ float sbc[2];
-    if (af.on) {
-        if (threadIdx.x == 0) adam_bias(af.step_ctr ? (*af.step_ctr + 1) : af.step, af.b1, af.b2, &sbc[0], &sbc[1]);
-        __syncthreads();
-    }
 
-    // The Adam state of the five parameter groups (14 scalars) is loaded first, with
-    // the parameters, so that its loads overlap the slot sums instead of following them.
+    // Every load that does not depend on another is issued here, before any of them is
+    // waited for: the slot count and offset of the first view, the Adam state of the
+    // five parameter groups (14 scalars) and the parameters.  The slot sums then wait
+    // for one round trip, and the Adam loads overlap them.
+    const unsigned int cnt0 = live ? w.cnt[g] : 0u, off0 = live ? w.off[g] : 0u;
     constexpr int kAdamRows[5] = {3, 3, 4, 1, 3};
     float ap[14], am[14], av[14];
     const bool adam_here = live && af.on && !over;
-    if (adam_here) {
+    if (live && af.on) {
         int j = 0;
 #pragma unroll
         for (int a = 0; a < 5; ++a)
@@ -128,11 +126,17 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
 #pragma unroll
         for (int c = 0; c < 3; ++c) S3[3 * r + c] = Mm[3 * r] * Mm[3 * c] + Mm[3 * r + 1] * Mm[3 * c + 1] + Mm[3 * r + 2] * Mm[3 * c + 2];
 
+    // Adam's bias corrections, per lane (no barrier, so no wait for the loads above)
+    float ibc1 = 1.0f, ibc2 = 1.0f;
+    if (adam_here) adam_bias(af.step_ctr ? (*af.step_ctr + 1) : af.step, af.b1, af.b2, &ibc1, &ibc2);
+
     for (int v = 0; v < vt.n; ++v) {
         float pose[6] = {0, 0, 0, 0, 0, 0};
         const size_t vg = (size_t)v * M + g;
-        unsigned int cnt = (live && !over) ? w.cnt[vg] : 0u;
-        const unsigned int o = cnt ? w.off[vg] : 0u;
+        const unsigned int cl = v == 0 ? cnt0 : (live ? w.cnt[vg] : 0u);
+        const unsigned int ol = v == 0 ? off0 : (live ? w.off[vg] : 0u);
+        unsigned int cnt = over ? 0u : cl;
+        const unsigned int o = cnt ? ol : 0u;
         if ((unsigned long long)o + cnt > w.hdr->n_inst) cnt = 0u;  // guard: stay inside the emitted slots
         // Slots of tiles removed by the depth cull were zeroed by the emission, so the
         // whole contiguous range is summed (in a fixed order).
@@ -377,7 +381,6 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
     if (adam_here) {
         // this lane's Gaussian only: its parameters and moments were read above by this
         // lane alone
-        const float ibc1 = sbc[0], ibc2 = sbc[1];
         const float* gr[5] = {gmean, gls, gq, &gop, grgb};
         int j = 0;
 #pragma unroll

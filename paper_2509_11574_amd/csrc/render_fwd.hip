@@ -360,7 +360,6 @@ __global__ void __launch_bounds__(kBlk) k_expand(const ViewTable* __restrict__ v
 {
     constexpr int kSplit = kBlk / kExpG;  // expansion blocks per projection block
     const ViewTable& vt = *vtp;
-    if (w.hdr->n_inst > rp.cap) return;
     __shared__ unsigned int pre[kExpG + 1];
     __shared__ float4 sbox[kExpG];  // mx, my, rxp, ryp
     __shared__ float4 scon[kExpG];  // the exponent's coefficients A, B, C and log2 sigma
@@ -369,24 +368,35 @@ __global__ void __launch_bounds__(kBlk) k_expand(const ViewTable* __restrict__ v
     const int pb = blockIdx.x / kSplit;
     const int g0 = (blockIdx.x % kSplit) * kExpG;  // first lane (Gaussian) of this block's share
     const int vg = pb * kBlk + threadIdx.x;         // lane k: Gaussian k of the projection block
+    const int k = threadIdx.x - g0;
+    // The count, the record of this block's share (written by the projection for every
+    // view-Gaussian) and the block's slot base are loaded together with the capacity
+    // check, before any of them is waited for.
+    const bool mine = k >= 0 && k < kExpG && vg < rp.nvg;
+    const unsigned long long n_inst = w.hdr->n_inst;
     const unsigned int c = vg < rp.nvg ? w.cnt[vg] : 0u;
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;
+    if (mine) {
+        r0 = w.rec[3 * (size_t)vg];
+        r1 = w.rec[3 * (size_t)vg + 1];
+        r2 = w.rec[3 * (size_t)vg + 2];
+    }
+    const unsigned int base = w.blk_off[pb];
+    if (n_inst > rp.cap) return;
     unsigned int tot;
     const unsigned int excl = block_excl_scan<kBlk>(c, &tot);  // prefix within the projection block
-    const int k = threadIdx.x - g0;
     if (k >= 0 && k < kExpG) {
         pre[k] = excl;
         if (k == kExpG - 1) pre[kExpG] = excl + c;
         if (c > 0) {
-            const float4 r0 = w.rec[3 * (size_t)vg], r1 = w.rec[3 * (size_t)vg + 1], r2 = w.rec[3 * (size_t)vg + 2];
             sbox[k] = make_float4(r0.x, r0.y, r2.z, r2.w);
             scon[k] = make_float4(r0.z, r0.w, r1.x, r1.y);
             sz[k] = r1.z;
             const DevView& V = vt.v[vg / rp.M];
             sview[k] = make_int4(V.tile_base, V.tiles_x, V.cam.W, V.cam.H);
         }
-        if (!EMIT && vg < rp.nvg) w.off[vg] = w.blk_off[pb] + excl;
+        if (!EMIT && vg < rp.nvg) w.off[vg] = base + excl;
     }
-    const unsigned int base = w.blk_off[pb];
     // sub-counter of this block: the same block index, so the same sub-counter, in both passes
     const size_t sub = (size_t)(blockIdx.x % kCntSplit) * vt.n_tiles;
     __syncthreads();
