@@ -21,6 +21,7 @@ namespace gps {
 
 // ------------------------------------------------------------- gauss bwd
 constexpr unsigned int kCoopSlots = 32;  // more slots than this: summed by the whole wavefront
+constexpr unsigned int kSlotGroup = 8;   // slots loaded together by one lane
 
 // EWA chain rule of one Gaussian in one view.  The summed instance partials are
 // first turned into A[10] = dL/d(mx, my, a, b, c), sigma dL/dsigma, dL/d(r, g, b, d),
@@ -166,11 +167,27 @@ __global__ void __launch_bounds__(kBlk) k_gauss_bwd(const ViewTable* __restrict_
             big &= big - 1ull;
         }
         if (cnt > 0 && cnt <= kCoopSlots) {
+            // The lane's slots in groups of kSlotGroup: the loads of a group are issued
+            // together, so a group costs one round trip (a position past the count reads
+            // the group's first slot again and adds zero); the slots are still added in
+            // order (adding +0.0 to a sum that starts at +0.0 leaves it unchanged).
             const float* part = w.partial + (size_t)o * kAdj;
-#pragma unroll 4
-            for (unsigned int k = 0; k < cnt; ++k)
+            for (unsigned int k0 = 0; k0 < cnt; k0 += kSlotGroup) {
+                float sv[kSlotGroup][kAdj];
 #pragma unroll
-                for (int q = 0; q < kAdj; ++q) A[q] += part[(size_t)k * kAdj + q];
+                for (unsigned int i = 0; i < kSlotGroup; ++i) {
+                    const bool has = k0 + i < cnt;
+                    const float* ps = part + (size_t)(has ? k0 + i : k0) * kAdj;
+#pragma unroll
+                    for (int q = 0; q < kAdj; ++q) sv[i][q] = ps[q];
+#pragma unroll
+                    for (int q = 0; q < kAdj; ++q) sv[i][q] = has ? sv[i][q] : 0.0f;
+                }
+#pragma unroll
+                for (unsigned int i = 0; i < kSlotGroup; ++i)
+#pragma unroll
+                    for (int q = 0; q < kAdj; ++q) A[q] += sv[i][q];
+            }
         }
         if (cnt > 0) {
             // The compositing kernel accumulates, with u = dL/dalpha * alpha, the sums
