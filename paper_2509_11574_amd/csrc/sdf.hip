@@ -77,9 +77,50 @@ struct BrickArgs {
     float* bmin;
 };
 
-// Brick minima: one wavefront per 8^3 brick, over its 9^3 lattice points (the
-// brick and the first plane of its +x, +y, +z neighbours: every 2x2x2 sample
-// stencil based in the brick), four bricks per block.
+// Brick minima over the 9^3 lattice points of each brick (the brick and the first
+// plane of its +x, +y, +z neighbours: every 2x2x2 sample stencil based in the brick).
+// One block per row of bricks along x: each lane takes lattice columns x (lanes along
+// x, so every load of the block reads whole rows of the lattice) and the minimum over
+// the 9 x 9 (y, z) points of its column, kept in LDS; then each brick takes the
+// minimum over its 9 columns.  Rows of up to kRowCols columns; longer ones use the
+// per-brick kernel below.
+constexpr int kRowCols = 4096;
+
+__global__ void __launch_bounds__(256) k_brick_min_rows(BrickArgs a)
+{
+    __shared__ float scol[kRowCols];
+    const int byi = (int)blockIdx.x % a.by, bzi = (int)blockIdx.x / a.by;
+    const int y0 = byi * kBrick, z0 = bzi * kBrick;
+    const int ny = min(kBrick + 1, a.ny - y0), nz = min(kBrick + 1, a.nz - z0);
+    for (int x = threadIdx.x; x < a.nx; x += 256) {
+        // the 81 loads of a column are issued before the first is used (a point past
+        // the lattice edge reads the column's first point again)
+        float v[kBrick + 1][kBrick + 1];
+#pragma unroll
+        for (int dz = 0; dz < kBrick + 1; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < kBrick + 1; ++dy) {
+                const int yy = y0 + (dy < ny ? dy : 0), zz = z0 + (dz < nz ? dz : 0);
+                v[dz][dy] = a.tsdf[x + (size_t)a.nx * ((size_t)yy + (size_t)a.ny * (size_t)zz)];
+            }
+        float m = INFINITY;
+#pragma unroll
+        for (int dz = 0; dz < kBrick + 1; ++dz)
+#pragma unroll
+            for (int dy = 0; dy < kBrick + 1; ++dy) m = fminf(m, v[dz][dy]);
+        scol[x] = m;
+    }
+    __syncthreads();
+    for (int bxi = threadIdx.x; bxi < a.bx; bxi += 256) {
+        const int x0 = bxi * kBrick, x1 = min(x0 + kBrick, a.nx - 1);
+        float m = INFINITY;
+        for (int x = x0; x <= x1; ++x) m = fminf(m, scol[x]);
+        a.bmin[bxi + (size_t)a.bx * (byi + (size_t)a.by * bzi)] = m;
+    }
+}
+
+// The same minima, one wavefront per 8^3 brick, four bricks per block (rows longer
+// than kRowCols).
 __global__ void __launch_bounds__(256) k_brick_min(BrickArgs a)
 {
     const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -205,7 +246,10 @@ gps_status launch_raycast(const gps_volume* vol, const gps_camera* cams, int n_v
     f.smin = vol->brick_min ? vol->brick_min + (size_t)f.bx * f.by * bz : nullptr;
     if (vol->brick_min) {
         BrickArgs b{vol->nx, vol->ny, vol->nz, f.bx, f.by, bz, vol->tsdf, vol->brick_min};
-        GPS_LAUNCH(K_BRICK_MIN, s, k_brick_min, dim3((f.bx * f.by * bz + 3) / 4), dim3(256), 0, s, b);
+        if (vol->nx <= kRowCols)
+            GPS_LAUNCH(K_BRICK_MIN, s, k_brick_min_rows, dim3(f.by * bz), dim3(256), 0, s, b);
+        else
+            GPS_LAUNCH(K_BRICK_MIN, s, k_brick_min, dim3((f.bx * f.by * bz + 3) / 4), dim3(256), 0, s, b);
         const int ns = f.sx * f.sy * sz;
         GPS_LAUNCH(K_BRICK_MIN, s, k_super_min, dim3((ns + 3) / 4), dim3(256), 0, s, vol->brick_min,
                    vol->brick_min + (size_t)f.bx * f.by * bz, f.bx, f.by, bz, f.sx, f.sy, sz);

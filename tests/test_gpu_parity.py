@@ -136,6 +136,46 @@ def test_raycast_bricks_do_not_change_result(P, O, small):
     np.testing.assert_array_equal(outs[0][1], outs[1][1])
 
 
+def _brick_minima(tsdf):
+    """Minimum over the 9^3 lattice points [8b, 8b + 8] (clipped) of each brick, then over
+    each 4^3 group of bricks; tsdf indexed [z, y, x]."""
+    nz, ny, nx = tsdf.shape
+    B = [(n + 7) // 8 for n in (nx, ny, nz)]
+    bm = np.empty((B[2], B[1], B[0]), np.float32)
+    for k in range(B[2]):
+        for j in range(B[1]):
+            for i in range(B[0]):
+                bm[k, j, i] = tsdf[8 * k:8 * k + 9, 8 * j:8 * j + 9, 8 * i:8 * i + 9].min()
+    S = [(b + 3) // 4 for b in B]
+    sm = np.empty((S[2], S[1], S[0]), np.float32)
+    for k in range(S[2]):
+        for j in range(S[1]):
+            for i in range(S[0]):
+                sm[k, j, i] = bm[4 * k:4 * k + 4, 4 * j:4 * j + 4, 4 * i:4 * i + 4].min()
+    return bm.reshape(-1), sm.reshape(-1)
+
+
+@pytest.mark.parametrize("dims", [(64, 64, 64), (70, 45, 37), (4100, 3, 10)],
+                         ids=["64^3", "ragged", "long-rows"])
+def test_brick_minima(P, dims):
+    """The brick and superbrick minima the raycast rebuilds, against their definition, on
+    random values: a whole lattice, ragged edges in every axis, and rows longer than the
+    row kernel takes (the per-brick kernel)."""
+    nx, ny, nz = dims
+    rng = np.random.Generator(np.random.PCG64(31))
+    vals = rng.uniform(-1.0, 1.0, (nz, ny, nx)).astype(np.float32)
+    vol = P.Volume(dims, (0.0, 0.0, 0.0), 0.02, 0.08, device=DEV, skip_bricks=True)
+    vol.tsdf.copy_(t(vals.reshape(-1)))
+    cam = synth.Camera(64, 48, 60.0, 60.0, 32.0, 24.0, np.eye(3, dtype=np.float32),
+                       np.array([-0.3, -0.3, -1.0], np.float32))
+    P.raycast(vol, [cam.as_dict()], z_near=0.2)
+    torch.cuda.synchronize()
+    bm, sm = _brick_minima(vals)
+    got = h(vol.brick_min)
+    np.testing.assert_array_equal(got[:bm.size], bm)
+    np.testing.assert_array_equal(got[bm.size:bm.size + sm.size], sm)
+
+
 # ------------------------------------------------------------ render fwd
 TILES = [(16, 16, 256, 1), (8, 8, 128, 1), (16, 16, 128, 2), (16, 16, 512, 4), (16, 32, 256, 2), (16, 32, 128, 1),
          (32, 16, 128, 2)]
