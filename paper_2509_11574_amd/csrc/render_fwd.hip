@@ -264,6 +264,7 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(RParams rp, WsPtrs w, int n
     }
     __syncthreads();
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    unsigned int last_tot[4] = {0u, 0u, 0u, 0u};  // the lane's tile lengths in the last chunk
     // One pass per chunk of 4 tiles per lane: the sub-counts are read once, their
     // totals scanned over the block (chunks carried in order) into the tile
     // ranges, each sub-counter replaced by the start of its range inside its
@@ -310,6 +311,7 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(RParams rp, WsPtrs w, int n
                 atomicAdd(&hist[31 - __clz(tot[i] + 1u)], 1u);
                 if (tot[i] >= kLongTile) atomicAdd(&n_large, 1u);
             }
+            last_tot[i] = tot[i];
             run += tot[i];
         }
         __syncthreads();
@@ -327,6 +329,15 @@ __global__ void __launch_bounds__(1024) k_scan_tiles(RParams rp, WsPtrs w, int n
         }
     }
     __syncthreads();
+    if (n_tiles <= 4 * 1024) {
+        // one chunk: this lane's four tile lengths are still in registers
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int t = threadIdx.x * 4 + i;
+            if (t < n_tiles) w.tile_queue[atomicAdd(&cur[31 - __clz(last_tot[i] + 1u)], 1u)] = (unsigned int)t;
+        }
+        return;
+    }
     for (int i = threadIdx.x; i < n_tiles; i += 1024) {
         const unsigned int pos = atomicAdd(&cur[31 - __clz(w.tile_start[i + 1] - w.tile_start[i] + 1u)], 1u);
         w.tile_queue[pos] = (unsigned int)i;

@@ -166,6 +166,10 @@ struct DenseField {
     const float* bmin;  // may be null
     const float* smin;  // superbrick minima (null with bmin)
     int bx, by, sx, sy;
+    // The last brick found not positive (and its superbrick not positive), or -1:
+    // successive samples of a ray mostly stay in one brick, whose answer does not
+    // change during a raycast, so its minima are not read again.
+    mutable int cbrick = -1;
 
     __device__ __forceinline__ void fetch8(int plane, const int b[3], float q[8]) const
     {
@@ -188,19 +192,24 @@ struct DenseField {
     {
         if (!bmin) return false;
         const int i0 = b[0] >> 3, i1 = b[1] >> 3, i2 = b[2] >> 3;
+        const int bi = i0 + bx * (i1 + by * i2);
+        if (bi == cbrick) return false;
         const int j0 = i0 / kSuper, j1 = i1 / kSuper, j2 = i2 / kSuper;
+        // both minima are read before either is tested (one round trip)
+        const float ms = smin[j0 + sx * (j1 + sy * j2)], mb = bmin[bi];
         int edge, bb[3];
-        if (smin[j0 + sx * (j1 + sy * j2)] > kBrickPositive) {
+        if (ms > kBrickPositive) {
             edge = kBrick * kSuper;  // the whole superbrick is positive
             bb[0] = j0;
             bb[1] = j1;
             bb[2] = j2;
-        } else if (bmin[i0 + bx * (i1 + by * i2)] > kBrickPositive) {
+        } else if (mb > kBrickPositive) {
             edge = kBrick;
             bb[0] = i0;
             bb[1] = i1;
             bb[2] = i2;
         } else {
+            cbrick = bi;
             return false;
         }
 #pragma unroll
@@ -219,7 +228,8 @@ __global__ void __launch_bounds__(256) k_raycast(MarchArgs a, DenseField fld)
     const int col = blockIdx.x * 16 + (threadIdx.x & 15);
     const int row = blockIdx.y * 16 + (threadIdx.x >> 4);
     if (col >= c.W || row >= c.H) return;
-    march_pixel(a, fld, view, col, row);
+    const DenseField f = fld;  // this lane's copy (it keeps the last brick found not positive)
+    march_pixel(a, f, view, col, row);
 }
 
 gps_status launch_raycast(const gps_volume* vol, const gps_camera* cams, int n_views, float* const* out_depth,
