@@ -15,12 +15,26 @@ __device__ __forceinline__ void adam_one(float& p, float g, float& m, float& v, 
     p -= lr * mh / (sqrtf(vh) + eps);
 }
 
+// beta^t for an integer t >= 0 by repeated squaring in binary64: at most 2 log2 t
+// products, so a relative error below 1e-14, far under the binary32 rounding of the
+// bias correction it feeds (a few dozen instructions instead of a general pow).
+__device__ __forceinline__ double pow_uint(double b, unsigned int t)
+{
+    double r = 1.0, p = b;
+    for (; t; t >>= 1) {
+        if (t & 1u) r *= p;
+        p *= p;
+    }
+    return r;
+}
+
 // Bias corrections 1 / (1 - beta^t), in double (1 - beta^t loses digits in
 // binary32 for small t).
 __device__ __forceinline__ void adam_bias(int t, float b1, float b2, float* ibc1, float* ibc2)
 {
-    *ibc1 = (float)(1.0 / (1.0 - pow((double)b1, (double)t)));
-    *ibc2 = (float)(1.0 / (1.0 - pow((double)b2, (double)t)));
+    const unsigned int ut = t > 0 ? (unsigned int)t : 0u;
+    *ibc1 = (float)(1.0 / (1.0 - pow_uint((double)b1, ut)));
+    *ibc2 = (float)(1.0 / (1.0 - pow_uint((double)b2, ut)));
 }
 
 }  // namespace gps
