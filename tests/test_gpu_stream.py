@@ -1,10 +1,10 @@
 """The large streaming configuration over a long sequence: a 512^3 lattice at 5 mm
-(3.2 GB) fused with 600 orbit frames of 1280x720 (six turns of the orbit, new depth
+(3.2 GB) fused with 1000 orbit frames of 1280x720 (ten turns of the orbit, new depth
 noise every frame) while 1,000,000 Gaussians are optimised -- 10 batched iterations per
 frame over the latest 4 keyframes, a new keyframe every 10 frames (Sec. 3.2.1 fusion,
 Sec. 3.1 mapping over a window of target views).
 
-Spot checks every 150 frames:
+Spot checks every 100 frames:
 * Fusion, at 20,000 lattice points (half uniform over the lattice, half within 4 voxels of
   the scene's surfaces, chosen from the synthetic scene's own geometry): the reference's
   update of those points alone over every frame so far (orc_fuse_points).  Weights are
@@ -23,7 +23,7 @@ import synth
 from tests.gpu_util import DEV, h, say
 
 pytestmark = pytest.mark.gpu
-N_FRAMES, CHECK_EVERY, N_POINTS = 600, 150, 20_000
+N_FRAMES, CHECK_EVERY, N_POINTS = 1000, 100, 20_000
 
 
 @pytest.fixture(scope="module")
